@@ -1,0 +1,187 @@
+"""Benchmark: Hessian-vector products per second on one MI355X.
+
+One step = one pass of the whole hot path over one batch: float64 chunked
+H.v for Rosenbrock, Ackley and Fletcher-Powell, each at n = 16 over 2^20
+resident points (seeded synthetic inputs), three launches through the C ABI.
+`value` is the total HVPs of a step divided by the step time.
+
+Also reported:
+  roofline      the dominant kernel's paper-model flops per launch divided by
+                its average launch time (HIP events around each launch inside
+                the timed region), against the float64 vector peak;
+  cpu_baseline  the CPU oracle's chunked method (plain C, OpenMP over points,
+                all host cores) timed on a bounded sample of the same inputs.
+
+    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+FUNCS = (0, 1, 2)
+NAMES = {0: "rosenbrock", 1: "ackley", 2: "fletcher_powell"}
+N = 16
+NPTS = 1 << 20
+PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (FMA = 2)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chunk", type=int, default=0, help="0 = library default per function")
+    ap.add_argument("--npts", type=int, default=NPTS)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(workloads, E, chunks, budget_s):
+    """Time the oracle's chunked CHESS-VEC (C, OpenMP) on a bounded sample."""
+    from oracle import chunked
+
+    chunked.build()
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    # calibrate on a small sample, then size the sample to the budget
+    sample = 64
+    while True:
+        t0 = time.perf_counter()
+        for f in FUNCS:
+            w = workloads[f]
+            chunked.hvp(f, w.x[:sample], w.v[:sample], chunks[f], w.A, w.B, E[f], nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt > 0.5 or sample >= 1 << 16:
+            break
+        sample *= 2
+    sample = int(min(NPTS, max(sample, sample * budget_s / max(dt, 1e-9))))
+    t0 = time.perf_counter()
+    per = {}
+    for f in FUNCS:
+        w = workloads[f]
+        t1 = time.perf_counter()
+        chunked.hvp(f, w.x[:sample], w.v[:sample], chunks[f], w.A, w.B, E[f], nthreads=threads)
+        per[NAMES[f]] = sample / (time.perf_counter() - t1)
+    dt = time.perf_counter() - t0
+    return {"value": 3 * sample / dt, "unit": "HVP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of the {NPTS} points of each function (n=16, same chunk sizes), "
+                      f"oracle/chunked.c CHESS-VEC with OpenMP over points",
+            "per_function": per}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(points shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2410_22575_amd import binding, flops, inputs
+    from oracle import closed_form as cf
+
+    binding.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    npts = args.npts
+
+    # seeded synthetic inputs, resident in HBM before timing
+    workloads, E, xs, vs, outs, chunks = {}, {}, {}, {}, {}, {}
+    for f in FUNCS:
+        w = inputs.make_workload(f, N, npts, inputs.rng_for(1))
+        workloads[f] = w
+        xs[f] = torch.from_numpy(w.x).to(dev)
+        vs[f] = torch.from_numpy(w.v).to(dev)
+        outs[f] = torch.empty_like(xs[f])
+        E[f] = None
+        if f == 2:
+            binding.chessfad_fp_set_params(torch.from_numpy(w.A).to(dev), torch.from_numpy(w.B).to(dev),
+                                           torch.from_numpy(w.alpha).to(dev))
+            E[f] = cf.fp_offsets(w.A, w.B, w.alpha)
+        chunks[f] = args.chunk or binding.chessfad_default_chunk(f, N)
+    torch.cuda.synchronize()
+
+    def step(events=None):
+        for f in FUNCS:
+            if events is not None:
+                events[f][0].record()
+            binding.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=chunks[f])
+            if events is not None:
+                events[f][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [{f: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for f in FUNCS}
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    kernel_ms = {f: float(np.mean([e[f][0].elapsed_time(e[f][1]) for e in evs])) for f in FUNCS}
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = len(FUNCS) * npts / (elapsed / args.steps)
+
+    per_func = {}
+    for f in FUNCS:
+        mf = flops.flops_per_hvp(f, N, chunks[f])
+        per_func[NAMES[f]] = {
+            "chunk": chunks[f], "kernel_ms": round(kernel_ms[f], 4),
+            "hvps_per_s": npts / (kernel_ms[f] * 1e-3),
+            "model_tflops": mf * npts / (kernel_ms[f] * 1e-3) / 1e12,
+            "model_flops_per_hvp": mf,
+        }
+    dom = max(FUNCS, key=lambda f: kernel_ms[f])
+    achieved = per_func[NAMES[dom]]["model_tflops"]
+
+    # quick sanity check of the last outputs on a few points (oracle on CPU)
+    max_err = {}
+    for f in FUNCS:
+        w = workloads[f]
+        idx = np.arange(0, npts, max(1, npts // 64))
+        H = cf.hessian(f, w.x[idx], w.A, w.B, E[f])
+        ref = np.einsum("pij,pj->pi", H, w.v[idx])
+        got = outs[f].cpu().numpy()[idx]
+        err = np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
+        max_err[NAMES[f]] = float(err.max())
+
+    result = {
+        "metric": "HVPs/sec (float64 chunked forward-mode H.v, n=16)",
+        "value": value,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain FP64 H.v: Rosenbrock, Ackley, Fletcher-Powell; n=16; "
+                               f"{npts} points each; chunk per function",
+                   "n": N, "npts": npts, "chunks": {NAMES[f]: chunks[f] for f in FUNCS}},
+        "roofline": {"bound": "alu", "kernel": f"plain_kernel<{NAMES[dom]}, C={chunks[dom]}, H.v>",
+                     "achieved": achieved, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_F64_TFLOPS, "traffic": None},
+        "per_function": per_func,
+        "max_rel_err_sampled": max_err,
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(workloads, E, chunks, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

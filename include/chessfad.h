@@ -1,0 +1,113 @@
+/*
+ * chessfad.h - C ABI of the MI355X (gfx950) chunked forward-mode Hessian library.
+ *
+ * The library computes, at many independent points, full Hessians and
+ * Hessian-vector products of three test functions (Rosenbrock, Ackley,
+ * Fletcher-Powell; Sec. VII) by the chunked forward-mode method of
+ * Sec. III.B: every value is an hDual carrying the value, the derivative
+ * with respect to the row variable x_i, a chunk of csize first derivatives
+ * and the matching chunk of row i of the Hessian (Sec. IV), and f is
+ * evaluated once per (point, row i, chunk) with CHUNK-INIT seeds.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd memory or a
+ *     torch CUDA tensor) owned by the caller; the library never frees it.
+ *   - Arrays are dense, row-major and point-major: point p occupies
+ *     x[p*n .. p*n+n), v[p*n .. p*n+n), out[p*n .. p*n+n) and, for Hessians,
+ *     H[p*n*n .. p*n*n+n*n) with H[p][i][j] at p*n*n + i*n + j.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Compute calls
+ *     only enqueue work and return without synchronising.
+ *   - Return value: CHESSFAD_OK (0) or a negative chessfad_status.  All
+ *     argument checks happen on the host before anything is enqueued; a
+ *     failed check leaves every output untouched.  CHESSFAD_E_HIP reports a
+ *     HIP launch/runtime error (text via chessfad_strerror).
+ *   - npts == 0 is a no-op returning CHESSFAD_OK.
+ *   - chunk is the chunk size csize; 0 picks the library default for
+ *     (func_id, n).  Compiled sizes: 1, 2, 4, 8, 16.  chunk may not exceed
+ *     n; when n is not a multiple of chunk the last chunk of every row is
+ *     ragged (it seeds only the columns < n; Sec. III.B assumes csize | n).
+ *   - Calls on different streams are independent.  chessfad_fp_set_params
+ *     and chessfad_fp_release must not race with compute calls that read
+ *     the same n.
+ */
+#ifndef CHESSFAD_H
+#define CHESSFAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum chessfad_func {
+    CHESSFAD_ROSENBROCK = 0,      /* sum_{k<n-1} 100 (x_{k+1} - x_k^2)^2 + (1 - x_k)^2, n >= 2 */
+    CHESSFAD_ACKLEY = 1,          /* -20 exp(-0.2 sqrt(sum x^2 / n)) - exp(sum cos(2 pi x) / n) + 20 + e */
+    CHESSFAD_FLETCHER_POWELL = 2  /* sum_m (E_m - sum_j A_mj sin x_j + B_mj cos x_j)^2 */
+};
+
+enum chessfad_status {
+    CHESSFAD_OK = 0,
+    CHESSFAD_E_FUNC = -1,     /* func_id is not one of chessfad_func */
+    CHESSFAD_E_N = -2,        /* n < 1, n > CHESSFAD_MAX_N, or n < 2 for Rosenbrock */
+    CHESSFAD_E_CHUNK = -3,    /* chunk not compiled, negative, or larger than n */
+    CHESSFAD_E_NULL = -4,     /* a required pointer is NULL while npts > 0 */
+    CHESSFAD_E_PARAMS = -5,   /* Fletcher-Powell parameters not set for this n */
+    CHESSFAD_E_OVERLAP = -6,  /* an output array overlaps an input array */
+    CHESSFAD_E_HIP = -7,      /* HIP error while allocating or launching */
+    CHESSFAD_E_ARG = -8       /* npts < 0 or another malformed argument */
+};
+
+#define CHESSFAD_MAX_N 512
+
+/*
+ * Hessian-vector products, plain float64 (CHESS-VEC, Sec. VI; Sec. III.C).
+ *   x   [npts][n]  points at which H(x) is taken (read only)
+ *   v   [npts][n]  vectors to multiply (read only)
+ *   out [npts][n]  out[p] = H(x[p]) v[p]; must not overlap x or v
+ * Row i of the Hessian is produced chunk by chunk, each chunk dotted with
+ * the matching entries of v and summed (H is never stored).
+ */
+int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double* v,
+                 double* out, int chunk, void* stream);
+
+/*
+ * Full Hessians, plain float64 (CHUNK-HESS, Sec. III.B).
+ *   x [npts][n]     points (read only)
+ *   H [npts][n][n]  H[p][i][j] = d2f/dx_i dx_j at x[p]; every entry is
+ *                   computed by its own row's call (no symmetry is used),
+ *                   so the output is symmetric only up to rounding.
+ */
+int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* H,
+                     int chunk, void* stream);
+
+/*
+ * Fletcher-Powell parameters for problem size n.  The function needs two
+ * n x n integer-valued matrices A, B and a base point alpha; the method's
+ * signatures have no slot for them, so they are registered per n.
+ *   A, B   [n][n] device arrays (row-major), alpha [n] device array.
+ * The library copies them into memory it owns, computes
+ * E_m = sum_j A_mj sin(alpha_j) + B_mj cos(alpha_j) in float64 on `stream`,
+ * and keeps the set until chessfad_fp_release(n) or a new set for n.
+ * Returns CHESSFAD_E_N for a bad n, CHESSFAD_E_NULL for a NULL array,
+ * CHESSFAD_E_HIP if allocation or the copy fails.
+ */
+int chessfad_fp_set_params(int n, const double* A, const double* B, const double* alpha,
+                           void* stream);
+
+/* Frees the Fletcher-Powell parameter set of size n (no-op if none).  The
+ * caller must ensure no enqueued work still reads it. */
+int chessfad_fp_release(int n);
+
+/* Static description of a status code (for CHESSFAD_E_HIP, the text of the
+ * last HIP error seen by the calling thread). */
+const char* chessfad_strerror(int code);
+
+/* Default chunk size the library uses for (func_id, n) when chunk == 0,
+ * or a negative status for invalid arguments. */
+int chessfad_default_chunk(int func_id, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHESSFAD_H */

@@ -1,0 +1,211 @@
+// C ABI of the chunked Hessian library (declared in include/chessfad.h).
+//
+// Host side only: argument checks (all before anything is enqueued), launch
+// geometry, the Fletcher-Powell parameter registry, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+
+#include "chessfad.h"
+#include "dispatch.hpp"
+
+using namespace chessfad;
+
+namespace {
+
+thread_local std::string g_hip_error;
+
+int hip_fail(hipError_t e) {
+    g_hip_error = hipGetErrorString(e);
+    return CHESSFAD_E_HIP;
+}
+
+bool chunk_compiled(int c) {
+    for (int k = 0; k < kNumChunks; ++k)
+        if (kChunks[k] == c) return true;
+    return false;
+}
+
+int check_func_n(int func_id, int n) {
+    if (func_id < CHESSFAD_ROSENBROCK || func_id > CHESSFAD_FLETCHER_POWELL) return CHESSFAD_E_FUNC;
+    if (n < 1 || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
+    if (func_id == CHESSFAD_ROSENBROCK && n < 2) return CHESSFAD_E_N;
+    return CHESSFAD_OK;
+}
+
+int default_chunk(int n) {
+    int c = 1;
+    for (int k = 0; k < kNumChunks; ++k)
+        if (kChunks[k] <= n && kChunks[k] <= 4) c = kChunks[k];
+    return c;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+// ------------------------------------------------ Fletcher-Powell parameters
+struct FpSet {
+    double* A = nullptr;
+    double* B = nullptr;
+    double* E = nullptr;
+    int device = -1;
+};
+
+std::mutex g_fp_mu;
+FpSet g_fp[CHESSFAD_MAX_N + 1];
+
+void fp_free(FpSet& s) {
+    if (s.A) (void)hipFree(s.A);
+    if (s.B) (void)hipFree(s.B);
+    if (s.E) (void)hipFree(s.E);
+    s = FpSet{};
+}
+
+// E_m = sum_j A_mj sin(alpha_j) + B_mj cos(alpha_j), one thread per m, float64
+__global__ void fp_offsets_kernel(int n, const double* A, const double* B, const double* alpha, double* E) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s, c;
+        sincos(alpha[j], &s, &c);
+        acc += A[(size_t)m * n + j] * s;
+        acc += B[(size_t)m * n + j] * c;
+    }
+    E[m] = acc;
+}
+
+int fp_lookup(int n, FpParams& out) {
+    std::lock_guard<std::mutex> lk(g_fp_mu);
+    const FpSet& s = g_fp[n];
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return CHESSFAD_E_HIP;
+    if (!s.A || s.device != dev) return CHESSFAD_E_PARAMS;
+    out = FpParams{s.A, s.B, s.E};
+    return CHESSFAD_OK;
+}
+
+PlainLaunch plain_table(int func_id, int C, bool hess) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return plain_rosenbrock(C, hess);
+        case CHESSFAD_ACKLEY: return plain_ackley(C, hess);
+        default: return plain_fletcher_powell(C, hess);
+    }
+}
+
+struct Geometry {
+    int nc, rows, block, pstride;
+    int64_t grid;
+    size_t lds;
+};
+
+Geometry plain_geometry(int func_id, int n, int64_t npts, int C, bool hess) {
+    Geometry g;
+    g.nc = (n + C - 1) / C;
+    g.rows = g.nc >= 256 ? 1 : 256 / g.nc;
+    g.block = g.rows * g.nc;
+    g.pstride = (g.rows - 1) / n + 2;
+    const int64_t nrows = npts * (int64_t)n;
+    g.grid = (nrows + g.rows - 1) / g.rows;
+    const int arrays = 1 + (hess ? 0 : 1) + (func_id == CHESSFAD_ROSENBROCK ? 0 : 2);
+    g.lds = sizeof(double) * ((size_t)arrays * n * g.pstride + g.block);
+    return g;
+}
+
+int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+              void* stream, bool hess) {
+    int rc = check_func_n(func_id, n);
+    if (rc) return rc;
+    if (chunk == 0) chunk = default_chunk(n);
+    if (chunk < 0 || !chunk_compiled(chunk) || chunk > n) return CHESSFAD_E_CHUNK;
+    if (npts < 0) return CHESSFAD_E_ARG;
+    if (npts == 0) return CHESSFAD_OK;
+    if (!x || !out || (!hess && !v)) return CHESSFAD_E_NULL;
+    const size_t in_bytes = sizeof(double) * (size_t)npts * n;
+    const size_t out_bytes = hess ? in_bytes * n : in_bytes;
+    if (overlaps(out, out_bytes, x, in_bytes) || (!hess && overlaps(out, out_bytes, v, in_bytes)))
+        return CHESSFAD_E_OVERLAP;
+    FpParams fp{nullptr, nullptr, nullptr};
+    if (func_id == CHESSFAD_FLETCHER_POWELL) {
+        rc = fp_lookup(n, fp);
+        if (rc) return rc;
+    }
+    const Geometry g = plain_geometry(func_id, n, npts, chunk, hess);
+    if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+    PlainLaunch launch = plain_table(func_id, chunk, hess);
+    if (!launch) return CHESSFAD_E_CHUNK;
+    PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
+    hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), g.lds, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+                 void* stream) {
+    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false);
+}
+
+int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* H, int chunk, void* stream) {
+    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true);
+}
+
+int chessfad_fp_set_params(int n, const double* A, const double* B, const double* alpha, void* stream) {
+    if (n < 1 || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
+    if (!A || !B || !alpha) return CHESSFAD_E_NULL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_fp_mu);
+    FpSet& set = g_fp[n];
+    fp_free(set);
+    const size_t mat = sizeof(double) * (size_t)n * n;
+    hipError_t e = hipGetDevice(&set.device);
+    if (e == hipSuccess) e = hipMalloc(&set.A, mat);
+    if (e == hipSuccess) e = hipMalloc(&set.B, mat);
+    if (e == hipSuccess) e = hipMalloc(&set.E, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(set.A, A, mat, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(set.B, B, mat, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(fp_offsets_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, set.A, set.B, alpha, set.E);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        fp_free(set);
+        return hip_fail(e);
+    }
+    return CHESSFAD_OK;
+}
+
+int chessfad_fp_release(int n) {
+    if (n < 1 || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
+    std::lock_guard<std::mutex> lk(g_fp_mu);
+    fp_free(g_fp[n]);
+    return CHESSFAD_OK;
+}
+
+const char* chessfad_strerror(int code) {
+    switch (code) {
+        case CHESSFAD_OK: return "ok";
+        case CHESSFAD_E_FUNC: return "unknown func_id";
+        case CHESSFAD_E_N: return "n out of range for this function";
+        case CHESSFAD_E_CHUNK: return "chunk size not compiled or larger than n";
+        case CHESSFAD_E_NULL: return "NULL array pointer";
+        case CHESSFAD_E_PARAMS: return "Fletcher-Powell parameters not set for this n on this device";
+        case CHESSFAD_E_OVERLAP: return "output overlaps an input";
+        case CHESSFAD_E_HIP: return g_hip_error.empty() ? "HIP error" : g_hip_error.c_str();
+        case CHESSFAD_E_ARG: return "invalid argument";
+        default: return "unknown status";
+    }
+}
+
+int chessfad_default_chunk(int func_id, int n) {
+    int rc = check_func_n(func_id, n);
+    return rc ? rc : default_chunk(n);
+}
+
+}  // extern "C"

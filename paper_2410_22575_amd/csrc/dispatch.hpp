@@ -1,0 +1,39 @@
+// Kernel tables shared by the instantiation units and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernel_plain.hpp"
+
+namespace chessfad {
+
+using PlainLaunch = hipError_t (*)(const PlainArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
+
+// Chunk sizes compiled into the library.
+constexpr int kChunks[] = {1, 2, 4, 8, 16};
+constexpr int kNumChunks = sizeof(kChunks) / sizeof(kChunks[0]);
+
+template <class F, int C, bool kHess>
+hipError_t launch_plain(const PlainArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((plain_kernel<F, C, kHess>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class F, bool kHess>
+PlainLaunch plain_entry(int C) {
+    switch (C) {
+        case 1: return &launch_plain<F, 1, kHess>;
+        case 2: return &launch_plain<F, 2, kHess>;
+        case 4: return &launch_plain<F, 4, kHess>;
+        case 8: return &launch_plain<F, 8, kHess>;
+        case 16: return &launch_plain<F, 16, kHess>;
+        default: return nullptr;
+    }
+}
+
+// One per function, each defined in its own translation unit.
+PlainLaunch plain_rosenbrock(int C, bool hess);
+PlainLaunch plain_ackley(int C, bool hess);
+PlainLaunch plain_fletcher_powell(int C, bool hess);
+
+}  // namespace chessfad

@@ -1,0 +1,137 @@
+// Register-resident hDual<C> for gfx950 kernels.
+//
+// An hDual with chunk size C (Sec. III.B, Sec. IV) holds 2C + 2 numbers:
+//   v      the value
+//   d      the derivative along the row variable x_i
+//   g[l]   the derivatives along the chunk's columns x_{cs+l}, l < C
+//   h[l]   the second derivatives d2/(dx_i dx_{cs+l})
+// Every field is a named scalar so the whole value lives in VGPRs (4C + 4
+// of them in float64); nothing is indexed dynamically.
+//
+// Operator rules (Sec. III.A, Fig. 1): sums act componentwise; the product
+// is u0 w + w0 u on the first-order part and
+//   u0 w_h + u_d w_g + w_d u_g + w0 u_h
+// on the second-order part; a unary g(u) is the chain rule
+//   <g, g' u_d, g' u_g, g' u_h + g'' u_d u_g>
+// where g, g', g'' are scalars the caller supplies (so transcendental values
+// that every call of a point shares can be computed once per point).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace chessfad {
+
+#define CF_DEV __device__ __forceinline__
+
+template <typename T, int C>
+struct HD {
+    T v, d;
+    T g[C], h[C];
+};
+
+// CHUNK-INIT for one variable: y_k = <x_k, [k = i], [k = cs + l], 0>.
+template <typename T, int C>
+CF_DEV HD<T, C> seed(T xk, int k, int i, int cs) {
+    HD<T, C> y;
+    y.v = xk;
+    y.d = (k == i) ? T(1) : T(0);
+    const int u = k - cs;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        y.g[l] = (u == l) ? T(1) : T(0);
+        y.h[l] = T(0);
+    }
+    return y;
+}
+
+template <typename T, int C>
+CF_DEV HD<T, C> operator+(const HD<T, C>& a, const HD<T, C>& b) {
+    HD<T, C> r;
+    r.v = a.v + b.v;
+    r.d = a.d + b.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.g[l] + b.g[l];
+        r.h[l] = a.h[l] + b.h[l];
+    }
+    return r;
+}
+
+template <typename T, int C>
+CF_DEV HD<T, C> operator-(const HD<T, C>& a, const HD<T, C>& b) {
+    HD<T, C> r;
+    r.v = a.v - b.v;
+    r.d = a.d - b.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.g[l] - b.g[l];
+        r.h[l] = a.h[l] - b.h[l];
+    }
+    return r;
+}
+
+template <typename T, int C>
+CF_DEV HD<T, C> operator*(const HD<T, C>& a, const HD<T, C>& b) {
+    HD<T, C> r;
+    r.v = a.v * b.v;
+    r.d = a.v * b.d + b.v * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.v * b.g[l] + b.v * a.g[l];
+        r.h[l] = a.v * b.h[l] + a.d * b.g[l] + b.d * a.g[l] + b.v * a.h[l];
+    }
+    return r;
+}
+
+// scalar x hDual scales every component
+template <typename T, int C>
+CF_DEV HD<T, C> operator*(T s, const HD<T, C>& a) {
+    HD<T, C> r;
+    r.v = s * a.v;
+    r.d = s * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = s * a.g[l];
+        r.h[l] = s * a.h[l];
+    }
+    return r;
+}
+
+// scalar + hDual changes only the value
+template <typename T, int C>
+CF_DEV HD<T, C> operator+(const HD<T, C>& a, T s) {
+    HD<T, C> r = a;
+    r.v = a.v + s;
+    return r;
+}
+
+// scalar - hDual: value subtracts, the derivatives change sign
+template <typename T, int C>
+CF_DEV HD<T, C> operator-(T s, const HD<T, C>& a) {
+    HD<T, C> r;
+    r.v = s - a.v;
+    r.d = -a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = -a.g[l];
+        r.h[l] = -a.h[l];
+    }
+    return r;
+}
+
+// chain rule with caller-supplied g(u0), g'(u0), g''(u0)
+template <typename T, int C>
+CF_DEV HD<T, C> chain(const HD<T, C>& a, T g0, T g1, T g2) {
+    HD<T, C> r;
+    r.v = g0;
+    r.d = g1 * a.d;
+    const T g2d = g2 * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = g1 * a.g[l];
+        r.h[l] = g1 * a.h[l] + g2d * a.g[l];
+    }
+    return r;
+}
+
+}  // namespace chessfad

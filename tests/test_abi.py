@@ -1,0 +1,115 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+symbol include/chessfad.h declares, and rejects bad arguments with the
+documented status before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_22575_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chessfad.h")
+
+OK, E_FUNC, E_N, E_CHUNK, E_NULL, E_PARAMS, E_OVERLAP, E_HIP, E_ARG = 0, -1, -2, -3, -4, -5, -6, -7, -8
+R, A, FP = 0, 1, 2
+FAKE = 0x100000  # never dereferenced: every call below fails its host checks first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chessfad_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load()
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 6
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_status_strings(lib):
+    for code in (OK, E_FUNC, E_N, E_CHUNK, E_NULL, E_PARAMS, E_OVERLAP, E_HIP, E_ARG):
+        assert binding.strerror(code)
+    assert binding.strerror(-99) == "unknown status"
+
+
+def hvp(lib, func, n, npts, x=FAKE, v=FAKE * 2, out=FAKE * 4, chunk=4):
+    return lib.chessfad_hvp(func, n, npts, x, v, out, chunk, None)
+
+
+def hess(lib, func, n, npts, x=FAKE, H=FAKE * 4, chunk=4):
+    return lib.chessfad_hessian(func, n, npts, x, H, chunk, None)
+
+
+def test_bad_func(lib):
+    assert hvp(lib, 3, 16, 10) == E_FUNC
+    assert hvp(lib, -1, 16, 10) == E_FUNC
+    assert hess(lib, 7, 16, 10) == E_FUNC
+
+
+def test_bad_n(lib):
+    assert hvp(lib, R, 1, 10, chunk=1) == E_N      # Rosenbrock needs two variables
+    assert hvp(lib, A, 0, 10, chunk=1) == E_N
+    assert hvp(lib, A, 513, 10) == E_N
+    assert hess(lib, FP, -4, 10) == E_N
+
+
+def test_bad_chunk(lib):
+    assert hvp(lib, R, 16, 10, chunk=3) == E_CHUNK   # not compiled
+    assert hvp(lib, R, 16, 10, chunk=32) == E_CHUNK
+    assert hvp(lib, R, 4, 10, chunk=8) == E_CHUNK    # larger than n
+    assert hvp(lib, R, 16, 10, chunk=-1) == E_CHUNK
+
+
+def test_npts(lib):
+    assert hvp(lib, R, 16, -1) == E_ARG
+    assert hvp(lib, R, 16, 0, x=None, v=None, out=None) == OK     # empty batch is a no-op
+    assert hess(lib, A, 16, 0, x=None, H=None) == OK
+
+
+def test_null_pointers(lib):
+    assert hvp(lib, R, 16, 10, x=None) == E_NULL
+    assert hvp(lib, R, 16, 10, v=None) == E_NULL
+    assert hvp(lib, R, 16, 10, out=None) == E_NULL
+    assert hess(lib, A, 16, 10, H=None) == E_NULL
+
+
+def test_overlap(lib):
+    n, npts = 16, 10
+    nbytes = 8 * n * npts
+    assert hvp(lib, R, n, npts, x=FAKE, v=FAKE + 10 * nbytes, out=FAKE + nbytes - 8) == E_OVERLAP
+    assert hvp(lib, A, n, npts, x=FAKE, v=FAKE + 10 * nbytes, out=FAKE + 10 * nbytes) == E_OVERLAP
+    assert hess(lib, R, n, npts, x=FAKE + 8 * n * n * npts - 8, H=FAKE) == E_OVERLAP
+
+
+def test_default_chunk(lib):
+    assert lib.chessfad_default_chunk(R, 16) in (1, 2, 4, 8, 16)
+    assert lib.chessfad_default_chunk(A, 1) == 1
+    assert lib.chessfad_default_chunk(5, 16) == E_FUNC
+    assert lib.chessfad_default_chunk(R, 1) == E_N
+
+
+def test_fp_params_argument_checks(lib):
+    assert lib.chessfad_fp_set_params(0, FAKE, FAKE, FAKE, None) == E_N
+    assert lib.chessfad_fp_set_params(600, FAKE, FAKE, FAKE, None) == E_N
+    assert lib.chessfad_fp_set_params(8, None, FAKE, FAKE, None) == E_NULL
+    assert lib.chessfad_fp_release(0) == E_N
+
+
+def test_binding_rejects_bad_tensors():
+    import torch
+
+    x = torch.zeros(4, 8, dtype=torch.float64)  # CPU tensor: refused before any call
+    with pytest.raises(ValueError):
+        binding.chessfad_hvp(R, x, x)
+    with pytest.raises(ValueError):
+        binding.chessfad_hessian(R, x)

@@ -1,0 +1,165 @@
+"""Parity of the HIP path (through the C ABI) against the float64 CPU oracle.
+
+Bar (float64 path): per point, the normwise relative error
+    e = max|r - r*| / (max|H*| * max|v|)   for H.v,
+    e = max|H - H*| / max|H*|              for the Hessian,
+must stay below 1e-12 (a few hundred units of float64 rounding for the sums
+of up to a few thousand products in f; the observed values are ~1e-16).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import closed_form as cf
+from paper_2410_22575_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, A, FP = 0, 1, 2
+TOL64 = 1e-12
+CHUNKS = (1, 2, 4, 8, 16)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(gpu_lib, w):
+    E = None
+    if w.func == FP:
+        gpu_lib.chessfad_fp_set_params(_dev(w.A), _dev(w.B), _dev(w.alpha))
+        E = cf.fp_offsets(w.A, w.B, w.alpha)
+    return E
+
+
+def _hvp_err(r, rs, Hmax, v):
+    return np.max(np.abs(r - rs), axis=1) / (Hmax * np.max(np.abs(v), axis=1))
+
+
+def _hmax(func, w, E, idx=None):
+    x = w.x if idx is None else w.x[idx]
+    H = cf.hessian(func, x, w.A, w.B, E)
+    return H, np.max(np.abs(H), axis=(1, 2))
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+@pytest.mark.parametrize("n", [2, 5, 13, 16])
+def test_hvp_and_hessian_small(gpu_lib, func, n):
+    npts = 300  # several workgroups and a ragged last one
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(1000 + 10 * func + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref, hmax = _hmax(func, w, E)
+    r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+    H_first = None
+    for c in CHUNKS:
+        if c > n:
+            continue
+        print(f"[case] func={func} n={n} chunk={c} npts={npts}", flush=True)
+        r = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+        assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64, (func, n, c)
+        H = gpu_lib.chessfad_hessian(func, x, chunk=c).cpu().numpy()
+        eH = np.max(np.abs(H - H_ref), axis=(1, 2)) / hmax
+        assert np.max(eH) <= TOL64, (func, n, c)
+        # the chunk size changes how many columns one call carries, not the
+        # expression that produces each entry
+        if H_first is None:
+            H_first = H
+        else:
+            np.testing.assert_allclose(H, H_first, rtol=0, atol=TOL64 * hmax.max())
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_hvp_matches_own_hessian(gpu_lib, func):
+    n, npts = 16, 500
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(2000 + func))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    for c in (1, 4, 16):
+        H = gpu_lib.chessfad_hessian(func, x, chunk=c)
+        r = gpu_lib.chessfad_hvp(func, x, v, chunk=c)
+        r2 = torch.bmm(H, v.unsqueeze(2)).squeeze(2)
+        hmax = H.abs().amax(dim=(1, 2))
+        e = (r - r2).abs().amax(dim=1) / (hmax * v.abs().amax(dim=1))
+        assert e.max().item() <= TOL64
+
+
+def test_rosenbrock_exact_structure(gpu_lib):
+    # entries off the tridiagonal are products with an exactly-zero seed: 0.0
+    n, npts = 13, 64
+    w = inputs.make_workload(R, n, npts, inputs.rng_for(3000))
+    H = gpu_lib.chessfad_hessian(R, _dev(w.x), chunk=4).cpu().numpy()
+    i, j = np.indices((n, n))
+    assert np.all(H[:, np.abs(i - j) > 1] == 0.0)
+    # at the minimizer the Hessian is the integer matrix of the textbook case
+    ones = torch.ones(3, n, dtype=torch.float64, device="cuda")
+    H1 = gpu_lib.chessfad_hessian(R, ones, chunk=2).cpu().numpy()
+    np.testing.assert_array_equal(H1, cf.hess_rosenbrock(np.ones((3, n))))
+
+
+def test_ackley_equal_coordinates(gpu_lib):
+    n = 8
+    x = np.tile(np.array([[0.3], [-1.7], [2.2]]), (1, n))
+    H = gpu_lib.chessfad_hessian(A, _dev(x), chunk=4).cpu().numpy()
+    for p in range(3):
+        d = np.diag(H[p])
+        off = H[p][~np.eye(n, dtype=bool)]
+        s = np.abs(H[p]).max()
+        assert np.ptp(d) <= 1e-13 * s and np.ptp(off) <= 1e-13 * s
+
+
+def test_fletcher_powell_psd_at_alpha(gpu_lib):
+    n = 12
+    w = inputs.make_workload(FP, n, 4, inputs.rng_for(3100))
+    _setup(gpu_lib, w)
+    x = np.tile(w.alpha, (4, 1))
+    H = gpu_lib.chessfad_hessian(FP, _dev(x), chunk=4).cpu().numpy()
+    for p in range(4):
+        Hs = 0.5 * (H[p] + H[p].T)
+        assert np.linalg.eigvalsh(Hs).min() >= -1e-10 * np.abs(Hs).max()
+
+
+@pytest.mark.parametrize("func,n,c", [(R, 512, 16), (R, 512, 1), (A, 256, 8), (FP, 64, 16), (FP, 33, 4)])
+def test_large_n(gpu_lib, func, n, c):
+    npts = 3
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(4000 + n))
+    E = _setup(gpu_lib, w)
+    print(f"[case] large n func={func} n={n} chunk={c}", flush=True)
+    r = gpu_lib.chessfad_hvp(func, _dev(w.x), _dev(w.v), chunk=c).cpu().numpy()
+    _, hmax = _hmax(func, w, E)
+    r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+    assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_full_size_sampled(gpu_lib, func):
+    """n = 16, 2^20 points, chunk 4 (the benchmark's launch), checked on a
+    random sample of points against the oracle."""
+    n, npts = 16, 1 << 20
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(1))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    print(f"[case] full size func={func}", flush=True)
+    r = gpu_lib.chessfad_hvp(func, x, v, chunk=4).cpu().numpy()
+    assert np.all(np.isfinite(r))
+    idx = np.sort(np.random.default_rng(5).choice(npts, 2048, replace=False))
+    idx = np.concatenate([[0, npts - 1], idx])
+    H, hmax = _hmax(func, w, E, idx)
+    r_ref = np.einsum("pij,pj->pi", H, w.v[idx])
+    assert np.max(_hvp_err(r[idx], r_ref, hmax, w.v[idx])) <= TOL64
+
+
+def test_edge_cases(gpu_lib):
+    x = torch.zeros(0, 8, dtype=torch.float64, device="cuda")
+    out = gpu_lib.chessfad_hvp(R, x, x)
+    assert out.shape == (0, 8)
+    # a single point
+    w = inputs.make_workload(A, 6, 1, inputs.rng_for(5000))
+    r = gpu_lib.chessfad_hvp(A, _dev(w.x), _dev(w.v), chunk=2).cpu().numpy()
+    np.testing.assert_allclose(r, cf.hvp(A, w.x, w.v), rtol=0, atol=1e-13 * np.abs(cf.hess_ackley(w.x)).max() * 3)
+    # Fletcher-Powell without parameters for this n is refused
+    gpu_lib.chessfad_fp_release(7)
+    xx = torch.zeros(2, 7, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.ChessfadError) as ei:
+        gpu_lib.chessfad_hvp(FP, xx, xx.clone())
+    assert ei.value.code == -5
