@@ -40,7 +40,24 @@ def parse():
     ap.add_argument("--npts", type=int, default=NPTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib, reps=3):
+    """A plain copy kernel of known size: each launch reads and writes
+    exactly `mib` MiB, so FETCH_SIZE / WRITE_SIZE per dispatch should read
+    mib * 1024 KiB each; the ratio calibrates the counters."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "reps": reps, "kib_per_launch_each_way": mib * 1024}), flush=True)
 
 
 def cpu_baseline(workloads, E, chunks, budget_s):
@@ -81,6 +98,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               f"(points shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
 

@@ -102,6 +102,19 @@ int chessfad_fp_release(int n);
  * last HIP error seen by the calling thread). */
 const char* chessfad_strerror(int code);
 
+/*
+ * Process-wide options (not thread-safe against concurrent compute calls).
+ * Returns the previous value, or CHESSFAD_E_ARG for an unknown option or value.
+ *   CHESSFAD_OPT_FP_MFMA  1 (default): for Fletcher-Powell with n <= 16 the
+ *                         dense [A B] . [sin y; cos y] contraction over the
+ *                         hDual components runs on float64 MFMA;
+ *                         0: every step runs on the vector ALUs.
+ *                         Both give the same derivative components; only
+ *                         the order of the final sum over residuals differs.
+ */
+enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1 };
+int chessfad_set_option(int option, int value);
+
 /* Default chunk size the library uses for (func_id, n) when chunk == 0,
  * or a negative status for invalid arguments. */
 int chessfad_default_chunk(int func_id, int n);

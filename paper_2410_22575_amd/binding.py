@@ -24,7 +24,10 @@ SIGNATURES = {
     "chessfad_fp_release": (_i, [_i]),
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
+    "chessfad_set_option": (_i, [_i, _i]),
 }
+
+CHESSFAD_OPT_FP_MFMA = 1
 
 _lib = None
 
@@ -121,4 +124,12 @@ def chessfad_default_chunk(func_id: int, n: int) -> int:
     rc = load().chessfad_default_chunk(func_id, n)
     if rc < 0:
         raise ChessfadError(rc, "chessfad_default_chunk")
+    return rc
+
+
+def chessfad_set_option(option: int, value: int) -> int:
+    """Set a process-wide option; returns the previous value."""
+    rc = load().chessfad_set_option(option, value)
+    if rc < 0:
+        raise ChessfadError(rc, "chessfad_set_option")
     return rc

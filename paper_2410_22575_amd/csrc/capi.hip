@@ -16,6 +16,9 @@ namespace {
 
 thread_local std::string g_hip_error;
 
+// CHESSFAD_OPT_FP_MFMA: Fletcher-Powell contraction on MFMA when n <= 16
+int g_opt_fp_mfma = 1;
+
 int hip_fail(hipError_t e) {
     g_hip_error = hipGetErrorString(e);
     return CHESSFAD_E_HIP;
@@ -134,12 +137,24 @@ int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v
         rc = fp_lookup(n, fp);
         if (rc) return rc;
     }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma) {
+        FpMfmaLaunch launch = fp_mfma_entry(chunk, fp_mfma_steps(n), hess);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        const int nc = (n + chunk - 1) / chunk;
+        const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
+        const int64_t grid = (npts + per_block - 1) / per_block;
+        if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        FpMfmaArgs a{x, v, out, fp, npts, n, nc};
+        hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
     const Geometry g = plain_geometry(func_id, n, npts, chunk, hess);
     if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
     PlainLaunch launch = plain_table(func_id, chunk, hess);
     if (!launch) return CHESSFAD_E_CHUNK;
     PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
-    hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), g.lds, static_cast<hipStream_t>(stream));
+    hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), g.lds, s);
     return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
 }
 
@@ -201,6 +216,16 @@ const char* chessfad_strerror(int code) {
         case CHESSFAD_E_ARG: return "invalid argument";
         default: return "unknown status";
     }
+}
+
+int chessfad_set_option(int option, int value) {
+    if (option == CHESSFAD_OPT_FP_MFMA) {
+        if (value != 0 && value != 1) return CHESSFAD_E_ARG;
+        const int prev = g_opt_fp_mfma;
+        g_opt_fp_mfma = value;
+        return prev;
+    }
+    return CHESSFAD_E_ARG;
 }
 
 int chessfad_default_chunk(int func_id, int n) {

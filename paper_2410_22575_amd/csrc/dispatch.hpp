@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kernel_fp_mfma.hpp"
 #include "kernel_plain.hpp"
 
 namespace chessfad {
@@ -30,6 +31,34 @@ PlainLaunch plain_entry(int C) {
         default: return nullptr;
     }
 }
+
+using FpMfmaLaunch = hipError_t (*)(const FpMfmaArgs&, dim3 grid, dim3 block, hipStream_t);
+
+template <int C, int NK, bool kHess>
+hipError_t launch_fp_mfma(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((fp_mfma_kernel<C, NK, kHess>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NK, bool kHess>
+FpMfmaLaunch fp_mfma_entry_c(int C) {
+    switch (C) {
+        case 1: return &launch_fp_mfma<1, NK, kHess>;
+        case 2: return &launch_fp_mfma<2, NK, kHess>;
+        case 4: return &launch_fp_mfma<4, NK, kHess>;
+        case 8: return &launch_fp_mfma<8, NK, kHess>;
+        case 16: return &launch_fp_mfma<16, NK, kHess>;
+        default: return nullptr;
+    }
+}
+
+// K steps of 4 that cover K = 2n, rounded up to 1, 2, 4 or 8.
+inline int fp_mfma_steps(int n) {
+    const int need = (2 * n + 3) / 4;
+    return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess);
 
 // One per function, each defined in its own translation unit.
 PlainLaunch plain_rosenbrock(int C, bool hess);

@@ -20,6 +20,24 @@ TOL64 = 1e-12
 CHUNKS = (1, 2, 4, 8, 16)
 
 
+FUNC_PATHS = [(R, None), (A, None), (FP, 1), (FP, 0)]  # (function, Fletcher-Powell MFMA option)
+
+
+class fp_path:
+    """Select the Fletcher-Powell path (1 = MFMA contraction, 0 = vector ALUs)."""
+
+    def __init__(self, lib, mfma):
+        self.lib, self.mfma = lib, mfma
+
+    def __enter__(self):
+        if self.mfma is not None:
+            self.prev = self.lib.chessfad_set_option(self.lib.CHESSFAD_OPT_FP_MFMA, self.mfma)
+
+    def __exit__(self, *exc):
+        if self.mfma is not None:
+            self.lib.chessfad_set_option(self.lib.CHESSFAD_OPT_FP_MFMA, self.prev)
+
+
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -42,10 +60,15 @@ def _hmax(func, w, E, idx=None):
     return H, np.max(np.abs(H), axis=(1, 2))
 
 
-@pytest.mark.parametrize("func", [R, A, FP])
+@pytest.mark.parametrize("func,mfma", FUNC_PATHS)
 @pytest.mark.parametrize("n", [2, 5, 13, 16])
-def test_hvp_and_hessian_small(gpu_lib, func, n):
-    npts = 300  # several workgroups and a ragged last one
+def test_hvp_and_hessian_small(gpu_lib, func, mfma, n):
+    with fp_path(gpu_lib, mfma):
+        _small_case(gpu_lib, func, n)
+
+
+def _small_case(gpu_lib, func, n):
+    npts = 301  # several workgroups and a ragged last one
     w = inputs.make_workload(func, n, npts, inputs.rng_for(1000 + 10 * func + n))
     E = _setup(gpu_lib, w)
     x, v = _dev(w.x), _dev(w.v)
@@ -69,8 +92,13 @@ def test_hvp_and_hessian_small(gpu_lib, func, n):
             np.testing.assert_allclose(H, H_first, rtol=0, atol=TOL64 * hmax.max())
 
 
-@pytest.mark.parametrize("func", [R, A, FP])
-def test_hvp_matches_own_hessian(gpu_lib, func):
+@pytest.mark.parametrize("func,mfma", FUNC_PATHS)
+def test_hvp_matches_own_hessian(gpu_lib, func, mfma):
+    with fp_path(gpu_lib, mfma):
+        _hvp_vs_hessian(gpu_lib, func)
+
+
+def _hvp_vs_hessian(gpu_lib, func):
     n, npts = 16, 500
     w = inputs.make_workload(func, n, npts, inputs.rng_for(2000 + func))
     E = _setup(gpu_lib, w)
@@ -131,10 +159,15 @@ def test_large_n(gpu_lib, func, n, c):
     assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
 
 
-@pytest.mark.parametrize("func", [R, A, FP])
-def test_full_size_sampled(gpu_lib, func):
+@pytest.mark.parametrize("func,mfma", FUNC_PATHS)
+def test_full_size_sampled(gpu_lib, func, mfma):
     """n = 16, 2^20 points, chunk 4 (the benchmark's launch), checked on a
     random sample of points against the oracle."""
+    with fp_path(gpu_lib, mfma):
+        _full_size(gpu_lib, func)
+
+
+def _full_size(gpu_lib, func):
     n, npts = 16, 1 << 20
     w = inputs.make_workload(func, n, npts, inputs.rng_for(1))
     E = _setup(gpu_lib, w)
@@ -163,3 +196,20 @@ def test_edge_cases(gpu_lib):
     with pytest.raises(gpu_lib.ChessfadError) as ei:
         gpu_lib.chessfad_hvp(FP, xx, xx.clone())
     assert ei.value.code == -5
+
+
+def test_fp_mfma_matches_vector_path(gpu_lib):
+    """Both Fletcher-Powell paths form the derivative components with the
+    same single products; only the order of the sum over residuals differs."""
+    n, npts = 16, 700
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(6000))
+    _setup(gpu_lib, w)
+    x = _dev(w.x)
+    for c in (1, 2, 4, 8, 16):
+        with fp_path(gpu_lib, 1):
+            H1 = gpu_lib.chessfad_hessian(FP, x, chunk=c)
+        with fp_path(gpu_lib, 0):
+            H0 = gpu_lib.chessfad_hessian(FP, x, chunk=c)
+        hmax = H0.abs().amax(dim=(1, 2))
+        e = (H1 - H0).abs().amax(dim=(1, 2)) / hmax
+        assert e.max().item() <= 1e-14
