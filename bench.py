@@ -28,7 +28,16 @@ FUNCS = (0, 1, 2)
 NAMES = {0: "rosenbrock", 1: "ackley", 2: "fletcher_powell"}
 N = 16
 NPTS = 1 << 20
-PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (FMA = 2)
+PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (FMA = 2), vector and MFMA
+METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at stated error"
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0,
+# copy-kernel calibration), keyed by the kernel as it stood when the counters
+# were taken; a kernel absent here reports traffic null.
+MEASURED_TRAFFIC = {
+    "plain_kernel<rosenbrock, C=4, H.v>": 4.028e8,
+    "plain_kernel<ackley, C=4, H.v>": 4.028e8,
+}
 
 
 def parse():
@@ -165,20 +174,74 @@ def main():
         }
     dom = max(FUNCS, key=lambda f: kernel_ms[f])
     achieved = per_func[NAMES[dom]]["model_tflops"]
+    fp_mfma = N <= 16
+    if dom == 2 and fp_mfma:
+        kname = f"fp_mfma_kernel<C={chunks[2]}, NK={min(8, max(1, (2 * N + 3) // 4))}, H.v>"
+        bound = "mfma"
+    else:
+        kname = f"plain_kernel<{NAMES[dom]}, C={chunks[dom]}, H.v>"
+        bound = "alu"
+    roofline = {"bound": bound, "kernel": kname, "achieved": achieved, "peak": PEAK_F64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": MEASURED_TRAFFIC.get(kname),
+                "flops_per_launch": flops.flops_per_hvp(dom, N, chunks[dom]) * npts}
+    if dom == 2 and fp_mfma:
+        # MFMA flops the kernel executes: per 16-point wave, NK steps for the
+        # value column, NK per row for the d component (shared by the row's
+        # chunks) and 2 NK per (call, chunk column) for g and h
+        nk = min(8, max(1, (2 * N + 3) // 4))
+        c = chunks[2]
+        tiles = 1 + N * (1 + sum(2 * min(c, N - cs) for cs in range(0, N, c)))
+        mf = nk * tiles * 2 * 16 * 16 * 4 * (npts / 16)
+        roofline["executed_mfma_tflops"] = mf / (kernel_ms[2] * 1e-3) / 1e12
+        roofline["measured_mfma_f64_peak"] = 72.8
+
+    # the Fletcher-Powell vector-ALU path, for comparison (outside the timed region)
+    fp_vector_ms = None
+    if fp_mfma:
+        prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=chunks[2])
+        e0.record()
+        for _ in range(3):
+            binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=chunks[2])
+        e1.record()
+        torch.cuda.synchronize()
+        fp_vector_ms = e0.elapsed_time(e1) / 3
+        binding.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, prev)
+        binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=chunks[2])
+        torch.cuda.synchronize()
 
     # quick sanity check of the last outputs on a few points (oracle on CPU)
-    max_err = {}
+    idx = np.arange(0, npts, max(1, npts // 64))
+    refs = {}
     for f in FUNCS:
         w = workloads[f]
-        idx = np.arange(0, npts, max(1, npts // 64))
         H = cf.hessian(f, w.x[idx], w.A, w.B, E[f])
-        ref = np.einsum("pij,pj->pi", H, w.v[idx])
-        got = outs[f].cpu().numpy()[idx]
-        err = np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
-        max_err[NAMES[f]] = float(err.max())
+        refs[f] = (np.einsum("pij,pj->pi", H, w.v[idx]), np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
+
+    def rel_err(f, out):
+        ref, scale = refs[f]
+        return float((np.abs(out.cpu().numpy()[idx] - ref).max(axis=1) / scale).max())
+
+    max_err = {NAMES[f]: rel_err(f, outs[f]) for f in FUNCS}
+
+    # the mixed-precision path on the same inputs (outside the timed region)
+    mixed = {}
+    for f in FUNCS:
+        mo = torch.empty_like(xs[f])
+        binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=chunks[f])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=chunks[f])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        mixed[NAMES[f]] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
+                           "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
 
     result = {
-        "metric": "HVPs/sec (float64 chunked forward-mode H.v, n=16)",
+        "metric": METRIC,
         "value": value,
         "unit": "HVP/s",
         "n_gpus": 1,
@@ -193,11 +256,11 @@ def main():
         "config": {"workload": "plain FP64 H.v: Rosenbrock, Ackley, Fletcher-Powell; n=16; "
                                f"{npts} points each; chunk per function",
                    "n": N, "npts": npts, "chunks": {NAMES[f]: chunks[f] for f in FUNCS}},
-        "roofline": {"bound": "alu", "kernel": f"plain_kernel<{NAMES[dom]}, C={chunks[dom]}, H.v>",
-                     "achieved": achieved, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_F64_TFLOPS, "traffic": None},
+        "roofline": roofline,
         "per_function": per_func,
         "max_rel_err_sampled": max_err,
+        "fp_vector_path_ms": fp_vector_ms,
+        "mixed_f32": mixed,
     }
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(workloads, E, chunks, args.cpu_seconds)

@@ -81,6 +81,27 @@ int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* 
                      int chunk, void* stream);
 
 /*
+ * Mixed precision: the same H.v and Hessian with float32 hDual arithmetic
+ * (same arguments, layouts and checks as chessfad_hvp / chessfad_hessian;
+ * inputs and outputs stay float64).
+ *   - every hDual component is carried in float32 (coordinates, v and the
+ *     per-coordinate sin/cos tables are rounded to float32 where used);
+ *   - the Hessian-chunk components of the sums inside f (Rosenbrock's sum of
+ *     terms, Ackley's two sums, the Fletcher-Powell sum of squared
+ *     residuals) accumulate with two-sum compensation; the chunk dot uses
+ *     two-product and two-sum; the row sum over chunks is float64;
+ *   - per-point float64 islands: Ackley's sqrt of the mean square and both
+ *     exponentials (as g, g', g''), and the Fletcher-Powell residual values
+ *     E_m - sum_j (A_mj sin x_j + B_mj cos x_j), which cancel.
+ * The error is bounded by float32 rounding of the inputs and of the hDual
+ * arithmetic: normwise relative errors of a few 1e-7 on the test inputs.
+ */
+int chessfad_hvp_mixed(int func_id, int n, int64_t npts, const double* x, const double* v,
+                       double* out, int chunk, void* stream);
+int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, double* H,
+                           int chunk, void* stream);
+
+/*
  * Fletcher-Powell parameters for problem size n.  The function needs two
  * n x n integer-valued matrices A, B and a base point alpha; the method's
  * signatures have no slot for them, so they are registered per n.

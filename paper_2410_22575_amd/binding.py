@@ -20,6 +20,8 @@ _i, _i64, _p, _s = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_char_
 SIGNATURES = {
     "chessfad_hvp": (_i, [_i, _i, _i64, _p, _p, _p, _i, _p]),
     "chessfad_hessian": (_i, [_i, _i, _i64, _p, _p, _i, _p]),
+    "chessfad_hvp_mixed": (_i, [_i, _i, _i64, _p, _p, _p, _i, _p]),
+    "chessfad_hessian_mixed": (_i, [_i, _i, _i64, _p, _p, _i, _p]),
     "chessfad_fp_set_params": (_i, [_i, _p, _p, _p, _p]),
     "chessfad_fp_release": (_i, [_i]),
     "chessfad_strerror": (_s, [_i]),
@@ -77,33 +79,53 @@ def _raise(rc, what):
         raise ChessfadError(rc, what)
 
 
-def chessfad_hvp(func_id: int, x: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None,
-                 chunk: int = 0, stream=None) -> torch.Tensor:
-    """out[p] = H(x[p]) v[p] (float64 hDual arithmetic)."""
+def _hvp(name, func_id, x, v, out, chunk, stream):
     _check_pts("x", x)
     npts, n = x.shape
     _check_pts("v", v, n)
     if out is None:
         out = torch.empty_like(x)
     _check_pts("out", out, n)
-    rc = load().chessfad_hvp(func_id, n, npts, x.data_ptr(), v.data_ptr(), out.data_ptr(), chunk,
-                             _stream(stream))
-    _raise(rc, "chessfad_hvp")
+    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), v.data_ptr(), out.data_ptr(), chunk,
+                               _stream(stream))
+    _raise(rc, name)
     return out
 
 
-def chessfad_hessian(func_id: int, x: torch.Tensor, out: torch.Tensor | None = None, chunk: int = 0,
-                     stream=None) -> torch.Tensor:
-    """out[p] = H(x[p]) as [npts, n, n] (float64 hDual arithmetic)."""
+def _hessian(name, func_id, x, out, chunk, stream):
     _check_pts("x", x)
     npts, n = x.shape
     if out is None:
         out = torch.empty((npts, n, n), dtype=torch.float64, device=x.device)
     if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (npts, n, n)):
         raise ValueError("out must be a contiguous float64 CUDA tensor of shape [npts, n, n]")
-    rc = load().chessfad_hessian(func_id, n, npts, x.data_ptr(), out.data_ptr(), chunk, _stream(stream))
-    _raise(rc, "chessfad_hessian")
+    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), out.data_ptr(), chunk, _stream(stream))
+    _raise(rc, name)
     return out
+
+
+def chessfad_hvp(func_id: int, x: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None,
+                 chunk: int = 0, stream=None) -> torch.Tensor:
+    """out[p] = H(x[p]) v[p] (float64 hDual arithmetic)."""
+    return _hvp("chessfad_hvp", func_id, x, v, out, chunk, stream)
+
+
+def chessfad_hessian(func_id: int, x: torch.Tensor, out: torch.Tensor | None = None, chunk: int = 0,
+                     stream=None) -> torch.Tensor:
+    """out[p] = H(x[p]) as [npts, n, n] (float64 hDual arithmetic)."""
+    return _hessian("chessfad_hessian", func_id, x, out, chunk, stream)
+
+
+def chessfad_hvp_mixed(func_id: int, x: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None,
+                       chunk: int = 0, stream=None) -> torch.Tensor:
+    """H.v with float32 hDuals, compensated sums and float64 islands."""
+    return _hvp("chessfad_hvp_mixed", func_id, x, v, out, chunk, stream)
+
+
+def chessfad_hessian_mixed(func_id: int, x: torch.Tensor, out: torch.Tensor | None = None, chunk: int = 0,
+                           stream=None) -> torch.Tensor:
+    """Hessians with float32 hDuals, compensated sums and float64 islands."""
+    return _hessian("chessfad_hessian_mixed", func_id, x, out, chunk, stream)
 
 
 def chessfad_fp_set_params(A: torch.Tensor, B: torch.Tensor, alpha: torch.Tensor, stream=None) -> None:

@@ -55,6 +55,8 @@ struct FpSet {
     double* A = nullptr;
     double* B = nullptr;
     double* E = nullptr;
+    float* A32 = nullptr;
+    float* B32 = nullptr;
     int device = -1;
 };
 
@@ -65,6 +67,8 @@ void fp_free(FpSet& s) {
     if (s.A) (void)hipFree(s.A);
     if (s.B) (void)hipFree(s.B);
     if (s.E) (void)hipFree(s.E);
+    if (s.A32) (void)hipFree(s.A32);
+    if (s.B32) (void)hipFree(s.B32);
     s = FpSet{};
 }
 
@@ -82,31 +86,40 @@ __global__ void fp_offsets_kernel(int n, const double* A, const double* B, const
     E[m] = acc;
 }
 
+// float32 copies of A and B (their entries are integers of magnitude <= 100: exact)
+__global__ void fp_to_f32_kernel(int count, const double* A, const double* B, float* A32, float* B32) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    A32[k] = (float)A[k];
+    B32[k] = (float)B[k];
+}
+
 int fp_lookup(int n, FpParams& out) {
     std::lock_guard<std::mutex> lk(g_fp_mu);
     const FpSet& s = g_fp[n];
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return CHESSFAD_E_HIP;
     if (!s.A || s.device != dev) return CHESSFAD_E_PARAMS;
-    out = FpParams{s.A, s.B, s.E};
+    out = FpParams{s.A, s.B, s.E, s.A32, s.B32};
     return CHESSFAD_OK;
 }
 
-PlainLaunch plain_table(int func_id, int C, bool hess) {
+PlainLaunch plain_table(int func_id, int C, bool hess, bool mixed) {
     switch (func_id) {
-        case CHESSFAD_ROSENBROCK: return plain_rosenbrock(C, hess);
-        case CHESSFAD_ACKLEY: return plain_ackley(C, hess);
-        default: return plain_fletcher_powell(C, hess);
+        case CHESSFAD_ROSENBROCK: return mixed ? mixed_rosenbrock(C, hess) : plain_rosenbrock(C, hess);
+        case CHESSFAD_ACKLEY: return mixed ? mixed_ackley(C, hess) : plain_ackley(C, hess);
+        default: return mixed ? mixed_fletcher_powell(C, hess) : plain_fletcher_powell(C, hess);
     }
 }
 
 struct Geometry {
     int nc, rows, block, pstride;
     int64_t grid;
-    size_t lds;
 };
 
-Geometry plain_geometry(int func_id, int n, int64_t npts, int C, bool hess) {
+// Row tasks of nc lanes, about 256 lanes per workgroup (512 when one row
+// needs more).  With n <= 512 the LDS image stays below 45 KiB.
+Geometry plain_geometry(int n, int64_t npts, int C) {
     Geometry g;
     g.nc = (n + C - 1) / C;
     g.rows = g.nc >= 256 ? 1 : 256 / g.nc;
@@ -114,13 +127,11 @@ Geometry plain_geometry(int func_id, int n, int64_t npts, int C, bool hess) {
     g.pstride = (g.rows - 1) / n + 2;
     const int64_t nrows = npts * (int64_t)n;
     g.grid = (nrows + g.rows - 1) / g.rows;
-    const int arrays = 1 + (hess ? 0 : 1) + (func_id == CHESSFAD_ROSENBROCK ? 0 : 2);
-    g.lds = sizeof(double) * ((size_t)arrays * n * g.pstride + g.block);
     return g;
 }
 
 int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-              void* stream, bool hess) {
+              void* stream, bool hess, bool mixed) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     if (chunk == 0) chunk = default_chunk(n);
@@ -139,7 +150,8 @@ int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma) {
-        FpMfmaLaunch launch = fp_mfma_entry(chunk, fp_mfma_steps(n), hess);
+        FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess)
+                                    : fp_mfma_entry(chunk, fp_mfma_steps(n), hess);
         if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
@@ -149,12 +161,12 @@ int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
-    const Geometry g = plain_geometry(func_id, n, npts, chunk, hess);
+    const Geometry g = plain_geometry(n, npts, chunk);
     if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-    PlainLaunch launch = plain_table(func_id, chunk, hess);
+    PlainLaunch launch = plain_table(func_id, chunk, hess, mixed);
     if (!launch) return CHESSFAD_E_CHUNK;
     PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
-    hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), g.lds, s);
+    hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), s);
     return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
 }
 
@@ -164,11 +176,21 @@ extern "C" {
 
 int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
                  void* stream) {
-    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false);
+    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false, false);
 }
 
 int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* H, int chunk, void* stream) {
-    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true);
+    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true, false);
+}
+
+int chessfad_hvp_mixed(int func_id, int n, int64_t npts, const double* x, const double* v, double* out,
+                       int chunk, void* stream) {
+    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false, true);
+}
+
+int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, double* H, int chunk,
+                           void* stream) {
+    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true, true);
 }
 
 int chessfad_fp_set_params(int n, const double* A, const double* B, const double* alpha, void* stream) {
@@ -183,10 +205,18 @@ int chessfad_fp_set_params(int n, const double* A, const double* B, const double
     if (e == hipSuccess) e = hipMalloc(&set.A, mat);
     if (e == hipSuccess) e = hipMalloc(&set.B, mat);
     if (e == hipSuccess) e = hipMalloc(&set.E, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&set.A32, sizeof(float) * (size_t)n * n);
+    if (e == hipSuccess) e = hipMalloc(&set.B32, sizeof(float) * (size_t)n * n);
     if (e == hipSuccess) e = hipMemcpyAsync(set.A, A, mat, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(set.B, B, mat, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(fp_offsets_kernel, dim3((n + 63) / 64), dim3(64), 0, s, n, set.A, set.B, alpha, set.E);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const int count = n * n;
+        hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, set.A, set.B,
+                           set.A32, set.B32);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {

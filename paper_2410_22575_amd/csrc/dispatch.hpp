@@ -8,46 +8,47 @@
 
 namespace chessfad {
 
-using PlainLaunch = hipError_t (*)(const PlainArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
+using PlainLaunch = hipError_t (*)(const PlainArgs&, dim3 grid, dim3 block, hipStream_t);
 
 // Chunk sizes compiled into the library.
 constexpr int kChunks[] = {1, 2, 4, 8, 16};
 constexpr int kNumChunks = sizeof(kChunks) / sizeof(kChunks[0]);
 
-template <class F, int C, bool kHess>
-hipError_t launch_plain(const PlainArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((plain_kernel<F, C, kHess>), grid, block, lds, s, a);
+template <class P, class F, int C, bool kHess>
+hipError_t launch_plain(const PlainArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    const size_t lds = plain_lds_bytes<P, F>(a.n, a.pstride, (int)block.x, kHess);
+    hipLaunchKernelGGL((plain_kernel<P, F, C, kHess>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
-template <class F, bool kHess>
+template <class P, class F, bool kHess>
 PlainLaunch plain_entry(int C) {
     switch (C) {
-        case 1: return &launch_plain<F, 1, kHess>;
-        case 2: return &launch_plain<F, 2, kHess>;
-        case 4: return &launch_plain<F, 4, kHess>;
-        case 8: return &launch_plain<F, 8, kHess>;
-        case 16: return &launch_plain<F, 16, kHess>;
+        case 1: return &launch_plain<P, F, 1, kHess>;
+        case 2: return &launch_plain<P, F, 2, kHess>;
+        case 4: return &launch_plain<P, F, 4, kHess>;
+        case 8: return &launch_plain<P, F, 8, kHess>;
+        case 16: return &launch_plain<P, F, 16, kHess>;
         default: return nullptr;
     }
 }
 
 using FpMfmaLaunch = hipError_t (*)(const FpMfmaArgs&, dim3 grid, dim3 block, hipStream_t);
 
-template <int C, int NK, bool kHess>
+template <class P, int C, int NK, bool kHess>
 hipError_t launch_fp_mfma(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((fp_mfma_kernel<C, NK, kHess>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((fp_mfma_kernel<P, C, NK, kHess>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-template <int NK, bool kHess>
+template <class P, int NK, bool kHess>
 FpMfmaLaunch fp_mfma_entry_c(int C) {
     switch (C) {
-        case 1: return &launch_fp_mfma<1, NK, kHess>;
-        case 2: return &launch_fp_mfma<2, NK, kHess>;
-        case 4: return &launch_fp_mfma<4, NK, kHess>;
-        case 8: return &launch_fp_mfma<8, NK, kHess>;
-        case 16: return &launch_fp_mfma<16, NK, kHess>;
+        case 1: return &launch_fp_mfma<P, 1, NK, kHess>;
+        case 2: return &launch_fp_mfma<P, 2, NK, kHess>;
+        case 4: return &launch_fp_mfma<P, 4, NK, kHess>;
+        case 8: return &launch_fp_mfma<P, 8, NK, kHess>;
+        case 16: return &launch_fp_mfma<P, 16, NK, kHess>;
         default: return nullptr;
     }
 }
@@ -59,10 +60,14 @@ inline int fp_mfma_steps(int n) {
 }
 
 FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess);
+FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess);
 
-// One per function, each defined in its own translation unit.
+// One per (function, precision), each defined in its own translation unit.
 PlainLaunch plain_rosenbrock(int C, bool hess);
 PlainLaunch plain_ackley(int C, bool hess);
 PlainLaunch plain_fletcher_powell(int C, bool hess);
+PlainLaunch mixed_rosenbrock(int C, bool hess);
+PlainLaunch mixed_ackley(int C, bool hess);
+PlainLaunch mixed_fletcher_powell(int C, bool hess);
 
 }  // namespace chessfad

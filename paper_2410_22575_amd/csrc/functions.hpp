@@ -1,15 +1,19 @@
-// The three test functions (Sec. VII), written once over hDual<C> values.
+// The three test functions (Sec. VII), written once over hDual<C> values and
+// a precision policy P (float64, or float32 with compensated sums).
 //
 // Each function struct provides
-//   kTables            how many per-(point, variable) tables it uses (0 or 2)
-//   tables(x, t0, t1)  the transcendental values of one input coordinate
-//   eval<C>(pv, prm)   f evaluated on the CHUNK-INIT seeds of one
-//                      (point, row i, chunk cs) work item
-// A unary function applied to an expression whose value is an exact
-// function of one coordinate (cos(2 pi x_k) in Ackley, sin/cos(x_j) in
-// Fletcher-Powell) takes g, g', g'' from the per-point tables: every call of
-// a point would compute the same numbers, so they are computed once per
-// point and coordinate.  The hDual arithmetic itself is unchanged.
+//   kTables              per-(point, coordinate) transcendental tables (0 or 2)
+//   tables(x, t0, t1)    those values for one coordinate, in float64
+//   isl_tasks / isl_size per-point float64 "island" work: how many tasks and
+//                        how many values per point
+//   island(task, ...)    one task of it, in float64
+//   eval<P, C>(pv, prm)  f evaluated on the CHUNK-INIT seeds of one
+//                        (point, row i, chunk cs) work item
+// Values that every call of a point shares - the transcendentals of single
+// coordinates, Ackley's sqrt and exponentials of its two sums, the
+// Fletcher-Powell residual values - are computed once per point in float64
+// and enter the hDual arithmetic as the (g, g', g'') of the chain rule or as
+// a value component.  The derivative components are unchanged.
 #pragma once
 
 #include "hd.hpp"
@@ -17,25 +21,43 @@
 namespace chessfad {
 
 // One work item's view of its point, staged in LDS in structure-of-arrays
-// form: coordinate k of the point lives at base[k * stride].
+// form: entry k of the point lives at base[k * stride].
+template <typename T>
 struct PointView {
-    const double* xs;
-    const double* t0;
+    const T* xs;          // coordinates (hDual precision)
+    const double* t0;     // tables (float64)
     const double* t1;
+    const T* isl;         // per-point island values (hDual precision)
     int stride;
     int n, i, cs;
-    CF_DEV double x(int k) const { return xs[k * stride]; }
-    CF_DEV double tab0(int k) const { return t0[k * stride]; }
-    CF_DEV double tab1(int k) const { return t1[k * stride]; }
+    CF_DEV T x(int k) const { return xs[k * stride]; }
+    CF_DEV T tab0(int k) const { return (T)t0[k * stride]; }
+    CF_DEV T tab1(int k) const { return (T)t1[k * stride]; }
+    CF_DEV T island(int q) const { return isl[q * stride]; }
     template <int C>
-    CF_DEV HD<double, C> y(int k) const { return seed<double, C>(x(k), k, i, cs); }
+    CF_DEV HD<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
 };
 
 struct FpParams {
-    const double* A;  // [n][n]
-    const double* B;  // [n][n]
-    const double* E;  // [n]
+    const double* A;    // [n][n]
+    const double* B;    // [n][n]
+    const double* E;    // [n]
+    const float* A32;   // float32 copies (exact: the entries are small integers)
+    const float* B32;
 };
+
+template <typename T>
+CF_DEV T fp_a(const FpParams& p, size_t idx);
+template <>
+CF_DEV double fp_a<double>(const FpParams& p, size_t idx) { return p.A[idx]; }
+template <>
+CF_DEV float fp_a<float>(const FpParams& p, size_t idx) { return p.A32[idx]; }
+template <typename T>
+CF_DEV T fp_b(const FpParams& p, size_t idx);
+template <>
+CF_DEV double fp_b<double>(const FpParams& p, size_t idx) { return p.B[idx]; }
+template <>
+CF_DEV float fp_b<float>(const FpParams& p, size_t idx) { return p.B32[idx]; }
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kE = 2.718281828459045235360287471352;
@@ -44,25 +66,30 @@ constexpr double kE = 2.718281828459045235360287471352;
 struct Rosenbrock {
     static constexpr int kTables = 0;
     static CF_DEV void tables(double, double&, double&) {}
+    __host__ __device__ static int isl_tasks(int) { return 0; }
+    __host__ __device__ static int isl_size(int) { return 0; }
+    template <typename T>
+    static CF_DEV void island(int, int, const double*, const double*, const double*, int, const FpParams&, T*) {}
 
-    template <int C>
-    static CF_DEV HD<double, C> term(const HD<double, C>& yk, const HD<double, C>& yk1) {
-        HD<double, C> b = yk1 - yk * yk;
-        HD<double, C> e = 1.0 - yk;
-        return 100.0 * (b * b) + e * e;
+    template <typename T, int C>
+    static CF_DEV HD<T, C> term(const HD<T, C>& yk, const HD<T, C>& yk1) {
+        HD<T, C> b = yk1 - yk * yk;
+        HD<T, C> e = T(1) - yk;
+        return T(100) * (b * b) + e * e;
     }
 
-    template <int C>
-    static CF_DEV HD<double, C> eval(const PointView& pv, const FpParams&) {
-        HD<double, C> yk = pv.y<C>(0);
-        HD<double, C> yk1 = pv.y<C>(1);
-        HD<double, C> s = term<C>(yk, yk1);
+    template <class P, int C>
+    static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
+        using T = typename P::T;
+        HD<T, C> yk = pv.template y<C>(0);
+        HD<T, C> yk1 = pv.template y<C>(1);
+        auto s = P::start(term<T, C>(yk, yk1));
         for (int k = 1; k + 1 < pv.n; ++k) {
             yk = yk1;
-            yk1 = pv.y<C>(k + 1);
-            s = s + term<C>(yk, yk1);
+            yk1 = pv.template y<C>(k + 1);
+            P::add(s, term<T, C>(yk, yk1));
         }
-        return s;
+        return P::value(s);
     }
 };
 
@@ -71,34 +98,56 @@ struct Ackley {
     static constexpr int kTables = 2;
     // t0 = cos(2 pi x), t1 = sin(2 pi x)
     static CF_DEV void tables(double x, double& t0, double& t1) { sincos(kTwoPi * x, &t1, &t0); }
+    __host__ __device__ static int isl_tasks(int) { return 1; }
+    __host__ __device__ static int isl_size(int) { return 5; }
 
-    template <int C>
-    static CF_DEV HD<double, C> cos_term(const PointView& pv, int k) {
-        const double c = pv.tab0(k), s = pv.tab1(k);
-        return chain(kTwoPi * pv.y<C>(k), c, -s, -c);
+    // float64 per-point values: sqrt(u) and its two derivatives at
+    // u = sum x^2 / n, exp(-0.2 sqrt(u)), exp(sum cos(2 pi x) / n)
+    template <typename T>
+    static CF_DEV void island(int, int n, const double* xg, const double* t0, const double*, int stride,
+                              const FpParams&, T* isl) {
+        double ss = xg[0] * xg[0], cs = t0[0];
+        for (int k = 1; k < n; ++k) {
+            ss += xg[k] * xg[k];
+            cs += t0[k * stride];
+        }
+        const double inv_n = 1.0 / n;
+        const double u = inv_n * ss;
+        const double rt = sqrt(u);
+        isl[0] = (T)rt;
+        isl[1 * stride] = (T)(0.5 / rt);
+        isl[2 * stride] = (T)(-0.25 / (rt * u));
+        isl[3 * stride] = (T)exp(-0.2 * rt);
+        isl[4 * stride] = (T)exp(inv_n * cs);
     }
 
-    template <int C>
-    static CF_DEV HD<double, C> eval(const PointView& pv, const FpParams&) {
-        HD<double, C> y = pv.y<C>(0);
-        HD<double, C> ss = y * y;
-        HD<double, C> cs = cos_term<C>(pv, 0);
+    template <typename T, int C>
+    static CF_DEV HD<T, C> cos_term(const PointView<T>& pv, int k) {
+        const T c = pv.tab0(k), s = pv.tab1(k);
+        return chain(T(kTwoPi) * pv.template y<C>(k), c, -s, -c);
+    }
+
+    template <class P, int C>
+    static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
+        using T = typename P::T;
+        HD<T, C> y = pv.template y<C>(0);
+        auto ss = P::start(y * y);
+        auto cs = P::start(cos_term<T, C>(pv, 0));
         for (int k = 1; k < pv.n; ++k) {
-            y = pv.y<C>(k);
-            ss = ss + y * y;
-            cs = cs + cos_term<C>(pv, k);
+            y = pv.template y<C>(k);
+            P::add(ss, y * y);
+            P::add(cs, cos_term<T, C>(pv, k));
         }
-        const double inv_n = 1.0 / pv.n;
-        HD<double, C> t = inv_n * ss;
-        const double rt = sqrt(t.v);
-        t = chain(t, rt, 0.5 / rt, -0.25 / (rt * t.v));
-        t = -0.2 * t;
-        const double e1 = exp(t.v);
-        t = -20.0 * chain(t, e1, e1, e1);
-        HD<double, C> u = inv_n * cs;
-        const double e2 = exp(u.v);
+        const T inv_n = T(1.0 / pv.n);
+        HD<T, C> t = inv_n * P::value(ss);
+        t = chain(t, pv.island(0), pv.island(1), pv.island(2));   // sqrt
+        t = T(-0.2) * t;
+        const T e1 = pv.island(3);
+        t = T(-20) * chain(t, e1, e1, e1);
+        HD<T, C> u = inv_n * P::value(cs);
+        const T e2 = pv.island(4);
         t = t - chain(u, e2, e2, e2);
-        return t + (20.0 + kE);
+        return t + T(20.0 + kE);
     }
 };
 
@@ -107,34 +156,55 @@ struct FletcherPowell {
     static constexpr int kTables = 2;
     // t0 = sin(x), t1 = cos(x)
     static CF_DEV void tables(double x, double& t0, double& t1) { sincos(x, &t0, &t1); }
+    __host__ __device__ static int isl_tasks(int n) { return n; }
+    __host__ __device__ static int isl_size(int n) { return n; }
 
-    template <int C>
-    static CF_DEV HD<double, C> inner(const PointView& pv, const FpParams& prm, int m) {
-        const double* Am = prm.A + (size_t)m * pv.n;
-        const double* Bm = prm.B + (size_t)m * pv.n;
-        HD<double, C> y = pv.y<C>(0);
-        double s = pv.tab0(0), c = pv.tab1(0);
-        HD<double, C> acc = Am[0] * chain(y, s, c, -s);
-        acc = acc + Bm[0] * chain(y, c, -s, -c);
-        for (int j = 1; j < pv.n; ++j) {
-            y = pv.y<C>(j);
-            s = pv.tab0(j);
-            c = pv.tab1(j);
-            acc = acc + Am[j] * chain(y, s, c, -s);
-            acc = acc + Bm[j] * chain(y, c, -s, -c);
+    // float64 residual value r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j
+    template <typename T>
+    static CF_DEV void island(int m, int n, const double*, const double* t0, const double* t1, int stride,
+                              const FpParams& prm, T* isl) {
+        const double* Am = prm.A + (size_t)m * n;
+        const double* Bm = prm.B + (size_t)m * n;
+        double acc = Am[0] * t0[0];
+        acc = acc + Bm[0] * t1[0];
+        for (int j = 1; j < n; ++j) {
+            acc = acc + Am[j] * t0[j * stride];
+            acc = acc + Bm[j] * t1[j * stride];
         }
-        return acc;
+        isl[m * stride] = (T)(prm.E[m] - acc);
     }
 
-    template <int C>
-    static CF_DEV HD<double, C> eval(const PointView& pv, const FpParams& prm) {
-        HD<double, C> r = prm.E[0] - inner<C>(pv, prm, 0);
-        HD<double, C> f = r * r;
-        for (int m = 1; m < pv.n; ++m) {
-            r = prm.E[m] - inner<C>(pv, prm, m);
-            f = f + r * r;
+    // the derivative components of inner_m = sum_j A_mj sin y_j + B_mj cos y_j;
+    // its value is the per-point island
+    template <typename T, int C>
+    static CF_DEV HD<T, C> residual(const PointView<T>& pv, const FpParams& prm, int m) {
+        const size_t row = (size_t)m * pv.n;
+        HD<T, C> y = pv.template y<C>(0);
+        T s = pv.tab0(0), c = pv.tab1(0);
+        HD<T, C> acc = fp_a<T>(prm, row) * chain(y, s, c, -s);
+        acc = acc + fp_b<T>(prm, row) * chain(y, c, -s, -c);
+        for (int j = 1; j < pv.n; ++j) {
+            y = pv.template y<C>(j);
+            s = pv.tab0(j);
+            c = pv.tab1(j);
+            acc = acc + fp_a<T>(prm, row + j) * chain(y, s, c, -s);
+            acc = acc + fp_b<T>(prm, row + j) * chain(y, c, -s, -c);
         }
-        return f;
+        HD<T, C> r = T(prm.E[m]) - acc;
+        r.v = pv.island(m);
+        return r;
+    }
+
+    template <class P, int C>
+    static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams& prm) {
+        using T = typename P::T;
+        HD<T, C> r = residual<T, C>(pv, prm, 0);
+        auto f = P::start(r * r);
+        for (int m = 1; m < pv.n; ++m) {
+            r = residual<T, C>(pv, prm, m);
+            P::add(f, r * r);
+        }
+        return P::value(f);
     }
 };
 

@@ -135,3 +135,94 @@ CF_DEV HD<T, C> chain(const HD<T, C>& a, T g0, T g1, T g2) {
 }
 
 }  // namespace chessfad
+
+namespace chessfad {
+
+// ---------------------------------------------------------------- precision
+// Error-free transformations (Knuth's two-sum; the fma form of two-product).
+// The _rn intrinsics keep the compiler from contracting a neighbouring
+// multiply into these additions, which would break the exact error terms.
+CF_DEV void two_sum(float a, float b, float& s, float& e) {
+    s = __fadd_rn(a, b);
+    const float bb = __fsub_rn(s, a);
+    e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, bb)), __fsub_rn(b, bb));
+}
+
+CF_DEV void two_prod(float a, float b, float& p, float& e) {
+    p = __fmul_rn(a, b);
+    e = fmaf(a, b, -p);
+}
+
+// Plain float64 hDuals: accumulations are ordinary hDual sums.
+struct F64 {
+    using T = double;
+    template <int C>
+    struct Acc {
+        HD<double, C> x;
+    };
+    template <int C>
+    static CF_DEV Acc<C> start(const HD<T, C>& t) { return Acc<C>{t}; }
+    template <int C>
+    static CF_DEV void add(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
+    template <int C>
+    static CF_DEV HD<T, C> value(const Acc<C>& a) { return a.x; }
+    // chunk dot sum_l h[l] v[l]
+    struct Dot {
+        double s = 0.0;
+        CF_DEV void add(T a, T b) { s += a * b; }
+        CF_DEV double get() const { return s; }
+    };
+};
+
+// float32 hDuals whose Hessian-chunk components are accumulated with
+// two-sum compensation (a running low part per component); the chunk dot
+// uses two-product and two-sum and is returned in float64.
+struct F32C {
+    using T = float;
+    template <int C>
+    struct Acc {
+        HD<float, C> x;
+        float lo[C];
+    };
+    template <int C>
+    static CF_DEV Acc<C> start(const HD<T, C>& t) {
+        Acc<C> a;
+        a.x = t;
+#pragma unroll
+        for (int l = 0; l < C; ++l) a.lo[l] = 0.0f;
+        return a;
+    }
+    template <int C>
+    static CF_DEV void add(Acc<C>& a, const HD<T, C>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
+#pragma unroll
+        for (int l = 0; l < C; ++l) {
+            a.x.g[l] += t.g[l];
+            float s, e;
+            two_sum(a.x.h[l], t.h[l], s, e);
+            a.x.h[l] = s;
+            a.lo[l] += e;
+        }
+    }
+    template <int C>
+    static CF_DEV HD<T, C> value(const Acc<C>& a) {
+        HD<T, C> r = a.x;
+#pragma unroll
+        for (int l = 0; l < C; ++l) r.h[l] = a.x.h[l] + a.lo[l];
+        return r;
+    }
+    struct Dot {
+        float hi = 0.0f, lo = 0.0f;
+        CF_DEV void add(T a, T b) {
+            float p, pe, s, e;
+            two_prod(a, b, p, pe);
+            two_sum(hi, p, s, e);
+            hi = s;
+            lo += e + pe;
+        }
+        CF_DEV double get() const { return (double)hi + (double)lo; }
+    };
+};
+
+}  // namespace chessfad

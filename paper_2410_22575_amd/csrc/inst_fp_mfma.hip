@@ -1,4 +1,4 @@
-// Fletcher-Powell float64 MFMA kernels (n <= 16): every compiled chunk size,
+// Fletcher-Powell MFMA kernels (n <= 16), float64: every compiled chunk size,
 // K-step count and output kind.
 #include "dispatch.hpp"
 
@@ -7,10 +7,10 @@ namespace chessfad {
 template <bool kHess>
 static FpMfmaLaunch by_steps(int C, int nk) {
     switch (nk) {
-        case 1: return fp_mfma_entry_c<1, kHess>(C);
-        case 2: return fp_mfma_entry_c<2, kHess>(C);
-        case 4: return fp_mfma_entry_c<4, kHess>(C);
-        case 8: return fp_mfma_entry_c<8, kHess>(C);
+        case 1: return fp_mfma_entry_c<F64, 1, kHess>(C);
+        case 2: return fp_mfma_entry_c<F64, 2, kHess>(C);
+        case 4: return fp_mfma_entry_c<F64, 4, kHess>(C);
+        case 8: return fp_mfma_entry_c<F64, 8, kHess>(C);
         default: return nullptr;
     }
 }

@@ -27,9 +27,16 @@
 // finishes with two lane exchanges.  H.v: the chunk dot and the row sum (in
 // chunk order) stay in registers; Hessian: H[p][i][cs + l] is stored.
 //
-// Operand layouts of v_mfma_f64_16x16x4f64 (lane l = 0..63):
+// Precision policies: F64 runs every step in float64 (v_mfma_f64_16x16x4f64);
+// F32C runs the derivative columns on v_mfma_f32_16x16x4f32 with float32
+// seeded factors and [A B], keeps the value column and the residual values
+// r_m in float64 (their difference E_m - inner_m cancels), and accumulates
+// the sum over m and the chunk dot with two-sum / two-product compensation.
+//
+// Operand layouts (lane l = 0..63), both instructions:
 //   A: lane l holds A[l % 16][l / 16];   B: lane l holds B[l / 16][l % 16];
-//   D: lane l, element r holds D[4 r + l / 16][l % 16].
+//   D (f64): lane l, element r holds D[4 r + l / 16][l % 16];
+//   D (f32): lane l, element r holds D[4 (l / 16) + r][l % 16].
 #pragma once
 
 #include <stdint.h>
@@ -39,6 +46,7 @@
 namespace chessfad {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct FpMfmaArgs {
     const double* x;    // [npts][n]
@@ -55,11 +63,58 @@ constexpr int kFpWaves = 4;                 // waves per workgroup
 constexpr int kFpPointsPerWave = 16;
 constexpr int kFpVStride = kFpMaxN + 1;     // padded LDS row of v
 
-CF_DEV f64x4 mfma_f64(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+CF_DEV f64x4 mfma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+CF_DEV f32x4 mfma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-template <int C, int NK, bool kHess>
+// MFMA accumulator type and the residual row held in element r of lane group lg
+template <typename T>
+struct MfmaTile;
+template <>
+struct MfmaTile<double> {
+    using V = f64x4;
+    static CF_DEV int row(int r, int lg) { return 4 * r + lg; }
+};
+template <>
+struct MfmaTile<float> {
+    using V = f32x4;
+    static CF_DEV int row(int r, int lg) { return 4 * lg + r; }
+};
+
+// Sum over the residual rows of one lane and then across the four lane
+// groups: plain float64, or float32 with two-sum compensation.
+CF_DEV double row_sum4(const double (&t)[4]) {
+    double h = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h += t[r];
+    h += __shfl_xor(h, 16);
+    h += __shfl_xor(h, 32);
+    return h;
+}
+CF_DEV float row_sum4(const float (&t)[4]) {
+    float hi = t[0], lo = 0.0f;
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        float s, e;
+        two_sum(hi, t[r], s, e);
+        hi = s;
+        lo += e;
+    }
+#pragma unroll
+    for (int x = 16; x <= 32; x *= 2) {
+        const float ohi = __shfl_xor(hi, x), olo = __shfl_xor(lo, x);
+        float s, e;
+        two_sum(hi, ohi, s, e);
+        hi = s;
+        lo += e + olo;
+    }
+    return hi + lo;
+}
+
+template <class P, int C, int NK, bool kHess>
 __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
-    __shared__ double vs[kHess ? 1 : kFpWaves * kFpPointsPerWave * kFpVStride];
+    using T = typename P::T;
+    using V = typename MfmaTile<T>::V;
+    __shared__ T vs[kHess ? 1 : kFpWaves * kFpPointsPerWave * kFpVStride];
 
     const int n = a.n, nc = a.nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -70,90 +125,115 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     const double* xp = a.x + (live ? p : 0) * n;
 
     // [A B] operand: row m = li, column k = 4 s + lg (zero outside n x 2n)
-    double aop[NK];
+    double aop64[NK];
+    T aop[NK];
     // seeded sin/cos factors of coordinate jj[s] of this lane's point
-    double g1[NK], g2[NK], gv[NK];
+    T g1[NK], g2[NK];
+    double gv[NK];
     int jj[NK];
 #pragma unroll
     for (int s = 0; s < NK; ++s) {
         const int k = 4 * s + lg;
         const bool in = k < 2 * n;
         const int j = k < n ? k : k - n;
-        aop[s] = (li < n && in) ? (k < n ? a.fp.A[li * n + k] : a.fp.B[li * n + j]) : 0.0;
+        aop64[s] = (li < n && in) ? (k < n ? a.fp.A[li * n + k] : a.fp.B[li * n + j]) : 0.0;
+        aop[s] = (T)aop64[s];
         double sj = 0.0, cj = 0.0;
         if (in && live) sincos(xp[j], &sj, &cj);
         jj[s] = in ? j : -1;
-        gv[s] = k < n ? sj : cj;     // value
-        g1[s] = k < n ? cj : -sj;    // first-derivative factor
-        g2[s] = k < n ? -sj : -cj;   // second-derivative factor
+        gv[s] = k < n ? sj : cj;          // value
+        g1[s] = (T)(k < n ? cj : -sj);    // first-derivative factor
+        g2[s] = (T)(k < n ? -sj : -cj);   // second-derivative factor
     }
 
-    // value column, once per point: r_m = E_m - sum_k [A B][m][k] S[k][value]
-    double rv[4];
+    // value column in float64, once per point: r_m = E_m - sum_k [A B][m][k] S[k][value]
+    // (rows of the f64 tile: m = 4 r + lg; rv[] is indexed like the T tile)
+    T rv[4];
     {
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < NK; ++s) acc = mfma_f64(aop[s], gv[s], acc);
+        for (int s = 0; s < NK; ++s) acc = mfma16(aop64[s], gv[s], acc);
+        double r64[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int m = 4 * r + lg;
-            rv[r] = m < n ? a.fp.E[m] - acc[r] : 0.0;
+            r64[r] = m < n ? a.fp.E[m] - acc[r] : 0.0;
+        }
+        if constexpr (sizeof(T) == sizeof(double)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rv[r] = (T)r64[r];
+        } else {
+            // move row 4 r' + lg' of the f64 layout to element r of lane group lg
+            // (f32 layout row 4 lg + r): row m lives in lane group m % 4, element m / 4
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = 4 * lg + r;
+                const int src = (m & 3) * 16 + li;
+                double val = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const double got = __shfl(r64[rr], src);
+                    if (rr == (m >> 2)) val = got;
+                }
+                rv[r] = (T)val;
+            }
         }
     }
 
-    double* vw = vs + wave * kFpPointsPerWave * kFpVStride;
+    T* vw = vs + wave * kFpPointsPerWave * kFpVStride;
     if (!kHess) {
         // stage the wave's 16 vectors (contiguous in global memory) in LDS
         const double* vg = a.v + pbase * n;
         const int64_t avail = (a.npts - pbase) * n;
         for (int idx = lane; idx < kFpPointsPerWave * n; idx += 64) {
             const int pl = idx / n, k = idx - pl * n;
-            vw[pl * kFpVStride + k] = idx < avail ? vg[idx] : 0.0;
+            vw[pl * kFpVStride + k] = (T)(idx < avail ? vg[idx] : 0.0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
+    const T zero = T(0);
     for (int i = 0; i < n; ++i) {
         // d component (row derivative) of every residual, shared by the row's chunks
-        f64x4 dd = {0.0, 0.0, 0.0, 0.0};
+        V dd = {zero, zero, zero, zero};
 #pragma unroll
-        for (int s = 0; s < NK; ++s) dd = mfma_f64(aop[s], jj[s] == i ? g1[s] : 0.0, dd);
-        double rd[4];
+        for (int s = 0; s < NK; ++s) dd = mfma16(aop[s], jj[s] == i ? g1[s] : zero, dd);
+        T rd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) rd[r] = -dd[r];
 
         double row = 0.0;
         for (int jc = 0; jc < nc; ++jc) {
             const int cs = jc * C;
-            double dot = 0.0;
+            typename P::Dot dot;
 #pragma unroll
             for (int l = 0; l < C; ++l) {
                 if (cs + l >= n) break;  // surplus columns of a ragged last chunk
-                f64x4 ag = {0.0, 0.0, 0.0, 0.0}, ah = {0.0, 0.0, 0.0, 0.0};
+                V ag = {zero, zero, zero, zero}, ah = {zero, zero, zero, zero};
 #pragma unroll
                 for (int s = 0; s < NK; ++s) {
                     const bool col = jj[s] == cs + l;
-                    ag = mfma_f64(aop[s], col ? g1[s] : 0.0, ag);
-                    ah = mfma_f64(aop[s], (col && jj[s] == i) ? g2[s] : 0.0, ah);
+                    ag = mfma16(aop[s], col ? g1[s] : zero, ag);
+                    ah = mfma16(aop[s], (col && jj[s] == i) ? g2[s] : zero, ah);
                 }
-                // second-order component l of r * r, summed over this lane's rows
-                double h = 0.0;
+                // second-order component l of r * r for this lane's rows, then
+                // summed over all residual rows
+                T t[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const double rg = -ag[r], rh = -ah[r];
-                    h += rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh;
+                    const T rg = -ag[r], rh = -ah[r];
+                    t[r] = rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh;
                 }
-                h += __shfl_xor(h, 16);
-                h += __shfl_xor(h, 32);
+                const T h = row_sum4(t);
                 if (kHess) {
-                    if (live && lg == 0) a.out[p * n * n + (int64_t)i * n + cs + l] = h;
+                    if (live && lg == 0) a.out[p * n * n + (int64_t)i * n + cs + l] = (double)h;
                 } else {
-                    dot += h * vw[li * kFpVStride + cs + l];
+                    dot.add(h, vw[li * kFpVStride + cs + l]);
                 }
             }
-            row += dot;
+            if (!kHess) row += dot.get();
         }
         if (!kHess && live && lg == 0) a.out[p * n + i] = row;
     }

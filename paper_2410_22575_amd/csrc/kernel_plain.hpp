@@ -1,18 +1,19 @@
-// Plain float64 chunked Hessian / Hessian-vector kernel for gfx950.
+// Vector-ALU chunked Hessian / Hessian-vector kernel for gfx950.
 //
 // Work decomposition (the paper's finest GPU mapping, Sec. VI, L2): one lane
 // per (point p, row i, chunk j).  A "row task" (p, i) owns nc = ceil(n / C)
 // adjacent lanes; a workgroup owns `rows` consecutive row tasks of the
 // flattened (p, i) index q = p * n + i, so rows of one point may span two
-// workgroups and one workgroup may hold several points.  Each lane:
-//   1. (cooperatively) stages the coordinates of the workgroup's points and,
-//      for H.v, their vectors, into LDS as structure-of-arrays, together with
-//      the function's per-coordinate transcendental tables;
-//   2. evaluates f once on CHUNK-INIT seeds for (i, cs = j * C), entirely in
-//      registers;
-//   3. Hessian: writes H[p][i][cs .. cs + C) (columns < n only, CHUNK-HESS);
+// workgroups and one workgroup may hold several points.  Each workgroup:
+//   1. stages the coordinates of its points and, for H.v, their vectors into
+//      LDS as structure-of-arrays, with the function's per-coordinate
+//      transcendental tables (float64);
+//   2. computes the per-point float64 island values (one task per thread);
+//   3. per lane: evaluates f once on CHUNK-INIT seeds for (i, cs = j * C),
+//      entirely in registers, in the precision of the policy P;
+//   4. Hessian: writes H[p][i][cs .. cs + C) (columns < n only, CHUNK-HESS);
 //      H.v: dots its Hessian chunk with v[p][cs .. cs + C), then the row's
-//      nc partial sums are added in chunk order (CHESS-VEC) through LDS.
+//      nc partial sums are added in chunk order in float64 (CHESS-VEC).
 #pragma once
 
 #include <stdint.h>
@@ -30,15 +31,24 @@ struct PlainArgs {
     int n;              // variables
     int nc;             // chunks per row, ceil(n / C)
     int rows;           // row tasks per workgroup; blockDim.x == rows * nc
-    int pstride;        // LDS stride between coordinates (>= points per workgroup)
+    int pstride;        // LDS stride between entries of one point (>= points per workgroup)
 };
 
 constexpr int kMaxBlock = 512;
 
-// LDS layout, in doubles: xs[n][pstride], vs[n][pstride], t0, t1 [n][pstride],
-// red[blockDim].
-template <class F, int C, bool kHess>
+// LDS bytes for one workgroup (host and device agree on this layout):
+// doubles: red[block], t0, t1 [n][pstride]; T: xs, vs [n][pstride], isl [isl][pstride]
+template <class P, class F>
+__host__ __device__ inline size_t plain_lds_bytes(int n, int pstride, int block, bool hess) {
+    using T = typename P::T;
+    const size_t dbl = (size_t)block + (F::kTables ? 2 * (size_t)n * pstride : 0);
+    const size_t tt = (size_t)n * pstride * (hess ? 1 : 2) + (size_t)F::isl_size(n) * pstride;
+    return dbl * sizeof(double) + tt * sizeof(T);
+}
+
+template <class P, class F, int C, bool kHess>
 __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
+    using T = typename P::T;
     extern __shared__ double lds[];
     const int n = a.n, nc = a.nc, ps = a.pstride;
     const int64_t nrows = a.npts * (int64_t)n;
@@ -47,11 +57,12 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
     const int64_t p0 = q0 / n;
     const int npb = (int)(qlast / n - p0 + 1);  // points touched by this workgroup
 
-    double* xs = lds;
-    double* vs = xs + n * ps;
-    double* t0 = vs + (kHess ? 0 : n * ps);
+    double* red = lds;
+    double* t0 = red + blockDim.x;
     double* t1 = t0 + (F::kTables ? n * ps : 0);
-    double* red = t1 + (F::kTables ? n * ps : 0);
+    T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? n * ps : 0));
+    T* vs = xs + n * ps;
+    T* isl = vs + (kHess ? 0 : n * ps);
 
     // 1. stage coordinates (contiguous in global memory) into SoA LDS
     const double* xg = a.x + p0 * n;
@@ -59,11 +70,20 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
     for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
         const int pl = idx / n, k = idx - pl * n;
         const double xv = xg[idx];
-        xs[k * ps + pl] = xv;
-        if (!kHess) vs[k * ps + pl] = vg[idx];
+        xs[k * ps + pl] = (T)xv;
+        if (!kHess) vs[k * ps + pl] = (T)vg[idx];
         if (F::kTables) F::tables(xv, t0[k * ps + pl], t1[k * ps + pl]);
     }
     __syncthreads();
+    // 2. per-point float64 island values
+    const int tasks = F::isl_tasks(n);
+    if (tasks) {
+        for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
+            const int pl = idx / tasks, task = idx - pl * tasks;
+            F::island(task, n, xg + (size_t)pl * n, t0 + pl, t1 + pl, ps, a.fp, isl + pl);
+        }
+        __syncthreads();
+    }
 
     const int r = threadIdx.x / nc;
     const int j = threadIdx.x - r * nc;
@@ -76,20 +96,22 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
 
     double dot = 0.0;
     if (active) {
-        PointView pv{xs + pl, t0 + pl, t1 + pl, ps, n, i, cs};
-        // 2. one f evaluation on hDual<C> seeds
-        const HD<double, C> res = F::template eval<C>(pv, a.fp);
+        PointView<T> pv{xs + pl, t0 + pl, t1 + pl, isl + pl, ps, n, i, cs};
+        // 3. one f evaluation on hDual<C> seeds
+        const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
         if (kHess) {
-            // 3a. CHUNK-HESS: H[p][i][cs + l] = second-order component l
+            // 4a. CHUNK-HESS: H[p][i][cs + l] = second-order component l
             double* row = a.out + q * n + cs;
 #pragma unroll
             for (int l = 0; l < C; ++l)
-                if (cs + l < n) row[l] = res.h[l];
+                if (cs + l < n) row[l] = (double)res.h[l];
         } else {
-            // 3b. chunk dot with v[p][cs .. cs + C)
+            // 4b. chunk dot with v[p][cs .. cs + C)
+            typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)
-                if (cs + l < n) dot += res.h[l] * vs[(cs + l) * ps + pl];
+                if (cs + l < n) acc.add(res.h[l], vs[(cs + l) * ps + pl]);
+            dot = acc.get();
         }
     }
     if (!kHess) {

@@ -1,0 +1,90 @@
+"""Mixed-precision path (float32 hDuals, compensated sums, float64 islands)
+against the float64 oracle, through the C ABI.
+
+Bar: the same normwise relative errors as the float64 tests,
+    e_hvp = max|r - r*| / (max|H*| max|v|),  e_H = max|H - H*| / max|H*|,
+must stay below TOL32 = 1e-5 (about 170 float32 units of rounding: the
+inputs are rounded to float32 and each Hessian entry goes through a few
+dozen float32 operations before the compensated sums).  The measured
+maxima are printed; they are a few 1e-7.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import closed_form as cf
+from paper_2410_22575_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, A, FP = 0, 1, 2
+TOL32 = 1e-5
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(gpu_lib, w):
+    if w.func == FP:
+        gpu_lib.chessfad_fp_set_params(_dev(w.A), _dev(w.B), _dev(w.alpha))
+        return cf.fp_offsets(w.A, w.B, w.alpha)
+    return None
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+@pytest.mark.parametrize("n,chunks", [(5, (1, 2, 4)), (16, (1, 4, 16)), (64, (4, 16))])
+def test_mixed_against_oracle(gpu_lib, func, n, chunks):
+    npts = 257
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(7000 + 10 * func + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref = cf.hessian(func, w.x, w.A, w.B, E)
+    hmax = np.abs(H_ref).max(axis=(1, 2))
+    r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+    for c in chunks:
+        print(f"[case] mixed func={func} n={n} chunk={c}", flush=True)
+        r = gpu_lib.chessfad_hvp_mixed(func, x, v, chunk=c).cpu().numpy()
+        e_r = (np.abs(r - r_ref).max(axis=1) / (hmax * np.abs(w.v).max(axis=1))).max()
+        H = gpu_lib.chessfad_hessian_mixed(func, x, chunk=c).cpu().numpy()
+        e_H = (np.abs(H - H_ref).max(axis=(1, 2)) / hmax).max()
+        print(f"  max rel err: hvp {e_r:.3e}  hessian {e_H:.3e}", flush=True)
+        assert e_r <= TOL32 and e_H <= TOL32
+        assert e_r > 0.0  # it really is a float32 computation
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_mixed_full_size_sampled(gpu_lib, func):
+    n, npts = 16, 1 << 20
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(1))
+    E = _setup(gpu_lib, w)
+    r = gpu_lib.chessfad_hvp_mixed(func, _dev(w.x), _dev(w.v), chunk=4).cpu().numpy()
+    assert np.all(np.isfinite(r))
+    idx = np.sort(np.random.default_rng(9).choice(npts, 2048, replace=False))
+    H = cf.hessian(func, w.x[idx], w.A, w.B, E)
+    ref = np.einsum("pij,pj->pi", H, w.v[idx])
+    e = np.abs(r[idx] - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
+    print(f"  full size func={func}: max rel err {e.max():.3e}", flush=True)
+    assert e.max() <= TOL32
+
+
+def test_mixed_rosenbrock_structure(gpu_lib):
+    # exact zeros survive in float32 too; at x = 1 every entry is an integer
+    # well inside float32's exact range
+    n = 11
+    w = inputs.make_workload(R, n, 32, inputs.rng_for(7100))
+    H = gpu_lib.chessfad_hessian_mixed(R, _dev(w.x), chunk=4).cpu().numpy()
+    i, j = np.indices((n, n))
+    assert np.all(H[:, np.abs(i - j) > 1] == 0.0)
+    ones = torch.ones(2, n, dtype=torch.float64, device="cuda")
+    np.testing.assert_array_equal(gpu_lib.chessfad_hessian_mixed(R, ones, chunk=2).cpu().numpy(),
+                                  cf.hess_rosenbrock(np.ones((2, n))))
+
+
+def test_mixed_argument_checks(gpu_lib):
+    x = torch.zeros(3, 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.ChessfadError) as ei:
+        gpu_lib.chessfad_hvp_mixed(R, x, x.clone(), chunk=3)
+    assert ei.value.code == -3
+    empty = torch.zeros(0, 8, dtype=torch.float64, device="cuda")
+    assert gpu_lib.chessfad_hvp_mixed(A, empty, empty).shape == (0, 8)
