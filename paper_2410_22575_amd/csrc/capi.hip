@@ -16,7 +16,7 @@ namespace {
 
 thread_local std::string g_hip_error;
 
-// CHESSFAD_OPT_FP_MFMA: Fletcher-Powell contraction on MFMA when n <= 16
+// CHESSFAD_OPT_FP_MFMA: Fletcher-Powell contraction on MFMA
 int g_opt_fp_mfma = 1;
 
 int hip_fail(hipError_t e) {
@@ -159,6 +159,18 @@ int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v
         if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
         FpMfmaArgs a{x, v, out, fp, npts, n, nc};
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
+    if (func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma) {
+        FpRowsLaunch launch = fp_rows_entry(chunk, hess, mixed);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        const int nc = (n + chunk - 1) / chunk;
+        const int rows = nc <= 64 ? 64 / nc : 1;
+        const int row_blocks = (n + rows - 1) / rows;
+        const int64_t grid = npts * row_blocks;
+        if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        FpRowsArgs a{x, v, out, fp, npts, n, nc, rows, row_blocks};
+        hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpRowsWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
     const Geometry g = plain_geometry(n, npts, chunk);

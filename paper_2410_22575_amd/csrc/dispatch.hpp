@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernel_fp_mfma.hpp"
+#include "kernel_fp_rows.hpp"
 #include "kernel_plain.hpp"
 
 namespace chessfad {
@@ -60,6 +61,28 @@ inline int fp_mfma_steps(int n) {
 }
 
 FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess);
+
+using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
+
+template <class P, int C, bool kHess>
+hipError_t launch_fp_rows(const FpRowsArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((fp_rows_kernel<P, C, kHess>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <class P, bool kHess>
+FpRowsLaunch fp_rows_entry_c(int C) {
+    switch (C) {
+        case 1: return &launch_fp_rows<P, 1, kHess>;
+        case 2: return &launch_fp_rows<P, 2, kHess>;
+        case 4: return &launch_fp_rows<P, 4, kHess>;
+        case 8: return &launch_fp_rows<P, 8, kHess>;
+        case 16: return &launch_fp_rows<P, 16, kHess>;
+        default: return nullptr;
+    }
+}
+
+FpRowsLaunch fp_rows_entry(int C, bool hess, bool mixed);
 FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess);
 
 // One per (function, precision), each defined in its own translation unit.

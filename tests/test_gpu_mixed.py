@@ -33,7 +33,7 @@ def _setup(gpu_lib, w):
 
 
 @pytest.mark.parametrize("func", [R, A, FP])
-@pytest.mark.parametrize("n,chunks", [(5, (1, 2, 4)), (16, (1, 4, 16)), (64, (4, 16))])
+@pytest.mark.parametrize("n,chunks", [(5, (1, 2, 4)), (16, (1, 4, 16)), (40, (2, 8)), (64, (4, 16))])
 def test_mixed_against_oracle(gpu_lib, func, n, chunks):
     npts = 257
     w = inputs.make_workload(func, n, npts, inputs.rng_for(7000 + 10 * func + n))

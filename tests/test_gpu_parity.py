@@ -213,3 +213,26 @@ def test_fp_mfma_matches_vector_path(gpu_lib):
         hmax = H0.abs().amax(dim=(1, 2))
         e = (H1 - H0).abs().amax(dim=(1, 2)) / hmax
         assert e.max().item() <= 1e-14
+
+
+@pytest.mark.parametrize("n", [17, 24, 40, 64])
+def test_fp_general_n_mfma(gpu_lib, n):
+    """n > 16: the Fletcher-Powell MFMA kernel with calls as matrix columns
+    (one point per workgroup, several m tiles), against the oracle and the
+    vector path, every chunk size, H.v and Hessian."""
+    npts = 9
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(8000 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref, hmax = _hmax(FP, w, E)
+    r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
+    for c in CHUNKS:
+        print(f"[case] fp rows n={n} chunk={c}", flush=True)
+        with fp_path(gpu_lib, 1):
+            r = gpu_lib.chessfad_hvp(FP, x, v, chunk=c).cpu().numpy()
+            H = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
+        assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
+        assert np.max(np.abs(H - H_ref).max(axis=(1, 2)) / hmax) <= TOL64
+        with fp_path(gpu_lib, 0):
+            H0 = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
+        assert np.max(np.abs(H - H0).max(axis=(1, 2)) / hmax) <= 1e-14
