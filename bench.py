@@ -37,6 +37,7 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 MEASURED_TRAFFIC = {
     "plain_kernel<rosenbrock, C=4, H.v>": 4.028e8,
     "plain_kernel<ackley, C=4, H.v>": 4.028e8,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.030e8,
 }
 
 
