@@ -132,9 +132,76 @@ const char* chessfad_strerror(int code);
  *                         0: every step runs on the vector ALUs.
  *                         Both give the same derivative components; only
  *                         the order of the final sum over residuals differs.
+ *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
+ *                         plan's captured hipGraph; 0: it launches the same
+ *                         kernels directly on the stream.
  */
-enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1 };
+enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1, CHESSFAD_OPT_BATCH_GRAPH = 2 };
 int chessfad_set_option(int option, int value);
+
+/*
+ * Batched H.v over many instances of mixed functions and sizes in one
+ * persistent launch.
+ *
+ * An instance is one function with its own n, points, vectors, output,
+ * chunk, precision and (Fletcher-Powell) parameters.  chessfad_batch_create
+ * validates every instance (on failure *bad_index names it), prepares the
+ * Fletcher-Powell offsets and float32 copies, and splits every instance
+ * into work items of the single-instance kernels' workgroup bodies
+ * (Rosenbrock and Ackley: row blocks of the vector-ALU hDual evaluation;
+ * Fletcher-Powell: row blocks of the MFMA kernel with calls as matrix
+ * columns).  The items are sorted by their operation-count cost, largest
+ * first, and a persistent kernel per precision - sized to fill the GPU -
+ * takes them from an atomic counter until none is left.  The plan captures
+ * a counter reset kernel and the persistent kernels in one hipGraph;
+ * chessfad_batch_run replays it on `stream` (asynchronous; replays on one
+ * stream are ordered, replays of one plan on different streams race on its
+ * counters).
+ *
+ * chunk == 0 takes the autotuned chunk for (func_id, n, precision) if
+ * chessfad_autotune has recorded one, else the default; batched plans are
+ * compiled for chunks 1, 2, 4 and 8.  Rosenbrock and Ackley need
+ * ceil(n / chunk) <= 256.  All arrays are device pointers that must stay
+ * valid while the plan is used; outputs must not overlap their inputs.
+ * The plan owns its device memory (descriptors, work list, counters,
+ * Fletcher-Powell offsets and float32 copies); chessfad_batch_destroy frees it.
+ * Results are the same as chessfad_hvp / chessfad_hvp_mixed on each instance
+ * up to the order of the sum over residuals (Fletcher-Powell, n <= 16).
+ */
+typedef struct chessfad_instance {
+    int func_id;          /* chessfad_func */
+    int n;                /* variables, 1..CHESSFAD_MAX_N */
+    int chunk;            /* 0, 1, 2, 4 or 8 */
+    int precision;        /* 0: float64 hDuals; 1: mixed, as chessfad_hvp_mixed */
+    int64_t npts;         /* points of this instance, >= 0 */
+    const double* x;      /* [npts][n] */
+    const double* v;      /* [npts][n] */
+    double* out;          /* [npts][n] */
+    const double* A;      /* Fletcher-Powell only: [n][n] */
+    const double* B;      /* Fletcher-Powell only: [n][n] */
+    const double* alpha;  /* Fletcher-Powell only: [n] */
+} chessfad_instance;
+
+typedef struct chessfad_batch chessfad_batch;
+
+int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream, chessfad_batch** plan,
+                          int* bad_index);
+int chessfad_batch_run(chessfad_batch* plan, void* stream);
+int chessfad_batch_destroy(chessfad_batch* plan);
+/* Work items, persistent workgroups launched, and paper-model flops of one run. */
+int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgroups, double* model_flops);
+
+/*
+ * Autotuner: times chessfad_hvp (precision 0) or chessfad_hvp_mixed (1) for
+ * every compiled chunk <= n on npts device-generated points and records the
+ * fastest for (func_id, n, precision); chunk == 0 then uses it (single calls
+ * and batched plans; plans only take recorded chunks <= 8).  Fletcher-Powell
+ * needs its parameters registered for n.  Allocates and frees temporary
+ * device memory and synchronises `stream`.  Returns the chosen chunk in
+ * *best_chunk and its time per launch in *best_ms (either may be NULL).
+ */
+int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
+                      float* best_ms);
 
 /* Default chunk size the library uses for (func_id, n) when chunk == 0,
  * or a negative status for invalid arguments. */

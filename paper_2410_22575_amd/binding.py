@@ -17,6 +17,18 @@ LIB_PATH = os.path.join(PKG, "libchessfad.so")
 
 # ABI symbols and their ctypes signatures (must match include/chessfad.h)
 _i, _i64, _p, _s = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_char_p
+_pi, _pi64, _pd, _pf, _pp = (ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_void_p))
+
+
+class Instance(ctypes.Structure):
+    """struct chessfad_instance"""
+    _fields_ = [("func_id", ctypes.c_int), ("n", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("precision", ctypes.c_int), ("npts", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("out", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("B", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
 SIGNATURES = {
     "chessfad_hvp": (_i, [_i, _i, _i64, _p, _p, _p, _i, _p]),
     "chessfad_hessian": (_i, [_i, _i, _i64, _p, _p, _i, _p]),
@@ -27,9 +39,15 @@ SIGNATURES = {
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
     "chessfad_set_option": (_i, [_i, _i]),
+    "chessfad_batch_create": (_i, [_p, _i, _p, _pp, _pi]),
+    "chessfad_batch_run": (_i, [_p, _p]),
+    "chessfad_batch_destroy": (_i, [_p]),
+    "chessfad_batch_info": (_i, [_p, _pi64, _pi, _pd]),
+    "chessfad_autotune": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
 }
 
 CHESSFAD_OPT_FP_MFMA = 1
+CHESSFAD_OPT_BATCH_GRAPH = 2
 
 _lib = None
 
@@ -155,3 +173,74 @@ def chessfad_set_option(option: int, value: int) -> int:
     if rc < 0:
         raise ChessfadError(rc, "chessfad_set_option")
     return rc
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
+
+
+class BatchPlan:
+    """A chessfad_batch plan.  Holds references to every tensor it reads or
+    writes so they stay alive as long as the plan."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def run(self, stream=None):
+        _raise(load().chessfad_batch_run(self._h, _stream(stream)), "chessfad_batch_run")
+
+    def info(self):
+        items, wg, fl = ctypes.c_int64(), ctypes.c_int(), ctypes.c_double()
+        _raise(load().chessfad_batch_info(self._h, ctypes.byref(items), ctypes.byref(wg), ctypes.byref(fl)),
+               "chessfad_batch_info")
+        return {"items": items.value, "workgroups": wg.value, "model_flops": fl.value}
+
+    def destroy(self):
+        if self._h:
+            load().chessfad_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def chessfad_batch_create(instances, stream=None) -> BatchPlan:
+    """instances: list of dicts with func_id, x, v, out (float64 CUDA tensors
+    [npts, n]), optional chunk (0), precision (0 or 1) and, for
+    Fletcher-Powell, A, B, alpha (float64 CUDA tensors)."""
+    arr = (Instance * max(1, len(instances)))()
+    keep = []
+    for k, d in enumerate(instances):
+        x, v, out = d["x"], d["v"], d["out"]
+        _check_pts("x", x)
+        npts, n = x.shape
+        _check_pts("v", v, n)
+        _check_pts("out", out, n)
+        A, B, alpha = d.get("A"), d.get("B"), d.get("alpha")
+        for name, t in (("A", A), ("B", B), ("alpha", alpha)):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"instance {k}: {name} must be a contiguous float64 CUDA tensor")
+        arr[k] = Instance(d["func_id"], n, d.get("chunk", 0), d.get("precision", 0), npts, _ptr(x), _ptr(v),
+                          _ptr(out), _ptr(A), _ptr(B), _ptr(alpha))
+        keep += [t for t in (x, v, out, A, B, alpha) if t is not None]
+    h = ctypes.c_void_p()
+    bad = ctypes.c_int(-1)
+    rc = load().chessfad_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(instances), _stream(stream),
+                                      ctypes.byref(h), ctypes.byref(bad))
+    if rc != 0:
+        err = ChessfadError(rc, f"chessfad_batch_create (instance {bad.value})")
+        err.bad_index = bad.value
+        raise err
+    return BatchPlan(h, keep)
+
+
+def chessfad_autotune(func_id: int, n: int, precision: int = 0, npts: int = 1 << 16, stream=None):
+    """Time every compiled chunk and record the fastest; returns (chunk, ms)."""
+    c, ms = ctypes.c_int(), ctypes.c_float()
+    _raise(load().chessfad_autotune(func_id, n, precision, npts, _stream(stream), ctypes.byref(c), ctypes.byref(ms)),
+           "chessfad_autotune")
+    return c.value, ms.value

@@ -1,0 +1,344 @@
+// Batched plans (persistent kernel + hipGraph) and the chunk autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "batch.hpp"
+#include "dispatch.hpp"
+#include "chessfad.h"
+#include "fp_params.hpp"
+#include "runtime.hpp"
+
+using namespace chessfad;
+
+struct chessfad_batch {
+    int device = -1;
+    char* dmem = nullptr;            // descriptors, work lists, counters, FP workspace
+    unsigned* counters = nullptr;    // one per precision
+    BatchArgs args[2] = {};
+    int grid[2] = {0, 0};
+    size_t lds[2] = {0, 0};
+    int64_t items = 0;
+    double flops = 0.0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int kBatchChunks[] = {1, 2, 4, 8};
+
+bool batch_chunk(int c) {
+    for (int k : kBatchChunks)
+        if (k == c) return true;
+    return false;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct PlanEntry {
+    BatchDesc d;
+    int src;   // instance index
+    int prec;
+    int64_t blocks;
+    double cost_per_block;  // paper-model flops of a full block
+    int64_t calls_per_point;
+};
+
+template <class P>
+size_t plain_lds_for(const BatchDesc& d) {
+    return d.func == CHESSFAD_ROSENBROCK ? plain_lds_bytes<P, Rosenbrock>(d.n, d.pstride, d.rows * d.nc, false)
+                                         : plain_lds_bytes<P, Ackley>(d.n, d.pstride, d.rows * d.nc, false);
+}
+
+template <class P>
+hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(batch_kernel<P>, dim3(grid), dim3(kBatchThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_all(chessfad_batch* b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->counters, 2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && b->args[0].nitems) e = launch_batch<F64>(b->args[0], b->grid[0], b->lds[0], s);
+    if (e == hipSuccess && b->args[1].nitems) e = launch_batch<F32C>(b->args[1], b->grid[1], b->lds[1], s);
+    return e;
+}
+
+void destroy(chessfad_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->dmem) (void)hipFree(b->dmem);
+    delete b;
+}
+
+// deterministic points in a function's domain for timing (splitmix64 hash)
+__global__ void tune_fill_kernel(double* x, double* v, int64_t count, double lo, double hi) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    uint64_t z = (uint64_t)k * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    x[k] = lo + (hi - lo) * u;
+    v[k] = u - 0.5;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream, chessfad_batch** plan,
+                          int* bad_index) {
+    if (bad_index) *bad_index = -1;
+    if (!plan || (ninst > 0 && !inst) || ninst < 0) return CHESSFAD_E_ARG;
+    *plan = nullptr;
+    std::vector<PlanEntry> entries;
+    entries.reserve(ninst);
+    size_t ws_bytes = 0;  // Fletcher-Powell workspace
+    std::vector<size_t> ws_off(ninst, 0);
+    for (int k = 0; k < ninst; ++k) {
+        const chessfad_instance& c = inst[k];
+        auto bad = [&](int rc) {
+            if (bad_index) *bad_index = k;
+            return rc;
+        };
+        int rc = check_func_n(c.func_id, c.n);
+        if (rc) return bad(rc);
+        if (c.precision != 0 && c.precision != 1) return bad(CHESSFAD_E_ARG);
+        if (c.npts < 0) return bad(CHESSFAD_E_ARG);
+        int C = c.chunk ? c.chunk : resolve_chunk(c.func_id, c.n, c.precision, 8);
+        if (!batch_chunk(C) || C > c.n) return bad(CHESSFAD_E_CHUNK);
+        const int nc = (c.n + C - 1) / C;
+        const bool fp = c.func_id == CHESSFAD_FLETCHER_POWELL;
+        if (!fp && nc > kBatchThreads) return bad(CHESSFAD_E_CHUNK);
+        if (c.npts == 0) continue;
+        if (!c.x || !c.v || !c.out) return bad(CHESSFAD_E_NULL);
+        if (fp && (!c.A || !c.B || !c.alpha)) return bad(CHESSFAD_E_PARAMS);
+        const size_t bytes = sizeof(double) * (size_t)c.npts * c.n;
+        if (overlaps(c.out, bytes, c.x, bytes) || overlaps(c.out, bytes, c.v, bytes)) return bad(CHESSFAD_E_OVERLAP);
+
+        PlanEntry e{};
+        e.src = k;
+        e.prec = c.precision;
+        e.d.func = c.func_id;
+        e.d.C = C;
+        e.d.n = c.n;
+        e.d.nc = nc;
+        e.d.npts = c.npts;
+        e.d.x = c.x;
+        e.d.v = c.v;
+        e.d.out = c.out;
+        e.d.fp = FpParams{c.A, c.B, nullptr, nullptr, nullptr};
+        e.calls_per_point = (int64_t)c.n * nc;
+        if (fp) {
+            e.d.kind = 1;
+            e.d.rows = nc <= 64 ? 64 / nc : 1;
+            e.d.row_blocks = (c.n + e.d.rows - 1) / e.d.rows;
+            e.d.pstride = 0;
+            e.blocks = c.npts * e.d.row_blocks;
+            ws_off[k] = ws_bytes;
+            ws_bytes += align_up(sizeof(double) * c.n, 256) + 2 * align_up(sizeof(float) * (size_t)c.n * c.n, 256);
+        } else {
+            e.d.kind = 0;
+            e.d.rows = kBatchThreads / nc;
+            e.d.pstride = (e.d.rows - 1) / c.n + 2;
+            e.d.row_blocks = 0;
+            e.blocks = (c.npts * c.n + e.d.rows - 1) / e.d.rows;
+        }
+        if (e.blocks > 0x7fffffffLL) return bad(CHESSFAD_E_ARG);
+        e.cost_per_block = model_flops_per_call(c.func_id, c.n, C) * e.d.rows * nc;
+        entries.push_back(e);
+    }
+
+    // one device allocation: descriptors, items, counters, Fletcher-Powell workspace
+    size_t nitems[2] = {0, 0}, ndesc[2] = {0, 0};
+    for (const PlanEntry& e : entries) {
+        nitems[e.prec] += (size_t)e.blocks;
+        ndesc[e.prec] += 1;
+    }
+    size_t off_desc[2], off_items[2], total = 0;
+    for (int pr = 0; pr < 2; ++pr) {
+        off_desc[pr] = total;
+        total = align_up(total + sizeof(BatchDesc) * ndesc[pr], 256);
+        off_items[pr] = total;
+        total = align_up(total + sizeof(BatchItem) * nitems[pr], 256);
+    }
+    const size_t off_counters = total;
+    total = align_up(total + 2 * sizeof(unsigned), 256);
+    const size_t off_ws = total;
+    total += ws_bytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    chessfad_batch* b = new chessfad_batch;
+    hipError_t err = hipGetDevice(&b->device);
+    if (err == hipSuccess) err = hipMalloc(&b->dmem, std::max<size_t>(total, 256));
+    if (err != hipSuccess) {
+        destroy(b);
+        return hip_fail(err);
+    }
+    b->counters = reinterpret_cast<unsigned*>(b->dmem + off_counters);
+
+    // Fletcher-Powell offsets and float32 copies, per instance
+    for (PlanEntry& e : entries) {
+        if (e.d.kind != 1 || err != hipSuccess) continue;
+        const chessfad_instance& c = inst[e.src];
+        char* w = b->dmem + off_ws + ws_off[e.src];
+        double* E = reinterpret_cast<double*>(w);
+        float* A32 = reinterpret_cast<float*>(w + align_up(sizeof(double) * c.n, 256));
+        float* B32 = reinterpret_cast<float*>(reinterpret_cast<char*>(A32) + align_up(sizeof(float) * (size_t)c.n * c.n, 256));
+        hipLaunchKernelGGL(fp_offsets_kernel, dim3((c.n + 63) / 64), dim3(64), 0, s, c.n, c.A, c.B, c.alpha, E);
+        err = hipGetLastError();
+        if (err != hipSuccess) break;
+        const int count = c.n * c.n;
+        hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, c.A, c.B, A32, B32);
+        err = hipGetLastError();
+        e.d.fp = FpParams{c.A, c.B, E, A32, B32};
+    }
+    // work lists per precision, largest model cost first
+    std::vector<BatchDesc> descs[2];
+    std::vector<std::pair<double, BatchItem>> items[2];
+    for (const PlanEntry& e : entries) {
+        const int di = (int)descs[e.prec].size();
+        descs[e.prec].push_back(e.d);
+        for (int64_t blk = 0; blk < e.blocks; ++blk) {
+            double cost = e.cost_per_block;
+            if (e.d.kind == 0) {
+                const int64_t q0 = blk * e.d.rows, rows = std::min<int64_t>(e.d.rows, e.d.npts * e.d.n - q0);
+                cost = cost * (double)rows / e.d.rows;
+            } else {
+                const int r0 = (int)(blk % e.d.row_blocks) * e.d.rows;
+                cost = cost * (double)std::min(e.d.rows, e.d.n - r0) / e.d.rows;
+            }
+            items[e.prec].push_back({cost, BatchItem{di, (int)blk}});
+            b->flops += cost;
+        }
+    }
+    for (auto& it : items)
+        std::stable_sort(it.begin(), it.end(), [](const auto& l, const auto& r) { return l.first > r.first; });
+
+    // upload descriptors and sorted work lists; size the persistent grids
+    int cus = 0;
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    for (int pr = 0; pr < 2 && err == hipSuccess; ++pr) {
+        std::vector<BatchItem> flat;
+        flat.reserve(items[pr].size());
+        size_t lds = 0;
+        for (const auto& it : items[pr]) flat.push_back(it.second);
+        for (const BatchDesc& d : descs[pr]) {
+            const size_t need = d.kind == 1 ? sizeof(FpRowsShared) : (pr ? plain_lds_for<F32C>(d) : plain_lds_for<F64>(d));
+            lds = std::max(lds, need);
+        }
+        BatchDesc* dd = reinterpret_cast<BatchDesc*>(b->dmem + off_desc[pr]);
+        BatchItem* di = reinterpret_cast<BatchItem*>(b->dmem + off_items[pr]);
+        if (!descs[pr].empty()) err = hipMemcpyAsync(dd, descs[pr].data(), sizeof(BatchDesc) * descs[pr].size(), hipMemcpyHostToDevice, s);
+        if (err == hipSuccess && !flat.empty())
+            err = hipMemcpyAsync(di, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        b->args[pr] = BatchArgs{dd, di, (int)flat.size(), b->counters + pr};
+        b->lds[pr] = lds;
+        b->items += (int64_t)flat.size();
+        if (err == hipSuccess && !flat.empty()) {
+            int per_cu = 0;
+            err = pr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<F32C>, kBatchThreads, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<F64>, kBatchThreads, lds);
+            b->grid[pr] = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, (int64_t)flat.size());
+        }
+    }
+    // capture reset + persistent kernels in one graph
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+        hipError_t le = launch_all(b, b->capture);
+        err = hipStreamEndCapture(b->capture, &b->graph);
+        if (err == hipSuccess) err = le;
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        destroy(b);
+        return hip_fail(err);
+    }
+    *plan = b;
+    return CHESSFAD_OK;
+}
+
+int chessfad_batch_run(chessfad_batch* plan, void* stream) {
+    if (!plan) return CHESSFAD_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = option_value(CHESSFAD_OPT_BATCH_GRAPH) ? hipGraphLaunch(plan->exec, s) : launch_all(plan, s);
+    return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+}
+
+int chessfad_batch_destroy(chessfad_batch* plan) {
+    if (!plan) return CHESSFAD_E_ARG;
+    destroy(plan);
+    return CHESSFAD_OK;
+}
+
+int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgroups, double* model_flops) {
+    if (!plan) return CHESSFAD_E_ARG;
+    if (items) *items = plan->items;
+    if (workgroups) *workgroups = plan->grid[0] + plan->grid[1];
+    if (model_flops) *model_flops = plan->flops;
+    return CHESSFAD_OK;
+}
+
+int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
+                      float* best_ms) {
+    int rc = check_func_n(func_id, n);
+    if (rc) return rc;
+    if ((precision != 0 && precision != 1) || npts <= 0) return CHESSFAD_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t count = (size_t)npts * n;
+    double *x = nullptr, *v = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipMalloc(&x, count * sizeof(double));
+    if (err == hipSuccess) err = hipMalloc(&v, count * sizeof(double));
+    if (err == hipSuccess) err = hipMalloc(&out, count * sizeof(double));
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    const double lo = func_id == CHESSFAD_ROSENBROCK ? -2.0 : func_id == CHESSFAD_ACKLEY ? -5.0 : -3.141592653589793;
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(tune_fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, v,
+                           (int64_t)count, lo, -lo);
+        err = hipGetLastError();
+    }
+    int best = 0;
+    float best_t = 0.0f;
+    for (int k = 0; k < kNumChunks && err == hipSuccess && rc == CHESSFAD_OK; ++k) {
+        const int C = kChunks[k];
+        if (C > n) break;
+        rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1);  // warm-up
+        if (rc) break;
+        err = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && rc == CHESSFAD_OK; ++r)
+            rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        ms /= 3.0f;
+        if (err == hipSuccess && rc == CHESSFAD_OK && (best == 0 || ms < best_t)) {
+            best = C;
+            best_t = ms;
+        }
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (x) (void)hipFree(x);
+    if (v) (void)hipFree(v);
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (err != hipSuccess) return hip_fail(err);
+    record_tuned_chunk(func_id, n, precision, best);
+    if (best_chunk) *best_chunk = best;
+    if (best_ms) *best_ms = best_t;
+    return CHESSFAD_OK;
+}
+
+}  // extern "C"

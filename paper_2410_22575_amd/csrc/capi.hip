@@ -1,7 +1,9 @@
-// C ABI of the chunked Hessian library (declared in include/chessfad.h).
+// C ABI of the chunked Hessian library (declared in include/chessfad.h):
+// single-instance entry points, the Fletcher-Powell parameter registry,
+// options, status strings, and the host services shared with the batched
+// planner (tuned chunk table, operation-count model).
 //
-// Host side only: argument checks (all before anything is enqueued), launch
-// geometry, the Fletcher-Powell parameter registry, and error reporting.
+// Host side only: every argument check happens before anything is enqueued.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -9,25 +11,24 @@
 
 #include "chessfad.h"
 #include "dispatch.hpp"
+#include "fp_params.hpp"
+#include "runtime.hpp"
 
 using namespace chessfad;
 
 namespace {
-
 thread_local std::string g_hip_error;
+std::mutex g_tune_mu;
+int g_tuned[3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (func, precision, n); 0 = none
+int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
+int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
+}  // namespace
 
-// CHESSFAD_OPT_FP_MFMA: Fletcher-Powell contraction on MFMA
-int g_opt_fp_mfma = 1;
+namespace chessfad {
 
 int hip_fail(hipError_t e) {
     g_hip_error = hipGetErrorString(e);
     return CHESSFAD_E_HIP;
-}
-
-bool chunk_compiled(int c) {
-    for (int k = 0; k < kNumChunks; ++k)
-        if (kChunks[k] == c) return true;
-    return false;
 }
 
 int check_func_n(int func_id, int n) {
@@ -37,18 +38,47 @@ int check_func_n(int func_id, int n) {
     return CHESSFAD_OK;
 }
 
-int default_chunk(int n) {
+int resolve_chunk(int func_id, int n, int precision, int max_chunk) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const int t = g_tuned[func_id][precision][n];
+        if (t > 0 && t <= max_chunk) return t;
+    }
+    // built-in default: the largest compiled chunk <= min(4, n, max_chunk)
     int c = 1;
     for (int k = 0; k < kNumChunks; ++k)
-        if (kChunks[k] <= n && kChunks[k] <= 4) c = kChunks[k];
+        if (kChunks[k] <= n && kChunks[k] <= 4 && kChunks[k] <= max_chunk) c = kChunks[k];
     return c;
 }
 
-bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
-    const char* pa = static_cast<const char*>(a);
-    const char* pb = static_cast<const char*>(b);
-    return pa < pb + bbytes && pb < pa + abytes;
+void record_tuned_chunk(int func_id, int n, int precision, int chunk) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[func_id][precision][n] = chunk;
 }
+
+double model_flops_per_call(int func_id, int n, int C) {
+    const double hadd = 2.0 * C + 2, hmul = 10.0 * C + 4, scal = 2.0 * C + 2, unary = 4.0 * C + 2, dot = 2.0 * C;
+    if (func_id == CHESSFAD_ROSENBROCK) return (n - 1) * (3 * hmul + 3 * hadd + scal + 1) - hadd + dot;
+    if (func_id == CHESSFAD_ACKLEY)
+        return n * (hmul + hadd + scal + unary + hadd) - 2 * hadd + 4 * scal + 3 * unary + hadd + 1 + dot;
+    return 2.0 * n * unary + n * (2.0 * n * scal + (2.0 * n - 1) * hadd + 1 + hmul) + (n - 1) * hadd + dot;
+}
+
+bool chunk_compiled(int c) {
+    for (int k = 0; k < kNumChunks; ++k)
+        if (kChunks[k] == c) return true;
+    return false;
+}
+
+int option_value(int option) {
+    if (option == CHESSFAD_OPT_FP_MFMA) return g_opt_fp_mfma;
+    if (option == CHESSFAD_OPT_BATCH_GRAPH) return g_opt_batch_graph;
+    return CHESSFAD_E_ARG;
+}
+
+}  // namespace chessfad
+
+namespace {
 
 // ------------------------------------------------ Fletcher-Powell parameters
 struct FpSet {
@@ -70,28 +100,6 @@ void fp_free(FpSet& s) {
     if (s.A32) (void)hipFree(s.A32);
     if (s.B32) (void)hipFree(s.B32);
     s = FpSet{};
-}
-
-// E_m = sum_j A_mj sin(alpha_j) + B_mj cos(alpha_j), one thread per m, float64
-__global__ void fp_offsets_kernel(int n, const double* A, const double* B, const double* alpha, double* E) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) {
-        double s, c;
-        sincos(alpha[j], &s, &c);
-        acc += A[(size_t)m * n + j] * s;
-        acc += B[(size_t)m * n + j] * c;
-    }
-    E[m] = acc;
-}
-
-// float32 copies of A and B (their entries are integers of magnitude <= 100: exact)
-__global__ void fp_to_f32_kernel(int count, const double* A, const double* B, float* A32, float* B32) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
-    A32[k] = (float)A[k];
-    B32[k] = (float)B[k];
 }
 
 int fp_lookup(int n, FpParams& out) {
@@ -130,11 +138,13 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
     return g;
 }
 
-int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-              void* stream, bool hess, bool mixed) {
+}  // namespace
+
+int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+                         void* stream, bool hess, bool mixed) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
-    if (chunk == 0) chunk = default_chunk(n);
+    if (chunk == 0) chunk = resolve_chunk(func_id, n, mixed ? 1 : 0, 16);
     if (chunk < 0 || !chunk_compiled(chunk) || chunk > n) return CHESSFAD_E_CHUNK;
     if (npts < 0) return CHESSFAD_E_ARG;
     if (npts == 0) return CHESSFAD_OK;
@@ -182,27 +192,25 @@ int run_plain(int func_id, int n, int64_t npts, const double* x, const double* v
     return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
 }
 
-}  // namespace
-
 extern "C" {
 
 int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
                  void* stream) {
-    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false, false);
+    return run_single(func_id, n, npts, x, v, out, chunk, stream, false, false);
 }
 
 int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* H, int chunk, void* stream) {
-    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true, false);
+    return run_single(func_id, n, npts, x, nullptr, H, chunk, stream, true, false);
 }
 
 int chessfad_hvp_mixed(int func_id, int n, int64_t npts, const double* x, const double* v, double* out,
                        int chunk, void* stream) {
-    return run_plain(func_id, n, npts, x, v, out, chunk, stream, false, true);
+    return run_single(func_id, n, npts, x, v, out, chunk, stream, false, true);
 }
 
 int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, double* H, int chunk,
                            void* stream) {
-    return run_plain(func_id, n, npts, x, nullptr, H, chunk, stream, true, true);
+    return run_single(func_id, n, npts, x, nullptr, H, chunk, stream, true, true);
 }
 
 int chessfad_fp_set_params(int n, const double* A, const double* B, const double* alpha, void* stream) {
@@ -261,18 +269,17 @@ const char* chessfad_strerror(int code) {
 }
 
 int chessfad_set_option(int option, int value) {
-    if (option == CHESSFAD_OPT_FP_MFMA) {
-        if (value != 0 && value != 1) return CHESSFAD_E_ARG;
-        const int prev = g_opt_fp_mfma;
-        g_opt_fp_mfma = value;
-        return prev;
-    }
-    return CHESSFAD_E_ARG;
+    int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
+              : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph : nullptr;
+    if (!slot || (value != 0 && value != 1)) return CHESSFAD_E_ARG;
+    const int prev = *slot;
+    *slot = value;
+    return prev;
 }
 
 int chessfad_default_chunk(int func_id, int n) {
     int rc = check_func_n(func_id, n);
-    return rc ? rc : default_chunk(n);
+    return rc ? rc : resolve_chunk(func_id, n, 0, 16);
 }
 
 }  // extern "C"

@@ -80,19 +80,30 @@ struct RunSum<float> {
     }
 };
 
+// LDS of one workgroup (vv and dots are used only for H.v)
+struct FpRowsShared {
+    double s64[kFpRowsMaxN], c64[kFpRowsMaxN], rvs[kFpRowsMaxN];
+    double vv[kFpRowsMaxN];
+    double dots[kFpRowsMaxCalls];
+};
+
+// One workgroup's share: block blk = (point, row block).  Needs exactly
+// 64 * kFpRowsWaves threads.
 template <class P, int C, bool kHess>
-__global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a) {
+__device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, FpRowsShared& sh) {
     using T = typename P::T;
     using V = typename MfmaTile<T>::V;
     constexpr int LBMAX = sizeof(T) == sizeof(double) ? 4 : 8;
     constexpr int LB = C < LBMAX ? C : LBMAX;
-    __shared__ double s64[kFpRowsMaxN], c64[kFpRowsMaxN], rvs[kFpRowsMaxN];
-    __shared__ T vv[kHess ? 1 : kFpRowsMaxN];
-    __shared__ double dots[kHess ? 1 : kFpRowsMaxCalls];
+    double* s64 = sh.s64;
+    double* c64 = sh.c64;
+    double* rvs = sh.rvs;
+    double* vv = sh.vv;
+    double* dots = sh.dots;
 
     const int n = a.n, nc = a.nc;
-    const int64_t p = blockIdx.x / a.row_blocks;
-    const int r0 = (int)(blockIdx.x - p * a.row_blocks) * a.rows;
+    const int64_t p = blk / a.row_blocks;
+    const int r0 = (int)(blk - p * a.row_blocks) * a.rows;
     const int nrows = (r0 + a.rows <= n ? a.rows : n - r0);
     const int ncalls = nrows * nc;
     const double* xp = a.x + p * n;
@@ -104,7 +115,7 @@ __global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a
         sincos(xp[t], &s, &c);
         s64[t] = s;
         c64[t] = c;
-        if (!kHess) vv[t] = (T)a.v[p * n + t];
+        if (!kHess) vv[t] = a.v[p * n + t];
     }
     __syncthreads();
     for (int m = threadIdx.x; m < n; m += blockDim.x) {
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a
                 typename P::Dot dot;
 #pragma unroll
                 for (int l = 0; l < C; ++l)
-                    if (cs + l < n) dot.add(h[l], vv[cs + l]);
+                    if (cs + l < n) dot.add(h[l], (T)vv[cs + l]);
                 dots[cl] = dot.get();
             }
         }
@@ -219,6 +230,12 @@ __global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a
             a.out[p * n + r0 + t] = s;
         }
     }
+}
+
+template <class P, int C, bool kHess>
+__global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a) {
+    __shared__ FpRowsShared sh;
+    fp_rows_block<P, C, kHess>(a, blockIdx.x, sh);
 }
 
 }  // namespace chessfad

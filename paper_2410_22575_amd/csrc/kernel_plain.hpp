@@ -46,19 +46,22 @@ __host__ __device__ inline size_t plain_lds_bytes(int n, int pstride, int block,
     return dbl * sizeof(double) + tt * sizeof(T);
 }
 
+// One workgroup's share of the launch: row tasks [blk * rows, blk * rows + rows).
+// Uses the first rows * nc threads; any further threads of the workgroup
+// only take part in the barriers.  `lds` holds plain_lds_bytes() bytes.
 template <class P, class F, int C, bool kHess>
-__global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
+__device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, double* lds) {
     using T = typename P::T;
-    extern __shared__ double lds[];
     const int n = a.n, nc = a.nc, ps = a.pstride;
+    const int nthr = a.rows * nc;
     const int64_t nrows = a.npts * (int64_t)n;
-    const int64_t q0 = (int64_t)blockIdx.x * a.rows;
+    const int64_t q0 = blk * a.rows;
     const int64_t qlast = (q0 + a.rows < nrows ? q0 + a.rows : nrows) - 1;
     const int64_t p0 = q0 / n;
     const int npb = (int)(qlast / n - p0 + 1);  // points touched by this workgroup
 
     double* red = lds;
-    double* t0 = red + blockDim.x;
+    double* t0 = red + nthr;
     double* t1 = t0 + (F::kTables ? n * ps : 0);
     T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? n * ps : 0));
     T* vs = xs + n * ps;
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
     const int r = threadIdx.x / nc;
     const int j = threadIdx.x - r * nc;
     const int64_t q = q0 + r;
-    const bool active = q <= qlast;
+    const bool active = threadIdx.x < nthr && q <= qlast;
     const int64_t p = q / n;
     const int i = (int)(q - p * n);
     const int pl = (int)(p - p0);
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
     }
     if (!kHess) {
         // row sum over the nc chunk lanes, in chunk order
-        red[threadIdx.x] = dot;
+        if (threadIdx.x < nthr) red[threadIdx.x] = dot;
         __syncthreads();
         if (active && j == 0) {
             double s = red[threadIdx.x];
@@ -124,6 +127,12 @@ __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
             a.out[q] = s;
         }
     }
+}
+
+template <class P, class F, int C, bool kHess>
+__global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
+    extern __shared__ double lds[];
+    plain_block<P, F, C, kHess>(a, blockIdx.x, lds);
 }
 
 }  // namespace chessfad

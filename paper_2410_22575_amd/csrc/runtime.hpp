@@ -1,0 +1,38 @@
+// Host-side services shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chessfad {
+
+// Records the HIP error text for chessfad_strerror and returns CHESSFAD_E_HIP.
+int hip_fail(hipError_t e);
+
+// Checks (func_id, n) against the compiled limits.
+int check_func_n(int func_id, int n);
+
+// Chunk used when the caller passes 0: the autotuned choice for
+// (func_id, n, precision) if there is one, else the built-in default.
+int resolve_chunk(int func_id, int n, int precision, int max_chunk);
+void record_tuned_chunk(int func_id, int n, int precision, int chunk);
+
+// Single-instance launch shared by chessfad_hvp / _hessian / _mixed.
+int run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+               void* stream, bool hess, bool mixed);
+
+// Paper-model flops of one f call (Sec. V operation counts, chunk dot included).
+double model_flops_per_call(int func_id, int n, int C);
+
+bool chunk_compiled(int c);
+
+// Current value of a chessfad_option.
+int option_value(int option);
+
+inline bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+}  // namespace chessfad

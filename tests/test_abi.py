@@ -113,3 +113,41 @@ def test_binding_rejects_bad_tensors():
         binding.chessfad_hvp(R, x, x)
     with pytest.raises(ValueError):
         binding.chessfad_hessian(R, x)
+
+
+def _inst(func=R, n=16, chunk=4, precision=0, npts=3, x=FAKE, v=FAKE * 2, out=FAKE * 4, A=None, B=None, alpha=None):
+    return binding.Instance(func, n, chunk, precision, npts, x, v, out, A, B, alpha)
+
+
+def _create(lib, insts):
+    arr = (binding.Instance * len(insts))(*insts)
+    h, bad = ctypes.c_void_p(), ctypes.c_int(-7)
+    rc = lib.chessfad_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(insts), None, ctypes.byref(h),
+                                   ctypes.byref(bad))
+    return rc, bad.value
+
+
+def test_batch_validation_before_any_device_work(lib):
+    ok = _inst()
+    assert _create(lib, [ok, _inst(chunk=16)]) == (E_CHUNK, 1)          # batched chunks: 1, 2, 4, 8
+    assert _create(lib, [_inst(func=9), ok]) == (E_FUNC, 0)
+    assert _create(lib, [ok, ok, _inst(n=600)]) == (E_N, 2)
+    assert _create(lib, [_inst(precision=2)]) == (E_ARG, 0)
+    assert _create(lib, [_inst(npts=-1)]) == (E_ARG, 0)
+    assert _create(lib, [_inst(func=FP)]) == (E_PARAMS, 0)              # Fletcher-Powell without A, B, alpha
+    assert _create(lib, [_inst(x=None)]) == (E_NULL, 0)
+    assert _create(lib, [_inst(out=FAKE)]) == (E_OVERLAP, 0)
+    assert _create(lib, [_inst(n=8, chunk=8, func=A), _inst(n=300, chunk=1)]) == (E_CHUNK, 1)  # nc > 256
+    h = ctypes.c_void_p()
+    assert lib.chessfad_batch_create(None, 2, None, ctypes.byref(h), None) == E_ARG
+    assert lib.chessfad_batch_run(None, None) == E_ARG
+    assert lib.chessfad_batch_destroy(None) == E_ARG
+    assert lib.chessfad_batch_info(None, None, None, None) == E_ARG
+
+
+def test_autotune_argument_checks(lib):
+    c, ms = ctypes.c_int(), ctypes.c_float()
+    assert lib.chessfad_autotune(4, 16, 0, 100, None, ctypes.byref(c), ctypes.byref(ms)) == E_FUNC
+    assert lib.chessfad_autotune(R, 1, 0, 100, None, None, None) == E_N
+    assert lib.chessfad_autotune(A, 16, 3, 100, None, None, None) == E_ARG
+    assert lib.chessfad_autotune(A, 16, 0, 0, None, None, None) == E_ARG
