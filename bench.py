@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--npts", type=int, default=NPTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="use the default chunk instead of autotuning it")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance workload")
+    ap.add_argument("--batch-instances", type=int, default=8192)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -102,6 +105,78 @@ def cpu_baseline(workloads, E, chunks, budget_s):
             "per_function": per}
 
 
+def batched(ninst, binding, inputs, cf, torch):
+    """Mixed-function batch: `ninst` single-point instances, function uniform
+    over the three, n log-uniform in [8, 256], each Fletcher-Powell instance
+    with its own parameters.  Times one replay of the plan's hipGraph in
+    float32-mixed and in float64, and the same instances as separate
+    float64 chessfad_hvp launches (kernel time only, summed)."""
+    ws = inputs.mixed_instances(ninst, inputs.rng_for(4), 8, 256, npts=1)
+    dev = torch.device("cuda:0")
+    insts = []
+    for w in ws:
+        d = {"func_id": w.func, "x": torch.from_numpy(w.x).to(dev), "v": torch.from_numpy(w.v).to(dev),
+             "out": torch.empty((w.npts, w.n), dtype=torch.float64, device=dev)}
+        if w.func == 2:
+            d.update(A=torch.from_numpy(w.A).to(dev), B=torch.from_numpy(w.B).to(dev),
+                     alpha=torch.from_numpy(w.alpha).to(dev))
+        insts.append(d)
+    torch.cuda.synchronize()
+
+    def timed(plan, reps=3):
+        plan.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res = {"workload": f"{ninst} single-point instances, function uniform over Rosenbrock/Ackley/Fletcher-Powell, "
+                       "n log-uniform in [8, 256], own Fletcher-Powell parameters each; chunk per (function, n) "
+                       "from the autotuned table or the default"}
+    outs = {}
+    for prec, name in ((1, "mixed_f32"), (0, "f64")):
+        for d in insts:
+            d["precision"] = prec
+        plan = binding.chessfad_batch_create(insts)
+        ms = timed(plan)
+        info = plan.info()
+        res[name] = {"graph_ms": ms, "hvps_per_s": ninst / (ms * 1e-3), "model_tflops": info["model_flops"] / (ms * 1e-3) / 1e12,
+                     "items": info["items"], "workgroups": info["workgroups"]}
+        outs[name] = [d["out"].clone() for d in insts]
+        plan.destroy()
+    # the same instances one launch each (float64), kernel time only
+    total = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for d, w in zip(insts, ws):
+        if w.func == 2:
+            binding.chessfad_fp_set_params(d["A"], d["B"], d["alpha"])
+        e0.record()
+        binding.chessfad_hvp(w.func, d["x"], d["v"], d["out"], chunk=min(4, w.n))
+        e1.record()
+        e1.synchronize()
+        total += e0.elapsed_time(e1)
+    res["per_instance_f64_kernel_ms_sum"] = total
+    res["speedup_mixed_batched_vs_per_instance_f64"] = total / res["mixed_f32"]["graph_ms"]
+    res["speedup_mixed_batched_vs_f64_batched"] = res["f64"]["graph_ms"] / res["mixed_f32"]["graph_ms"]
+    # accuracy on a sample of instances
+    idx = np.random.default_rng(11).choice(ninst, min(64, ninst), replace=False)
+    for name in ("mixed_f32", "f64"):
+        worst = 0.0
+        for k in idx:
+            w = ws[k]
+            E = cf.fp_offsets(w.A, w.B, w.alpha) if w.func == 2 else None
+            H = cf.hessian(w.func, w.x, w.A, w.B, E)
+            ref = np.einsum("pij,pj->pi", H, w.v)
+            got = outs[name][k].cpu().numpy()
+            worst = max(worst, float((np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v).max(axis=1))).max()))
+        res[name]["max_rel_err_sampled"] = worst
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -136,7 +211,17 @@ def main():
             binding.chessfad_fp_set_params(torch.from_numpy(w.A).to(dev), torch.from_numpy(w.B).to(dev),
                                            torch.from_numpy(w.alpha).to(dev))
             E[f] = cf.fp_offsets(w.A, w.B, w.alpha)
-        chunks[f] = args.chunk or binding.chessfad_default_chunk(f, N)
+    torch.cuda.synchronize()
+    # chunk per function: explicit, autotuned (outside the timed region), or default
+    tuned = {}
+    for f in FUNCS:
+        if args.chunk:
+            chunks[f] = args.chunk
+        elif not args.no_tune:
+            chunks[f], tuned[NAMES[f]] = binding.chessfad_autotune(f, N, 0, npts=npts)
+            binding.chessfad_autotune(f, N, 1, npts=npts)  # records the mixed path's choice too
+        else:
+            chunks[f] = binding.chessfad_default_chunk(f, N)
     torch.cuda.synchronize()
 
     def step(events=None):
@@ -263,6 +348,9 @@ def main():
         "fp_vector_path_ms": fp_vector_ms,
         "mixed_f32": mixed,
     }
+    result["autotuned_ms"] = tuned or None
+    if not args.no_batch:
+        result["batched"] = batched(args.batch_instances, binding, inputs, cf, torch)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(workloads, E, chunks, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -194,7 +194,8 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
 /*
  * Autotuner: times chessfad_hvp (precision 0) or chessfad_hvp_mixed (1) for
  * every compiled chunk <= n on npts device-generated points and records the
- * fastest for (func_id, n, precision); chunk == 0 then uses it (single calls
+ * fastest for (func_id, n, precision) (a larger chunk within 2% of the
+ * fastest time wins the tie: it makes fewer f calls); chunk == 0 then uses it (single calls
  * and batched plans; plans only take recorded chunks <= 8).  Fletcher-Powell
  * needs its parameters registered for n.  Allocates and frees temporary
  * device memory and synchronises `stream`.  Returns the chosen chunk in
