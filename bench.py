@@ -38,6 +38,9 @@ MEASURED_TRAFFIC = {
     "plain_kernel<rosenbrock, C=4, H.v>": 4.028e8,
     "plain_kernel<ackley, C=4, H.v>": 4.028e8,
     "fp_mfma_kernel<C=4, NK=8, H.v>": 4.030e8,
+    "plain_kernel<rosenbrock, C=16, H.v>": 4.027e8,
+    "plain_kernel<ackley, C=16, H.v>": 4.028e8,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.031e8,
 }
 
 
