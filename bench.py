@@ -35,12 +35,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "plain_kernel<rosenbrock, C=4, H.v>": 4.028e8,
-    "plain_kernel<ackley, C=4, H.v>": 4.028e8,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.030e8,
-    "plain_kernel<rosenbrock, C=16, H.v>": 4.027e8,
-    "plain_kernel<ackley, C=16, H.v>": 4.028e8,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.031e8,
 }
 
 
@@ -56,6 +50,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="use the default chunk instead of autotuning it")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance workload")
     ap.add_argument("--batch-instances", type=int, default=8192)
+    ap.add_argument("--large", action="store_true",
+                    help="also time n=64 (2^18 points, float64 and mixed) and n=512 (1024 points) H.v")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -106,6 +102,47 @@ def cpu_baseline(workloads, E, chunks, budget_s):
             "sample": f"first {sample} of the {NPTS} points of each function (n=16, same chunk sizes), "
                       f"oracle/chunked.c CHESS-VEC with OpenMP over points",
             "per_function": per}
+
+
+def large_n(binding, inputs, cf, torch, flops):
+    """n = 64 over 2^18 points (all three functions, float64 and mixed) and
+    n = 512 over 1024 points (Fletcher-Powell float64 and mixed, Rosenbrock
+    float64): kernel time, HVP/s, paper-model TFLOP/s and the max error on
+    sampled points."""
+    dev = torch.device("cuda:0")
+    res = {}
+    cases = [(f, 64, 1 << 18, prec) for f in FUNCS for prec in (0, 1)]
+    cases += [(2, 512, 1024, 1), (2, 512, 1024, 0), (0, 512, 1024, 0)]
+    for f, n, npts, prec in cases:
+        w = inputs.make_workload(f, n, npts, inputs.rng_for(100 + n))
+        x, v = torch.from_numpy(w.x).to(dev), torch.from_numpy(w.v).to(dev)
+        E = None
+        if f == 2:
+            binding.chessfad_fp_set_params(*(torch.from_numpy(a).to(dev) for a in (w.A, w.B, w.alpha)))
+            E = cf.fp_offsets(w.A, w.B, w.alpha)
+        c = 16
+        fn = binding.chessfad_hvp_mixed if prec else binding.chessfad_hvp
+        out = fn(f, x, v, chunk=c)
+        torch.cuda.synchronize()
+        reps = 1 if n == 512 and f == 2 else 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(f, x, v, out, chunk=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        idx = np.random.default_rng(2).choice(npts, min(64, npts), replace=False)
+        H = cf.hessian(f, w.x[idx], w.A, w.B, E)
+        ref = np.einsum("pij,pj->pi", H, w.v[idx])
+        got = out.cpu().numpy()[idx]
+        err = float((np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))).max())
+        mf = flops.flops_per_hvp(f, n, c)
+        res[f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"] = {
+            "npts": npts, "chunk": c, "kernel_ms": ms, "hvps_per_s": npts / (ms * 1e-3),
+            "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
+        print(f"  large: {NAMES[f]} n={n} {'mixed' if prec else 'f64'} {ms:.2f} ms err {err:.2e}", file=sys.stderr, flush=True)
+    return res
 
 
 def batched(ninst, binding, inputs, cf, torch):
@@ -216,15 +253,15 @@ def main():
             E[f] = cf.fp_offsets(w.A, w.B, w.alpha)
     torch.cuda.synchronize()
     # chunk per function: explicit, autotuned (outside the timed region), or default
-    tuned = {}
+    tuned, mchunks = {}, {}
     for f in FUNCS:
         if args.chunk:
-            chunks[f] = args.chunk
+            chunks[f] = mchunks[f] = args.chunk
         elif not args.no_tune:
             chunks[f], tuned[NAMES[f]] = binding.chessfad_autotune(f, N, 0, npts=npts)
-            binding.chessfad_autotune(f, N, 1, npts=npts)  # records the mixed path's choice too
+            mchunks[f], _ = binding.chessfad_autotune(f, N, 1, npts=npts)
         else:
-            chunks[f] = binding.chessfad_default_chunk(f, N)
+            chunks[f] = mchunks[f] = binding.chessfad_default_chunk(f, N)
     torch.cuda.synchronize()
 
     def step(events=None):
@@ -318,15 +355,16 @@ def main():
     mixed = {}
     for f in FUNCS:
         mo = torch.empty_like(xs[f])
-        binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=chunks[f])
+        mc = mchunks[f]   # the mixed path's own tuned chunk
+        binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=mc)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(5):
-            binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=chunks[f])
+            binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=mc)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
-        mixed[NAMES[f]] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
+        mixed[NAMES[f]] = {"chunk": mc, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                            "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
 
     result = {
@@ -354,6 +392,8 @@ def main():
     result["autotuned_ms"] = tuned or None
     if not args.no_batch:
         result["batched"] = batched(args.batch_instances, binding, inputs, cf, torch)
+    if args.large:
+        result["large_n"] = large_n(binding, inputs, cf, torch, flops)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(workloads, E, chunks, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -26,6 +26,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-command-line-argument",
+    # keep MFMA sources and results in VGPRs: otherwise accumulators carried
+    # across runtime-length K loops are copied between AGPRs and VGPRs on
+    # every iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

@@ -15,10 +15,11 @@ using namespace chessfad;
 struct chessfad_batch {
     int device = -1;
     char* dmem = nullptr;            // descriptors, work lists, counters, FP workspace
-    unsigned* counters = nullptr;    // one per precision
-    BatchArgs args[2] = {};
-    int grid[2] = {0, 0};
-    size_t lds[2] = {0, 0};
+    unsigned* counters = nullptr;    // one per list
+    // lists: index 2 * precision + kind (kind 0: vector rows, 1: FP MFMA rows)
+    BatchArgs args[4] = {};
+    int grid[4] = {0, 0, 0, 0};
+    size_t lds[4] = {0, 0, 0, 0};
     int64_t items = 0;
     double flops = 0.0;
     hipStream_t capture = nullptr;
@@ -53,17 +54,25 @@ size_t plain_lds_for(const BatchDesc& d) {
                                          : plain_lds_bytes<P, Ackley>(d.n, d.pstride, d.rows * d.nc, false);
 }
 
-template <class P>
-hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(batch_kernel<P>, dim3(grid), dim3(kBatchThreads), lds, s, a);
-    return hipGetLastError();
+using BatchKernel = void (*)(BatchArgs);
+
+BatchKernel batch_kernel_for(int list) {
+    switch (list) {
+        case 0: return batch_kernel<F64, 0>;
+        case 1: return batch_kernel<F64, 1>;
+        case 2: return batch_kernel<F32C, 0>;
+        default: return batch_kernel<F32C, 1>;
+    }
 }
 
 hipError_t launch_all(chessfad_batch* b, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->counters, 2);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->counters, 4);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && b->args[0].nitems) e = launch_batch<F64>(b->args[0], b->grid[0], b->lds[0], s);
-    if (e == hipSuccess && b->args[1].nitems) e = launch_batch<F32C>(b->args[1], b->grid[1], b->lds[1], s);
+    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+        if (!b->args[l].nitems) continue;
+        hipLaunchKernelGGL(batch_kernel_for(l), dim3(b->grid[l]), dim3(kBatchThreads), b->lds[l], s, b->args[l]);
+        e = hipGetLastError();
+    }
     return e;
 }
 
@@ -157,20 +166,20 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
     }
 
     // one device allocation: descriptors, items, counters, Fletcher-Powell workspace
-    size_t nitems[2] = {0, 0}, ndesc[2] = {0, 0};
+    size_t nitems[4] = {0, 0, 0, 0}, ndesc[4] = {0, 0, 0, 0};
     for (const PlanEntry& e : entries) {
-        nitems[e.prec] += (size_t)e.blocks;
-        ndesc[e.prec] += 1;
+        nitems[2 * e.prec + e.d.kind] += (size_t)e.blocks;
+        ndesc[2 * e.prec + e.d.kind] += 1;
     }
-    size_t off_desc[2], off_items[2], total = 0;
-    for (int pr = 0; pr < 2; ++pr) {
-        off_desc[pr] = total;
-        total = align_up(total + sizeof(BatchDesc) * ndesc[pr], 256);
-        off_items[pr] = total;
-        total = align_up(total + sizeof(BatchItem) * nitems[pr], 256);
+    size_t off_desc[4], off_items[4], total = 0;
+    for (int l = 0; l < 4; ++l) {
+        off_desc[l] = total;
+        total = align_up(total + sizeof(BatchDesc) * ndesc[l], 256);
+        off_items[l] = total;
+        total = align_up(total + sizeof(BatchItem) * nitems[l], 256);
     }
     const size_t off_counters = total;
-    total = align_up(total + 2 * sizeof(unsigned), 256);
+    total = align_up(total + 4 * sizeof(unsigned), 256);
     const size_t off_ws = total;
     total += ws_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -199,12 +208,13 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         err = hipGetLastError();
         e.d.fp = FpParams{c.A, c.B, E, A32, B32};
     }
-    // work lists per precision, largest model cost first
-    std::vector<BatchDesc> descs[2];
-    std::vector<std::pair<double, BatchItem>> items[2];
+    // work lists per (precision, kind), largest model cost first
+    std::vector<BatchDesc> descs[4];
+    std::vector<std::pair<double, BatchItem>> items[4];
     for (const PlanEntry& e : entries) {
-        const int di = (int)descs[e.prec].size();
-        descs[e.prec].push_back(e.d);
+        const int list = 2 * e.prec + e.d.kind;
+        const int di = (int)descs[list].size();
+        descs[list].push_back(e.d);
         for (int64_t blk = 0; blk < e.blocks; ++blk) {
             double cost = e.cost_per_block;
             if (e.d.kind == 0) {
@@ -214,7 +224,7 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
                 const int r0 = (int)(blk % e.d.row_blocks) * e.d.rows;
                 cost = cost * (double)std::min(e.d.rows, e.d.n - r0) / e.d.rows;
             }
-            items[e.prec].push_back({cost, BatchItem{di, (int)blk}});
+            items[list].push_back({cost, BatchItem{di, (int)blk}});
             b->flops += cost;
         }
     }
@@ -224,29 +234,29 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
     // upload descriptors and sorted work lists; size the persistent grids
     int cus = 0;
     if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    for (int pr = 0; pr < 2 && err == hipSuccess; ++pr) {
+    for (int l = 0; l < 4 && err == hipSuccess; ++l) {
+        const int pr = l / 2;
         std::vector<BatchItem> flat;
-        flat.reserve(items[pr].size());
+        flat.reserve(items[l].size());
         size_t lds = 0;
-        for (const auto& it : items[pr]) flat.push_back(it.second);
-        for (const BatchDesc& d : descs[pr]) {
+        for (const auto& it : items[l]) flat.push_back(it.second);
+        for (const BatchDesc& d : descs[l]) {
             const size_t need = d.kind == 1 ? sizeof(FpRowsShared) : (pr ? plain_lds_for<F32C>(d) : plain_lds_for<F64>(d));
             lds = std::max(lds, need);
         }
-        BatchDesc* dd = reinterpret_cast<BatchDesc*>(b->dmem + off_desc[pr]);
-        BatchItem* di = reinterpret_cast<BatchItem*>(b->dmem + off_items[pr]);
-        if (!descs[pr].empty()) err = hipMemcpyAsync(dd, descs[pr].data(), sizeof(BatchDesc) * descs[pr].size(), hipMemcpyHostToDevice, s);
+        BatchDesc* dd = reinterpret_cast<BatchDesc*>(b->dmem + off_desc[l]);
+        BatchItem* di = reinterpret_cast<BatchItem*>(b->dmem + off_items[l]);
+        if (!descs[l].empty()) err = hipMemcpyAsync(dd, descs[l].data(), sizeof(BatchDesc) * descs[l].size(), hipMemcpyHostToDevice, s);
         if (err == hipSuccess && !flat.empty())
             err = hipMemcpyAsync(di, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
-        b->args[pr] = BatchArgs{dd, di, (int)flat.size(), b->counters + pr};
-        b->lds[pr] = lds;
+        b->args[l] = BatchArgs{dd, di, (int)flat.size(), b->counters + l};
+        b->lds[l] = lds;
         b->items += (int64_t)flat.size();
         if (err == hipSuccess && !flat.empty()) {
             int per_cu = 0;
-            err = pr ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<F32C>, kBatchThreads, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<F64>, kBatchThreads, lds);
-            b->grid[pr] = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, (int64_t)flat.size());
+            err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(l), kBatchThreads, lds);
+            b->grid[l] = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, (int64_t)flat.size());
         }
     }
     // capture reset + persistent kernels in one graph
@@ -282,7 +292,7 @@ int chessfad_batch_destroy(chessfad_batch* plan) {
 int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgroups, double* model_flops) {
     if (!plan) return CHESSFAD_E_ARG;
     if (items) *items = plan->items;
-    if (workgroups) *workgroups = plan->grid[0] + plan->grid[1];
+    if (workgroups) *workgroups = plan->grid[0] + plan->grid[1] + plan->grid[2] + plan->grid[3];
     if (model_flops) *model_flops = plan->flops;
     return CHESSFAD_OK;
 }

@@ -8,7 +8,9 @@
 // largest first, and a persistent kernel - one per precision, sized to fill
 // the chip - takes them from an atomic counter until the list is exhausted
 // (longest-processing-time-first list scheduling).  Every workgroup leaves
-// the loop when the counter passes the end of the list.
+// the loop when the counter passes the end of the list.  The two body kinds
+// get separate persistent kernels and lists, so each is compiled with the
+// registers its own bodies need.
 #pragma once
 
 #include <stdint.h>
@@ -57,7 +59,7 @@ __device__ __forceinline__ void batch_plain(const PlainArgs& pa, int C, int64_t 
     }
 }
 
-template <class P>
+template <class P, int kKind>
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs b) {
     extern __shared__ double lds[];
     __shared__ int s_item;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs b) {
         if (it >= b.nitems) break;
         const BatchItem item = b.items[it];
         const BatchDesc d = b.desc[item.inst];
-        if (d.kind == 1) {
+        if constexpr (kKind == 1) {
             FpRowsArgs fa{d.x, d.v, d.out, d.fp, d.npts, d.n, d.nc, d.rows, d.row_blocks};
             FpRowsShared& sh = *reinterpret_cast<FpRowsShared*>(lds);
             switch (d.C) {

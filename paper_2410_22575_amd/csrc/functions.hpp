@@ -35,7 +35,7 @@ struct PointView {
     CF_DEV T tab1(int k) const { return (T)t1[k * stride]; }
     CF_DEV T island(int q) const { return isl[q * stride]; }
     template <int C>
-    CF_DEV HD<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
+    CF_DEV HD1<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
 };
 
 struct FpParams {
@@ -72,17 +72,17 @@ struct Rosenbrock {
     static CF_DEV void island(int, int, const double*, const double*, const double*, int, const FpParams&, T*) {}
 
     template <typename T, int C>
-    static CF_DEV HD<T, C> term(const HD<T, C>& yk, const HD<T, C>& yk1) {
+    static CF_DEV HD<T, C> term(const HD1<T, C>& yk, const HD1<T, C>& yk1) {
         HD<T, C> b = yk1 - yk * yk;
-        HD<T, C> e = T(1) - yk;
+        HD1<T, C> e = T(1) - yk;
         return T(100) * (b * b) + e * e;
     }
 
     template <class P, int C>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        HD<T, C> yk = pv.template y<C>(0);
-        HD<T, C> yk1 = pv.template y<C>(1);
+        HD1<T, C> yk = pv.template y<C>(0);
+        HD1<T, C> yk1 = pv.template y<C>(1);
         auto s = P::start(term<T, C>(yk, yk1));
         for (int k = 1; k + 1 < pv.n; ++k) {
             yk = yk1;
@@ -130,7 +130,7 @@ struct Ackley {
     template <class P, int C>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        HD<T, C> y = pv.template y<C>(0);
+        HD1<T, C> y = pv.template y<C>(0);
         auto ss = P::start(y * y);
         auto cs = P::start(cos_term<T, C>(pv, 0));
         for (int k = 1; k < pv.n; ++k) {
@@ -179,7 +179,7 @@ struct FletcherPowell {
     template <typename T, int C>
     static CF_DEV HD<T, C> residual(const PointView<T>& pv, const FpParams& prm, int m) {
         const size_t row = (size_t)m * pv.n;
-        HD<T, C> y = pv.template y<C>(0);
+        HD1<T, C> y = pv.template y<C>(0);
         T s = pv.tab0(0), c = pv.tab1(0);
         HD<T, C> acc = fp_a<T>(prm, row) * chain(y, s, c, -s);
         acc = acc + fp_b<T>(prm, row) * chain(y, c, -s, -c);

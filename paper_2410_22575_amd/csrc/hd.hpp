@@ -15,6 +15,7 @@
 //   <g, g' u_d, g' u_g, g' u_h + g'' u_d u_g>
 // where g, g', g'' are scalars the caller supplies (so transcendental values
 // that every call of a point shares can be computed once per point).
+// HD1 below is the same number with its second-order part statically zero.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,21 +29,6 @@ struct HD {
     T v, d;
     T g[C], h[C];
 };
-
-// CHUNK-INIT for one variable: y_k = <x_k, [k = i], [k = cs + l], 0>.
-template <typename T, int C>
-CF_DEV HD<T, C> seed(T xk, int k, int i, int cs) {
-    HD<T, C> y;
-    y.v = xk;
-    y.d = (k == i) ? T(1) : T(0);
-    const int u = k - cs;
-#pragma unroll
-    for (int l = 0; l < C; ++l) {
-        y.g[l] = (u == l) ? T(1) : T(0);
-        y.h[l] = T(0);
-    }
-    return y;
-}
 
 template <typename T, int C>
 CF_DEV HD<T, C> operator+(const HD<T, C>& a, const HD<T, C>& b) {
@@ -130,6 +116,106 @@ CF_DEV HD<T, C> chain(const HD<T, C>& a, T g0, T g1, T g2) {
     for (int l = 0; l < C; ++l) {
         r.g[l] = g1 * a.g[l];
         r.h[l] = g1 * a.h[l] + g2d * a.g[l];
+    }
+    return r;
+}
+
+// ------------------------------------------------------- first-order hDuals
+// An hDual whose second-order part is statically zero: the CHUNK-INIT seeds
+// and values that are affine in them (sums, scalings).  Its operators are the
+// rules above with the products against that zero part left out; the values
+// they produce are the same (a product with an exact zero adds nothing, up
+// to the sign of a zero result).
+template <typename T, int C>
+struct HD1 {
+    T v, d;
+    T g[C];
+};
+
+// CHUNK-INIT for one variable: y_k = <x_k, [k = i], [k = cs + l], 0>.
+template <typename T, int C>
+CF_DEV HD1<T, C> seed(T xk, int k, int i, int cs) {
+    HD1<T, C> y;
+    y.v = xk;
+    y.d = (k == i) ? T(1) : T(0);
+    const int u = k - cs;
+#pragma unroll
+    for (int l = 0; l < C; ++l) y.g[l] = (u == l) ? T(1) : T(0);
+    return y;
+}
+
+template <typename T, int C>
+CF_DEV HD<T, C> widen(const HD1<T, C>& a) {
+    HD<T, C> r;
+    r.v = a.v;
+    r.d = a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.g[l];
+        r.h[l] = T(0);
+    }
+    return r;
+}
+
+template <typename T, int C>
+CF_DEV HD1<T, C> operator*(T s, const HD1<T, C>& a) {
+    HD1<T, C> r;
+    r.v = s * a.v;
+    r.d = s * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) r.g[l] = s * a.g[l];
+    return r;
+}
+
+template <typename T, int C>
+CF_DEV HD1<T, C> operator-(T s, const HD1<T, C>& a) {
+    HD1<T, C> r;
+    r.v = s - a.v;
+    r.d = -a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) r.g[l] = -a.g[l];
+    return r;
+}
+
+// product of two first-order hDuals: second-order part u_d w_g + w_d u_g
+template <typename T, int C>
+CF_DEV HD<T, C> operator*(const HD1<T, C>& a, const HD1<T, C>& b) {
+    HD<T, C> r;
+    r.v = a.v * b.v;
+    r.d = a.v * b.d + b.v * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.v * b.g[l] + b.v * a.g[l];
+        r.h[l] = a.d * b.g[l] + b.d * a.g[l];
+    }
+    return r;
+}
+
+// first-order minus full: the second-order part is the negated one of b
+template <typename T, int C>
+CF_DEV HD<T, C> operator-(const HD1<T, C>& a, const HD<T, C>& b) {
+    HD<T, C> r;
+    r.v = a.v - b.v;
+    r.d = a.d - b.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = a.g[l] - b.g[l];
+        r.h[l] = -b.h[l];
+    }
+    return r;
+}
+
+// chain rule on a first-order hDual: <g, g' u_d, g' u_g, g'' u_d u_g>
+template <typename T, int C>
+CF_DEV HD<T, C> chain(const HD1<T, C>& a, T g0, T g1, T g2) {
+    HD<T, C> r;
+    r.v = g0;
+    r.d = g1 * a.d;
+    const T g2d = g2 * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = g1 * a.g[l];
+        r.h[l] = g2d * a.g[l];
     }
     return r;
 }
