@@ -17,6 +17,12 @@
  * chunk_hess  : CHUNK-HESS (Sec. III.B) - n * ceil(n/csize) calls of f.
  * chess_vec   : CHESS-VEC (Sec. VI) - the same calls, each chunk dotted with
  *               the input vector and summed per row; H is never stored.
+ * schunk_hess : SCHUNK-HESS (Sec. IV) - only the chunks that reach the
+ *               diagonal or lie right of it are evaluated; the entries left
+ *               of a row's own chunk are copied from their mirror images.
+ * sc_hess_vec : SC-HESS-VEC (Sec. VI) - the same calls; a computed entry
+ *               H(i, s) right of row i's own chunk also adds H(i, s) in[i] to
+ *               r(s), in place of the call that would have computed H(s, i).
  * When n is not a multiple of csize the last chunk seeds only columns < n
  * and its surplus components are ignored.
  *
@@ -170,7 +176,15 @@ static void f_fletcher_powell(const ctx_t *c, double *res, double *const *y) {
     free(cy);
 }
 
+#ifdef CHESSFAD_COUNT_OPS
+static long g_calls;
+#define COUNT_CALL() (g_calls++)
+#else
+#define COUNT_CALL() ((void)0)
+#endif
+
 static void eval_f(int func, const ctx_t *c, double *res, double *const *y) {
+    COUNT_CALL();
     if (func == ROSENBROCK) f_rosenbrock(c, res, y);
     else if (func == ACKLEY) f_ackley(c, res, y);
     else f_fletcher_powell(c, res, y);
@@ -233,6 +247,49 @@ static void chunk_hess(int func, const ctx_t *c, scratch_t *s, const double *a, 
         }
 }
 
+/* SC-HESS-VEC for one point.  Row i evaluates its own chunk scn = i / csize
+ * and every chunk after it; an entry in a later chunk updates both r(i) and
+ * its mirror r(s).  Inside the own chunk every row computes its entries
+ * itself, so nothing is added twice.  All csize components of each call are
+ * used (the last chunk: those below n). */
+static void sc_hess_vec(int func, const ctx_t *c, scratch_t *s, const double *a, const double *in, double *out) {
+    const int n = c->n, cs = c->cs, nchunk = (n + cs - 1) / cs;
+    for (int k = 0; k < n; k++) out[k] = 0.0;
+    for (int i = 0; i < n; i++) {
+        const int scn = i / cs;
+        for (int cn = scn; cn < nchunk; cn++) {
+            const int cstart = cn * cs;
+            chunk_init(c, s->y, a, i, cstart);
+            eval_f(func, c, s->temp, s->y);
+            for (int l = 0; l < cs && cstart + l < n; l++) {
+                const int col = cstart + l;
+                const double h = s->temp[cs + 2 + l];
+                out[i] = ADD(out[i], MUL(h, in[col]));
+                if (cn > scn) out[col] = ADD(out[col], MUL(h, in[i]));
+            }
+        }
+    }
+}
+
+/* SCHUNK-HESS for one point: the evaluated chunks as in CHUNK-HESS, then for
+ * every row i the columns left of its own chunk, j < (i / csize) csize, are
+ * copied from H[j][i] (which row j evaluated, since i lies in a later chunk
+ * than j). */
+static void schunk_hess(int func, const ctx_t *c, scratch_t *s, const double *a, double *H) {
+    const int n = c->n, cs = c->cs, nchunk = (n + cs - 1) / cs;
+    for (int i = 0; i < n; i++)
+        for (int j = i / cs; j < nchunk; j++) {
+            int cstart = j * cs;
+            chunk_init(c, s->y, a, i, cstart);
+            eval_f(func, c, s->temp, s->y);
+            for (int l = 0; l < cs && cstart + l < n; l++) H[(size_t)i * n + cstart + l] = s->temp[cs + 2 + l];
+        }
+    for (int i = cs; i < n; i++) {
+        const int endindex = (i / cs) * cs;
+        for (int j = 0; j < endindex; j++) H[(size_t)i * n + j] = H[(size_t)j * n + i];
+    }
+}
+
 static int check(int func, int n, int csize, const double *A, const double *B, const double *E) {
     if (func < 0 || func > 2) return -1;
     if (n < 1 || (func == ROSENBROCK && n < 2)) return -2;
@@ -241,8 +298,8 @@ static int check(int func, int n, int csize, const double *A, const double *B, c
     return 0;
 }
 
-int oracle_hvp(int func, int n, long npts, const double *x, const double *v, double *out, int csize,
-               const double *A, const double *B, const double *E, int nthreads) {
+static int run_hvp(int func, int n, long npts, const double *x, const double *v, double *out, int csize,
+                   const double *A, const double *B, const double *E, int nthreads, int sym) {
     int rc = check(func, n, csize, A, B, E);
     if (rc) return rc;
     ctx_t c = {n, csize, 2 * csize + 2, A, B, E};
@@ -258,15 +315,16 @@ int oracle_hvp(int func, int n, long npts, const double *x, const double *v, dou
 #pragma omp for schedule(static)
 #endif
             for (long p = 0; p < npts; p++)
-                chess_vec(func, &c, &s, x + (size_t)p * n, v + (size_t)p * n, out + (size_t)p * n);
+                (sym ? sc_hess_vec : chess_vec)(func, &c, &s, x + (size_t)p * n, v + (size_t)p * n,
+                                                out + (size_t)p * n);
         }
         scratch_free(&s);
     }
     return err ? -8 : 0;
 }
 
-int oracle_hessian(int func, int n, long npts, const double *x, double *H, int csize,
-                   const double *A, const double *B, const double *E, int nthreads) {
+static int run_hessian(int func, int n, long npts, const double *x, double *H, int csize,
+                       const double *A, const double *B, const double *E, int nthreads, int sym) {
     int rc = check(func, n, csize, A, B, E);
     if (rc) return rc;
     ctx_t c = {n, csize, 2 * csize + 2, A, B, E};
@@ -282,11 +340,31 @@ int oracle_hessian(int func, int n, long npts, const double *x, double *H, int c
 #pragma omp for schedule(static)
 #endif
             for (long p = 0; p < npts; p++)
-                chunk_hess(func, &c, &s, x + (size_t)p * n, H + (size_t)p * n * n);
+                (sym ? schunk_hess : chunk_hess)(func, &c, &s, x + (size_t)p * n, H + (size_t)p * n * n);
         }
         scratch_free(&s);
     }
     return err ? -8 : 0;
+}
+
+int oracle_hvp(int func, int n, long npts, const double *x, const double *v, double *out, int csize,
+               const double *A, const double *B, const double *E, int nthreads) {
+    return run_hvp(func, n, npts, x, v, out, csize, A, B, E, nthreads, 0);
+}
+
+int oracle_hvp_sym(int func, int n, long npts, const double *x, const double *v, double *out, int csize,
+                   const double *A, const double *B, const double *E, int nthreads) {
+    return run_hvp(func, n, npts, x, v, out, csize, A, B, E, nthreads, 1);
+}
+
+int oracle_hessian(int func, int n, long npts, const double *x, double *H, int csize,
+                   const double *A, const double *B, const double *E, int nthreads) {
+    return run_hessian(func, n, npts, x, H, csize, A, B, E, nthreads, 0);
+}
+
+int oracle_hessian_sym(int func, int n, long npts, const double *x, double *H, int csize,
+                       const double *A, const double *B, const double *E, int nthreads) {
+    return run_hessian(func, n, npts, x, H, csize, A, B, E, nthreads, 1);
 }
 
 /* Gradient and value from the first-order components of row i's calls. */
@@ -308,20 +386,22 @@ int oracle_value_grad(int func, int n, const double *x, double *fval, double *gr
 }
 
 #ifdef CHESSFAD_COUNT_OPS
-/* Scalar operation counts of one CHESS-VEC (one point), and the number of
- * f calls it makes; also the counts for single operator applications. */
+/* Scalar operation counts of one CHESS-VEC (sym = 0) or SC-HESS-VEC (sym = 1)
+ * on one point, and the number of f calls it makes; also the counts for
+ * single operator applications. */
 int oracle_count_hvp(int func, int n, const double *x, const double *v, double *out, int csize,
-                     const double *A, const double *B, const double *E, long *adds, long *muls, long *calls) {
+                     const double *A, const double *B, const double *E, long *adds, long *muls, long *calls,
+                     int sym) {
     int rc = check(func, n, csize, A, B, E);
     if (rc) return rc;
     ctx_t c = {n, csize, 2 * csize + 2, A, B, E};
     scratch_t s;
     if (scratch_init(&s, &c)) return -8;
-    g_adds = g_muls = 0;
-    chess_vec(func, &c, &s, x, v, out);
+    g_adds = g_muls = g_calls = 0;
+    (sym ? sc_hess_vec : chess_vec)(func, &c, &s, x, v, out);
     *adds = g_adds;
     *muls = g_muls;
-    *calls = (long)n * ((n + csize - 1) / csize);
+    *calls = g_calls;
     scratch_free(&s);
     return 0;
 }

@@ -43,7 +43,7 @@ def _lib(path):
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
             build()
         lib = ctypes.CDLL(path)
-        for name in ("oracle_hvp", "oracle_hessian"):
+        for name in ("oracle_hvp", "oracle_hessian", "oracle_hvp_sym", "oracle_hessian_sym"):
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
         lib.oracle_value_grad.restype = ctypes.c_int
@@ -65,28 +65,32 @@ def _params(func, A, B, E):
             np.ascontiguousarray(E, np.float64))
 
 
-def hvp(func, x, v, csize, A=None, B=None, E=None, nthreads=1):
+def hvp(func, x, v, csize, A=None, B=None, E=None, nthreads=1, sym=False):
+    """CHESS-VEC, or SC-HESS-VEC with sym=True, at every point."""
     x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
     v = np.ascontiguousarray(np.atleast_2d(v), np.float64)
     npts, n = x.shape
     out = np.empty_like(x)
     A, B, E = _params(func, A, B, E)
-    rc = _lib(LIB_PLAIN).oracle_hvp(func, n, ctypes.c_long(npts), _ptr(x), _ptr(v), _ptr(out), csize,
-                                    _ptr(A), _ptr(B), _ptr(E), nthreads)
+    name = "oracle_hvp_sym" if sym else "oracle_hvp"
+    rc = getattr(_lib(LIB_PLAIN), name)(func, n, ctypes.c_long(npts), _ptr(x), _ptr(v), _ptr(out), csize,
+                                        _ptr(A), _ptr(B), _ptr(E), nthreads)
     if rc:
-        raise ValueError(f"oracle_hvp failed: {rc}")
+        raise ValueError(f"{name} failed: {rc}")
     return out
 
 
-def hessian(func, x, csize, A=None, B=None, E=None, nthreads=1):
+def hessian(func, x, csize, A=None, B=None, E=None, nthreads=1, sym=False):
+    """CHUNK-HESS, or SCHUNK-HESS with sym=True, at every point."""
     x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
     npts, n = x.shape
-    H = np.empty((npts, n, n))
+    H = np.full((npts, n, n), np.nan)
     A, B, E = _params(func, A, B, E)
-    rc = _lib(LIB_PLAIN).oracle_hessian(func, n, ctypes.c_long(npts), _ptr(x), _ptr(H), csize,
+    name = "oracle_hessian_sym" if sym else "oracle_hessian"
+    rc = getattr(_lib(LIB_PLAIN), name)(func, n, ctypes.c_long(npts), _ptr(x), _ptr(H), csize,
                                         _ptr(A), _ptr(B), _ptr(E), nthreads)
     if rc:
-        raise ValueError(f"oracle_hessian failed: {rc}")
+        raise ValueError(f"{name} failed: {rc}")
     return H
 
 
@@ -103,8 +107,8 @@ def value_grad(func, x, csize, A=None, B=None, E=None):
     return fv.value, g
 
 
-def count_hvp(func, x, v, csize, A=None, B=None, E=None):
-    """(adds, muls, calls) executed by one CHESS-VEC on one point."""
+def count_hvp(func, x, v, csize, A=None, B=None, E=None, sym=False):
+    """(adds, muls, calls) executed by one CHESS-VEC (or SC-HESS-VEC) on one point."""
     x = np.ascontiguousarray(x, np.float64).ravel()
     v = np.ascontiguousarray(v, np.float64).ravel()
     n = x.size
@@ -113,7 +117,7 @@ def count_hvp(func, x, v, csize, A=None, B=None, E=None):
     A, B, E = _params(func, A, B, E)
     rc = _lib(LIB_COUNT).oracle_count_hvp(func, n, _ptr(x), _ptr(v), _ptr(out), csize, _ptr(A), _ptr(B),
                                           _ptr(E), ctypes.byref(adds), ctypes.byref(muls),
-                                          ctypes.byref(calls))
+                                          ctypes.byref(calls), int(sym))
     if rc:
         raise ValueError(f"oracle_count_hvp failed: {rc}")
     return adds.value, muls.value, calls.value

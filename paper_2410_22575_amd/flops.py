@@ -16,7 +16,10 @@ rules are written (Sec. V, Fig. 1):
                        are per-point work and not counted
   chunk dot with v     2c
 One f call per (row, chunk): n * ceil(n / c) calls per point (CHUNK-HESS,
-CHESS-VEC).  The per-call totals below follow the operation sequence of the
+CHESS-VEC).  The symmetric forms (SCHUNK-HESS, SC-HESS-VEC) evaluate only
+the chunks from a row's own chunk onwards, n (n / c + 1) / 2 calls when c
+divides n (Sec. V), and each call right of the own chunk adds a mirror update
+(another 2c).  The per-call totals below follow the operation sequence of the
 three functions as the kernels evaluate them.
 """
 from __future__ import annotations
@@ -26,6 +29,11 @@ ROSENBROCK, ACKLEY, FLETCHER_POWELL = 0, 1, 2
 
 def calls_per_point(n: int, c: int) -> int:
     return n * ((n + c - 1) // c)
+
+
+def calls_per_point_sym(n: int, c: int) -> int:
+    nc = (n + c - 1) // c
+    return sum(nc - i // c for i in range(n))
 
 
 def flops_per_call(func: int, n: int, c: int) -> int:
@@ -53,6 +61,11 @@ def flops_per_call(func: int, n: int, c: int) -> int:
 
 def flops_per_hvp(func: int, n: int, c: int) -> int:
     return calls_per_point(n, c) * flops_per_call(func, n, c)
+
+
+def flops_per_hvp_sym(func: int, n: int, c: int) -> int:
+    calls = calls_per_point_sym(n, c)
+    return calls * flops_per_call(func, n, c) + (calls - n) * 2 * c
 
 
 def contraction_flops_per_hvp(func: int, n: int, c: int) -> int:

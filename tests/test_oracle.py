@@ -216,6 +216,92 @@ def test_chunked_c_threads_agree():
                                   chunked.hvp(R, w.x, w.v, 4, nthreads=4))
 
 
+# ------------------------------- symmetric variants (Sec. IV, Sec. V, Sec. VI)
+@pytest.mark.parametrize("func", [R, A, FP])
+@pytest.mark.parametrize("n,c", [(2, 1), (2, 2), (5, 2), (5, 3), (8, 4), (16, 4), (16, 16), (13, 4), (7, 16),
+                                 (12, 1)])
+def test_symmetric_chunked_matches_closed_form(func, n, c):
+    w = inputs.make_workload(func, n, 8, inputs.rng_for(50 + n))
+    E = cf.fp_offsets(w.A, w.B, w.alpha) if func == FP else None
+    Hs = cf.hessian(func, w.x, w.A, w.B, E)
+    H = chunked.hessian(func, w.x, c, w.A, w.B, E, sym=True)      # starts as NaN: every entry written
+    r = chunked.hvp(func, w.x, w.v, c, w.A, w.B, E, sym=True)
+    rs = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+    for p in range(w.npts):
+        scale = np.abs(Hs[p]).max()
+        assert np.abs(H[p] - Hs[p]).max() <= 1e-13 * scale
+        assert np.abs(r[p] - rs[p]).max() <= 1e-13 * scale * np.abs(w.v[p]).max()
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_symmetric_hessian_structure(func):
+    # entries a row evaluates itself are the CHUNK-HESS entries bit for bit;
+    # entries left of the row's own chunk are exact copies of their mirrors
+    n, c = 11, 3
+    w = inputs.make_workload(func, n, 3, inputs.rng_for(52))
+    E = cf.fp_offsets(w.A, w.B, w.alpha) if func == FP else None
+    Hf = chunked.hessian(func, w.x, c, w.A, w.B, E)
+    Hy = chunked.hessian(func, w.x, c, w.A, w.B, E, sym=True)
+    for i in range(n):
+        own = (i // c) * c
+        np.testing.assert_array_equal(Hy[:, i, own:], Hf[:, i, own:])
+        np.testing.assert_array_equal(Hy[:, i, :own], Hy[:, :own, i])
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_symmetric_hvp_of_unit_vectors_gives_columns(func):
+    # v = e_k picks column k of H: the symmetric product then returns the
+    # column assembled from row k's own evaluations and the mirrors of the
+    # rows before it, which must equal row k of the full CHUNK-HESS
+    n, c = 9, 2
+    w = inputs.make_workload(func, n, 1, inputs.rng_for(53))
+    E = cf.fp_offsets(w.A, w.B, w.alpha) if func == FP else None
+    Hf = chunked.hessian(func, w.x, c, w.A, w.B, E)[0]
+    scale = np.abs(Hf).max()
+    for k in range(n):
+        e = np.zeros((1, n))
+        e[0, k] = 1.0
+        col = chunked.hvp(func, w.x, e, c, w.A, w.B, E, sym=True)[0]
+        assert np.abs(col - Hf[:, k]).max() <= 1e-14 * scale
+
+
+def test_symmetric_call_count_formula():
+    # Sec. V: n (n / c + 1) / 2 evaluated chunks when c divides n; c = 1 gives
+    # n (n + 1) / 2 and c = n gives n
+    w = inputs.make_workload(R, 16, 1, inputs.rng_for(54))
+    for c in (1, 2, 4, 8, 16):
+        calls = chunked.count_hvp(R, w.x[0], w.v[0], c, sym=True)[2]
+        assert calls == 16 * (16 // c + 1) // 2 == flops.calls_per_point_sym(16, c)
+    assert chunked.count_hvp(R, w.x[0], w.v[0], 1, sym=True)[2] == 16 * 17 // 2
+    assert chunked.count_hvp(R, w.x[0], w.v[0], 16, sym=True)[2] == 16
+    # ragged: every row evaluates its own chunk and the ones after it
+    w = inputs.make_workload(R, 7, 1, inputs.rng_for(55))
+    assert chunked.count_hvp(R, w.x[0], w.v[0], 3, sym=True)[2] == 3 * 3 + 3 * 2 + 1 * 1
+
+
+def test_symmetric_multiplication_count_formula():
+    # Sec. V: n (n / c + 1) / 2 calls with M hDual products each cost
+    # (3/2) n (2n + 2c + n/c + 1) M multiplications (Rosenbrock, c | n); the
+    # other multiplications are the 100 x (.) scalings, the own chunk dot of
+    # every call and the mirror update of every call right of the own chunk
+    for n, c in ((8, 2), (8, 4), (16, 4), (16, 8)):
+        w = inputs.make_workload(R, n, 1, inputs.rng_for(56))
+        _, muls, calls = chunked.count_hvp(R, w.x[0], w.v[0], c, sym=True)
+        M = 3 * (n - 1)
+        scalings = (n - 1) * (2 * c + 2)
+        assert muls == calls * (M * (6 * c + 3) + scalings + c) + (calls - n) * c
+        assert 2 * calls * M * (6 * c + 3) == 3 * n * (2 * n + 2 * c + n // c + 1) * M
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+@pytest.mark.parametrize("n,c", [(8, 2), (16, 4), (12, 3)])
+def test_symmetric_model_flops_match_executed_counts(func, n, c):
+    w = inputs.make_workload(func, n, 1, inputs.rng_for(57))
+    E = cf.fp_offsets(w.A, w.B, w.alpha) if func == FP else None
+    adds, muls, _ = chunked.count_hvp(func, w.x[0], w.v[0], c, w.A, w.B, E, sym=True)
+    assert adds + muls == flops.flops_per_hvp_sym(func, n, c)
+
+
 # ------------------------------------------------- operation counts (Sec. V)
 @pytest.mark.parametrize("c", [1, 2, 4, 8, 16])
 def test_operator_counts(c):
