@@ -35,6 +35,21 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0294e+08,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0295e+08,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0297e+08,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0302e+08,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0310e+08,
+    "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
+    "plain_kernel<ackley, C=2, H.v>": 4.0279e+08,
+    "plain_kernel<ackley, C=4, H.v>": 4.0280e+08,
+    "plain_kernel<ackley, C=8, H.v>": 4.0281e+08,
+    "plain_kernel<ackley, C=16, H.v>": 4.0284e+08,
+    "plain_kernel<rosenbrock, C=1, H.v>": 4.0275e+08,
+    "plain_kernel<rosenbrock, C=2, H.v>": 4.0274e+08,
+    "plain_kernel<rosenbrock, C=4, H.v>": 4.0275e+08,
+    "plain_kernel<rosenbrock, C=8, H.v>": 4.0275e+08,
+    "plain_kernel<rosenbrock, C=16, H.v>": 4.0277e+08,
 }
 
 
@@ -351,6 +366,25 @@ def main():
 
     max_err = {NAMES[f]: rel_err(f, outs[f]) for f in FUNCS}
 
+    # full Hessians on the same points (outside the timed region): 8 n^2
+    # bytes per point written on top of the H.v path's 16 n read
+    hess = {}
+    for f in FUNCS:
+        sub = min(npts, 1 << 19)
+        Hbuf = torch.empty((sub, N, N), dtype=torch.float64, device=dev)
+        binding.chessfad_hessian(f, xs[f][:sub], Hbuf, chunk=chunks[f])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            binding.chessfad_hessian(f, xs[f][:sub], Hbuf, chunk=chunks[f])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        hess[NAMES[f]] = {"npts": sub, "kernel_ms": round(ms, 4), "hessians_per_s": sub / (ms * 1e-3),
+                          "hbm_gb_per_s": sub * (8 * N * N + 8 * N) / (ms * 1e-3) / 1e9}
+        del Hbuf
+    torch.cuda.synchronize()
+
     # the mixed-precision path on the same inputs (outside the timed region)
     mixed = {}
     for f in FUNCS:
@@ -388,6 +422,7 @@ def main():
         "max_rel_err_sampled": max_err,
         "fp_vector_path_ms": fp_vector_ms,
         "mixed_f32": mixed,
+        "hessian_f64": hess,
     }
     result["autotuned_ms"] = tuned or None
     if not args.no_batch:
