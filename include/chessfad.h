@@ -102,6 +102,34 @@ int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, do
                            int chunk, void* stream);
 
 /*
+ * Symmetric forms (SCHUNK-HESS, Sec. IV; SC-HESS-VEC, Sec. VI; count in
+ * Sec. V).  Row i evaluates f only for its own chunk i / chunk and the
+ * chunks after it: n (n / chunk + 1) / 2 calls per point when chunk divides
+ * n, instead of n * ceil(n / chunk).  An entry H(i, s) of a later chunk
+ * stands in for H(s, i):
+ *   chessfad_hessian_sym  stores it at both places, so H is exactly
+ *                         symmetric outside the diagonal blocks;
+ *   chessfad_hvp_sym      adds H(i, s) v[s] to out[i] and H(i, s) v[i] to
+ *                         out[s] (the mirror terms are summed in float64).
+ * Arguments, layouts, ownership and checks as chessfad_hvp /
+ * chessfad_hessian, plus
+ *   precision  0: float64 hDuals; 1: the mixed-precision arithmetic of
+ *              chessfad_hvp_mixed.  Anything else: CHESSFAD_E_ARG.
+ *   chunk      0 picks the chessfad_autotune_sym choice if there is one,
+ *              else the compiled chunk that minimises Sec. V's
+ *              multiplication count (near sqrt(n / 2)).
+ * The vector-ALU kernels hold a whole point's partial sums in LDS
+ * (n * ceil(n / chunk) doubles for H.v): a chunk for which that does not
+ * fit returns CHESSFAD_E_CHUNK (with chunk = 0 the next larger chunk that
+ * fits is used).  Fletcher-Powell with n <= 16 runs on MFMA as in the full
+ * form and has no such limit.
+ */
+int chessfad_hvp_sym(int func_id, int n, int64_t npts, const double* x, const double* v,
+                     double* out, int chunk, int precision, void* stream);
+int chessfad_hessian_sym(int func_id, int n, int64_t npts, const double* x, double* H,
+                         int chunk, int precision, void* stream);
+
+/*
  * Fletcher-Powell parameters for problem size n.  The function needs two
  * n x n integer-valued matrices A, B and a base point alpha; the method's
  * signatures have no slot for them, so they are registered per n.
@@ -151,8 +179,8 @@ int chessfad_set_option(int option, int value);
  * (Rosenbrock and Ackley: row blocks of the vector-ALU hDual evaluation;
  * Fletcher-Powell: row blocks of the MFMA kernel with calls as matrix
  * columns).  The items are sorted by their operation-count cost, largest
- * first, and a persistent kernel per precision - sized to fill the GPU -
- * takes them from an atomic counter until none is left.  The plan captures
+ * first, and a persistent kernel per (precision, body kind) - sized to fill
+ * the GPU - takes them from an atomic counter until none is left.  The plan captures
  * a counter reset kernel and the persistent kernels in one hipGraph;
  * chessfad_batch_run replays it on `stream` (asynchronous; replays on one
  * stream are ordered, replays of one plan on different streams race on its
@@ -203,6 +231,13 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
  */
 int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
                       float* best_ms);
+
+/* The same search for the symmetric H.v (chessfad_hvp_sym); the choice is
+ * recorded for chunk = 0 in chessfad_hvp_sym / chessfad_hessian_sym.
+ * Chunks whose symmetric workgroup does not fit in LDS are skipped;
+ * CHESSFAD_E_CHUNK if none fits. */
+int chessfad_autotune_sym(int func_id, int n, int precision, int64_t npts, void* stream,
+                          int* best_chunk, float* best_ms);
 
 /* Default chunk size the library uses for (func_id, n) when chunk == 0,
  * or a negative status for invalid arguments. */

@@ -44,6 +44,9 @@ SIGNATURES = {
     "chessfad_batch_destroy": (_i, [_p]),
     "chessfad_batch_info": (_i, [_p, _pi64, _pi, _pd]),
     "chessfad_autotune": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
+    "chessfad_hvp_sym": (_i, [_i, _i, _i64, _p, _p, _p, _i, _i, _p]),
+    "chessfad_hessian_sym": (_i, [_i, _i, _i64, _p, _p, _i, _i, _p]),
+    "chessfad_autotune_sym": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
 }
 
 CHESSFAD_OPT_FP_MFMA = 1
@@ -97,27 +100,27 @@ def _raise(rc, what):
         raise ChessfadError(rc, what)
 
 
-def _hvp(name, func_id, x, v, out, chunk, stream):
+def _hvp(name, func_id, x, v, out, chunk, stream, *extra):
     _check_pts("x", x)
     npts, n = x.shape
     _check_pts("v", v, n)
     if out is None:
         out = torch.empty_like(x)
     _check_pts("out", out, n)
-    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), v.data_ptr(), out.data_ptr(), chunk,
+    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), v.data_ptr(), out.data_ptr(), chunk, *extra,
                                _stream(stream))
     _raise(rc, name)
     return out
 
 
-def _hessian(name, func_id, x, out, chunk, stream):
+def _hessian(name, func_id, x, out, chunk, stream, *extra):
     _check_pts("x", x)
     npts, n = x.shape
     if out is None:
         out = torch.empty((npts, n, n), dtype=torch.float64, device=x.device)
     if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (npts, n, n)):
         raise ValueError("out must be a contiguous float64 CUDA tensor of shape [npts, n, n]")
-    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), out.data_ptr(), chunk, _stream(stream))
+    rc = getattr(load(), name)(func_id, n, npts, x.data_ptr(), out.data_ptr(), chunk, *extra, _stream(stream))
     _raise(rc, name)
     return out
 
@@ -144,6 +147,18 @@ def chessfad_hessian_mixed(func_id: int, x: torch.Tensor, out: torch.Tensor | No
                            stream=None) -> torch.Tensor:
     """Hessians with float32 hDuals, compensated sums and float64 islands."""
     return _hessian("chessfad_hessian_mixed", func_id, x, out, chunk, stream)
+
+
+def chessfad_hvp_sym(func_id: int, x: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None,
+                     chunk: int = 0, precision: int = 0, stream=None) -> torch.Tensor:
+    """SC-HESS-VEC: H.v evaluating only the chunks from each row's own chunk on."""
+    return _hvp("chessfad_hvp_sym", func_id, x, v, out, chunk, stream, precision)
+
+
+def chessfad_hessian_sym(func_id: int, x: torch.Tensor, out: torch.Tensor | None = None, chunk: int = 0,
+                         precision: int = 0, stream=None) -> torch.Tensor:
+    """SCHUNK-HESS: Hessians with the entries left of each row's own chunk mirrored."""
+    return _hessian("chessfad_hessian_sym", func_id, x, out, chunk, stream, precision)
 
 
 def chessfad_fp_set_params(A: torch.Tensor, B: torch.Tensor, alpha: torch.Tensor, stream=None) -> None:
@@ -243,4 +258,12 @@ def chessfad_autotune(func_id: int, n: int, precision: int = 0, npts: int = 1 <<
     c, ms = ctypes.c_int(), ctypes.c_float()
     _raise(load().chessfad_autotune(func_id, n, precision, npts, _stream(stream), ctypes.byref(c), ctypes.byref(ms)),
            "chessfad_autotune")
+    return c.value, ms.value
+
+
+def chessfad_autotune_sym(func_id: int, n: int, precision: int = 0, npts: int = 1 << 16, stream=None):
+    """The same search for the symmetric H.v; returns (chunk, ms)."""
+    c, ms = ctypes.c_int(), ctypes.c_float()
+    _raise(load().chessfad_autotune_sym(func_id, n, precision, npts, _stream(stream), ctypes.byref(c),
+                                        ctypes.byref(ms)), "chessfad_autotune_sym")
     return c.value, ms.value

@@ -297,8 +297,15 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
     return CHESSFAD_OK;
 }
 
-int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
-                      float* best_ms) {
+}  // extern "C"
+
+namespace {
+
+// Times H.v (full or symmetric form) at every compiled chunk <= n and records
+// the choice for chunk = 0.  A symmetric chunk whose workgroup does not fit
+// in LDS is skipped.
+int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk, float* best_ms,
+             bool sym) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     if ((precision != 0 && precision != 1) || npts <= 0) return CHESSFAD_E_ARG;
@@ -322,27 +329,33 @@ int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* str
     for (int k = 0; k < kNumChunks && err == hipSuccess && rc == CHESSFAD_OK; ++k) {
         const int C = kChunks[k];
         if (C > n) break;
-        rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1);  // warm-up
+        times[k] = -1.0f;
+        tried = k + 1;
+        rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym);  // warm-up
+        if (sym && rc == CHESSFAD_E_CHUNK) {
+            rc = CHESSFAD_OK;
+            continue;
+        }
         if (rc) break;
         err = hipEventRecord(e0, s);
         for (int r = 0; r < 3 && rc == CHESSFAD_OK; ++r)
-            rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1);
+            rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
         times[k] = ms / 3.0f;
-        tried = k + 1;
     }
     // the largest chunk within 2% (timing noise) of the fastest: fewer f calls
     // for the same Hessian entries
     int best = 0;
     float best_t = 0.0f;
     if (err == hipSuccess && rc == CHESSFAD_OK && tried > 0) {
-        float fastest = times[0];
-        for (int k = 1; k < tried; ++k) fastest = std::min(fastest, times[k]);
+        float fastest = -1.0f;
         for (int k = 0; k < tried; ++k)
-            if (times[k] <= 1.02f * fastest) {
+            if (times[k] >= 0.0f && (fastest < 0.0f || times[k] < fastest)) fastest = times[k];
+        for (int k = 0; k < tried; ++k)
+            if (times[k] >= 0.0f && times[k] <= 1.02f * fastest) {
                 best = kChunks[k];
                 best_t = times[k];
             }
@@ -355,10 +368,25 @@ int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* str
     if (e1) (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (err != hipSuccess) return hip_fail(err);
-    record_tuned_chunk(func_id, n, precision, best);
+    if (!best) return CHESSFAD_E_CHUNK;
+    record_tuned_chunk(func_id, n, precision, best, sym);
     if (best_chunk) *best_chunk = best;
     if (best_ms) *best_ms = best_t;
     return CHESSFAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
+                      float* best_ms) {
+    return autotune(func_id, n, precision, npts, stream, best_chunk, best_ms, false);
+}
+
+int chessfad_autotune_sym(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
+                          float* best_ms) {
+    return autotune(func_id, n, precision, npts, stream, best_chunk, best_ms, true);
 }
 
 }  // extern "C"

@@ -5,8 +5,8 @@
 // the single-instance kernels use: plain_block (Rosenbrock, Ackley; the
 // vector-ALU hDual evaluation) and fp_rows_block (Fletcher-Powell on MFMA,
 // calls as matrix columns).  Items are sorted by their paper-model cost,
-// largest first, and a persistent kernel - one per precision, sized to fill
-// the chip - takes them from an atomic counter until the list is exhausted
+// largest first, and a persistent kernel - one per precision and body kind,
+// sized to fill the chip - takes them from an atomic counter until its list is exhausted
 // (longest-processing-time-first list scheduling).  Every workgroup leaves
 // the loop when the counter passes the end of the list.  The two body kinds
 // get separate persistent kernels and lists, so each is compiled with the

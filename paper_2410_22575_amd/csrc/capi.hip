@@ -19,7 +19,7 @@ using namespace chessfad;
 namespace {
 thread_local std::string g_hip_error;
 std::mutex g_tune_mu;
-int g_tuned[3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (func, precision, n); 0 = none
+int g_tuned[2][3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (form, func, precision, n); 0 = none
 int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 }  // namespace
@@ -38,22 +38,38 @@ int check_func_n(int func_id, int n) {
     return CHESSFAD_OK;
 }
 
-int resolve_chunk(int func_id, int n, int precision, int max_chunk) {
+int resolve_chunk(int func_id, int n, int precision, int max_chunk, bool sym) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        const int t = g_tuned[func_id][precision][n];
+        const int t = g_tuned[sym][func_id][precision][n];
         if (t > 0 && t <= max_chunk) return t;
     }
-    // built-in default: the largest compiled chunk <= min(4, n, max_chunk)
     int c = 1;
+    if (sym) {
+        // Sec. V: the symmetric form needs (3/2) n (2n + 2c + n/c + 1) M
+        // multiplications, smallest near c = sqrt(n / 2); ties go to the
+        // larger chunk
+        double best = 1e300;
+        for (int k = 0; k < kNumChunks; ++k) {
+            const int ck = kChunks[k];
+            if (ck > n || ck > max_chunk) break;
+            const double cost = 2.0 * ck + (double)n / ck;
+            if (cost <= best) {
+                best = cost;
+                c = ck;
+            }
+        }
+        return c;
+    }
+    // full form: the largest compiled chunk <= min(4, n, max_chunk)
     for (int k = 0; k < kNumChunks; ++k)
         if (kChunks[k] <= n && kChunks[k] <= 4 && kChunks[k] <= max_chunk) c = kChunks[k];
     return c;
 }
 
-void record_tuned_chunk(int func_id, int n, int precision, int chunk) {
+void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[func_id][precision][n] = chunk;
+    g_tuned[sym][func_id][precision][n] = chunk;
 }
 
 double model_flops_per_call(int func_id, int n, int C) {
@@ -112,6 +128,60 @@ int fp_lookup(int n, FpParams& out) {
     return CHESSFAD_OK;
 }
 
+SymLaunch sym_table(int func_id, int C, bool hess, bool mixed) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return sym_rosenbrock(C, hess, mixed);
+        case CHESSFAD_ACKLEY: return sym_ackley(C, hess, mixed);
+        default: return sym_fletcher_powell(C, hess, mixed);
+    }
+}
+
+template <class P>
+size_t sym_lds_p(int func_id, int n, int C, int ppb, int ps, bool hess) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return sym_lds_bytes<P, Rosenbrock>(n, C, ppb, ps, hess);
+        case CHESSFAD_ACKLEY: return sym_lds_bytes<P, Ackley>(n, C, ppb, ps, hess);
+        default: return sym_lds_bytes<P, FletcherPowell>(n, C, ppb, ps, hess);
+    }
+}
+
+struct SymGeometry {
+    int nc, ppb, pstride;
+    size_t lds;
+    int64_t grid;
+};
+
+// Points per workgroup for the symmetric kernel: the count (up to 256) that
+// leaves the fewest idle lanes in the last pass over the calls (the smallest
+// such count when several are within half a percent), with the LDS image at
+// most 32 KiB, or 64 KiB for a single point.  False when one point does not fit.
+bool sym_geometry(int func_id, bool mixed, int n, int64_t npts, int C, bool hess, SymGeometry& g) {
+    g.nc = (n + C - 1) / C;
+    const int64_t per_point = (int64_t)C * g.nc * (g.nc + 1) / 2;
+    const int max_ppb = (int)(npts < 256 ? npts : 256);
+    int best = 0;
+    double best_use = -1.0;
+    for (int ppb = 1; ppb <= max_ppb; ++ppb) {
+        const int ps = ppb | 1;
+        const size_t lds = mixed ? sym_lds_p<F32C>(func_id, n, C, ppb, ps, hess)
+                                 : sym_lds_p<F64>(func_id, n, C, ppb, ps, hess);
+        if (lds > (ppb == 1 ? kSymMaxLds : kSymMaxLds / 2)) break;
+        const int64_t total = ppb * per_point;
+        const int64_t passes = (total + kSymThreads - 1) / kSymThreads;
+        const double use = (double)total / (double)(passes * kSymThreads);
+        if (use > best_use + 0.005) {
+            best_use = use;
+            best = ppb;
+            g.lds = lds;
+        }
+    }
+    if (!best) return false;
+    g.ppb = best;
+    g.pstride = best | 1;
+    g.grid = (npts + best - 1) / best;
+    return true;
+}
+
 PlainLaunch plain_table(int func_id, int C, bool hess, bool mixed) {
     switch (func_id) {
         case CHESSFAD_ROSENBROCK: return mixed ? mixed_rosenbrock(C, hess) : plain_rosenbrock(C, hess);
@@ -141,10 +211,11 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 }  // namespace
 
 int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-                         void* stream, bool hess, bool mixed) {
+                         void* stream, bool hess, bool mixed, bool sym) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
-    if (chunk == 0) chunk = resolve_chunk(func_id, n, mixed ? 1 : 0, 16);
+    const bool auto_chunk = chunk == 0;
+    if (auto_chunk) chunk = resolve_chunk(func_id, n, mixed ? 1 : 0, 16, sym);
     if (chunk < 0 || !chunk_compiled(chunk) || chunk > n) return CHESSFAD_E_CHUNK;
     if (npts < 0) return CHESSFAD_E_ARG;
     if (npts == 0) return CHESSFAD_OK;
@@ -160,8 +231,8 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma) {
-        FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess)
-                                    : fp_mfma_entry(chunk, fp_mfma_steps(n), hess);
+        FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess, sym)
+                                    : fp_mfma_entry(chunk, fp_mfma_steps(n), hess, sym);
         if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
@@ -169,6 +240,24 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
         FpMfmaArgs a{x, v, out, fp, npts, n, nc};
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
+    if (sym) {
+        // symmetric vector kernel (all three functions; Fletcher-Powell with
+        // n > 16 runs its contraction on the vector unit here)
+        SymGeometry g;
+        bool fits = sym_geometry(func_id, mixed, n, npts, chunk, hess, g);
+        for (int k = 0; k < kNumChunks && !fits && auto_chunk; ++k)
+            if (kChunks[k] > chunk && kChunks[k] <= n && sym_geometry(func_id, mixed, n, npts, kChunks[k], hess, g)) {
+                chunk = kChunks[k];
+                fits = true;
+            }
+        if (!fits) return CHESSFAD_E_CHUNK;
+        if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        SymLaunch launch = sym_table(func_id, chunk, hess, mixed);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        SymArgs a{x, v, out, fp, npts, n, g.nc, g.ppb, g.pstride};
+        hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kSymThreads), g.lds, s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
     if (func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma) {
@@ -211,6 +300,18 @@ int chessfad_hvp_mixed(int func_id, int n, int64_t npts, const double* x, const 
 int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, double* H, int chunk,
                            void* stream) {
     return run_single(func_id, n, npts, x, nullptr, H, chunk, stream, true, true);
+}
+
+int chessfad_hvp_sym(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+                     int precision, void* stream) {
+    if (precision != 0 && precision != 1) return CHESSFAD_E_ARG;
+    return run_single(func_id, n, npts, x, v, out, chunk, stream, false, precision == 1, true);
+}
+
+int chessfad_hessian_sym(int func_id, int n, int64_t npts, const double* x, double* H, int chunk, int precision,
+                         void* stream) {
+    if (precision != 0 && precision != 1) return CHESSFAD_E_ARG;
+    return run_single(func_id, n, npts, x, nullptr, H, chunk, stream, true, precision == 1, true);
 }
 
 int chessfad_fp_set_params(int n, const double* A, const double* B, const double* alpha, void* stream) {

@@ -6,6 +6,7 @@
 #include "kernel_fp_mfma.hpp"
 #include "kernel_fp_rows.hpp"
 #include "kernel_plain.hpp"
+#include "kernel_sym.hpp"
 
 namespace chessfad {
 
@@ -36,20 +37,20 @@ PlainLaunch plain_entry(int C) {
 
 using FpMfmaLaunch = hipError_t (*)(const FpMfmaArgs&, dim3 grid, dim3 block, hipStream_t);
 
-template <class P, int C, int NK, bool kHess>
+template <class P, int C, int NK, bool kHess, bool kSym>
 hipError_t launch_fp_mfma(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((fp_mfma_kernel<P, C, NK, kHess>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((fp_mfma_kernel<P, C, NK, kHess, kSym>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-template <class P, int NK, bool kHess>
+template <class P, int NK, bool kHess, bool kSym>
 FpMfmaLaunch fp_mfma_entry_c(int C) {
     switch (C) {
-        case 1: return &launch_fp_mfma<P, 1, NK, kHess>;
-        case 2: return &launch_fp_mfma<P, 2, NK, kHess>;
-        case 4: return &launch_fp_mfma<P, 4, NK, kHess>;
-        case 8: return &launch_fp_mfma<P, 8, NK, kHess>;
-        case 16: return &launch_fp_mfma<P, 16, NK, kHess>;
+        case 1: return &launch_fp_mfma<P, 1, NK, kHess, kSym>;
+        case 2: return &launch_fp_mfma<P, 2, NK, kHess, kSym>;
+        case 4: return &launch_fp_mfma<P, 4, NK, kHess, kSym>;
+        case 8: return &launch_fp_mfma<P, 8, NK, kHess, kSym>;
+        case 16: return &launch_fp_mfma<P, 16, NK, kHess, kSym>;
         default: return nullptr;
     }
 }
@@ -60,7 +61,7 @@ inline int fp_mfma_steps(int n) {
     return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
 }
 
-FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess);
+FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess, bool sym);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 
@@ -83,7 +84,33 @@ FpRowsLaunch fp_rows_entry_c(int C) {
 }
 
 FpRowsLaunch fp_rows_entry(int C, bool hess, bool mixed);
-FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess);
+FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess, bool sym);
+
+using SymLaunch = hipError_t (*)(const SymArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
+
+template <class P, class F, int C, bool kHess>
+hipError_t launch_sym(const SymArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((sym_kernel<P, F, C, kHess>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class P, class F, bool kHess>
+SymLaunch sym_entry(int C) {
+    switch (C) {
+        case 1: return &launch_sym<P, F, 1, kHess>;
+        case 2: return &launch_sym<P, F, 2, kHess>;
+        case 4: return &launch_sym<P, F, 4, kHess>;
+        case 8: return &launch_sym<P, F, 8, kHess>;
+        case 16: return &launch_sym<P, F, 16, kHess>;
+        default: return nullptr;
+    }
+}
+
+// Symmetric vector kernels, one per function (both precisions), each in its
+// own translation unit.
+SymLaunch sym_rosenbrock(int C, bool hess, bool mixed);
+SymLaunch sym_ackley(int C, bool hess, bool mixed);
+SymLaunch sym_fletcher_powell(int C, bool hess, bool mixed);
 
 // One per (function, precision), each defined in its own translation unit.
 PlainLaunch plain_rosenbrock(int C, bool hess);

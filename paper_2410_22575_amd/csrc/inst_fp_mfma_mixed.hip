@@ -1,20 +1,23 @@
 // Fletcher-Powell MFMA kernels (n <= 16), float32 derivative columns, float64 values: every compiled chunk size,
-// K-step count and output kind.
+// K-step count, output kind and form (full or symmetric).
 #include "dispatch.hpp"
 
 namespace chessfad {
 
-template <bool kHess>
+template <bool kHess, bool kSym>
 static FpMfmaLaunch by_steps(int C, int nk) {
     switch (nk) {
-        case 1: return fp_mfma_entry_c<F32C, 1, kHess>(C);
-        case 2: return fp_mfma_entry_c<F32C, 2, kHess>(C);
-        case 4: return fp_mfma_entry_c<F32C, 4, kHess>(C);
-        case 8: return fp_mfma_entry_c<F32C, 8, kHess>(C);
+        case 1: return fp_mfma_entry_c<F32C, 1, kHess, kSym>(C);
+        case 2: return fp_mfma_entry_c<F32C, 2, kHess, kSym>(C);
+        case 4: return fp_mfma_entry_c<F32C, 4, kHess, kSym>(C);
+        case 8: return fp_mfma_entry_c<F32C, 8, kHess, kSym>(C);
         default: return nullptr;
     }
 }
 
-FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess) { return hess ? by_steps<true>(C, nk) : by_steps<false>(C, nk); }
+FpMfmaLaunch fp_mfma_entry_mixed(int C, int nk, bool hess, bool sym) {
+    if (sym) return hess ? by_steps<true, true>(C, nk) : by_steps<false, true>(C, nk);
+    return hess ? by_steps<true, false>(C, nk) : by_steps<false, false>(C, nk);
+}
 
 }  // namespace chessfad

@@ -27,6 +27,13 @@
 // finishes with two lane exchanges.  H.v: the chunk dot and the row sum (in
 // chunk order) stay in registers; Hessian: H[p][i][cs + l] is stored.
 //
+// Symmetric form (kSym, SCHUNK-HESS / SC-HESS-VEC): row i walks only the
+// chunks from its own chunk i / C onwards.  An entry H(i, s) of a later chunk
+// is also stored at H(s, i) (Hessian), or adds H(i, s) v[i] to r(s) through a
+// per-point float64 accumulator in LDS (H.v).  Rows run in increasing order,
+// so r(s) has all its mirror terms (from rows before s's chunk) by the time
+// row s is finished.
+//
 // Precision policies: F64 runs every step in float64 (v_mfma_f64_16x16x4f64);
 // F32C runs the derivative columns on v_mfma_f32_16x16x4f32 with float32
 // seeded factors and [A B], keeps the value column and the residual values
@@ -110,11 +117,13 @@ CF_DEV float row_sum4(const float (&t)[4]) {
     return hi + lo;
 }
 
-template <class P, int C, int NK, bool kHess>
+template <class P, int C, int NK, bool kHess, bool kSym>
 __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     using T = typename P::T;
     using V = typename MfmaTile<T>::V;
     __shared__ T vs[kHess ? 1 : kFpWaves * kFpPointsPerWave * kFpVStride];
+    // mirror sums of the symmetric H.v, one row of kFpVStride per point
+    __shared__ double msum[(kSym && !kHess) ? kFpWaves * kFpPointsPerWave * kFpVStride : 1];
 
     const int n = a.n, nc = a.nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -181,6 +190,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     }
 
     T* vw = vs + wave * kFpPointsPerWave * kFpVStride;
+    double* mw = msum + ((kSym && !kHess) ? wave * kFpPointsPerWave * kFpVStride : 0);
     if (!kHess) {
         // stage the wave's 16 vectors (contiguous in global memory) in LDS
         const double* vg = a.v + pbase * n;
@@ -188,6 +198,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         for (int idx = lane; idx < kFpPointsPerWave * n; idx += 64) {
             const int pl = idx / n, k = idx - pl * n;
             vw[pl * kFpVStride + k] = (T)(idx < avail ? vg[idx] : 0.0);
+            if (kSym) mw[pl * kFpVStride + k] = 0.0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -205,8 +216,10 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         for (int r = 0; r < 4; ++r) rd[r] = -dd[r];
 
         double row = 0.0;
-        for (int jc = 0; jc < nc; ++jc) {
+        const int own = i / C;
+        for (int jc = kSym ? own : 0; jc < nc; ++jc) {
             const int cs = jc * C;
+            const bool mirrored = kSym && jc > own;
             typename P::Dot dot;
 #pragma unroll
             for (int l = 0; l < C; ++l) {
@@ -228,13 +241,18 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                 }
                 const T h = row_sum4(t);
                 if (kHess) {
-                    if (live && lg == 0) a.out[p * n * n + (int64_t)i * n + cs + l] = (double)h;
+                    if (live && lg == 0) {
+                        a.out[p * n * n + (int64_t)i * n + cs + l] = (double)h;
+                        if (mirrored) a.out[p * n * n + (int64_t)(cs + l) * n + i] = (double)h;
+                    }
                 } else {
                     dot.add(h, vw[li * kFpVStride + cs + l]);
+                    if (mirrored && lg == 0) mw[li * kFpVStride + cs + l] += (double)h * (double)vw[li * kFpVStride + i];
                 }
             }
             if (!kHess) row += dot.get();
         }
+        if (kSym && !kHess) row += mw[li * kFpVStride + i];
         if (!kHess && live && lg == 0) a.out[p * n + i] = row;
     }
 }

@@ -13,13 +13,17 @@ int hip_fail(hipError_t e);
 int check_func_n(int func_id, int n);
 
 // Chunk used when the caller passes 0: the autotuned choice for
-// (func_id, n, precision) if there is one, else the built-in default.
-int resolve_chunk(int func_id, int n, int precision, int max_chunk);
-void record_tuned_chunk(int func_id, int n, int precision, int chunk);
+// (form, func_id, n, precision) if there is one, else the built-in default
+// (full form: the largest compiled chunk <= 4; symmetric form: the compiled
+// chunk that minimises the multiplication count of Sec. V).
+int resolve_chunk(int func_id, int n, int precision, int max_chunk, bool sym = false);
+void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym = false);
 
-// Single-instance launch shared by chessfad_hvp / _hessian / _mixed.
+// Single-instance launch shared by chessfad_hvp / _hessian / _mixed / _sym.
+// With chunk == 0 and sym, a chunk whose symmetric workgroup would not fit
+// in LDS is replaced by the next larger one that fits.
 int run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-               void* stream, bool hess, bool mixed);
+               void* stream, bool hess, bool mixed, bool sym = false);
 
 // Paper-model flops of one f call (Sec. V operation counts, chunk dot included).
 double model_flops_per_call(int func_id, int n, int C);

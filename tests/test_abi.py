@@ -91,6 +91,32 @@ def test_overlap(lib):
     assert hess(lib, R, n, npts, x=FAKE + 8 * n * n * npts - 8, H=FAKE) == E_OVERLAP
 
 
+def symhvp(lib, func, n, npts, x=FAKE, v=FAKE * 2, out=FAKE * 4, chunk=4, precision=0):
+    return lib.chessfad_hvp_sym(func, n, npts, x, v, out, chunk, precision, None)
+
+
+def test_symmetric_argument_checks(lib):
+    assert symhvp(lib, 3, 16, 10) == E_FUNC
+    assert symhvp(lib, R, 1, 10, chunk=1) == E_N
+    assert symhvp(lib, R, 16, 10, chunk=3) == E_CHUNK
+    assert symhvp(lib, R, 4, 10, chunk=8) == E_CHUNK
+    assert symhvp(lib, R, 16, 10, precision=2) == E_ARG
+    assert symhvp(lib, R, 16, -1) == E_ARG
+    assert symhvp(lib, R, 16, 0, x=None, v=None, out=None) == OK
+    assert symhvp(lib, A, 16, 10, v=None) == E_NULL
+    nbytes = 8 * 16 * 10
+    assert symhvp(lib, R, 16, 10, x=FAKE, v=FAKE + 10 * nbytes, out=FAKE + nbytes - 8) == E_OVERLAP
+    assert lib.chessfad_hessian_sym(A, 16, 10, FAKE, None, 4, 0, None) == E_NULL
+    assert lib.chessfad_hessian_sym(A, 16, 10, FAKE, FAKE * 4, 4, -1, None) == E_ARG
+    # a point's partial sums must fit in LDS: n ceil(n / chunk) doubles
+    assert symhvp(lib, R, 512, 10, chunk=1) == E_CHUNK
+    assert symhvp(lib, R, 512, 10, chunk=16) == E_CHUNK
+    assert symhvp(lib, A, 512, 10, chunk=0) == E_CHUNK        # no compiled chunk fits
+    c, ms = ctypes.c_int(), ctypes.c_float()
+    assert lib.chessfad_autotune_sym(4, 16, 0, 100, None, ctypes.byref(c), ctypes.byref(ms)) == E_FUNC
+    assert lib.chessfad_autotune_sym(A, 16, 2, 100, None, None, None) == E_ARG
+
+
 def test_default_chunk(lib):
     assert lib.chessfad_default_chunk(R, 16) in (1, 2, 4, 8, 16)
     assert lib.chessfad_default_chunk(A, 1) == 1
