@@ -35,11 +35,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0294e+08,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0295e+08,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0297e+08,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0302e+08,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0310e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=2, H.v>": 4.0279e+08,
     "plain_kernel<ackley, C=4, H.v>": 4.0280e+08,
@@ -51,6 +46,40 @@ MEASURED_TRAFFIC = {
     "plain_kernel<rosenbrock, C=8, H.v>": 4.0275e+08,
     "plain_kernel<rosenbrock, C=16, H.v>": 4.0277e+08,
 }
+
+# float64 flops the vector ALUs execute per launch (rocprofv3
+# SQ_INSTS_VALU_FLOPS_FP64, which counts per wavefront, x 64 lanes; FMA = 2),
+# same keying and rule as MEASURED_TRAFFIC.  The kernels execute fewer flops
+# than the paper's operation model counts: first-order seeds carry no
+# second-order part and the compiler folds the constant seed components.
+MEASURED_VALU_FLOPS = {
+    "plain_kernel<ackley, C=1, H.v>": 9.7039e+10,
+    "plain_kernel<ackley, C=2, H.v>": 6.7713e+10,
+    "plain_kernel<ackley, C=4, H.v>": 5.7949e+10,
+    "plain_kernel<ackley, C=8, H.v>": 5.2219e+10,
+    "plain_kernel<ackley, C=16, H.v>": 4.9405e+10,
+    "plain_kernel<rosenbrock, C=1, H.v>": 8.4826e+10,
+    "plain_kernel<rosenbrock, C=2, H.v>": 6.7646e+10,
+    "plain_kernel<rosenbrock, C=4, H.v>": 5.7915e+10,
+    "plain_kernel<rosenbrock, C=8, H.v>": 6.0633e+10,
+    "plain_kernel<rosenbrock, C=16, H.v>": 5.8754e+10,
+}
+
+
+def kernel_key(f, c, n=N):
+    if f == 2 and n <= 16:
+        return f"fp_mfma_kernel<C={c}, NK={min(8, max(1, (2 * n + 3) // 4))}, H.v>"
+    return f"plain_kernel<{NAMES[f]}, C={c}, H.v>"
+
+
+def fp_mfma_flops(n, c, npts):
+    """MFMA flops the n <= 16 Fletcher-Powell kernel executes per launch: per
+    16-point wave, NK steps of 16x16x4 for the value column, then per row NK
+    for the d column, NK per chunk column for g and NK for the one nonzero h
+    column (2 x 16 x 16 x 4 flops per step)."""
+    nk = min(8, max(1, (2 * n + 3) // 4))
+    tiles = 1 + n * (1 + n + 1)
+    return nk * tiles * 2 * 16 * 16 * 4 * (npts / 16)
 
 
 def parse():
@@ -268,15 +297,17 @@ def main():
             E[f] = cf.fp_offsets(w.A, w.B, w.alpha)
     torch.cuda.synchronize()
     # chunk per function: explicit, autotuned (outside the timed region), or default
-    tuned, mchunks = {}, {}
+    tuned, mchunks, schunks = {}, {}, {}
     for f in FUNCS:
         if args.chunk:
-            chunks[f] = mchunks[f] = args.chunk
+            chunks[f] = mchunks[f] = schunks[f] = args.chunk
         elif not args.no_tune:
             chunks[f], tuned[NAMES[f]] = binding.chessfad_autotune(f, N, 0, npts=npts)
             mchunks[f], _ = binding.chessfad_autotune(f, N, 1, npts=npts)
+            schunks[f], _ = binding.chessfad_autotune_sym(f, N, 0, npts=npts)
         else:
             chunks[f] = mchunks[f] = binding.chessfad_default_chunk(f, N)
+            schunks[f] = 0
     torch.cuda.synchronize()
 
     def step(events=None):
@@ -313,27 +344,34 @@ def main():
             "model_tflops": mf * npts / (kernel_ms[f] * 1e-3) / 1e12,
             "model_flops_per_hvp": mf,
         }
-    dom = max(FUNCS, key=lambda f: kernel_ms[f])
-    achieved = per_func[NAMES[dom]]["model_tflops"]
+    for f in FUNCS:
+        # executed flops where known: MFMA from the tile schedule, vector
+        # float64 from the counters taken for this kernel
+        key = kernel_key(f, chunks[f])
+        ex = (fp_mfma_flops(N, chunks[f], npts) if key.startswith("fp_mfma") else 0.0)
+        valu = MEASURED_VALU_FLOPS.get(key)
+        per_func[NAMES[f]]["executed_mfma_tflops"] = ex / (kernel_ms[f] * 1e-3) / 1e12 if ex else None
+        per_func[NAMES[f]]["executed_valu_f64_tflops"] = valu / (kernel_ms[f] * 1e-3) / 1e12 if valu else None
     fp_mfma = N <= 16
-    if dom == 2 and fp_mfma:
-        kname = f"fp_mfma_kernel<C={chunks[2]}, NK={min(8, max(1, (2 * N + 3) // 4))}, H.v>"
-        bound = "mfma"
+    dom = max(FUNCS, key=lambda f: kernel_ms[f])
+    kname = kernel_key(dom, chunks[dom])
+    model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
+    t_dom = kernel_ms[dom] * 1e-3
+    if kname.startswith("fp_mfma"):
+        # the matrix cores: executed MFMA flops (fewer than the model counts)
+        bound, work, basis = "mfma", fp_mfma_flops(N, chunks[dom], npts), "executed MFMA flops (tile schedule)"
+    elif kname in MEASURED_VALU_FLOPS:
+        bound, work, basis = "alu", MEASURED_VALU_FLOPS[kname], "executed float64 VALU flops (counters)"
     else:
-        kname = f"plain_kernel<{NAMES[dom]}, C={chunks[dom]}, H.v>"
-        bound = "alu"
+        bound, work, basis = "alu", model_launch, "paper-model flops"
+    if work > model_launch:
+        work, basis = model_launch, "paper-model flops (below the executed count)"
+    achieved = work / t_dom / 1e12
     roofline = {"bound": bound, "kernel": kname, "achieved": achieved, "peak": PEAK_F64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": MEASURED_TRAFFIC.get(kname),
-                "flops_per_launch": flops.flops_per_hvp(dom, N, chunks[dom]) * npts}
-    if dom == 2 and fp_mfma:
-        # MFMA flops the kernel executes: per 16-point wave, NK steps for the
-        # value column, NK per row for the d component (shared by the row's
-        # chunks) and 2 NK per (call, chunk column) for g and h
-        nk = min(8, max(1, (2 * N + 3) // 4))
-        c = chunks[2]
-        tiles = 1 + N * (1 + sum(2 * min(c, N - cs) for cs in range(0, N, c)))
-        mf = nk * tiles * 2 * 16 * 16 * 4 * (npts / 16)
-        roofline["executed_mfma_tflops"] = mf / (kernel_ms[2] * 1e-3) / 1e12
+                "flops_per_launch": work, "basis": basis, "model_flops_per_launch": model_launch,
+                "model_tflops": model_launch / t_dom / 1e12}
+    if bound == "mfma":
         roofline["measured_mfma_f64_peak"] = 72.8
 
     # the Fletcher-Powell vector-ALU path, for comparison (outside the timed region)
@@ -401,6 +439,27 @@ def main():
         mixed[NAMES[f]] = {"chunk": mc, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                            "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
 
+    # the symmetric form (SC-HESS-VEC) on the same inputs, outside the timed
+    # region: fewer f calls per point, the same H.v
+    sym = {}
+    for f in FUNCS:
+        so = torch.empty_like(xs[f])
+        sc = schunks[f]
+        binding.chessfad_hvp_sym(f, xs[f], vs[f], so, chunk=sc)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            binding.chessfad_hvp_sym(f, xs[f], vs[f], so, chunk=sc)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        sym[NAMES[f]] = {"chunk": sc or "library default", "kernel_ms": round(ms, 4),
+                         "hvps_per_s": npts / (ms * 1e-3), "speedup_vs_full_f64": kernel_ms[f] / ms,
+                         "calls_per_point": flops.calls_per_point_sym(N, sc) if sc else None,
+                         "max_rel_err_sampled": rel_err(f, so)}
+    sym_step = sum(v["kernel_ms"] for v in sym.values())
+    sym_total = {"kernel_ms_sum": round(sym_step, 4), "hvps_per_s": len(FUNCS) * npts / (sym_step * 1e-3)}
+
     result = {
         "metric": METRIC,
         "value": value,
@@ -423,6 +482,7 @@ def main():
         "fp_vector_path_ms": fp_vector_ms,
         "mixed_f32": mixed,
         "hessian_f64": hess,
+        "symmetric_f64": {"per_function": sym, "all_three": sym_total},
     }
     result["autotuned_ms"] = tuned or None
     if not args.no_batch:

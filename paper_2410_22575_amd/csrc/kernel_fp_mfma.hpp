@@ -20,9 +20,13 @@
 // For one call and one hDual component the 16 x 16 result tile
 //   D[m][point] = sum_k [A B][m][k] S_point[k][component]
 // comes from NK = ceil(2n / 4) v_mfma_f64_16x16x4f64 steps over K = 2n
-// (dense: every step is executed, whatever the seeds make zero).  The rest of
-// f runs on the vector unit: r_m = E_m - inner_m and f = sum_m r_m * r_m,
-// forming only the second-order components the output needs.  Each lane
+// (dense: every step is executed, whatever the seeds make zero).  Only the
+// h[l] column with cs + l = i has nonzero S entries (the second-order part of
+// a seeded sin/cos needs both seeds on the same coordinate); every other
+// h[l] column of S is zero, so its tile is zero and is not contracted.  The
+// rest of f runs on the vector unit: r_m = E_m - inner_m and
+// f = sum_m r_m * r_m, forming only the second-order components the output
+// needs (with the zero h tiles, the terms r_m.v r_m.h[l] drop out).  Each lane
 // holds four residual rows m = 4 r + lane / 16 of its column; the sum over m
 // finishes with two lane exchanges.  H.v: the chunk dot and the row sum (in
 // chunk order) stay in registers; Hessian: H[p][i][cs + l] is stored.
@@ -224,20 +228,28 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
 #pragma unroll
             for (int l = 0; l < C; ++l) {
                 if (cs + l >= n) break;  // surplus columns of a ragged last chunk
-                V ag = {zero, zero, zero, zero}, ah = {zero, zero, zero, zero};
+                V ag = {zero, zero, zero, zero};
 #pragma unroll
-                for (int s = 0; s < NK; ++s) {
-                    const bool col = jj[s] == cs + l;
-                    ag = mfma16(aop[s], col ? g1[s] : zero, ag);
-                    ah = mfma16(aop[s], (col && jj[s] == i) ? g2[s] : zero, ah);
-                }
+                for (int s = 0; s < NK; ++s) ag = mfma16(aop[s], jj[s] == cs + l ? g1[s] : zero, ag);
                 // second-order component l of r * r for this lane's rows, then
                 // summed over all residual rows
                 T t[4];
+                if (cs + l == i) {
+                    // the one column whose S entries are not all zero
+                    V ah = {zero, zero, zero, zero};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const T rg = -ag[r], rh = -ah[r];
-                    t[r] = rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh;
+                    for (int s = 0; s < NK; ++s) ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const T rg = -ag[r], rh = -ah[r];
+                        t[r] = rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const T rg = -ag[r];
+                        t[r] = rd[r] * rg + rd[r] * rg;
+                    }
                 }
                 const T h = row_sum4(t);
                 if (kHess) {
