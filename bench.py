@@ -74,11 +74,12 @@ def kernel_key(f, c, n=N):
 
 def fp_mfma_flops(n, c, npts):
     """MFMA flops the n <= 16 Fletcher-Powell kernel executes per launch: per
-    16-point wave, NK steps of 16x16x4 for the value column, then per row NK
-    for the d column, NK per chunk column for g and NK for the one nonzero h
-    column (2 x 16 x 16 x 4 flops per step)."""
+    16-point wave, NK steps of 16x16x4 for the value column, NK for the g
+    column of each variable, and per row NK for the d column and NK for the
+    one nonzero h column (2 x 16 x 16 x 4 flops per step).  The chunk size
+    does not change it."""
     nk = min(8, max(1, (2 * n + 3) // 4))
-    tiles = 1 + n * (1 + n + 1)
+    tiles = 1 + n + 2 * n
     return nk * tiles * 2 * 16 * 16 * 4 * (npts / 16)
 
 

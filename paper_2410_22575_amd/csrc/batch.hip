@@ -147,7 +147,7 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         e.calls_per_point = (int64_t)c.n * nc;
         if (fp) {
             e.d.kind = 1;
-            e.d.rows = nc <= 64 ? 64 / nc : 1;
+            e.d.rows = fp_rows_per_block(c.n, nc);
             e.d.row_blocks = (c.n + e.d.rows - 1) / e.d.rows;
             e.d.pstride = 0;
             e.blocks = c.npts * e.d.row_blocks;
@@ -241,7 +241,8 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         size_t lds = 0;
         for (const auto& it : items[l]) flat.push_back(it.second);
         for (const BatchDesc& d : descs[l]) {
-            const size_t need = d.kind == 1 ? sizeof(FpRowsShared) : (pr ? plain_lds_for<F32C>(d) : plain_lds_for<F64>(d));
+            const size_t need = d.kind == 1 ? (pr ? sizeof(FpRowsShared<float>) : sizeof(FpRowsShared<double>))
+                                            : (pr ? plain_lds_for<F32C>(d) : plain_lds_for<F64>(d));
             lds = std::max(lds, need);
         }
         BatchDesc* dd = reinterpret_cast<BatchDesc*>(b->dmem + off_desc[l]);

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs b) {
         const BatchDesc d = b.desc[item.inst];
         if constexpr (kKind == 1) {
             FpRowsArgs fa{d.x, d.v, d.out, d.fp, d.npts, d.n, d.nc, d.rows, d.row_blocks};
-            FpRowsShared& sh = *reinterpret_cast<FpRowsShared*>(lds);
+            FpRowsShared<typename P::T>& sh = *reinterpret_cast<FpRowsShared<typename P::T>*>(lds);
             switch (d.C) {
                 case 1: fp_rows_block<P, 1, false>(fa, item.blk, sh); break;
                 case 2: fp_rows_block<P, 2, false>(fa, item.blk, sh); break;

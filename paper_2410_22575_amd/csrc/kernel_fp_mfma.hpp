@@ -17,16 +17,23 @@
 //
 // Mapping: a wave owns 16 consecutive points, one per MFMA column (lane % 16),
 // and walks through every call (i, cs) of those points in row-major order.
-// For one call and one hDual component the 16 x 16 result tile
+// For one hDual component the 16 x 16 result tile
 //   D[m][point] = sum_k [A B][m][k] S_point[k][component]
 // comes from NK = ceil(2n / 4) v_mfma_f64_16x16x4f64 steps over K = 2n
-// (dense: every step is executed, whatever the seeds make zero).  Only the
-// h[l] column with cs + l = i has nonzero S entries (the second-order part of
-// a seeded sin/cos needs both seeds on the same coordinate); every other
-// h[l] column of S is zero, so its tile is zero and is not contracted.  The
-// rest of f runs on the vector unit: r_m = E_m - inner_m and
-// f = sum_m r_m * r_m, forming only the second-order components the output
-// needs (with the zero h tiles, the terms r_m.v r_m.h[l] drop out).  Each lane
+// (dense: every step is executed, whatever the seeds make zero).  Each
+// column of S depends on fewer indices than the call, so each tile is
+// contracted once for all the calls that share it:
+//   value        depends on the point only        - once per point
+//   d            on the row i                     - once per row
+//   g[l]         on the variable k = cs + l       - once per variable
+//   h[l]         nonzero only for k = i (the second-order part of a seeded
+//                sin/cos needs both seeds on one coordinate) - once per row;
+//                the other h columns of S are zero and are not contracted.
+// Every component of every call is therefore the same sum of the same
+// products as when the call contracts its own columns.  The rest of f runs on
+// the vector unit, per call: r_m = E_m - inner_m and f = sum_m r_m * r_m,
+// forming only the second-order components the output needs (with the zero
+// h columns, the terms r_m.v r_m.h[l] drop out).  Each lane
 // holds four residual rows m = 4 r + lane / 16 of its column; the sum over m
 // finishes with two lane exchanges.  H.v: the chunk dot and the row sum (in
 // chunk order) stay in registers; Hessian: H[p][i][cs + l] is stored.
@@ -210,59 +217,77 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     }
 
     const T zero = T(0);
+    // g column of every variable k: the same in every call whose chunk holds
+    // k, whatever the row, so it is contracted once here (r_m.g = -inner_m.g)
+    constexpr int KMAX = 2 * NK;  // n <= 2 NK
+    T rg[KMAX][4];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        V ag = {zero, zero, zero, zero};
+        if (k < n) {
+#pragma unroll
+            for (int s = 0; s < NK; ++s) ag = mfma16(aop[s], jj[s] == k ? g1[s] : zero, ag);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rg[k][r] = -ag[r];
+    }
+
+    constexpr int KCH = (KMAX + C - 1) / C;  // chunks that can hold a variable
     for (int i = 0; i < n; ++i) {
-        // d component (row derivative) of every residual, shared by the row's chunks
-        V dd = {zero, zero, zero, zero};
+        // d column (row derivative), shared by the row's chunks, and the one
+        // nonzero h column (the row's own variable)
+        V dd = {zero, zero, zero, zero}, ah = {zero, zero, zero, zero};
 #pragma unroll
-        for (int s = 0; s < NK; ++s) dd = mfma16(aop[s], jj[s] == i ? g1[s] : zero, dd);
-        T rd[4];
+        for (int s = 0; s < NK; ++s) {
+            dd = mfma16(aop[s], jj[s] == i ? g1[s] : zero, dd);
+            ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
+        }
+        T rd[4], rh[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) rd[r] = -dd[r];
+        for (int r = 0; r < 4; ++r) {
+            rd[r] = -dd[r];
+            rh[r] = -ah[r];
+        }
 
         double row = 0.0;
         const int own = i / C;
-        for (int jc = kSym ? own : 0; jc < nc; ++jc) {
-            const int cs = jc * C;
-            const bool mirrored = kSym && jc > own;
-            typename P::Dot dot;
+        // fixed trip counts (no early exit) so that rg is indexed statically
 #pragma unroll
-            for (int l = 0; l < C; ++l) {
-                if (cs + l >= n) break;  // surplus columns of a ragged last chunk
-                V ag = {zero, zero, zero, zero};
+        for (int jc = 0; jc < KCH; ++jc) {
+            if (jc < nc && (!kSym || jc >= own)) {
+                const bool mirrored = kSym && jc > own;
+                typename P::Dot dot;
 #pragma unroll
-                for (int s = 0; s < NK; ++s) ag = mfma16(aop[s], jj[s] == cs + l ? g1[s] : zero, ag);
-                // second-order component l of r * r for this lane's rows, then
-                // summed over all residual rows
-                T t[4];
-                if (cs + l == i) {
-                    // the one column whose S entries are not all zero
-                    V ah = {zero, zero, zero, zero};
+                for (int l = 0; l < C; ++l) {
+                    const int k = jc * C + l;
+                    // surplus columns of a ragged last chunk are skipped
+                    if (k < KMAX && k < n) {
+                        // second-order component l of r * r for this lane's
+                        // rows, then summed over all residual rows
+                        T t[4];
+                        if (k == i) {
 #pragma unroll
-                    for (int s = 0; s < NK; ++s) ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
+                            for (int r = 0; r < 4; ++r)
+                                t[r] = rv[r] * rh[r] + rd[r] * rg[k][r] + rd[r] * rg[k][r] + rv[r] * rh[r];
+                        } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const T rg = -ag[r], rh = -ah[r];
-                        t[r] = rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const T rg = -ag[r];
-                        t[r] = rd[r] * rg + rd[r] * rg;
+                            for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
+                        }
+                        const T h = row_sum4(t);
+                        if (kHess) {
+                            if (live && lg == 0) {
+                                a.out[p * n * n + (int64_t)i * n + k] = (double)h;
+                                if (mirrored) a.out[p * n * n + (int64_t)k * n + i] = (double)h;
+                            }
+                        } else {
+                            dot.add(h, vw[li * kFpVStride + k]);
+                            if (mirrored && lg == 0)
+                                mw[li * kFpVStride + k] += (double)h * (double)vw[li * kFpVStride + i];
+                        }
                     }
                 }
-                const T h = row_sum4(t);
-                if (kHess) {
-                    if (live && lg == 0) {
-                        a.out[p * n * n + (int64_t)i * n + cs + l] = (double)h;
-                        if (mirrored) a.out[p * n * n + (int64_t)(cs + l) * n + i] = (double)h;
-                    }
-                } else {
-                    dot.add(h, vw[li * kFpVStride + cs + l]);
-                    if (mirrored && lg == 0) mw[li * kFpVStride + cs + l] += (double)h * (double)vw[li * kFpVStride + i];
-                }
+                if (!kHess) row += dot.get();
             }
-            if (!kHess) row += dot.get();
         }
         if (kSym && !kHess) row += mw[li * kFpVStride + i];
         if (!kHess && live && lg == 0) a.out[p * n + i] = row;

@@ -1,24 +1,29 @@
-// Fletcher-Powell on MFMA for any n <= 512: one point per workgroup, calls as
-// matrix columns.
+// Fletcher-Powell on MFMA for any n <= 512: R rows of one point per workgroup.
 //
 // The residual layer inner_m = sum_j A_mj sin y_j + B_mj cos y_j of every call
-// is the product [A B] (n x 2n) . S_call (2n x (2C + 1)) over the derivative
-// components (d, g[l], h[l]) of the seeded sin/cos values (see
-// kernel_fp_mfma.hpp for the entries of S).  Here a wave takes 16 calls of
-// one point as the 16 MFMA columns and walks the 16-row tiles of m and the
-// K = 2n steps of 4; each step loads one [A B] operand per lane and feeds it
-// to all component tiles of the pass (dense: every step runs).  Per m tile
-// the vector unit forms r_m = E_m - inner_m and the second-order components
-// of r_m * r_m and adds them into the call's running f.h[l]; after the last
-// tile the four lane groups are summed with two lane exchanges.
+// is the product [A B] (n x 2n) . S_call over the derivative components of the
+// seeded sin/cos values (kernel_fp_mfma.hpp lists the entries of S).  The S
+// columns depend on fewer indices than the call, so each is contracted once
+// per workgroup and m tile and shared by every call that uses it:
+//   g column of variable k (also the d column of row k)  - factors (cos, -sin)
+//   h column of row i (nonzero only for k = i)            - factors (-sin, -cos)
+// as 16 x 16 MFMA tiles (16 residual rows m x 16 variables), dense over
+// K = 2n in steps of 4.  The tiles, negated into r_m's components, go to LDS:
+// the g columns of a block of up to kFpRowsKB variables at a time, and the
+// d and h columns of the workgroup's rows.
 //
-// A workgroup owns R consecutive rows of one point (R = 64 / nc when nc <= 64,
-// else 1): it stages the point's sin/cos(x_j) (float64), its vector and the
-// float64 residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j in
-// LDS, its four waves take the R * nc calls 16 at a time, and the row sums
-// over chunks (H.v) are formed in chunk order from LDS.  Per m tile the d
-// tile is formed first; the g and h tiles follow LB at a time (LB = 8 in
-// float32, 4 in float64) to bound the accumulator registers.
+// Each lane then evaluates the rest of f for whole calls (i, cs) - at most
+// kFpRowsCallsPerLane of them - on the vector unit: for every residual m in
+// order, the second-order components of r_m * r_m,
+//   2 r_m.v r_m.h[l] [cs + l = i] + 2 r_m.d r_m.g[l],
+// added into the call's running sums (two-sum compensated in float32).  The
+// residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j are float64
+// and computed once per point.  H.v: chunk dot with v, then the row sums over
+// chunks in chunk order from LDS; Hessian: H[p][i][cs + l] is stored.
+//
+// A workgroup owns R = fp_rows_per_block(n, nc) consecutive rows of one point
+// (at most 64, and at most 512 calls), so every workgroup of a point forms
+// the g columns of all n variables.
 #pragma once
 
 #include <stdint.h>
@@ -35,13 +40,25 @@ struct FpRowsArgs {
     int64_t npts;
     int n;
     int nc;             // chunks per row
-    int rows;           // rows per workgroup
+    int rows;           // rows per workgroup, fp_rows_per_block(n, nc)
     int row_blocks;     // workgroups per point, ceil(n / rows)
 };
 
 constexpr int kFpRowsMaxN = 512;
 constexpr int kFpRowsWaves = 4;
-constexpr int kFpRowsMaxCalls = 512;  // rows * nc <= max(64, nc) <= 512
+constexpr int kFpRowsKB = 128;          // variables whose g columns are in LDS at once (a multiple of every C)
+constexpr int kFpRowsMaxRows = 64;
+constexpr int kFpRowsCallsPerLane = 2;
+constexpr int kFpRowsMaxCalls = 64 * kFpRowsWaves * kFpRowsCallsPerLane;
+
+// Rows per workgroup: as many as keep the calls within kFpRowsMaxCalls, at
+// most kFpRowsMaxRows and n.
+__host__ __device__ inline int fp_rows_per_block(int n, int nc) {
+    int r = kFpRowsMaxCalls / nc;
+    if (r > kFpRowsMaxRows) r = kFpRowsMaxRows;
+    if (r > n) r = n;
+    return r < 1 ? 1 : r;
+}
 
 // running sum: plain float64, or float32 with a two-sum low part
 template <typename T>
@@ -50,12 +67,7 @@ template <>
 struct RunSum<double> {
     double s = 0.0;
     CF_DEV void add(double t) { s += t; }
-    CF_DEV double lane_total() {
-        double h = s;
-        h += __shfl_xor(h, 16);
-        h += __shfl_xor(h, 32);
-        return h;
-    }
+    CF_DEV double value() const { return s; }
 };
 template <>
 struct RunSum<float> {
@@ -66,40 +78,27 @@ struct RunSum<float> {
         hi = s;
         lo += e;
     }
-    CF_DEV float lane_total() {
-        float h = hi, l = lo;
-#pragma unroll
-        for (int x = 16; x <= 32; x *= 2) {
-            const float oh = __shfl_xor(h, x), ol = __shfl_xor(l, x);
-            float s, e;
-            two_sum(h, oh, s, e);
-            h = s;
-            l += e + ol;
-        }
-        return h + l;
-    }
+    CF_DEV float value() const { return hi + lo; }
 };
 
 // LDS of one workgroup (vv and dots are used only for H.v)
+template <typename T>
 struct FpRowsShared {
     double s64[kFpRowsMaxN], c64[kFpRowsMaxN], rvs[kFpRowsMaxN];
     double vv[kFpRowsMaxN];
     double dots[kFpRowsMaxCalls];
+    T gk[16][kFpRowsKB];           // r_m.g of the variables of the current block
+    T gi[16][kFpRowsMaxRows];      // r_m.d of the workgroup's rows (when n > kFpRowsKB)
+    T hi[16][kFpRowsMaxRows];      // r_m.h of the rows' own column
 };
 
 // One workgroup's share: block blk = (point, row block).  Needs exactly
 // 64 * kFpRowsWaves threads.
 template <class P, int C, bool kHess>
-__device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, FpRowsShared& sh) {
+__device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, FpRowsShared<typename P::T>& sh) {
     using T = typename P::T;
     using V = typename MfmaTile<T>::V;
-    constexpr int LBMAX = sizeof(T) == sizeof(double) ? 4 : 8;
-    constexpr int LB = C < LBMAX ? C : LBMAX;
-    double* s64 = sh.s64;
-    double* c64 = sh.c64;
-    double* rvs = sh.rvs;
-    double* vv = sh.vv;
-    double* dots = sh.dots;
+    constexpr int Q = kFpRowsCallsPerLane;
 
     const int n = a.n, nc = a.nc;
     const int64_t p = blk / a.row_blocks;
@@ -113,120 +112,147 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         double s, c;
         sincos(xp[t], &s, &c);
-        s64[t] = s;
-        c64[t] = c;
-        if (!kHess) vv[t] = a.v[p * n + t];
+        sh.s64[t] = s;
+        sh.c64[t] = c;
+        if (!kHess) sh.vv[t] = a.v[p * n + t];
     }
     __syncthreads();
     for (int m = threadIdx.x; m < n; m += blockDim.x) {
         const double* Am = a.fp.A + (size_t)m * n;
         const double* Bm = a.fp.B + (size_t)m * n;
-        double acc = Am[0] * s64[0];
-        acc = acc + Bm[0] * c64[0];
+        double acc = Am[0] * sh.s64[0];
+        acc = acc + Bm[0] * sh.c64[0];
         for (int j = 1; j < n; ++j) {
-            acc = acc + Am[j] * s64[j];
-            acc = acc + Bm[j] * c64[j];
+            acc = acc + Am[j] * sh.s64[j];
+            acc = acc + Bm[j] * sh.c64[j];
         }
-        rvs[m] = a.fp.E[m] - acc;
+        sh.rvs[m] = a.fp.E[m] - acc;
     }
-    __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int mtiles = (n + 15) / 16;
     const int nk = (2 * n + 3) / 4;
-    const int groups = (ncalls + 15) / 16;
+    const int kblocks = (n + kFpRowsKB - 1) / kFpRowsKB;
+    const bool gi_in_gk = kblocks == 1;  // every row's d column is a column of the one g block
+    const int rtiles = (nrows + 15) / 16;
     const T zero = T(0);
 
-    for (int grp = wave; grp < groups; grp += kFpRowsWaves) {
-        const int cl = grp * 16 + li;          // this lane's call within the workgroup
-        const bool valid = cl < ncalls;
-        const int i = valid ? r0 + cl / nc : -1;
-        const int cs = valid ? (cl - (cl / nc) * nc) * C : -8192;
+    // the lane's calls (i, cs)
+    int ci[Q], ccs[Q];
+    bool cval[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int cl = threadIdx.x + q * (int)blockDim.x;
+        cval[q] = cl < ncalls;
+        const int rr = cval[q] ? cl / nc : 0;
+        ci[q] = r0 + rr;
+        ccs[q] = cval[q] ? (cl - rr * nc) * C : 0;
+    }
+    RunSum<T> fh[Q][C];
 
-        RunSum<T> fh[C];
-        for (int mt = 0; mt < mtiles; ++mt) {
-            const int m_op = mt * 16 + li;     // A-operand row of this lane
-            // [A B] operand and seeded sin/cos factors of K step s
-            auto operands = [&](int s, T& aop, T& g1, T& g2, int& jm) {
-                const int k = 4 * s + lg;
-                const bool in = k < 2 * n;
+    // -r_m components of S columns col0 .. col0 + 15 (variables or rows) for
+    // the residual rows of m tile mt: the g/d column (h = false) or the h
+    // column (h = true) of each
+    auto tile = [&](int mt, int col0, bool h) -> V {
+        V acc = {zero, zero, zero, zero};
+        const int m_op = mt * 16 + li;      // A-operand row of this lane
+        const int var = col0 + li;          // B-operand column of this lane
+        for (int s = 0; s < nk; ++s) {
+            const int k = 4 * s + lg;
+            T aop = zero, b = zero;
+            if (k < 2 * n) {
                 const int j = k < n ? k : k - n;
-                aop = g1 = g2 = zero;
-                if (in) {
-                    if (m_op < n) aop = k < n ? fp_a<T>(a.fp, (size_t)m_op * n + k) : fp_b<T>(a.fp, (size_t)m_op * n + j);
-                    const double sj = s64[j], cj = c64[j];
-                    g1 = (T)(k < n ? cj : -sj);
-                    g2 = (T)(k < n ? -sj : -cj);
+                if (m_op < n) aop = k < n ? fp_a<T>(a.fp, (size_t)m_op * n + k) : fp_b<T>(a.fp, (size_t)m_op * n + j);
+                if (j == var) {
+                    const double sj = sh.s64[j], cj = sh.c64[j];
+                    b = (T)(h ? (k < n ? -sj : -cj) : (k < n ? cj : -sj));
                 }
-                jm = in ? j : -1;
-            };
-            V ad = {zero, zero, zero, zero};
-            for (int s = 0; s < nk; ++s) {
-                T aop, g1, g2;
-                int jm;
-                operands(s, aop, g1, g2, jm);
-                ad = mfma16(aop, jm == i ? g1 : zero, ad);
             }
-            T rv[4], rd[4];
+            acc = mfma16(aop, b, acc);
+        }
+        return acc;
+    };
+    for (int mt = 0; mt < mtiles; ++mt) {
+        for (int kb = 0; kb < kblocks; ++kb) {
+            const int kbase = kb * kFpRowsKB;
+            const int kcount = n - kbase < kFpRowsKB ? n - kbase : kFpRowsKB;
+            const int ktiles = (kcount + 15) / 16;
+            const int rt_tasks = kb == 0 ? (gi_in_gk ? rtiles : 2 * rtiles) : 0;
+            // MFMA phase: the block's g columns, and (first block) the rows' h
+            // (and d) columns
+            __syncthreads();  // the previous phase has finished reading LDS
+            for (int t = wave; t < ktiles + rt_tasks; t += kFpRowsWaves) {
+                if (t < ktiles) {
+                    const V acc = tile(mt, kbase + 16 * t, false);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = mt * 16 + MfmaTile<T>::row(r, lg);
-                rv[r] = m < n ? (T)rvs[m] : zero;
-                rd[r] = -ad[r];
-            }
+                    for (int r = 0; r < 4; ++r) sh.gk[MfmaTile<T>::row(r, lg)][16 * t + li] = -acc[r];
+                } else {
+                    const int u = t - ktiles;
+                    const bool hcol = gi_in_gk || u >= rtiles;
+                    const int rt = u < rtiles ? u : u - rtiles;
+                    const V acc = tile(mt, r0 + 16 * rt, hcol);
 #pragma unroll
-            for (int lb = 0; lb < C; lb += LB) {
-                V ag[LB], ah[LB];
-#pragma unroll
-                for (int l = 0; l < LB; ++l) ag[l] = ah[l] = V{zero, zero, zero, zero};
-                for (int s = 0; s < nk; ++s) {
-                    T aop, g1, g2;
-                    int jm;
-                    operands(s, aop, g1, g2, jm);
-#pragma unroll
-                    for (int l = 0; l < LB; ++l) {
-                        const bool col = jm == cs + lb + l;
-                        ag[l] = mfma16(aop, col ? g1 : zero, ag[l]);
-                        ah[l] = mfma16(aop, (col && jm == i) ? g2 : zero, ah[l]);
+                    for (int r = 0; r < 4; ++r) {
+                        if (hcol)
+                            sh.hi[MfmaTile<T>::row(r, lg)][16 * rt + li] = -acc[r];
+                        else
+                            sh.gi[MfmaTile<T>::row(r, lg)][16 * rt + li] = -acc[r];
                     }
                 }
-                // second-order components of r_m * r_m for this lane's rows m
-                // (rows m >= n have rv = rd = rg = rh = 0 and add nothing)
+            }
+            __syncthreads();
+            // vector phase: every call whose chunk lies in this block takes the
+            // second-order components of r_m * r_m for the tile's residuals
+            const int mcount = n - mt * 16 < 16 ? n - mt * 16 : 16;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+            for (int q = 0; q < Q; ++q) {
+                const int i = ci[q], cs = ccs[q], il = i - r0;
+                if (cval[q] && cs / kFpRowsKB == kb) {
+                for (int mm = 0; mm < mcount; ++mm) {
+                    const T rd = gi_in_gk ? sh.gk[mm][i - kbase] : sh.gi[mm][il];
+                    const T* gm = &sh.gk[mm][cs - kbase];
 #pragma unroll
-                    for (int l = 0; l < LB; ++l) {
-                        const T rg = -ag[l][r], rh = -ah[l][r];
-                        fh[lb + l].add(rv[r] * rh + rd[r] * rg + rd[r] * rg + rv[r] * rh);
+                    for (int l = 0; l < C; ++l) {
+                        if (cs + l < n) {
+                            const T rg = gm[l];
+                            if (cs + l == i) {
+                                const T rv = (T)sh.rvs[mt * 16 + mm], rh = sh.hi[mm][il];
+                                fh[q][l].add(rv * rh + rd * rg + rd * rg + rv * rh);
+                            } else {
+                                fh[q][l].add(rd * rg + rd * rg);
+                            }
+                        }
                     }
+                }
                 }
             }
         }
-        T h[C];
-#pragma unroll
-        for (int l = 0; l < C; ++l) h[l] = fh[l].lane_total();
+    }
 
-        if (valid && lg == 0) {
-            if (kHess) {
-                double* row = a.out + p * n * n + (int64_t)i * n + cs;
+    // per call: store the Hessian chunk, or its dot with v
 #pragma unroll
-                for (int l = 0; l < C; ++l)
-                    if (cs + l < n) row[l] = (double)h[l];
-            } else {
-                typename P::Dot dot;
+    for (int q = 0; q < Q; ++q) {
+        const int i = ci[q], cs = ccs[q];
+        if (!cval[q]) {
+        } else if (kHess) {
+            double* row = a.out + p * n * n + (int64_t)i * n + cs;
 #pragma unroll
-                for (int l = 0; l < C; ++l)
-                    if (cs + l < n) dot.add(h[l], (T)vv[cs + l]);
-                dots[cl] = dot.get();
-            }
+            for (int l = 0; l < C; ++l)
+                if (cs + l < n) row[l] = (double)fh[q][l].value();
+        } else {
+            typename P::Dot dot;
+#pragma unroll
+            for (int l = 0; l < C; ++l)
+                if (cs + l < n) dot.add(fh[q][l].value(), (T)sh.vv[cs + l]);
+            sh.dots[threadIdx.x + q * blockDim.x] = dot.get();
         }
     }
     if (!kHess) {
         __syncthreads();
         for (int t = threadIdx.x; t < nrows; t += blockDim.x) {
-            double s = dots[t * nc];
-            for (int jc = 1; jc < nc; ++jc) s += dots[t * nc + jc];
+            double s = sh.dots[t * nc];
+            for (int jc = 1; jc < nc; ++jc) s += sh.dots[t * nc + jc];
             a.out[p * n + r0 + t] = s;
         }
     }
@@ -234,7 +260,7 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
 
 template <class P, int C, bool kHess>
 __global__ __launch_bounds__(64 * kFpRowsWaves) void fp_rows_kernel(FpRowsArgs a) {
-    __shared__ FpRowsShared sh;
+    __shared__ FpRowsShared<typename P::T> sh;
     fp_rows_block<P, C, kHess>(a, blockIdx.x, sh);
 }
 

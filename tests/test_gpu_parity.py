@@ -147,7 +147,8 @@ def test_fletcher_powell_psd_at_alpha(gpu_lib):
         assert np.linalg.eigvalsh(Hs).min() >= -1e-10 * np.abs(Hs).max()
 
 
-@pytest.mark.parametrize("func,n,c", [(R, 512, 16), (R, 512, 1), (A, 256, 8), (FP, 64, 16), (FP, 33, 4)])
+@pytest.mark.parametrize("func,n,c", [(R, 512, 16), (R, 512, 1), (A, 256, 8), (FP, 64, 16), (FP, 33, 4),
+                                      (FP, 512, 16), (FP, 300, 4)])
 def test_large_n(gpu_lib, func, n, c):
     npts = 3
     w = inputs.make_workload(func, n, npts, inputs.rng_for(4000 + n))
@@ -215,12 +216,12 @@ def test_fp_mfma_matches_vector_path(gpu_lib):
         assert e.max().item() <= 1e-14
 
 
-@pytest.mark.parametrize("n", [17, 24, 40, 64])
+@pytest.mark.parametrize("n", [17, 24, 40, 64, 130, 200])
 def test_fp_general_n_mfma(gpu_lib, n):
-    """n > 16: the Fletcher-Powell MFMA kernel with calls as matrix columns
-    (one point per workgroup, several m tiles), against the oracle and the
-    vector path, every chunk size, H.v and Hessian."""
-    npts = 9
+    """n > 16: the Fletcher-Powell MFMA kernel (row blocks of a point, shared
+    g columns per m tile, several variable blocks once n > 128), against the
+    oracle and the vector path, every chunk size, H.v and Hessian."""
+    npts = 9 if n <= 64 else 3
     w = inputs.make_workload(FP, n, npts, inputs.rng_for(8000 + n))
     E = _setup(gpu_lib, w)
     x, v = _dev(w.x), _dev(w.v)
