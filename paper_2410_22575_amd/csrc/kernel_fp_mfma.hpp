@@ -98,15 +98,57 @@ struct MfmaTile<float> {
     static CF_DEV int row(int r, int lg) { return 4 * lg + r; }
 };
 
+// Both members of each lane pair (l, l ^ 16) or (l, l ^ 32), from the gfx950
+// row swaps: v_permlane16_swap exchanges the odd 16-lane rows of its first
+// operand with the even rows of its second, v_permlane32_swap the upper half
+// of the first with the lower half of the second.  With both operands equal
+// to x, lane l gets x from the lower member of its pair in .first and from
+// the upper member in .second.
+template <int X>
+CF_DEV void lane_pair(unsigned x, unsigned& first, unsigned& second) {
+    if constexpr (X == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        first = r[0];
+        second = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        first = r[0];
+        second = r[1];
+    }
+}
+template <int X>
+CF_DEV double pair_sum(double h) {
+    unsigned l0, l1, h0, h1;
+    lane_pair<X>((unsigned)__double2loint(h), l0, l1);
+    lane_pair<X>((unsigned)__double2hiint(h), h0, h1);
+    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
+}
+template <int X>
+CF_DEV void pair_floats(float x, float& first, float& second) {
+    unsigned a, b;
+    lane_pair<X>(__float_as_uint(x), a, b);
+    first = __uint_as_float(a);
+    second = __uint_as_float(b);
+}
+
 // Sum over the residual rows of one lane and then across the four lane
-// groups: plain float64, or float32 with two-sum compensation.
+// groups: plain float64, or float32 with two-sum compensation.  Every lane
+// ends with the same total.
 CF_DEV double row_sum4(const double (&t)[4]) {
     double h = 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) h += t[r];
-    h += __shfl_xor(h, 16);
-    h += __shfl_xor(h, 32);
-    return h;
+    h = pair_sum<16>(h);
+    return pair_sum<32>(h);
+}
+template <int X>
+CF_DEV void pair_two_sum(float& hi, float& lo) {
+    float h0, h1, l0, l1, s, e;
+    pair_floats<X>(hi, h0, h1);
+    pair_floats<X>(lo, l0, l1);
+    two_sum(h0, h1, s, e);
+    hi = s;
+    lo = e + (l0 + l1);
 }
 CF_DEV float row_sum4(const float (&t)[4]) {
     float hi = t[0], lo = 0.0f;
@@ -117,14 +159,8 @@ CF_DEV float row_sum4(const float (&t)[4]) {
         hi = s;
         lo += e;
     }
-#pragma unroll
-    for (int x = 16; x <= 32; x *= 2) {
-        const float ohi = __shfl_xor(hi, x), olo = __shfl_xor(lo, x);
-        float s, e;
-        two_sum(hi, ohi, s, e);
-        hi = s;
-        lo += e + olo;
-    }
+    pair_two_sum<16>(hi, lo);
+    pair_two_sum<32>(hi, lo);
     return hi + lo;
 }
 
@@ -263,7 +299,8 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                     // surplus columns of a ragged last chunk are skipped
                     if (k < KMAX && k < n) {
                         // second-order component l of r * r for this lane's
-                        // rows, then summed over all residual rows
+                        // rows, then summed over all residual rows (independent
+                        // terms: a chain through one accumulator is slower)
                         T t[4];
                         if (k == i) {
 #pragma unroll
