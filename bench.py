@@ -440,6 +440,29 @@ def main():
         mixed[NAMES[f]] = {"chunk": mc, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                            "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
 
+    # the paper's three GPU mappings of H.v (Sec. VI) for the vector-ALU
+    # functions, outside the timed region: L0 one lane per point, L1 per
+    # row, L2 per (row, chunk) - the same sums in every case
+    mappings = {}
+    for f in (0, 1):
+        mo = torch.empty_like(xs[f])
+        res = {}
+        for level in (0, 1, 2):
+            prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, level)
+            try:
+                binding.chessfad_hvp(f, xs[f], vs[f], mo, chunk=chunks[f])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    binding.chessfad_hvp(f, xs[f], vs[f], mo, chunk=chunks[f])
+                e1.record()
+                torch.cuda.synchronize()
+            finally:
+                binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev)
+            ms = e0.elapsed_time(e1) / 3
+            res[f"L{level}"] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3)}
+        mappings[NAMES[f]] = {"chunk": chunks[f], **res}
+
     # the symmetric form (SC-HESS-VEC) on the same inputs, outside the timed
     # region: fewer f calls per point, the same H.v
     sym = {}
@@ -460,6 +483,19 @@ def main():
                          "max_rel_err_sampled": rel_err(f, so)}
     sym_step = sum(v["kernel_ms"] for v in sym.values())
     sym_total = {"kernel_ms_sum": round(sym_step, 4), "hvps_per_s": len(FUNCS) * npts / (sym_step * 1e-3)}
+
+    # Sec. V's chunk-size analysis against the autotuner: the multiplication
+    # count (6 + 3/c) n^2 M falls with c for the full form; the symmetric
+    # form's (3/2) n (2n + 2c + n/c + 1) M is smallest near sqrt(n / 2)
+    def sym_model_chunk(n):
+        best, bc = None, 1
+        for c in (1, 2, 4, 8, 16):
+            if c <= n and (best is None or 2 * c + n / c <= best):
+                best, bc = 2 * c + n / c, c
+        return bc
+    chunk_model = {NAMES[f]: {"full": {"model": max(c for c in (1, 2, 4, 8, 16) if c <= N), "tuned": chunks[f]},
+                              "symmetric": {"model": sym_model_chunk(N), "tuned": schunks[f] or None}}
+                   for f in FUNCS}
 
     result = {
         "metric": METRIC,
@@ -484,6 +520,8 @@ def main():
         "mixed_f32": mixed,
         "hessian_f64": hess,
         "symmetric_f64": {"per_function": sym, "all_three": sym_total},
+        "mappings_f64": mappings,
+        "chunk_model_vs_tuned": chunk_model,
     }
     result["autotuned_ms"] = tuned or None
     if not args.no_batch:

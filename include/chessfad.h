@@ -71,6 +71,22 @@ int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double
                  double* out, int chunk, void* stream);
 
 /*
+ * H.v together with the gradient and f (float64).  The calls that form H.v
+ * also carry f's value and first derivatives (Sec. III.B: the second and
+ * first hDual components), so the row's first call hands them out at no
+ * extra evaluation:
+ *   out  [npts][n]  as chessfad_hvp (the same result; when a row has a
+ *                   single chunk chessfad_hvp runs its L1 kernel, which may
+ *                   differ in the last bits)
+ *   grad [npts][n]  grad[p][i] = df/dx_i at x[p]  (required)
+ *   fval [npts]     f(x[p])  (may be NULL)
+ * grad and fval must not overlap x, v, out or each other (CHESSFAD_E_OVERLAP).
+ * Always the L2 mapping; otherwise as chessfad_hvp.
+ */
+int chessfad_hvp_grad(int func_id, int n, int64_t npts, const double* x, const double* v,
+                      double* out, double* grad, double* fval, int chunk, void* stream);
+
+/*
  * Full Hessians, plain float64 (CHUNK-HESS, Sec. III.B).
  *   x [npts][n]     points (read only)
  *   H [npts][n][n]  H[p][i][j] = d2f/dx_i dx_j at x[p]; every entry is
@@ -163,8 +179,21 @@ const char* chessfad_strerror(int code);
  *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
  *                         plan's captured hipGraph; 0: it launches the same
  *                         kernels directly on the stream.
+ *   CHESSFAD_OPT_MAPPING  the GPU mapping of chessfad_hvp (Sec. VI) where
+ *                         f runs on the vector ALUs (Rosenbrock, Ackley;
+ *                         Fletcher-Powell with CHESSFAD_OPT_FP_MFMA = 0):
+ *                         2 (default): L2, one lane per (point, row, chunk)
+ *                            (a row with a single chunk runs on the L1
+ *                            kernel, the same mapping then);
+ *                         1: L1, one lane per (point, row), walking its chunks;
+ *                         0: L0, one lane per point, walking rows and chunks.
+ *                         Every mapping computes the same sums in the same
+ *                         order (the compiler may contract multiply-adds
+ *                         differently in each kernel, so results can differ
+ *                         in the last bits).  Other entry points always use
+ *                         their own mapping.
  */
-enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1, CHESSFAD_OPT_BATCH_GRAPH = 2 };
+enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1, CHESSFAD_OPT_BATCH_GRAPH = 2, CHESSFAD_OPT_MAPPING = 3 };
 int chessfad_set_option(int option, int value);
 
 /*

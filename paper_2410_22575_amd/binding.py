@@ -45,12 +45,14 @@ SIGNATURES = {
     "chessfad_batch_info": (_i, [_p, _pi64, _pi, _pd]),
     "chessfad_autotune": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
     "chessfad_hvp_sym": (_i, [_i, _i, _i64, _p, _p, _p, _i, _i, _p]),
+    "chessfad_hvp_grad": (_i, [_i, _i, _i64, _p, _p, _p, _p, _p, _i, _p]),
     "chessfad_hessian_sym": (_i, [_i, _i, _i64, _p, _p, _i, _i, _p]),
     "chessfad_autotune_sym": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
 }
 
 CHESSFAD_OPT_FP_MFMA = 1
 CHESSFAD_OPT_BATCH_GRAPH = 2
+CHESSFAD_OPT_MAPPING = 3
 
 _lib = None
 
@@ -147,6 +149,20 @@ def chessfad_hessian_mixed(func_id: int, x: torch.Tensor, out: torch.Tensor | No
                            stream=None) -> torch.Tensor:
     """Hessians with float32 hDuals, compensated sums and float64 islands."""
     return _hessian("chessfad_hessian_mixed", func_id, x, out, chunk, stream)
+
+
+def chessfad_hvp_grad(func_id: int, x: torch.Tensor, v: torch.Tensor, chunk: int = 0, want_f: bool = True,
+                      stream=None):
+    """(H.v, gradient, f or None) from the same calls (float64)."""
+    _check_pts("x", x)
+    npts, n = x.shape
+    _check_pts("v", v, n)
+    out, grad = torch.empty_like(x), torch.empty_like(x)
+    fval = torch.empty(npts, dtype=torch.float64, device=x.device) if want_f else None
+    rc = load().chessfad_hvp_grad(func_id, n, npts, x.data_ptr(), v.data_ptr(), out.data_ptr(), grad.data_ptr(),
+                                  fval.data_ptr() if want_f else None, chunk, _stream(stream))
+    _raise(rc, "chessfad_hvp_grad")
+    return out, grad, fval
 
 
 def chessfad_hvp_sym(func_id: int, x: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None,

@@ -22,6 +22,7 @@ std::mutex g_tune_mu;
 int g_tuned[2][3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (form, func, precision, n); 0 = none
 int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
+int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
 }  // namespace
 
 namespace chessfad {
@@ -89,6 +90,7 @@ bool chunk_compiled(int c) {
 int option_value(int option) {
     if (option == CHESSFAD_OPT_FP_MFMA) return g_opt_fp_mfma;
     if (option == CHESSFAD_OPT_BATCH_GRAPH) return g_opt_batch_graph;
+    if (option == CHESSFAD_OPT_MAPPING) return g_opt_mapping;
     return CHESSFAD_E_ARG;
 }
 
@@ -190,10 +192,51 @@ PlainLaunch plain_table(int func_id, int C, bool hess, bool mixed) {
     }
 }
 
+CoarseLaunch coarse_table(int func_id, int C, int level) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return coarse_rosenbrock(C, level);
+        case CHESSFAD_ACKLEY: return coarse_ackley(C, level);
+        default: return coarse_fletcher_powell(C, level);
+    }
+}
+
 struct Geometry {
     int nc, rows, block, pstride;
     int64_t grid;
 };
+
+template <class F>
+size_t coarse_lds(int n, int ps) { return plain_lds_bytes<F64, F>(n, ps, 0, false); }
+
+size_t coarse_lds_for(int func_id, int n, int ps) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return coarse_lds<Rosenbrock>(n, ps);
+        case CHESSFAD_ACKLEY: return coarse_lds<Ackley>(n, ps);
+        default: return coarse_lds<FletcherPowell>(n, ps);
+    }
+}
+
+// L1: 256 lanes, one per row task.  L0: one lane per point, up to 64 points
+// per workgroup (fewer when their staging would pass 48 KiB of LDS).
+Geometry coarse_geometry(int func_id, int n, int64_t npts, int C, int level, size_t& lds) {
+    Geometry g;
+    g.nc = (n + C - 1) / C;
+    if (level == 1) {
+        g.rows = 256;
+        g.block = 256;
+        g.pstride = (g.rows - 1) / n + 2;
+    } else {
+        int pts = 64;
+        while (pts > 1 && coarse_lds_for(func_id, n, pts | 1) > 48 * 1024) pts /= 2;
+        g.rows = pts * n;
+        g.block = pts < 64 ? 64 : pts;
+        g.pstride = pts | 1;
+    }
+    lds = coarse_lds_for(func_id, n, g.pstride);
+    const int64_t nrows = npts * (int64_t)n;
+    g.grid = (nrows + g.rows - 1) / g.rows;
+    return g;
+}
 
 // Row tasks of nc lanes, about 256 lanes per workgroup (512 when one row
 // needs more).  With n <= 512 the LDS image stays below 45 KiB.
@@ -211,7 +254,7 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 }  // namespace
 
 int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-                         void* stream, bool hess, bool mixed, bool sym) {
+                         void* stream, bool hess, bool mixed, bool sym, double* grad, double* fval) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     const bool auto_chunk = chunk == 0;
@@ -223,6 +266,13 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     const size_t in_bytes = sizeof(double) * (size_t)npts * n;
     const size_t out_bytes = hess ? in_bytes * n : in_bytes;
     if (overlaps(out, out_bytes, x, in_bytes) || (!hess && overlaps(out, out_bytes, v, in_bytes)))
+        return CHESSFAD_E_OVERLAP;
+    const size_t f_bytes = sizeof(double) * (size_t)npts;
+    if (grad && (overlaps(grad, in_bytes, x, in_bytes) || overlaps(grad, in_bytes, v, in_bytes) ||
+                 overlaps(grad, in_bytes, out, out_bytes)))
+        return CHESSFAD_E_OVERLAP;
+    if (fval && (overlaps(fval, f_bytes, x, in_bytes) || overlaps(fval, f_bytes, v, in_bytes) ||
+                 overlaps(fval, f_bytes, out, out_bytes) || (grad && overlaps(fval, f_bytes, grad, in_bytes))))
         return CHESSFAD_E_OVERLAP;
     FpParams fp{nullptr, nullptr, nullptr};
     if (func_id == CHESSFAD_FLETCHER_POWELL) {
@@ -238,7 +288,7 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
         const int64_t grid = (npts + per_block - 1) / per_block;
         if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-        FpMfmaArgs a{x, v, out, fp, npts, n, nc};
+        FpMfmaArgs a{x, v, out, fp, npts, n, nc, grad, fval};
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
@@ -268,15 +318,29 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         const int row_blocks = (n + rows - 1) / rows;
         const int64_t grid = npts * row_blocks;
         if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-        FpRowsArgs a{x, v, out, fp, npts, n, nc, rows, row_blocks};
+        FpRowsArgs a{x, v, out, fp, npts, n, nc, rows, row_blocks, grad, fval};
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpRowsWaves), s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
+    // L0 / L1 when asked for; with one chunk per row L2 is L1, whose kernel
+    // needs fewer registers
+    const bool one_chunk = (n + chunk - 1) / chunk == 1;
+    if (!hess && !mixed && !grad && !fval && (g_opt_mapping != 2 || one_chunk)) {
+        const int level = g_opt_mapping == 2 ? 1 : g_opt_mapping;
+        size_t lds = 0;
+        const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, lds);
+        if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        CoarseLaunch launch = coarse_table(func_id, chunk, level);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
+        hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), lds, s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
     const Geometry g = plain_geometry(n, npts, chunk);
     if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
     PlainLaunch launch = plain_table(func_id, chunk, hess, mixed);
     if (!launch) return CHESSFAD_E_CHUNK;
-    PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
+    PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride, grad, fval};
     hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), s);
     return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
 }
@@ -300,6 +364,12 @@ int chessfad_hvp_mixed(int func_id, int n, int64_t npts, const double* x, const 
 int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, double* H, int chunk,
                            void* stream) {
     return run_single(func_id, n, npts, x, nullptr, H, chunk, stream, true, true);
+}
+
+int chessfad_hvp_grad(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, double* grad,
+                      double* fval, int chunk, void* stream) {
+    if (npts > 0 && !grad) return CHESSFAD_E_NULL;
+    return run_single(func_id, n, npts, x, v, out, chunk, stream, false, false, false, grad, fval);
 }
 
 int chessfad_hvp_sym(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
@@ -371,8 +441,10 @@ const char* chessfad_strerror(int code) {
 
 int chessfad_set_option(int option, int value) {
     int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
-              : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph : nullptr;
-    if (!slot || (value != 0 && value != 1)) return CHESSFAD_E_ARG;
+              : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
+              : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping : nullptr;
+    const int maxv = option == CHESSFAD_OPT_MAPPING ? 2 : 1;
+    if (!slot || value < 0 || value > maxv) return CHESSFAD_E_ARG;
     const int prev = *slot;
     *slot = value;
     return prev;

@@ -35,6 +35,31 @@ PlainLaunch plain_entry(int C) {
     }
 }
 
+using CoarseLaunch = hipError_t (*)(const PlainArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
+
+template <class P, class F, int C, int kLevel>
+hipError_t launch_coarse(const PlainArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((coarse_kernel<P, F, C, kLevel>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class P, class F, int kLevel>
+CoarseLaunch coarse_entry(int C) {
+    switch (C) {
+        case 1: return &launch_coarse<P, F, 1, kLevel>;
+        case 2: return &launch_coarse<P, F, 2, kLevel>;
+        case 4: return &launch_coarse<P, F, 4, kLevel>;
+        case 8: return &launch_coarse<P, F, 8, kLevel>;
+        case 16: return &launch_coarse<P, F, 16, kLevel>;
+        default: return nullptr;
+    }
+}
+
+// The coarser L0 / L1 mappings (float64 H.v), one per function.
+CoarseLaunch coarse_rosenbrock(int C, int level);
+CoarseLaunch coarse_ackley(int C, int level);
+CoarseLaunch coarse_fletcher_powell(int C, int level);
+
 using FpMfmaLaunch = hipError_t (*)(const FpMfmaArgs&, dim3 grid, dim3 block, hipStream_t);
 
 template <class P, int C, int NK, bool kHess, bool kSym>

@@ -1,10 +1,14 @@
-// Ackley: float64, every compiled chunk size, H.v and Hessian.
+// Ackley: float64, every compiled chunk size, H.v and Hessian; the L0 / L1 mappings of H.v.
 #include "dispatch.hpp"
 
 namespace chessfad {
 
 PlainLaunch plain_ackley(int C, bool hess) {
     return hess ? plain_entry<F64, Ackley, true>(C) : plain_entry<F64, Ackley, false>(C);
+}
+
+CoarseLaunch coarse_ackley(int C, int level) {
+    return level == 0 ? coarse_entry<F64, Ackley, 0>(C) : coarse_entry<F64, Ackley, 1>(C);
 }
 
 }  // namespace chessfad

@@ -1,10 +1,14 @@
-// Rosenbrock: float64, every compiled chunk size, H.v and Hessian.
+// Rosenbrock: float64, every compiled chunk size, H.v and Hessian; the L0 / L1 mappings of H.v.
 #include "dispatch.hpp"
 
 namespace chessfad {
 
 PlainLaunch plain_rosenbrock(int C, bool hess) {
     return hess ? plain_entry<F64, Rosenbrock, true>(C) : plain_entry<F64, Rosenbrock, false>(C);
+}
+
+CoarseLaunch coarse_rosenbrock(int C, int level) {
+    return level == 0 ? coarse_entry<F64, Rosenbrock, 0>(C) : coarse_entry<F64, Rosenbrock, 1>(C);
 }
 
 }  // namespace chessfad

@@ -74,6 +74,8 @@ struct FpMfmaArgs {
     int64_t npts;
     int n;              // <= 16
     int nc;             // chunks per row
+    double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
+    double* fval = nullptr;  // H.v only, optional: [npts] f
 };
 
 constexpr int kFpMaxN = 16;
@@ -283,6 +285,20 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         for (int r = 0; r < 4; ++r) {
             rd[r] = -dd[r];
             rh[r] = -ah[r];
+        }
+        if (!kHess && !kSym && (a.grad || a.fval)) {
+            // first-order (and, once, value) component of f = sum_m r_m * r_m
+            T t[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[r] = rv[r] * rd[r] + rd[r] * rv[r];
+            const T gd = row_sum4(t);
+            if (a.grad && live && lg == 0) a.grad[p * n + i] = (double)gd;
+            if (a.fval && i == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) t[r] = rv[r] * rv[r];
+                const T fv = row_sum4(t);
+                if (live && lg == 0) a.fval[p] = (double)fv;
+            }
         }
 
         double row = 0.0;

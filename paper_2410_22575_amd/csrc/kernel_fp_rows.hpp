@@ -42,6 +42,8 @@ struct FpRowsArgs {
     int nc;             // chunks per row
     int rows;           // rows per workgroup, fp_rows_per_block(n, nc)
     int row_blocks;     // workgroups per point, ceil(n / rows)
+    double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
+    double* fval = nullptr;  // H.v only, optional: [npts] f
 };
 
 constexpr int kFpRowsMaxN = 512;
@@ -128,6 +130,15 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
         }
         sh.rvs[m] = a.fp.E[m] - acc;
     }
+    if (!kHess && a.fval && r0 == 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // the value component of f = sum_m r_m * r_m, in order
+            double f = sh.rvs[0] * sh.rvs[0];
+            for (int m = 1; m < n; ++m) f += sh.rvs[m] * sh.rvs[m];
+            a.fval[p] = f;
+        }
+    }
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -150,6 +161,8 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
         ccs[q] = cval[q] ? (cl - rr * nc) * C : 0;
     }
     RunSum<T> fh[Q][C];
+    RunSum<T> fd[Q];  // first-order component (row's first chunk, when asked for)
+    const bool want_grad = !kHess && a.grad != nullptr;
 
     // -r_m components of S columns col0 .. col0 + 15 (variables or rows) for
     // the residual rows of m tile mt: the g/d column (h = false) or the h
@@ -212,6 +225,10 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
                 for (int mm = 0; mm < mcount; ++mm) {
                     const T rd = gi_in_gk ? sh.gk[mm][i - kbase] : sh.gi[mm][il];
                     const T* gm = &sh.gk[mm][cs - kbase];
+                    if (want_grad && cs == 0) {
+                        const T rv = (T)sh.rvs[mt * 16 + mm];
+                        fd[q].add(rv * rd + rd * rv);
+                    }
 #pragma unroll
                     for (int l = 0; l < C; ++l) {
                         if (cs + l < n) {
@@ -246,6 +263,7 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
             for (int l = 0; l < C; ++l)
                 if (cs + l < n) dot.add(fh[q][l].value(), (T)sh.vv[cs + l]);
             sh.dots[threadIdx.x + q * blockDim.x] = dot.get();
+            if (want_grad && cs == 0) a.grad[p * n + i] = (double)fd[q].value();
         }
     }
     if (!kHess) {

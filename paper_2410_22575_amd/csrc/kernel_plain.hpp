@@ -14,6 +14,8 @@
 //   4. Hessian: writes H[p][i][cs .. cs + C) (columns < n only, CHUNK-HESS);
 //      H.v: dots its Hessian chunk with v[p][cs .. cs + C), then the row's
 //      nc partial sums are added in chunk order in float64 (CHESS-VEC).
+// coarse_kernel runs the paper's coarser mappings L1 and L0 on the same
+// staging, for comparison.
 #pragma once
 
 #include <stdint.h>
@@ -32,6 +34,8 @@ struct PlainArgs {
     int nc;             // chunks per row, ceil(n / C)
     int rows;           // row tasks per workgroup; blockDim.x == rows * nc
     int pstride;        // LDS stride between entries of one point (>= points per workgroup)
+    double* grad = nullptr;  // H.v only, optional: [npts][n] gradient (row i's d component)
+    double* fval = nullptr;  // H.v only, optional: [npts] f (the value component)
 };
 
 constexpr int kMaxBlock = 512;
@@ -44,6 +48,54 @@ __host__ __device__ inline size_t plain_lds_bytes(int n, int pstride, int block,
     const size_t dbl = (size_t)block + (F::kTables ? 2 * (size_t)n * pstride : 0);
     const size_t tt = (size_t)n * pstride * (hess ? 1 : 2) + (size_t)F::isl_size(n) * pstride;
     return dbl * sizeof(double) + tt * sizeof(T);
+}
+
+// The points a workgroup touches, staged in LDS (layout of plain_lds_bytes).
+template <typename T>
+struct PlainStage {
+    double* red;
+    double* t0;
+    double* t1;
+    T* xs;
+    T* vs;
+    T* isl;
+};
+
+// Steps 1 and 2 for the points p0 .. p0 + npb - 1: coordinates (and vectors)
+// as structure-of-arrays with the per-coordinate tables, then the per-point
+// float64 islands.  `nthr` doubles of reduction space come first.
+template <class P, class F, bool kHess>
+__device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs& a, int64_t p0, int npb, int nthr,
+                                                                 double* lds) {
+    using T = typename P::T;
+    const int n = a.n, ps = a.pstride;
+    PlainStage<T> st;
+    st.red = lds;
+    st.t0 = st.red + nthr;
+    st.t1 = st.t0 + (F::kTables ? n * ps : 0);
+    st.xs = reinterpret_cast<T*>(st.t1 + (F::kTables ? n * ps : 0));
+    st.vs = st.xs + n * ps;
+    st.isl = st.vs + (kHess ? 0 : n * ps);
+
+    const double* xg = a.x + p0 * n;
+    const double* vg = a.v + p0 * n;
+    for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
+        const int pl = idx / n, k = idx - pl * n;
+        const double xv = xg[idx];
+        st.xs[k * ps + pl] = (T)xv;
+        if (!kHess) st.vs[k * ps + pl] = (T)vg[idx];
+        if (F::kTables) F::tables(xv, st.t0[k * ps + pl], st.t1[k * ps + pl]);
+    }
+    __syncthreads();
+    const int tasks = F::isl_tasks(n);
+    if (tasks) {
+        for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
+            const int pl = idx / tasks, task = idx - pl * tasks;
+            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl, st.t1 + pl, ps, a.fp, st.isl + pl);
+        }
+        __syncthreads();
+    }
+    return st;
 }
 
 // One workgroup's share of the launch: row tasks [blk * rows, blk * rows + rows).
@@ -60,33 +112,8 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     const int64_t p0 = q0 / n;
     const int npb = (int)(qlast / n - p0 + 1);  // points touched by this workgroup
 
-    double* red = lds;
-    double* t0 = red + nthr;
-    double* t1 = t0 + (F::kTables ? n * ps : 0);
-    T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? n * ps : 0));
-    T* vs = xs + n * ps;
-    T* isl = vs + (kHess ? 0 : n * ps);
-
-    // 1. stage coordinates (contiguous in global memory) into SoA LDS
-    const double* xg = a.x + p0 * n;
-    const double* vg = a.v + p0 * n;
-    for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
-        const int pl = idx / n, k = idx - pl * n;
-        const double xv = xg[idx];
-        xs[k * ps + pl] = (T)xv;
-        if (!kHess) vs[k * ps + pl] = (T)vg[idx];
-        if (F::kTables) F::tables(xv, t0[k * ps + pl], t1[k * ps + pl]);
-    }
-    __syncthreads();
-    // 2. per-point float64 island values
-    const int tasks = F::isl_tasks(n);
-    if (tasks) {
-        for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
-            const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, t0 + pl, t1 + pl, ps, a.fp, isl + pl);
-        }
-        __syncthreads();
-    }
+    // 1-2. staging and islands
+    const PlainStage<T> st = plain_stage<P, F, kHess>(a, p0, npb, nthr, lds);
 
     const int r = threadIdx.x / nc;
     const int j = threadIdx.x - r * nc;
@@ -99,7 +126,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
 
     double dot = 0.0;
     if (active) {
-        PointView<T> pv{xs + pl, t0 + pl, t1 + pl, isl + pl, ps, n, i, cs};
+        PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
         // 3. one f evaluation on hDual<C> seeds
         const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
         if (kHess) {
@@ -113,20 +140,74 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
             typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)
-                if (cs + l < n) acc.add(res.h[l], vs[(cs + l) * ps + pl]);
+                if (cs + l < n) acc.add(res.h[l], st.vs[(cs + l) * ps + pl]);
             dot = acc.get();
+            // the first-order and value components of the same call
+            if (a.grad && j == 0) a.grad[q] = (double)res.d;
+            if (a.fval && j == 0 && i == 0) a.fval[p] = (double)res.v;
         }
     }
     if (!kHess) {
-        // row sum over the nc chunk lanes, in chunk order
-        if (threadIdx.x < nthr) red[threadIdx.x] = dot;
-        __syncthreads();
-        if (active && j == 0) {
-            double s = red[threadIdx.x];
-            for (int k = 1; k < nc; ++k) s += red[threadIdx.x + k];
-            a.out[q] = s;
+        if (nc == 1) {
+            // one chunk per row: the lane holds the row's whole sum
+            if (active) a.out[q] = dot;
+        } else {
+            // row sum over the nc chunk lanes, in chunk order
+            if (threadIdx.x < nthr) st.red[threadIdx.x] = dot;
+            __syncthreads();
+            if (active && j == 0) {
+                double s = st.red[threadIdx.x];
+                for (int k = 1; k < nc; ++k) s += st.red[threadIdx.x + k];
+                a.out[q] = s;
+            }
         }
     }
+}
+
+// The paper's coarser GPU mappings of CHESS-VEC (Sec. VI), H.v only:
+//   L1 (kLevel = 1): one lane per (point, row); it walks the row's chunks in
+//                    order and keeps the row sum;
+//   L0 (kLevel = 0): one lane per point; it walks every row and chunk.
+// The workgroup stages its points as plain_block does; `rows` row tasks per
+// workgroup (L0: a multiple of n, so the workgroup owns whole points).
+template <class P, class F, int C, int kLevel>
+__device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, double* lds) {
+    using T = typename P::T;
+    const int n = a.n, nc = a.nc, ps = a.pstride;
+    const int64_t nrows = a.npts * (int64_t)n;
+    const int64_t q0 = blk * a.rows;
+    const int64_t qlast = (q0 + a.rows < nrows ? q0 + a.rows : nrows) - 1;
+    const int64_t p0 = q0 / n;
+    const int npb = (int)(qlast / n - p0 + 1);
+    const PlainStage<T> st = plain_stage<P, F, false>(a, p0, npb, 0, lds);
+
+    // the rows this lane walks: L1 one, L0 all n of its point
+    const int64_t qa = kLevel == 1 ? q0 + threadIdx.x : (p0 + threadIdx.x) * n;
+    const int64_t qb = kLevel == 1 ? qa + 1 : qa + n;
+    if (threadIdx.x >= (kLevel == 1 ? a.rows : a.rows / n) || qa > qlast) return;
+    for (int64_t q = qa; q < qb; ++q) {
+        const int64_t p = q / n;
+        const int i = (int)(q - p * n);
+        const int pl = (int)(p - p0);
+        double res = 0.0;
+        for (int j = 0; j < nc; ++j) {
+            const int cs = j * C;
+            PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
+            const HD<T, C> h = F::template eval<P, C>(pv, a.fp);
+            typename P::Dot acc;
+#pragma unroll
+            for (int l = 0; l < C; ++l)
+                if (cs + l < n) acc.add(h.h[l], st.vs[(cs + l) * ps + pl]);
+            res += acc.get();
+        }
+        a.out[q] = res;
+    }
+}
+
+template <class P, class F, int C, int kLevel>
+__global__ __launch_bounds__(kMaxBlock) void coarse_kernel(PlainArgs a) {
+    extern __shared__ double lds[];
+    coarse_block<P, F, C, kLevel>(a, blockIdx.x, lds);
 }
 
 template <class P, class F, int C, bool kHess>

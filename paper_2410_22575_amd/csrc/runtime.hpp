@@ -22,8 +22,10 @@ void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym =
 // Single-instance launch shared by chessfad_hvp / _hessian / _mixed / _sym.
 // With chunk == 0 and sym, a chunk whose symmetric workgroup would not fit
 // in LDS is replaced by the next larger one that fits.
+// grad / fval (H.v, float64, full form only) receive the gradient and f.
 int run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-               void* stream, bool hess, bool mixed, bool sym = false);
+               void* stream, bool hess, bool mixed, bool sym = false, double* grad = nullptr,
+               double* fval = nullptr);
 
 // Paper-model flops of one f call (Sec. V operation counts, chunk dot included).
 double model_flops_per_call(int func_id, int n, int C);

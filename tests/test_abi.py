@@ -117,6 +117,28 @@ def test_symmetric_argument_checks(lib):
     assert lib.chessfad_autotune_sym(A, 16, 2, 100, None, None, None) == E_ARG
 
 
+def test_hvp_grad_argument_checks(lib):
+    n, npts = 16, 10
+    nbytes = 8 * n * npts
+    call = lambda grad, fval, out=FAKE * 4: lib.chessfad_hvp_grad(R, n, npts, FAKE, FAKE * 2, out, grad, fval, 4, None)
+    assert call(None, None) == E_NULL
+    assert call(FAKE * 4 + 8, None) == E_OVERLAP                     # grad inside out
+    assert call(FAKE * 8, FAKE * 8 + nbytes - 8) == E_OVERLAP         # fval inside grad
+    assert call(FAKE * 8, FAKE * 2 + 16) == E_OVERLAP                 # fval inside v
+    assert lib.chessfad_hvp_grad(R, n, 0, None, None, None, None, None, 4, None) == OK
+    assert lib.chessfad_hvp_grad(R, n, npts, FAKE, FAKE * 2, FAKE * 4, FAKE * 8, None, 3, None) == E_CHUNK
+
+
+def test_options(lib):
+    assert lib.chessfad_set_option(99, 0) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 2) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 3) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, -1) == E_ARG
+    prev = lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 0)
+    assert prev == 2
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev) == 0
+
+
 def test_default_chunk(lib):
     assert lib.chessfad_default_chunk(R, 16) in (1, 2, 4, 8, 16)
     assert lib.chessfad_default_chunk(A, 1) == 1

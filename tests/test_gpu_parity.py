@@ -237,3 +237,60 @@ def test_fp_general_n_mfma(gpu_lib, n):
         with fp_path(gpu_lib, 0):
             H0 = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
         assert np.max(np.abs(H - H0).max(axis=(1, 2)) / hmax) <= 1e-14
+
+
+@pytest.mark.parametrize("func", [R, A, FP])
+def test_coarse_mappings_match_l2(gpu_lib, func):
+    """The paper's L0 and L1 mappings (one lane per point / per row) compute
+    the same sums in the same order as L2; only the compiler's multiply-add
+    contraction may differ between the kernels, so H.v agrees to a few units
+    of rounding.  FP runs on its vector path here."""
+    prev_map = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 2)
+    try:
+        with fp_path(gpu_lib, 0 if func == FP else None):
+            for n, npts in ((5, 70), (16, 300), (33, 9)):
+                w = inputs.make_workload(func, n, npts, inputs.rng_for(8500 + 10 * func + n))
+                E = _setup(gpu_lib, w)
+                x, v = _dev(w.x), _dev(w.v)
+                r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+                _, hmax = _hmax(func, w, E)
+                for c in (1, 4, 16):
+                    if c > n:
+                        continue
+                    gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 2)
+                    r2 = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+                    for level in (1, 0):
+                        print(f"[case] mapping L{level} func={func} n={n} C={c}", flush=True)
+                        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, level)
+                        r = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+                        assert np.max(_hvp_err(r, r2, hmax, w.v)) <= 1e-14
+                    assert np.max(_hvp_err(r2, r_ref, hmax, w.v)) <= TOL64
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev_map)
+
+
+@pytest.mark.parametrize("func,mfma", FUNC_PATHS)
+@pytest.mark.parametrize("n", [2, 5, 16, 40])
+def test_hvp_with_gradient_and_value(gpu_lib, func, mfma, n):
+    """chessfad_hvp_grad: the same H.v bit for bit, plus the gradient and f
+    from the same calls, against the closed forms."""
+    npts = 150
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(8700 + 10 * func + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    g_ref = cf.grad(func, w.x, w.A, w.B, E)
+    f_ref = cf.f(func, w.x, w.A, w.B, E)
+    with fp_path(gpu_lib, mfma):
+        for c in (1, 4):
+            if c > n:
+                continue
+            print(f"[case] hvp+grad func={func} mfma={mfma} n={n} C={c}", flush=True)
+            out, g, f = gpu_lib.chessfad_hvp_grad(func, x, v, chunk=c)
+            np.testing.assert_array_equal(out.cpu().numpy(), gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy())
+            g, f = g.cpu().numpy(), f.cpu().numpy()
+            gscale = np.maximum(1.0, np.abs(g_ref).max(axis=1))
+            assert np.max(np.abs(g - g_ref).max(axis=1) / gscale) <= TOL64
+            assert np.max(np.abs(f - f_ref) / np.maximum(1.0, np.abs(f_ref))) <= TOL64
+            _, g2, f2 = gpu_lib.chessfad_hvp_grad(func, x, v, chunk=c, want_f=False)
+            assert f2 is None
+            np.testing.assert_array_equal(g2.cpu().numpy(), g)
