@@ -75,9 +75,9 @@ int chessfad_hvp(int func_id, int n, int64_t npts, const double* x, const double
  * also carry f's value and first derivatives (Sec. III.B: the second and
  * first hDual components), so the row's first call hands them out at no
  * extra evaluation:
- *   out  [npts][n]  as chessfad_hvp (the same result; when a row has a
- *                   single chunk chessfad_hvp runs its L1 kernel, which may
- *                   differ in the last bits)
+ *   out  [npts][n]  H.v as chessfad_hvp computes it (the vector-ALU
+ *                   functions run a separate instantiation of the kernel, so
+ *                   the last bits may differ)
  *   grad [npts][n]  grad[p][i] = df/dx_i at x[p]  (required)
  *   fval [npts]     f(x[p])  (may be NULL)
  * grad and fval must not overlap x, v, out or each other (CHESSFAD_E_OVERLAP).

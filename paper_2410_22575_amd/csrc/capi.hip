@@ -192,6 +192,14 @@ PlainLaunch plain_table(int func_id, int C, bool hess, bool mixed) {
     }
 }
 
+PlainLaunch grad_table(int func_id, int C) {
+    switch (func_id) {
+        case CHESSFAD_ROSENBROCK: return grad_rosenbrock(C);
+        case CHESSFAD_ACKLEY: return grad_ackley(C);
+        default: return grad_fletcher_powell(C);
+    }
+}
+
 CoarseLaunch coarse_table(int func_id, int C, int level) {
     switch (func_id) {
         case CHESSFAD_ROSENBROCK: return coarse_rosenbrock(C, level);
@@ -338,7 +346,7 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     }
     const Geometry g = plain_geometry(n, npts, chunk);
     if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-    PlainLaunch launch = plain_table(func_id, chunk, hess, mixed);
+    PlainLaunch launch = grad ? grad_table(func_id, chunk) : plain_table(func_id, chunk, hess, mixed);
     if (!launch) return CHESSFAD_E_CHUNK;
     PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride, grad, fval};
     hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), s);

@@ -16,21 +16,21 @@ using PlainLaunch = hipError_t (*)(const PlainArgs&, dim3 grid, dim3 block, hipS
 constexpr int kChunks[] = {1, 2, 4, 8, 16};
 constexpr int kNumChunks = sizeof(kChunks) / sizeof(kChunks[0]);
 
-template <class P, class F, int C, bool kHess>
+template <class P, class F, int C, bool kHess, bool kGrad>
 hipError_t launch_plain(const PlainArgs& a, dim3 grid, dim3 block, hipStream_t s) {
     const size_t lds = plain_lds_bytes<P, F>(a.n, a.pstride, (int)block.x, kHess);
-    hipLaunchKernelGGL((plain_kernel<P, F, C, kHess>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((plain_kernel<P, F, C, kHess, kGrad>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
-template <class P, class F, bool kHess>
+template <class P, class F, bool kHess, bool kGrad = false>
 PlainLaunch plain_entry(int C) {
     switch (C) {
-        case 1: return &launch_plain<P, F, 1, kHess>;
-        case 2: return &launch_plain<P, F, 2, kHess>;
-        case 4: return &launch_plain<P, F, 4, kHess>;
-        case 8: return &launch_plain<P, F, 8, kHess>;
-        case 16: return &launch_plain<P, F, 16, kHess>;
+        case 1: return &launch_plain<P, F, 1, kHess, kGrad>;
+        case 2: return &launch_plain<P, F, 2, kHess, kGrad>;
+        case 4: return &launch_plain<P, F, 4, kHess, kGrad>;
+        case 8: return &launch_plain<P, F, 8, kHess, kGrad>;
+        case 16: return &launch_plain<P, F, 16, kHess, kGrad>;
         default: return nullptr;
     }
 }
@@ -54,6 +54,11 @@ CoarseLaunch coarse_entry(int C) {
         default: return nullptr;
     }
 }
+
+// float64 H.v that also stores the gradient and f, one per function.
+PlainLaunch grad_rosenbrock(int C);
+PlainLaunch grad_ackley(int C);
+PlainLaunch grad_fletcher_powell(int C);
 
 // The coarser L0 / L1 mappings (float64 H.v), one per function.
 CoarseLaunch coarse_rosenbrock(int C, int level);

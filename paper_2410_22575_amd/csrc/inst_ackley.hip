@@ -1,4 +1,4 @@
-// Ackley: float64, every compiled chunk size, H.v and Hessian; the L0 / L1 mappings of H.v.
+// Ackley: float64, every compiled chunk size, H.v (also with the gradient) and Hessian; the L0 / L1 mappings of H.v.
 #include "dispatch.hpp"
 
 namespace chessfad {
@@ -6,6 +6,8 @@ namespace chessfad {
 PlainLaunch plain_ackley(int C, bool hess) {
     return hess ? plain_entry<F64, Ackley, true>(C) : plain_entry<F64, Ackley, false>(C);
 }
+
+PlainLaunch grad_ackley(int C) { return plain_entry<F64, Ackley, false, true>(C); }
 
 CoarseLaunch coarse_ackley(int C, int level) {
     return level == 0 ? coarse_entry<F64, Ackley, 0>(C) : coarse_entry<F64, Ackley, 1>(C);

@@ -34,8 +34,8 @@ struct PlainArgs {
     int nc;             // chunks per row, ceil(n / C)
     int rows;           // row tasks per workgroup; blockDim.x == rows * nc
     int pstride;        // LDS stride between entries of one point (>= points per workgroup)
-    double* grad = nullptr;  // H.v only, optional: [npts][n] gradient (row i's d component)
-    double* fval = nullptr;  // H.v only, optional: [npts] f (the value component)
+    double* grad = nullptr;  // kGrad kernels: [npts][n] gradient (row i's d component)
+    double* fval = nullptr;  // kGrad kernels, optional: [npts] f (the value component)
 };
 
 constexpr int kMaxBlock = 512;
@@ -101,7 +101,9 @@ __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs
 // One workgroup's share of the launch: row tasks [blk * rows, blk * rows + rows).
 // Uses the first rows * nc threads; any further threads of the workgroup
 // only take part in the barriers.  `lds` holds plain_lds_bytes() bytes.
-template <class P, class F, int C, bool kHess>
+// kGrad (H.v only) also stores the gradient and f (a.grad, a.fval); it is a
+// separate instantiation so that plain H.v keeps its register allocation.
+template <class P, class F, int C, bool kHess, bool kGrad = false>
 __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, double* lds) {
     using T = typename P::T;
     const int n = a.n, nc = a.nc, ps = a.pstride;
@@ -143,8 +145,10 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
                 if (cs + l < n) acc.add(res.h[l], st.vs[(cs + l) * ps + pl]);
             dot = acc.get();
             // the first-order and value components of the same call
-            if (a.grad && j == 0) a.grad[q] = (double)res.d;
-            if (a.fval && j == 0 && i == 0) a.fval[p] = (double)res.v;
+            if (kGrad && j == 0) {
+                a.grad[q] = (double)res.d;
+                if (a.fval && i == 0) a.fval[p] = (double)res.v;
+            }
         }
     }
     if (!kHess) {
@@ -210,10 +214,10 @@ __global__ __launch_bounds__(kMaxBlock) void coarse_kernel(PlainArgs a) {
     coarse_block<P, F, C, kLevel>(a, blockIdx.x, lds);
 }
 
-template <class P, class F, int C, bool kHess>
+template <class P, class F, int C, bool kHess, bool kGrad>
 __global__ __launch_bounds__(kMaxBlock) void plain_kernel(PlainArgs a) {
     extern __shared__ double lds[];
-    plain_block<P, F, C, kHess>(a, blockIdx.x, lds);
+    plain_block<P, F, C, kHess, kGrad>(a, blockIdx.x, lds);
 }
 
 }  // namespace chessfad

@@ -272,8 +272,8 @@ def test_coarse_mappings_match_l2(gpu_lib, func):
 @pytest.mark.parametrize("func,mfma", FUNC_PATHS)
 @pytest.mark.parametrize("n", [2, 5, 16, 40])
 def test_hvp_with_gradient_and_value(gpu_lib, func, mfma, n):
-    """chessfad_hvp_grad: the same H.v bit for bit, plus the gradient and f
-    from the same calls, against the closed forms."""
+    """chessfad_hvp_grad: the same H.v (to rounding), plus the gradient and
+    f from the same calls, against the closed forms."""
     npts = 150
     w = inputs.make_workload(func, n, npts, inputs.rng_for(8700 + 10 * func + n))
     E = _setup(gpu_lib, w)
@@ -286,7 +286,9 @@ def test_hvp_with_gradient_and_value(gpu_lib, func, mfma, n):
                 continue
             print(f"[case] hvp+grad func={func} mfma={mfma} n={n} C={c}", flush=True)
             out, g, f = gpu_lib.chessfad_hvp_grad(func, x, v, chunk=c)
-            np.testing.assert_array_equal(out.cpu().numpy(), gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy())
+            r = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+            _, hmax = _hmax(func, w, E)
+            assert np.max(_hvp_err(out.cpu().numpy(), r, hmax, w.v)) <= 1e-14
             g, f = g.cpu().numpy(), f.cpu().numpy()
             gscale = np.maximum(1.0, np.abs(g_ref).max(axis=1))
             assert np.max(np.abs(g - g_ref).max(axis=1) / gscale) <= TOL64
