@@ -35,16 +35,21 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
+    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0284e+08,
+    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0309e+08,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0308e+08,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0307e+08,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0307e+08,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0307e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
-    "plain_kernel<ackley, C=2, H.v>": 4.0279e+08,
-    "plain_kernel<ackley, C=4, H.v>": 4.0280e+08,
+    "plain_kernel<ackley, C=2, H.v>": 4.0280e+08,
+    "plain_kernel<ackley, C=4, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=8, H.v>": 4.0281e+08,
-    "plain_kernel<ackley, C=16, H.v>": 4.0284e+08,
     "plain_kernel<rosenbrock, C=1, H.v>": 4.0275e+08,
     "plain_kernel<rosenbrock, C=2, H.v>": 4.0274e+08,
     "plain_kernel<rosenbrock, C=4, H.v>": 4.0275e+08,
     "plain_kernel<rosenbrock, C=8, H.v>": 4.0275e+08,
-    "plain_kernel<rosenbrock, C=16, H.v>": 4.0277e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -53,22 +58,29 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
+    "coarse_kernel<ackley, C=16, L1, H.v>": 4.9421e+10,
+    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 5.8754e+10,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 2.0581e+10,
     "plain_kernel<ackley, C=1, H.v>": 9.7039e+10,
     "plain_kernel<ackley, C=2, H.v>": 6.7713e+10,
     "plain_kernel<ackley, C=4, H.v>": 5.7949e+10,
     "plain_kernel<ackley, C=8, H.v>": 5.2219e+10,
-    "plain_kernel<ackley, C=16, H.v>": 4.9405e+10,
     "plain_kernel<rosenbrock, C=1, H.v>": 8.4826e+10,
     "plain_kernel<rosenbrock, C=2, H.v>": 6.7646e+10,
     "plain_kernel<rosenbrock, C=4, H.v>": 5.7915e+10,
     "plain_kernel<rosenbrock, C=8, H.v>": 6.0633e+10,
-    "plain_kernel<rosenbrock, C=16, H.v>": 5.8754e+10,
 }
 
 
-def kernel_key(f, c, n=N):
+def kernel_key(f, c, n=N, mapping=2):
+    """The kernel chessfad_hvp runs for (function, chunk, mapping) at n, as
+    keyed in the measured tables: the n <= 16 Fletcher-Powell MFMA kernel,
+    the L1 kernel when a row has a single chunk or L1 was chosen, else the
+    L2 vector kernel."""
     if f == 2 and n <= 16:
         return f"fp_mfma_kernel<C={c}, NK={min(8, max(1, (2 * n + 3) // 4))}, H.v>"
+    if c >= n or mapping == 1:
+        return f"coarse_kernel<{NAMES[f]}, C={c}, L1, H.v>"
     return f"plain_kernel<{NAMES[f]}, C={c}, H.v>"
 
 
@@ -311,11 +323,16 @@ def main():
             schunks[f] = 0
     torch.cuda.synchronize()
 
+    # the step passes chunk 0 unless a chunk was forced: the library then runs
+    # the tuned chunk and mapping
+    step_chunk = {f: (args.chunk or 0) for f in FUNCS}
+    mapping = {f: (args.chunk and 2) or binding.chessfad_default_mapping(f, N) for f in FUNCS}
+
     def step(events=None):
         for f in FUNCS:
             if events is not None:
                 events[f][0].record()
-            binding.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=chunks[f])
+            binding.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=step_chunk[f])
             if events is not None:
                 events[f][1].record()
 
@@ -340,7 +357,8 @@ def main():
     for f in FUNCS:
         mf = flops.flops_per_hvp(f, N, chunks[f])
         per_func[NAMES[f]] = {
-            "chunk": chunks[f], "kernel_ms": round(kernel_ms[f], 4),
+            "chunk": chunks[f], "mapping": f"L{mapping[f]}" if f != 2 or N > 16 else "MFMA",
+            "kernel_ms": round(kernel_ms[f], 4),
             "hvps_per_s": npts / (kernel_ms[f] * 1e-3),
             "model_tflops": mf * npts / (kernel_ms[f] * 1e-3) / 1e12,
             "model_flops_per_hvp": mf,
@@ -348,14 +366,14 @@ def main():
     for f in FUNCS:
         # executed flops where known: MFMA from the tile schedule, vector
         # float64 from the counters taken for this kernel
-        key = kernel_key(f, chunks[f])
+        key = kernel_key(f, chunks[f], mapping=mapping[f])
         ex = (fp_mfma_flops(N, chunks[f], npts) if key.startswith("fp_mfma") else 0.0)
         valu = MEASURED_VALU_FLOPS.get(key)
         per_func[NAMES[f]]["executed_mfma_tflops"] = ex / (kernel_ms[f] * 1e-3) / 1e12 if ex else None
         per_func[NAMES[f]]["executed_valu_f64_tflops"] = valu / (kernel_ms[f] * 1e-3) / 1e12 if valu else None
     fp_mfma = N <= 16
     dom = max(FUNCS, key=lambda f: kernel_ms[f])
-    kname = kernel_key(dom, chunks[dom])
+    kname = kernel_key(dom, chunks[dom], mapping=mapping[dom])
     model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
     t_dom = kernel_ms[dom] * 1e-3
     if kname.startswith("fp_mfma"):
@@ -374,6 +392,8 @@ def main():
                 "model_tflops": model_launch / t_dom / 1e12}
     if bound == "mfma":
         roofline["measured_mfma_f64_peak"] = 72.8
+        valu = MEASURED_VALU_FLOPS.get(kname)
+        roofline["executed_valu_f64_tflops"] = valu / t_dom / 1e12 if valu else None
 
     # the Fletcher-Powell vector-ALU path, for comparison (outside the timed region)
     fp_vector_ms = None
@@ -463,6 +483,31 @@ def main():
             res[f"L{level}"] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3)}
         mappings[NAMES[f]] = {"chunk": chunks[f], **res}
 
+    # the same comparison across n (the shape of the paper's mapping figures):
+    # Rosenbrock and Ackley, C = 4, 2^17 points per n
+    sweep = {}
+    for f in (0, 1):
+        for nn in (4, 8, 16, 32, 64):
+            w = inputs.make_workload(f, nn, 1 << 17, inputs.rng_for(300 + nn))
+            xw, vw = torch.from_numpy(w.x).to(dev), torch.from_numpy(w.v).to(dev)
+            mo = torch.empty_like(xw)
+            row = {}
+            for level in (0, 1, 2):
+                prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, level)
+                try:
+                    binding.chessfad_hvp(f, xw, vw, mo, chunk=4)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(3):
+                        binding.chessfad_hvp(f, xw, vw, mo, chunk=4)
+                    e1.record()
+                    torch.cuda.synchronize()
+                finally:
+                    binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev)
+                row[f"L{level}_ms"] = round(e0.elapsed_time(e1) / 3, 4)
+            sweep[f"{NAMES[f]}_n{nn}"] = row
+        del xw, vw, mo
+
     # the symmetric form (SC-HESS-VEC) on the same inputs, outside the timed
     # region: fewer f calls per point, the same H.v
     sym = {}
@@ -521,6 +566,7 @@ def main():
         "hessian_f64": hess,
         "symmetric_f64": {"per_function": sym, "all_three": sym_total},
         "mappings_f64": mappings,
+        "mappings_f64_by_n": {"chunk": 4, "npts": 1 << 17, "kernel_ms": sweep},
         "chunk_model_vs_tuned": chunk_model,
     }
     result["autotuned_ms"] = tuned or None

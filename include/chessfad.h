@@ -184,7 +184,8 @@ const char* chessfad_strerror(int code);
  *                         Fletcher-Powell with CHESSFAD_OPT_FP_MFMA = 0):
  *                         2 (default): L2, one lane per (point, row, chunk)
  *                            (a row with a single chunk runs on the L1
- *                            kernel, the same mapping then);
+ *                            kernel, the same mapping then; with chunk = 0
+ *                            the mapping chessfad_autotune chose, if any);
  *                         1: L1, one lane per (point, row), walking its chunks;
  *                         0: L0, one lane per point, walking rows and chunks.
  *                         Every mapping computes the same sums in the same
@@ -257,6 +258,10 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
  * needs its parameters registered for n.  Allocates and frees temporary
  * device memory and synchronises `stream`.  Returns the chosen chunk in
  * *best_chunk and its time per launch in *best_ms (either may be NULL).
+ * For float64 H.v whose f runs on the vector ALUs it times the L1 mapping
+ * beside L2 at every chunk and records the faster one too: chessfad_hvp with
+ * chunk = 0 then runs that mapping (unless CHESSFAD_OPT_MAPPING is set to
+ * 0 or 1).
  */
 int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
                       float* best_ms);
@@ -271,6 +276,12 @@ int chessfad_autotune_sym(int func_id, int n, int precision, int64_t npts, void*
 /* Default chunk size the library uses for (func_id, n) when chunk == 0,
  * or a negative status for invalid arguments. */
 int chessfad_default_chunk(int func_id, int n);
+
+/* The GPU mapping chessfad_hvp uses for (func_id, n) with chunk = 0 when f
+ * runs on the vector ALUs: 0 (L0), 1 (L1) or 2 (L2); the option if set,
+ * else 1 when the default chunk leaves one chunk per row, else the tuned
+ * mapping, else 2.  Host only; a negative status for a bad func_id or n. */
+int chessfad_default_mapping(int func_id, int n);
 
 #ifdef __cplusplus
 }

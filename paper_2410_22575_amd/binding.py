@@ -38,6 +38,7 @@ SIGNATURES = {
     "chessfad_fp_release": (_i, [_i]),
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
+    "chessfad_default_mapping": (_i, [_i, _i]),
     "chessfad_set_option": (_i, [_i, _i]),
     "chessfad_batch_create": (_i, [_p, _i, _p, _pp, _pi]),
     "chessfad_batch_run": (_i, [_p, _p]),
@@ -189,6 +190,10 @@ def chessfad_fp_set_params(A: torch.Tensor, B: torch.Tensor, alpha: torch.Tensor
 
 def chessfad_fp_release(n: int) -> None:
     _raise(load().chessfad_fp_release(n), "chessfad_fp_release")
+
+
+def chessfad_default_mapping(func_id: int, n: int) -> int:
+    return load().chessfad_default_mapping(func_id, n)
 
 
 def chessfad_default_chunk(func_id: int, n: int) -> int:

@@ -325,31 +325,45 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
                            (int64_t)count, lo, -lo);
         err = hipGetLastError();
     }
+    // float64 H.v on the vector path: the L1 mapping is timed beside L2
+    const bool two_maps = !sym && precision == 0 && vector_path(func_id);
     float times[kNumChunks];
+    int maps[kNumChunks];
     int tried = 0;
     for (int k = 0; k < kNumChunks && err == hipSuccess && rc == CHESSFAD_OK; ++k) {
         const int C = kChunks[k];
         if (C > n) break;
         times[k] = -1.0f;
+        maps[k] = 2;
         tried = k + 1;
-        rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym);  // warm-up
-        if (sym && rc == CHESSFAD_E_CHUNK) {
-            rc = CHESSFAD_OK;
-            continue;
+        const bool both = two_maps && (n + C - 1) / C > 1;
+        for (int level = 2; level >= (both ? 1 : 2) && err == hipSuccess && rc == CHESSFAD_OK; --level) {
+            const int map = sym ? -1 : level;
+            rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym, nullptr, nullptr,
+                            map);  // warm-up
+            if (sym && rc == CHESSFAD_E_CHUNK) {
+                rc = CHESSFAD_OK;
+                break;
+            }
+            if (rc) break;
+            err = hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && rc == CHESSFAD_OK; ++r)
+                rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym, nullptr, nullptr,
+                                map);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            ms /= 3.0f;
+            if (times[k] < 0.0f || ms < times[k]) {
+                times[k] = ms;
+                maps[k] = level;
+            }
         }
-        if (rc) break;
-        err = hipEventRecord(e0, s);
-        for (int r = 0; r < 3 && rc == CHESSFAD_OK; ++r)
-            rc = run_single(func_id, n, npts, x, v, out, C, stream, false, precision == 1, sym);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        times[k] = ms / 3.0f;
     }
     // the largest chunk within 2% (timing noise) of the fastest: fewer f calls
     // for the same Hessian entries
-    int best = 0;
+    int best = 0, best_map = 2;
     float best_t = 0.0f;
     if (err == hipSuccess && rc == CHESSFAD_OK && tried > 0) {
         float fastest = -1.0f;
@@ -359,6 +373,7 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
             if (times[k] >= 0.0f && times[k] <= 1.02f * fastest) {
                 best = kChunks[k];
                 best_t = times[k];
+                best_map = maps[k];
             }
     }
     if (err == hipSuccess) err = hipStreamSynchronize(s);
@@ -371,6 +386,7 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
     if (err != hipSuccess) return hip_fail(err);
     if (!best) return CHESSFAD_E_CHUNK;
     record_tuned_chunk(func_id, n, precision, best, sym);
+    if (two_maps) record_tuned_mapping(func_id, n, best_map);
     if (best_chunk) *best_chunk = best;
     if (best_ms) *best_ms = best_t;
     return CHESSFAD_OK;

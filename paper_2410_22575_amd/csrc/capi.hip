@@ -20,6 +20,7 @@ namespace {
 thread_local std::string g_hip_error;
 std::mutex g_tune_mu;
 int g_tuned[2][3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (form, func, precision, n); 0 = none
+int g_tuned_map[3][CHESSFAD_MAX_N + 1];    // autotuned mapping of float64 H.v (1 or 2); 0 = none
 int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
@@ -72,6 +73,19 @@ void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym) 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[sym][func_id][precision][n] = chunk;
 }
+
+int tuned_mapping(int func_id, int n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int t = g_tuned_map[func_id][n];
+    return t ? t : 2;
+}
+
+void record_tuned_mapping(int func_id, int n, int level) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned_map[func_id][n] = level;
+}
+
+bool vector_path(int func_id) { return func_id != CHESSFAD_FLETCHER_POWELL || !g_opt_fp_mfma; }
 
 double model_flops_per_call(int func_id, int n, int C) {
     const double hadd = 2.0 * C + 2, hmul = 10.0 * C + 4, scal = 2.0 * C + 2, unary = 4.0 * C + 2, dot = 2.0 * C;
@@ -262,7 +276,7 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 }  // namespace
 
 int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
-                         void* stream, bool hess, bool mixed, bool sym, double* grad, double* fval) {
+                         void* stream, bool hess, bool mixed, bool sym, double* grad, double* fval, int mapping) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     const bool auto_chunk = chunk == 0;
@@ -330,11 +344,14 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpRowsWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
-    // L0 / L1 when asked for; with one chunk per row L2 is L1, whose kernel
+    // the mapping of float64 H.v: forced, asked for by the option, or the
+    // tuned one for chunk = 0; with one chunk per row L2 is L1, whose kernel
     // needs fewer registers
+    int want = mapping >= 0 ? mapping : g_opt_mapping;
+    if (mapping < 0 && want == 2 && auto_chunk) want = tuned_mapping(func_id, n);
     const bool one_chunk = (n + chunk - 1) / chunk == 1;
-    if (!hess && !mixed && !grad && !fval && (g_opt_mapping != 2 || one_chunk)) {
-        const int level = g_opt_mapping == 2 ? 1 : g_opt_mapping;
+    if (!hess && !mixed && !grad && !fval && (want != 2 || one_chunk)) {
+        const int level = want == 2 ? 1 : want;
         size_t lds = 0;
         const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, lds);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
@@ -461,6 +478,14 @@ int chessfad_set_option(int option, int value) {
 int chessfad_default_chunk(int func_id, int n) {
     int rc = check_func_n(func_id, n);
     return rc ? rc : resolve_chunk(func_id, n, 0, 16);
+}
+
+int chessfad_default_mapping(int func_id, int n) {
+    int rc = check_func_n(func_id, n);
+    if (rc) return rc;
+    if (g_opt_mapping != 2) return g_opt_mapping;
+    const int c = resolve_chunk(func_id, n, 0, 16);
+    return (n + c - 1) / c == 1 ? 1 : tuned_mapping(func_id, n);
 }
 
 }  // extern "C"

@@ -23,9 +23,19 @@ void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym =
 // With chunk == 0 and sym, a chunk whose symmetric workgroup would not fit
 // in LDS is replaced by the next larger one that fits.
 // grad / fval (H.v, float64, full form only) receive the gradient and f.
+// mapping: -1 decides from CHESSFAD_OPT_MAPPING and the tuned table; 1 or 2
+// forces L1 or L2 for float64 H.v on the vector path.
 int run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
                void* stream, bool hess, bool mixed, bool sym = false, double* grad = nullptr,
-               double* fval = nullptr);
+               double* fval = nullptr, int mapping = -1);
+
+// Float64 H.v of func_id runs its f on the vector ALUs (not on MFMA).
+bool vector_path(int func_id);
+
+// GPU mapping (1 = L1, 2 = L2) chosen by the autotuner for float64 H.v of
+// (func_id, n) with chunk = 0; 2 when none was recorded.
+int tuned_mapping(int func_id, int n);
+void record_tuned_mapping(int func_id, int n, int level);
 
 // Paper-model flops of one f call (Sec. V operation counts, chunk dot included).
 double model_flops_per_call(int func_id, int n, int C);

@@ -164,6 +164,13 @@ def test_autotune_records_default(gpu_lib):
         c, ms = gpu_lib.chessfad_autotune(func, 24, 0, npts=4096)
         assert c in (1, 2, 4, 8, 16) and ms > 0
         assert gpu_lib.chessfad_default_chunk(func, 24) == c
+        level = gpu_lib.chessfad_default_mapping(func, 24)
+        assert level in (1, 2)
+        # chunk = 0 now runs the tuned chunk and mapping
+        w = inputs.make_workload(func, 24, 40, inputs.rng_for(9450 + func))
+        d = _make([w])[0]
+        r = gpu_lib.chessfad_hvp(func, d["x"], d["v"]).cpu().numpy()
+        assert _oracle_err(w, r) <= 1e-12
     w = inputs.make_workload(FP, 20, 4, inputs.rng_for(9400))
     gpu_lib.chessfad_fp_set_params(_dev(w.A), _dev(w.B), _dev(w.alpha))
     c, ms = gpu_lib.chessfad_autotune(FP, 20, 1, npts=512)
