@@ -177,15 +177,21 @@ def large_n(binding, inputs, cf, torch, flops):
         if f == 2:
             binding.chessfad_fp_set_params(*(torch.from_numpy(a).to(dev) for a in (w.A, w.B, w.alpha)))
             E = cf.fp_offsets(w.A, w.B, w.alpha)
-        c = 16
+        # autotuned chunk (and mapping) except for Fletcher-Powell at n = 512,
+        # where one launch per chunk takes about a second: C = 16 there
+        if f == 2 and n == 512:
+            c = call_c = 16
+        else:
+            c, _ = binding.chessfad_autotune(f, n, prec, npts=min(npts, 1 << 16))
+            call_c = 0  # the tuned chunk and, for float64 on the vector ALUs, mapping
         fn = binding.chessfad_hvp_mixed if prec else binding.chessfad_hvp
-        out = fn(f, x, v, chunk=c)
+        out = fn(f, x, v, chunk=call_c)
         torch.cuda.synchronize()
         reps = 1 if n == 512 and f == 2 else 3
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            fn(f, x, v, out, chunk=c)
+            fn(f, x, v, out, chunk=call_c)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
@@ -196,7 +202,10 @@ def large_n(binding, inputs, cf, torch, flops):
         err = float((np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))).max())
         mf = flops.flops_per_hvp(f, n, c)
         res[f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"] = {
-            "npts": npts, "chunk": c, "kernel_ms": ms, "hvps_per_s": npts / (ms * 1e-3),
+            "npts": npts, "chunk": c,
+            "mapping": "MFMA" if f == 2 else (f"L{binding.chessfad_default_mapping(f, n)}" if not prec and call_c == 0
+                                              else "L2"),
+            "kernel_ms": ms, "hvps_per_s": npts / (ms * 1e-3),
             "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
         print(f"  large: {NAMES[f]} n={n} {'mixed' if prec else 'f64'} {ms:.2f} ms err {err:.2e}", file=sys.stderr, flush=True)
     return res
