@@ -47,17 +47,23 @@ enum chessfad_func {
 
 enum chessfad_status {
     CHESSFAD_OK = 0,
-    CHESSFAD_E_FUNC = -1,     /* func_id is not one of chessfad_func */
+    CHESSFAD_E_FUNC = -1,     /* func_id is neither a chessfad_func nor a registered user function,
+                                 or the entry point does not take user functions */
     CHESSFAD_E_N = -2,        /* n < 1, n > CHESSFAD_MAX_N, or n < 2 for Rosenbrock */
     CHESSFAD_E_CHUNK = -3,    /* chunk not compiled, negative, or larger than n */
     CHESSFAD_E_NULL = -4,     /* a required pointer is NULL while npts > 0 */
     CHESSFAD_E_PARAMS = -5,   /* Fletcher-Powell parameters not set for this n */
     CHESSFAD_E_OVERLAP = -6,  /* an output array overlaps an input array */
     CHESSFAD_E_HIP = -7,      /* HIP error while allocating or launching */
-    CHESSFAD_E_ARG = -8       /* npts < 0 or another malformed argument */
+    CHESSFAD_E_ARG = -8,      /* npts < 0 or another malformed argument */
+    CHESSFAD_E_COMPILE = -9   /* a user function did not compile (chessfad_strerror gives the log) */
 };
 
 #define CHESSFAD_MAX_N 512
+
+/* func_ids of registered user functions: CHESSFAD_USER_BASE + 0 .. CHESSFAD_MAX_USER - 1 */
+#define CHESSFAD_USER_BASE 16
+#define CHESSFAD_MAX_USER 64
 
 /*
  * Hessian-vector products, plain float64 (CHESS-VEC, Sec. VI; Sec. III.C).
@@ -144,6 +150,30 @@ int chessfad_hvp_sym(int func_id, int n, int64_t npts, const double* x, const do
                      double* out, int chunk, int precision, void* stream);
 int chessfad_hessian_sym(int func_id, int n, int64_t npts, const double* x, double* H,
                          int chunk, int precision, void* stream);
+
+/*
+ * User functions (the paper's library surface: "include the header; write f
+ * templated on the data type", Sec. I, Sec. IV).  `source` is HIP C++ that
+ * defines
+ *     template <class V, class Y> __device__ V chessfad_user_f(const Y& y, int n);
+ * over the hDual type and operators of chessfad_device.h (y[k], k < n, is
+ * the k-th variable as an hDual; return f).  The library compiles it with
+ * hipRTC for gfx950 together with that header (the call takes a second or
+ * so), keeps the code object, and returns a func_id in *func_id.
+ * chessfad_hvp and chessfad_hessian then accept that func_id for any n in
+ * 1..CHESSFAD_MAX_N and chunk in {0 (= min(4, n) rounded down to a
+ * compiled chunk), 1, 2, 4, 8, 16}; they run it in float64 on the paper's
+ * L1 mapping (one lane per (point, row), walking the row's chunks).  The
+ * other entry points return CHESSFAD_E_FUNC for user func_ids.
+ * Errors: CHESSFAD_E_NULL for NULL arguments; CHESSFAD_E_COMPILE when the
+ * source does not compile, with the compiler log available from
+ * chessfad_strerror(CHESSFAD_E_COMPILE) on the same thread;
+ * CHESSFAD_E_ARG when all CHESSFAD_MAX_USER slots are taken.
+ * chessfad_release_function frees the slot and its code (the caller ensures
+ * no enqueued work still runs it); CHESSFAD_E_FUNC for an unknown func_id.
+ */
+int chessfad_register_function(const char* source, int* func_id);
+int chessfad_release_function(int func_id);
 
 /*
  * Fletcher-Powell parameters for problem size n.  The function needs two

@@ -5,7 +5,9 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 Sec. III.A: an hDual <f, df/dx_i, df/dx_j, d2f/dx_i dx_j> carries one
 Hessian entry through f.  The component rules for + and x and sin are the
 ones the paper states; the other unary functions follow the same chain
-rule, g(u) = <g(u0), g'(u0) u1, g'(u0) u2, g'(u0) u3 + g''(u0) u1 u2>.
+rule, g(u) = <g(u0), g'(u0) u1, g'(u0) u2, g'(u0) u3 + g''(u0) u1 u2>, with
+g, g', g'' from calculus (1/x, log, tan, tanh, atan, x^p, |x| among them);
+a quotient is u * (1 / w).
 INITIALIZE seeds y_k = <a_k, [k = i], [k = j], 0> and HESSIAN calls f once
 per (i, j), n^2 calls in all.  This is independent of the closed forms and
 of the chunked C code, so it pins both on small inputs.
@@ -54,6 +56,22 @@ class HD4:
 
     __rmul__ = __mul__
 
+    # quotient: u * (1 / w), the reciprocal by the chain rule
+    def __truediv__(self, o):
+        if isinstance(o, HD4):
+            return self * HDMath.recip(o)
+        return self * (1.0 / o)
+
+    def __rtruediv__(self, o):
+        return o * HDMath.recip(self)
+
+    # comparisons follow the value
+    def __lt__(self, o):
+        return self.v[0] < (o.v[0] if isinstance(o, HD4) else o)
+
+    def __gt__(self, o):
+        return self.v[0] > (o.v[0] if isinstance(o, HD4) else o)
+
 
 def _unary(u, g, g1, g2):
     a = u.v
@@ -83,12 +101,53 @@ class HDMath:
         s = math.sqrt(u.v[0])
         return _unary(u, s, 0.5 / s, -0.25 / (s * u.v[0]))
 
+    @staticmethod
+    def recip(u):
+        x = u.v[0]
+        return _unary(u, 1.0 / x, -1.0 / (x * x), 2.0 / (x * x * x))
+
+    @staticmethod
+    def log(u):
+        x = u.v[0]
+        return _unary(u, math.log(x), 1.0 / x, -1.0 / (x * x))
+
+    @staticmethod
+    def tan(u):
+        t = math.tan(u.v[0])
+        return _unary(u, t, 1.0 + t * t, 2.0 * t * (1.0 + t * t))
+
+    @staticmethod
+    def tanh(u):
+        t = math.tanh(u.v[0])
+        return _unary(u, t, 1.0 - t * t, -2.0 * t * (1.0 - t * t))
+
+    @staticmethod
+    def atan(u):
+        x = u.v[0]
+        q = 1.0 / (1.0 + x * x)
+        return _unary(u, math.atan(x), q, -2.0 * x * q * q)
+
+    @staticmethod
+    def pow(u, p):
+        x = u.v[0]
+        return _unary(u, x ** p, p * x ** (p - 1.0), p * (p - 1.0) * x ** (p - 2.0))
+
+    @staticmethod
+    def abs(u):
+        return -u if u.v[0] < 0.0 else u
+
 
 class FloatMath:
     sin = staticmethod(math.sin)
     cos = staticmethod(math.cos)
     exp = staticmethod(math.exp)
     sqrt = staticmethod(math.sqrt)
+    log = staticmethod(math.log)
+    tan = staticmethod(math.tan)
+    tanh = staticmethod(math.tanh)
+    atan = staticmethod(math.atan)
+    pow = staticmethod(lambda x, p: x ** p)
+    abs = staticmethod(abs)
 
 
 # ------------------------------------------------ functions, generic in the number type
@@ -134,8 +193,9 @@ def initialize(a, i, j):
 
 
 def hessian(func, a, params=None):
-    """HESSIAN: one f call per (i, j); H[i][j] is the fourth component."""
-    f = FUNCS[func]
+    """HESSIAN: one f call per (i, j); H[i][j] is the fourth component.
+    func is one of the three test functions' ids or a callable f(y, M, params)."""
+    f = FUNCS[func] if isinstance(func, int) else func
     n = len(a)
     H = [[0.0] * n for _ in range(n)]
     for i in range(n):

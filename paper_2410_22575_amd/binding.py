@@ -39,6 +39,8 @@ SIGNATURES = {
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
     "chessfad_default_mapping": (_i, [_i, _i]),
+    "chessfad_register_function": (_i, [_s, _pi]),
+    "chessfad_release_function": (_i, [_i]),
     "chessfad_set_option": (_i, [_i, _i]),
     "chessfad_batch_create": (_i, [_p, _i, _p, _pp, _pi]),
     "chessfad_batch_run": (_i, [_p, _p]),
@@ -190,6 +192,18 @@ def chessfad_fp_set_params(A: torch.Tensor, B: torch.Tensor, alpha: torch.Tensor
 
 def chessfad_fp_release(n: int) -> None:
     _raise(load().chessfad_fp_release(n), "chessfad_fp_release")
+
+
+def chessfad_register_function(source: str) -> int:
+    """Compile a user function (chessfad_device.h) and return its func_id."""
+    fid = ctypes.c_int(-1)
+    rc = load().chessfad_register_function(source.encode(), ctypes.byref(fid))
+    _raise(rc, "chessfad_register_function")
+    return fid.value
+
+
+def chessfad_release_function(func_id: int) -> None:
+    _raise(load().chessfad_release_function(func_id), "chessfad_release_function")
 
 
 def chessfad_default_mapping(func_id: int, n: int) -> int:

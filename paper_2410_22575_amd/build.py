@@ -30,7 +30,7 @@ FLAGS = [
     # across runtime-length K loops are copied between AGPRs and VGPRs on
     # every iteration
     "-mllvm", "-amdgpu-mfma-vgpr-form",
-    "-I", INCLUDE, "-I", CSRC,
+    "-I", INCLUDE, "-I", CSRC, "-I", BUILD,
 ]
 
 
@@ -49,8 +49,20 @@ def _compile(src, verbose):
     return obj, res.stderr
 
 
+def write_device_header_inc() -> None:
+    """include/chessfad_device.h as a C++ raw string literal, for the run-time
+    compilation of user functions."""
+    text = open(os.path.join(INCLUDE, "chessfad_device.h")).read()
+    assert ")CHESSFADHDR" not in text
+    tmp = os.path.join(BUILD, "device_header.inc.tmp")
+    with open(tmp, "w") as fh:
+        fh.write('R"CHESSFADHDR(' + text + ')CHESSFADHDR"\n')
+    os.replace(tmp, os.path.join(BUILD, "device_header.inc"))
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    write_device_header_inc()
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
@@ -61,7 +73,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             if err.strip():
                 print(err, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -277,6 +277,21 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 
 int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
                          void* stream, bool hess, bool mixed, bool sym, double* grad, double* fval, int mapping) {
+    if (func_id >= CHESSFAD_USER_BASE) {
+        // a registered user function: float64 H.v or Hessian, full form
+        if (!user_registered(func_id) || mixed || sym || grad || fval) return CHESSFAD_E_FUNC;
+        if (n < 1 || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
+        if (chunk == 0) chunk = n >= 4 ? 4 : n >= 2 ? 2 : 1;
+        if (chunk < 0 || !chunk_compiled(chunk) || chunk > n) return CHESSFAD_E_CHUNK;
+        if (npts < 0) return CHESSFAD_E_ARG;
+        if (npts == 0) return CHESSFAD_OK;
+        if (!x || !out || (!hess && !v)) return CHESSFAD_E_NULL;
+        const size_t in_bytes = sizeof(double) * (size_t)npts * n;
+        const size_t out_bytes = hess ? in_bytes * n : in_bytes;
+        if (overlaps(out, out_bytes, x, in_bytes) || (!hess && overlaps(out, out_bytes, v, in_bytes)))
+            return CHESSFAD_E_OVERLAP;
+        return run_user(func_id, n, npts, x, v, out, chunk, static_cast<hipStream_t>(stream), hess);
+    }
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     const bool auto_chunk = chunk == 0;
@@ -460,6 +475,10 @@ const char* chessfad_strerror(int code) {
         case CHESSFAD_E_OVERLAP: return "output overlaps an input";
         case CHESSFAD_E_HIP: return g_hip_error.empty() ? "HIP error" : g_hip_error.c_str();
         case CHESSFAD_E_ARG: return "invalid argument";
+        case CHESSFAD_E_COMPILE: {
+            const char* log = user_compile_log();
+            return log && *log ? log : "user function failed to compile";
+        }
         default: return "unknown status";
     }
 }

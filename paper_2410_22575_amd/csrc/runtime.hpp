@@ -29,6 +29,13 @@ int run_single(int func_id, int n, int64_t npts, const double* x, const double* 
                void* stream, bool hess, bool mixed, bool sym = false, double* grad = nullptr,
                double* fval = nullptr, int mapping = -1);
 
+// User functions (user.hip): registered?, the last compile log of this
+// thread, and the H.v / Hessian launch (arguments already checked).
+bool user_registered(int func_id);
+const char* user_compile_log();
+int run_user(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
+             hipStream_t stream, bool hess);
+
 // Float64 H.v of func_id runs its f on the vector ALUs (not on MFMA).
 bool vector_path(int func_id);
 

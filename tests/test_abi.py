@@ -37,7 +37,7 @@ def test_header_symbols_exported(lib):
 
 
 def test_status_strings(lib):
-    for code in (OK, E_FUNC, E_N, E_CHUNK, E_NULL, E_PARAMS, E_OVERLAP, E_HIP, E_ARG):
+    for code in (OK, E_FUNC, E_N, E_CHUNK, E_NULL, E_PARAMS, E_OVERLAP, E_HIP, E_ARG, -9):
         assert binding.strerror(code)
     assert binding.strerror(-99) == "unknown status"
 
@@ -127,6 +127,33 @@ def test_hvp_grad_argument_checks(lib):
     assert call(FAKE * 8, FAKE * 2 + 16) == E_OVERLAP                 # fval inside v
     assert lib.chessfad_hvp_grad(R, n, 0, None, None, None, None, None, 4, None) == OK
     assert lib.chessfad_hvp_grad(R, n, npts, FAKE, FAKE * 2, FAKE * 4, FAKE * 8, None, 3, None) == E_CHUNK
+
+
+def test_user_function_registration_host_only(lib):
+    # hipRTC compiles on the host; nothing here touches a device
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import user_functions as uf
+
+    fid = binding.chessfad_register_function(uf.ROSENBROCK_HIP)
+    assert fid >= 16
+    try:
+        assert lib.chessfad_hvp(fid, 8, 10, FAKE, FAKE * 2, FAKE * 4, 3, None) == E_CHUNK
+        assert lib.chessfad_hvp(fid, 0, 10, FAKE, FAKE * 2, FAKE * 4, 1, None) == E_N
+        assert lib.chessfad_hvp(fid, 8, 0, None, None, None, 4, None) == OK
+        assert lib.chessfad_hvp(fid, 8, 10, FAKE, None, FAKE * 4, 4, None) == E_NULL
+        assert lib.chessfad_hvp_mixed(fid, 8, 10, FAKE, FAKE * 2, FAKE * 4, 4, None) == E_FUNC
+        assert lib.chessfad_hvp_sym(fid, 8, 10, FAKE, FAKE * 2, FAKE * 4, 4, 0, None) == E_FUNC
+        assert lib.chessfad_hvp_grad(fid, 8, 10, FAKE, FAKE * 2, FAKE * 4, FAKE * 8, None, 4, None) == E_FUNC
+    finally:
+        binding.chessfad_release_function(fid)
+    assert lib.chessfad_release_function(fid) == E_FUNC
+    assert lib.chessfad_hvp(fid, 8, 10, FAKE, FAKE * 2, FAKE * 4, 4, None) == E_FUNC
+    with pytest.raises(binding.ChessfadError) as ei:
+        binding.chessfad_register_function("template <class V, class Y> __device__ V chessfad_user_f(const Y& y, int n)"
+                                           " { return no_such_function(y[0]); }")
+    assert ei.value.code == -9 and "no_such_function" in str(ei.value)
+    assert lib.chessfad_register_function(None, None) == E_NULL
 
 
 def test_options(lib):

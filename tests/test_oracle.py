@@ -178,6 +178,33 @@ def test_ackley_equal_coordinates_structure():
         assert np.abs(H - Hb).max() <= 1e-13 * np.abs(H).max()
 
 
+def test_hd4_operator_set_against_calculus():
+    # second derivatives of single-variable compositions from calculus,
+    # f''(x) written out by hand, against the fourth hDual component
+    M = hyperdual.HDMath
+    cases = [
+        (lambda y: 1.0 / y, lambda x: 2.0 / x ** 3, 0.7),
+        (lambda y: M.log(y), lambda x: -1.0 / x ** 2, 1.9),
+        (lambda y: M.tan(y), lambda x: 2.0 * math.tan(x) / math.cos(x) ** 2, 0.4),
+        (lambda y: M.tanh(y), lambda x: -2.0 * math.tanh(x) / math.cosh(x) ** 2, -0.8),
+        (lambda y: M.atan(y), lambda x: -2.0 * x / (1.0 + x * x) ** 2, 1.3),
+        (lambda y: M.pow(y, 2.5), lambda x: 2.5 * 1.5 * x ** 0.5, 1.7),
+        (lambda y: M.abs(y), lambda x: 0.0, -0.6),
+        (lambda y: y / (1.0 + y * y), lambda x: (2 * x ** 3 - 6 * x) / (1 + x * x) ** 3, 0.9),
+        (lambda y: M.exp(y) / y, lambda x: math.exp(x) * (x * x - 2 * x + 2) / x ** 3, 1.1),
+    ]
+    for f, d2, x in cases:
+        y = hyperdual.initialize([x], 0, 0)
+        got = f(y[0]).v[3]
+        assert abs(got - d2(x)) <= 1e-13 * max(1.0, abs(d2(x))), (x, got, d2(x))
+    # a mixed quotient: d2/dx dy (x / y) = -1 / y^2
+    y = hyperdual.initialize([0.8, 1.6], 0, 1)
+    assert abs((y[0] / y[1]).v[3] + 1.0 / 1.6 ** 2) <= 1e-15
+    # first derivative of |x| follows the sign of the value
+    y = hyperdual.initialize([-0.6], 0, 0)
+    assert M.abs(y[0]).v[1] == -1.0
+
+
 # ------------------------------------------------------ the chunked C method
 @pytest.mark.parametrize("func", [R, A, FP])
 @pytest.mark.parametrize("n,c", [(2, 1), (2, 2), (5, 2), (5, 3), (8, 4), (16, 4), (16, 16), (13, 4), (7, 16)])
