@@ -37,11 +37,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 MEASURED_TRAFFIC = {
     "coarse_kernel<ackley, C=16, L1, H.v>": 4.0284e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0309e+08,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0308e+08,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0307e+08,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0307e+08,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0307e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=2, H.v>": 4.0280e+08,
     "plain_kernel<ackley, C=4, H.v>": 4.0281e+08,
@@ -60,7 +55,6 @@ MEASURED_TRAFFIC = {
 MEASURED_VALU_FLOPS = {
     "coarse_kernel<ackley, C=16, L1, H.v>": 4.9421e+10,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 5.8754e+10,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 2.0581e+10,
     "plain_kernel<ackley, C=1, H.v>": 9.7039e+10,
     "plain_kernel<ackley, C=2, H.v>": 6.7713e+10,
     "plain_kernel<ackley, C=4, H.v>": 5.7949e+10,

@@ -303,20 +303,27 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
 
         double row = 0.0;
         const int own = i / C;
+        // float64 H.v of the full form sums each lane's residual rows into the
+        // chunk dots and adds the four lane groups once per row (the same
+        // products, summed over m and the columns in another order); the
+        // Hessian, the symmetric form and float32 form every entry first
+        constexpr bool kLaneDot = !kHess && !kSym && sizeof(T) == sizeof(double);
+        double lane_row = 0.0;
         // fixed trip counts (no early exit) so that rg is indexed statically
 #pragma unroll
         for (int jc = 0; jc < KCH; ++jc) {
             if (jc < nc && (!kSym || jc >= own)) {
                 const bool mirrored = kSym && jc > own;
                 typename P::Dot dot;
+                double lane_dot = 0.0;
 #pragma unroll
                 for (int l = 0; l < C; ++l) {
                     const int k = jc * C + l;
                     // surplus columns of a ragged last chunk are skipped
                     if (k < KMAX && k < n) {
                         // second-order component l of r * r for this lane's
-                        // rows, then summed over all residual rows (independent
-                        // terms: a chain through one accumulator is slower)
+                        // rows (independent terms: a chain through one
+                        // accumulator is slower)
                         T t[4];
                         if (k == i) {
 #pragma unroll
@@ -326,22 +333,32 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
                         }
-                        const T h = row_sum4(t);
-                        if (kHess) {
-                            if (live && lg == 0) {
-                                a.out[p * n * n + (int64_t)i * n + k] = (double)h;
-                                if (mirrored) a.out[p * n * n + (int64_t)k * n + i] = (double)h;
-                            }
+                        if constexpr (kLaneDot) {
+                            const double tl = (t[0] + t[1]) + (t[2] + t[3]);
+                            lane_dot += tl * (double)vw[li * kFpVStride + k];
                         } else {
-                            dot.add(h, vw[li * kFpVStride + k]);
-                            if (mirrored && lg == 0)
-                                mw[li * kFpVStride + k] += (double)h * (double)vw[li * kFpVStride + i];
+                            // summed over all residual rows
+                            const T h = row_sum4(t);
+                            if (kHess) {
+                                if (live && lg == 0) {
+                                    a.out[p * n * n + (int64_t)i * n + k] = (double)h;
+                                    if (mirrored) a.out[p * n * n + (int64_t)k * n + i] = (double)h;
+                                }
+                            } else {
+                                dot.add(h, vw[li * kFpVStride + k]);
+                                if (mirrored && lg == 0)
+                                    mw[li * kFpVStride + k] += (double)h * (double)vw[li * kFpVStride + i];
+                            }
                         }
                     }
                 }
-                if (!kHess) row += dot.get();
+                if constexpr (kLaneDot)
+                    lane_row += lane_dot;
+                else if (!kHess)
+                    row += dot.get();
             }
         }
+        if constexpr (kLaneDot) row = pair_sum<32>(pair_sum<16>(lane_row));
         if (kSym && !kHess) row += mw[li * kFpVStride + i];
         if (!kHess && live && lg == 0) a.out[p * n + i] = row;
     }
