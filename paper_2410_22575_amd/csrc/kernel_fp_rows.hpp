@@ -167,24 +167,32 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
     // -r_m components of S columns col0 .. col0 + 15 (variables or rows) for
     // the residual rows of m tile mt: the g/d column (h = false) or the h
     // column (h = true) of each
-    auto tile = [&](int mt, int col0, bool h) -> V {
-        V acc = {zero, zero, zero, zero};
+    // Up to kJ tiles of one m tile share each K step's [A B] operand load and
+    // run as independent accumulation chains.
+    constexpr int kJ = 2;
+    auto tiles = [&](int mt, int count, const int (&col0)[kJ], const bool (&h)[kJ], V (&acc)[kJ]) {
+#pragma unroll
+        for (int t = 0; t < kJ; ++t) acc[t] = V{zero, zero, zero, zero};
         const int m_op = mt * 16 + li;      // A-operand row of this lane
-        const int var = col0 + li;          // B-operand column of this lane
         for (int s = 0; s < nk; ++s) {
             const int k = 4 * s + lg;
-            T aop = zero, b = zero;
+            T aop = zero;
+            int j = -1;
             if (k < 2 * n) {
-                const int j = k < n ? k : k - n;
+                j = k < n ? k : k - n;
                 if (m_op < n) aop = k < n ? fp_a<T>(a.fp, (size_t)m_op * n + k) : fp_b<T>(a.fp, (size_t)m_op * n + j);
-                if (j == var) {
-                    const double sj = sh.s64[j], cj = sh.c64[j];
-                    b = (T)(h ? (k < n ? -sj : -cj) : (k < n ? cj : -sj));
+            }
+            const double sj = j >= 0 ? sh.s64[j] : 0.0, cj = j >= 0 ? sh.c64[j] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kJ; ++t) {
+                if (t < count) {
+                    const int var = col0[t] + li;   // B-operand column of this lane
+                    T b = zero;
+                    if (j == var) b = (T)(h[t] ? (k < n ? -sj : -cj) : (k < n ? cj : -sj));
+                    acc[t] = mfma16(aop, b, acc[t]);
                 }
             }
-            acc = mfma16(aop, b, acc);
         }
-        return acc;
     };
     for (int mt = 0; mt < mtiles; ++mt) {
         for (int kb = 0; kb < kblocks; ++kb) {
@@ -192,25 +200,47 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
             const int kcount = n - kbase < kFpRowsKB ? n - kbase : kFpRowsKB;
             const int ktiles = (kcount + 15) / 16;
             const int rt_tasks = kb == 0 ? (gi_in_gk ? rtiles : 2 * rtiles) : 0;
+            const int ntasks = ktiles + rt_tasks;
             // MFMA phase: the block's g columns, and (first block) the rows' h
-            // (and d) columns
+            // (and d) columns; the wave's tasks kJ at a time
             __syncthreads();  // the previous phase has finished reading LDS
-            for (int t = wave; t < ktiles + rt_tasks; t += kFpRowsWaves) {
-                if (t < ktiles) {
-                    const V acc = tile(mt, kbase + 16 * t, false);
+            for (int t0 = wave; t0 < ntasks; t0 += kFpRowsWaves * kJ) {
+                int col0[kJ], count = 0;
+                bool hcol[kJ];
+                T* dst[kJ];
+                int dcol[kJ];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sh.gk[MfmaTile<T>::row(r, lg)][16 * t + li] = -acc[r];
-                } else {
-                    const int u = t - ktiles;
-                    const bool hcol = gi_in_gk || u >= rtiles;
-                    const int rt = u < rtiles ? u : u - rtiles;
-                    const V acc = tile(mt, r0 + 16 * rt, hcol);
+                for (int u = 0; u < kJ; ++u) {
+                    const int t = t0 + u * kFpRowsWaves;
+                    col0[u] = 0;
+                    hcol[u] = false;
+                    dst[u] = nullptr;
+                    dcol[u] = 0;
+                    if (t < ntasks) {
+                        count = u + 1;
+                        if (t < ktiles) {
+                            col0[u] = kbase + 16 * t;
+                            dst[u] = &sh.gk[0][0];
+                            dcol[u] = 16 * t;
+                        } else {
+                            const int w = t - ktiles;
+                            hcol[u] = gi_in_gk || w >= rtiles;
+                            const int rt = w < rtiles ? w : w - rtiles;
+                            col0[u] = r0 + 16 * rt;
+                            dst[u] = hcol[u] ? &sh.hi[0][0] : &sh.gi[0][0];
+                            dcol[u] = 16 * rt;
+                        }
+                    }
+                }
+                V acc[kJ];
+                tiles(mt, count, col0, hcol, acc);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (hcol)
-                            sh.hi[MfmaTile<T>::row(r, lg)][16 * rt + li] = -acc[r];
-                        else
-                            sh.gi[MfmaTile<T>::row(r, lg)][16 * rt + li] = -acc[r];
+                for (int u = 0; u < kJ; ++u) {
+                    if (u < count) {
+                        const int stride = dst[u] == &sh.gk[0][0] ? kFpRowsKB : kFpRowsMaxRows;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            dst[u][MfmaTile<T>::row(r, lg) * stride + dcol[u] + li] = -acc[u][r];
                     }
                 }
             }
