@@ -237,8 +237,8 @@ int chessfad_set_option(int option, int value);
  * Fletcher-Powell offsets and float32 copies, and splits every instance
  * into work items of the single-instance kernels' workgroup bodies
  * (Rosenbrock and Ackley: row blocks of the vector-ALU hDual evaluation;
- * Fletcher-Powell: row blocks of the MFMA kernel with calls as matrix
- * columns).  The items are sorted by their operation-count cost, largest
+ * Fletcher-Powell: row blocks of the MFMA kernel that shares each S
+ * column's contraction across the calls of its rows).  The items are sorted by their operation-count cost, largest
  * first, and a persistent kernel per (precision, body kind) - sized to fill
  * the GPU - takes them from an atomic counter until none is left.  The plan captures
  * a counter reset kernel and the persistent kernels in one hipGraph;
@@ -248,7 +248,8 @@ int chessfad_set_option(int option, int value);
  *
  * chunk == 0 takes the autotuned chunk for (func_id, n, precision) if
  * chessfad_autotune has recorded one, else the default; batched plans are
- * compiled for chunks 1, 2, 4 and 8.  Rosenbrock and Ackley need
+ * compiled for chunks 1, 2, 4 and 8 (Fletcher-Powell also 16, its default
+ * above 16 variables).  Rosenbrock and Ackley need
  * ceil(n / chunk) <= 256.  All arrays are device pointers that must stay
  * valid while the plan is used; outputs must not overlap their inputs.
  * The plan owns its device memory (descriptors, work list, counters,
@@ -259,7 +260,7 @@ int chessfad_set_option(int option, int value);
 typedef struct chessfad_instance {
     int func_id;          /* chessfad_func */
     int n;                /* variables, 1..CHESSFAD_MAX_N */
-    int chunk;            /* 0, 1, 2, 4 or 8 */
+    int chunk;            /* 0, 1, 2, 4 or 8; Fletcher-Powell also 16 */
     int precision;        /* 0: float64 hDuals; 1: mixed, as chessfad_hvp_mixed */
     int64_t npts;         /* points of this instance, >= 0 */
     const double* x;      /* [npts][n] */
@@ -284,7 +285,8 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
  * every compiled chunk <= n on npts device-generated points and records the
  * fastest for (func_id, n, precision) (a larger chunk within 2% of the
  * fastest time wins the tie: it makes fewer f calls); chunk == 0 then uses it (single calls
- * and batched plans; plans only take recorded chunks <= 8).  Fletcher-Powell
+ * and batched plans; plans take recorded chunks <= 8, or <= 16 for
+ * Fletcher-Powell).  Fletcher-Powell
  * needs its parameters registered for n.  Allocates and frees temporary
  * device memory and synchronises `stream`.  Returns the chosen chunk in
  * *best_chunk and its time per launch in *best_ms (either may be NULL).

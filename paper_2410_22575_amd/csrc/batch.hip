@@ -121,10 +121,12 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         if (rc) return bad(rc);
         if (c.precision != 0 && c.precision != 1) return bad(CHESSFAD_E_ARG);
         if (c.npts < 0) return bad(CHESSFAD_E_ARG);
-        int C = c.chunk ? c.chunk : resolve_chunk(c.func_id, c.n, c.precision, 8);
-        if (!batch_chunk(C) || C > c.n) return bad(CHESSFAD_E_CHUNK);
-        const int nc = (c.n + C - 1) / C;
+        // Fletcher-Powell bodies take every compiled chunk, the vector bodies
+        // up to 8 (their persistent kernel's registers are the maximum over them)
         const bool fp = c.func_id == CHESSFAD_FLETCHER_POWELL;
+        int C = c.chunk ? c.chunk : resolve_chunk(c.func_id, c.n, c.precision, fp ? 16 : 8);
+        if (!(fp ? chunk_compiled(C) : batch_chunk(C)) || C > c.n) return bad(CHESSFAD_E_CHUNK);
+        const int nc = (c.n + C - 1) / C;
         if (!fp && nc > kBatchThreads) return bad(CHESSFAD_E_CHUNK);
         if (c.npts == 0) continue;
         if (!c.x || !c.v || !c.out) return bad(CHESSFAD_E_NULL);

@@ -78,7 +78,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(BatchArgs b) {
                 case 1: fp_rows_block<P, 1, false>(fa, item.blk, sh); break;
                 case 2: fp_rows_block<P, 2, false>(fa, item.blk, sh); break;
                 case 4: fp_rows_block<P, 4, false>(fa, item.blk, sh); break;
-                default: fp_rows_block<P, 8, false>(fa, item.blk, sh); break;
+                case 8: fp_rows_block<P, 8, false>(fa, item.blk, sh); break;
+                default: fp_rows_block<P, 16, false>(fa, item.blk, sh); break;
             }
         } else {
             PlainArgs pa{d.x, d.v, d.out, d.fp, d.npts, d.n, d.nc, d.rows, d.pstride};

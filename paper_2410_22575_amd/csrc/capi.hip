@@ -63,9 +63,13 @@ int resolve_chunk(int func_id, int n, int precision, int max_chunk, bool sym) {
         }
         return c;
     }
-    // full form: the largest compiled chunk <= min(4, n, max_chunk)
+    // full form: the largest compiled chunk <= min(4, n, max_chunk); for
+    // Fletcher-Powell above 16 variables (the rows kernel, whose work per
+    // point does not grow with the chunk while its workgroups per point
+    // shrink) the largest one <= min(n, max_chunk)
+    const int cap = func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN ? 16 : 4;
     for (int k = 0; k < kNumChunks; ++k)
-        if (kChunks[k] <= n && kChunks[k] <= 4 && kChunks[k] <= max_chunk) c = kChunks[k];
+        if (kChunks[k] <= n && kChunks[k] <= cap && kChunks[k] <= max_chunk) c = kChunks[k];
     return c;
 }
 

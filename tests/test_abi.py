@@ -206,7 +206,8 @@ def _create(lib, insts):
 
 def test_batch_validation_before_any_device_work(lib):
     ok = _inst()
-    assert _create(lib, [ok, _inst(chunk=16)]) == (E_CHUNK, 1)          # batched chunks: 1, 2, 4, 8
+    assert _create(lib, [ok, _inst(chunk=16)]) == (E_CHUNK, 1)          # vector bodies: 1, 2, 4, 8
+    assert _create(lib, [_inst(func=FP, chunk=16)]) == (E_PARAMS, 0)   # Fletcher-Powell takes 16
     assert _create(lib, [_inst(func=9), ok]) == (E_FUNC, 0)
     assert _create(lib, [ok, ok, _inst(n=600)]) == (E_N, 2)
     assert _create(lib, [_inst(precision=2)]) == (E_ARG, 0)
