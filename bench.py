@@ -45,11 +45,6 @@ MEASURED_TRAFFIC = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0275e+08,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0275e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0311e+08,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0310e+08,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0309e+08,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0310e+08,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0309e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=2, H.v>": 4.0280e+08,
     "plain_kernel<ackley, C=4, H.v>": 4.0281e+08,
@@ -76,11 +71,6 @@ MEASURED_VALU_FLOPS = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 5.6858e+10,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 6.0314e+10,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 5.8754e+10,
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 1.8405e+10,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 1.7868e+10,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 1.7666e+10,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 1.7532e+10,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 1.7465e+10,
     "plain_kernel<ackley, C=1, H.v>": 9.7039e+10,
     "plain_kernel<ackley, C=2, H.v>": 6.7713e+10,
     "plain_kernel<ackley, C=4, H.v>": 5.7949e+10,
@@ -106,13 +96,15 @@ def kernel_key(f, c, n=N, mapping=2):
 
 def fp_mfma_flops(n, c, npts):
     """MFMA flops the n <= 16 Fletcher-Powell kernel executes per launch: per
-    16-point wave, NK steps of 16x16x4 for the value column, NK for the g
-    column of each variable, and per row NK for the d column and NK for the
-    one nonzero h column (2 x 16 x 16 x 4 flops per step).  The chunk size
+    16-point wave, NK steps of 16x16x4 for the value column, and for the g
+    column of each variable and the d and h columns of each row the steps
+    that hold the variable's K entries k and n + k (two steps, one when both
+    fall in the same step); 2 x 16 x 16 x 4 flops per step.  The chunk size
     does not change it."""
     nk = min(8, max(1, (2 * n + 3) // 4))
-    tiles = 1 + n + 2 * n
-    return nk * tiles * 2 * 16 * 16 * 4 * (npts / 16)
+    band = sum(len({k // 4, (n + k) // 4}) for k in range(n))
+    steps = nk + band + 2 * band
+    return steps * 2 * 16 * 16 * 4 * (npts / 16)
 
 
 def parse():

@@ -149,7 +149,7 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         e.calls_per_point = (int64_t)c.n * nc;
         if (fp) {
             e.d.kind = 1;
-            e.d.rows = fp_rows_per_block(c.n, nc);
+            e.d.rows = fp_rows_per_block(c.n, C);
             e.d.row_blocks = (c.n + e.d.rows - 1) / e.d.rows;
             e.d.pstride = 0;
             e.blocks = c.npts * e.d.row_blocks;

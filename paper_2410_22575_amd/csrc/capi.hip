@@ -355,7 +355,7 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpRowsLaunch launch = fp_rows_entry(chunk, hess, mixed);
         if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
-        const int rows = fp_rows_per_block(n, nc);
+        const int rows = fp_rows_per_block(n, chunk);
         const int row_blocks = (n + rows - 1) / rows;
         const int64_t grid = npts * row_blocks;
         if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;

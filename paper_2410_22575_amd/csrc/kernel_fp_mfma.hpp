@@ -19,10 +19,12 @@
 // and walks through every call (i, cs) of those points in row-major order.
 // For one hDual component the 16 x 16 result tile
 //   D[m][point] = sum_k [A B][m][k] S_point[k][component]
-// comes from NK = ceil(2n / 4) v_mfma_f64_16x16x4f64 steps over K = 2n
-// (dense: every step is executed, whatever the seeds make zero).  Each
-// column of S depends on fewer indices than the call, so each tile is
-// contracted once for all the calls that share it:
+// comes from v_mfma_f64_16x16x4f64 steps over K = 2n, four K entries per
+// step.  The value column is dense (all NK = ceil(2n / 4) steps).  A d, g or
+// h column of variable k is nonzero only in K entries k and n + k, which lie
+// in two steps; only those two are executed (the others would add exact
+// zeros).  Each column of S depends on fewer indices than the call, so each
+// tile is contracted once for all the calls that share it:
 //   value        depends on the point only        - once per point
 //   d            on the row i                     - once per row
 //   g[l]         on the variable k = cs + l       - once per variable
@@ -263,8 +265,12 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     for (int k = 0; k < KMAX; ++k) {
         V ag = {zero, zero, zero, zero};
         if (k < n) {
+            // only the steps holding K entries k (sin) and n + k (cos) have a
+            // nonzero B operand; the others would add exact zeros
+            const int s_cos = (n + k) >> 2;
 #pragma unroll
-            for (int s = 0; s < NK; ++s) ag = mfma16(aop[s], jj[s] == k ? g1[s] : zero, ag);
+            for (int s = 0; s < NK; ++s)
+                if (s == (k >> 2) || s == s_cos) ag = mfma16(aop[s], jj[s] == k ? g1[s] : zero, ag);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) rg[k][r] = -ag[r];
@@ -275,10 +281,13 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         // d column (row derivative), shared by the row's chunks, and the one
         // nonzero h column (the row's own variable)
         V dd = {zero, zero, zero, zero}, ah = {zero, zero, zero, zero};
+        const int s_sin = i >> 2, s_cos = (n + i) >> 2;   // the steps holding K entries i and n + i
 #pragma unroll
         for (int s = 0; s < NK; ++s) {
-            dd = mfma16(aop[s], jj[s] == i ? g1[s] : zero, dd);
-            ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
+            if (s == s_sin || s == s_cos) {
+                dd = mfma16(aop[s], jj[s] == i ? g1[s] : zero, dd);
+                ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
+            }
         }
         T rd[4], rh[4];
 #pragma unroll

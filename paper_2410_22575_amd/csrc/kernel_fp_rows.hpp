@@ -7,23 +7,33 @@
 // per workgroup and m tile and shared by every call that uses it:
 //   g column of variable k (also the d column of row k)  - factors (cos, -sin)
 //   h column of row i (nonzero only for k = i)            - factors (-sin, -cos)
-// as 16 x 16 MFMA tiles (16 residual rows m x 16 variables), dense over
-// K = 2n in steps of 4.  The tiles, negated into r_m's components, go to LDS:
-// the g columns of a block of up to kFpRowsKB variables at a time, and the
-// d and h columns of the workgroup's rows.
+// as 16 x 16 MFMA tiles (16 residual rows m x 16 variables).  A tile's
+// columns are nonzero only in the K entries of their own 16 variables (sin
+// and cos part), so a tile contracts those 32 entries in 8 steps of 4; the
+// other K steps of the dense product add exact zeros and are not executed
+// (at n <= 16 the two coincide).  The tiles, negated into r_m's components,
+// go to LDS.
 //
-// Each lane then evaluates the rest of f for whole calls (i, cs) - at most
-// kFpRowsCallsPerLane of them - on the vector unit: for every residual m in
-// order, the second-order components of r_m * r_m,
-//   2 r_m.v r_m.h[l] [cs + l = i] + 2 r_m.d r_m.g[l],
-// added into the call's running sums (two-sum compensated in float32).  The
-// residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j are float64
-// and computed once per point.  H.v: chunk dot with v, then the row sums over
-// chunks in chunk order from LDS; Hessian: H[p][i][cs + l] is stored.
+// The workgroup takes its calls (i, cs) in passes over blocks of up to
+// kFpRowsKB variables: a pass holds the calls of every row of the workgroup
+// whose chunk lies in the block (at most kFpRowsCallsPerLane per lane, all
+// lanes busy), and per m tile it forms the g columns of the block, the d
+// columns of the rows (from the block when there is one pass) and the h
+// columns of the rows whose own variable lies in the block.  Each lane then
+// evaluates the rest of f for its calls on the vector unit: for every
+// residual m in order, the second-order components of r_m * r_m,
+//   2 r_m.d r_m.g[l], and on the row's own column
+//   r_m.v r_m.h + r_m.d r_m.g + r_m.d r_m.g + r_m.v r_m.h (the product rule),
+// added into the call's running sums (two-sum compensated in float32); the
+// own column runs in a sum of its own, which replaces entry l = i - cs at the
+// end.  The residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j are
+// float64 and computed once per point.  H.v: chunk dot with v, then the row
+// sums over chunks in chunk order, pass after pass; Hessian: H[p][i][cs + l]
+// is stored.
 //
-// A workgroup owns R = fp_rows_per_block(n, nc) consecutive rows of one point
-// (at most 64, and at most 512 calls), so every workgroup of a point forms
-// the g columns of all n variables.
+// Calls are laid out chunk-major within a pass (consecutive lanes take
+// consecutive rows of one chunk), so the lanes of a wave read the same g
+// entries (LDS broadcast) and consecutive d and h entries.
 #pragma once
 
 #include <stdint.h>
@@ -40,7 +50,7 @@ struct FpRowsArgs {
     int64_t npts;
     int n;
     int nc;             // chunks per row
-    int rows;           // rows per workgroup, fp_rows_per_block(n, nc)
+    int rows;           // rows per workgroup, fp_rows_per_block(n, C)
     int row_blocks;     // workgroups per point, ceil(n / rows)
     double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
     double* fval = nullptr;  // H.v only, optional: [npts] f
@@ -48,15 +58,21 @@ struct FpRowsArgs {
 
 constexpr int kFpRowsMaxN = 512;
 constexpr int kFpRowsWaves = 4;
-constexpr int kFpRowsKB = 128;          // variables whose g columns are in LDS at once (a multiple of every C)
+constexpr int kFpRowsKB = 128;          // variables of one pass (a multiple of 16 and of every C)
 constexpr int kFpRowsMaxRows = 64;
 constexpr int kFpRowsCallsPerLane = 2;
 constexpr int kFpRowsMaxCalls = 64 * kFpRowsWaves * kFpRowsCallsPerLane;
 
-// Rows per workgroup: as many as keep the calls within kFpRowsMaxCalls, at
-// most kFpRowsMaxRows and n.
-__host__ __device__ inline int fp_rows_per_block(int n, int nc) {
-    int r = kFpRowsMaxCalls / nc;
+// Chunks per pass: all of a row's when they span at most kFpRowsKB variables.
+__host__ __device__ inline int fp_rows_pass_chunks(int n, int C) {
+    const int nc = (n + C - 1) / C;
+    return nc < kFpRowsKB / C ? nc : kFpRowsKB / C;
+}
+
+// Rows per workgroup: as many as keep a pass's calls within kFpRowsMaxCalls,
+// at most kFpRowsMaxRows and n.
+__host__ __device__ inline int fp_rows_per_block(int n, int C) {
+    int r = kFpRowsMaxCalls / fp_rows_pass_chunks(n, C);
     if (r > kFpRowsMaxRows) r = kFpRowsMaxRows;
     if (r > n) r = n;
     return r < 1 ? 1 : r;
@@ -88,9 +104,10 @@ template <typename T>
 struct FpRowsShared {
     double s64[kFpRowsMaxN], c64[kFpRowsMaxN], rvs[kFpRowsMaxN];
     double vv[kFpRowsMaxN];
-    double dots[kFpRowsMaxCalls];
-    T gk[16][kFpRowsKB];           // r_m.g of the variables of the current block
-    T gi[16][kFpRowsMaxRows];      // r_m.d of the workgroup's rows (when n > kFpRowsKB)
+    double dots[kFpRowsMaxCalls];  // a pass's chunk dots, [chunk][row]
+    double rowsum[kFpRowsMaxRows];  // H.v row sums over the passes so far
+    T gk[16][kFpRowsKB];           // r_m.g of the variables of the current pass
+    T gi[16][kFpRowsMaxRows];      // r_m.d of the workgroup's rows (more than one pass)
     T hi[16][kFpRowsMaxRows];      // r_m.h of the rows' own column
 };
 
@@ -143,165 +160,165 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int mtiles = (n + 15) / 16;
-    const int nk = (2 * n + 3) / 4;
-    const int kblocks = (n + kFpRowsKB - 1) / kFpRowsKB;
-    const bool gi_in_gk = kblocks == 1;  // every row's d column is a column of the one g block
+    const int cpp = fp_rows_pass_chunks(n, C);
+    const int npass = (nc + cpp - 1) / cpp;
+    const bool one_pass = npass == 1;   // every row's d column is a column of gk
     const int rtiles = (nrows + 15) / 16;
     const T zero = T(0);
-
-    // the lane's calls (i, cs)
-    int ci[Q], ccs[Q];
-    bool cval[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int cl = threadIdx.x + q * (int)blockDim.x;
-        cval[q] = cl < ncalls;
-        const int rr = cval[q] ? cl / nc : 0;
-        ci[q] = r0 + rr;
-        ccs[q] = cval[q] ? (cl - rr * nc) * C : 0;
-    }
-    RunSum<T> fh[Q][C];
-    RunSum<T> fd[Q];  // first-order component (row's first chunk, when asked for)
     const bool want_grad = !kHess && a.grad != nullptr;
 
     // -r_m components of S columns col0 .. col0 + 15 (variables or rows) for
-    // the residual rows of m tile mt: the g/d column (h = false) or the h
-    // column (h = true) of each
-    // Up to kJ tiles of one m tile share each K step's [A B] operand load and
-    // run as independent accumulation chains.
-    constexpr int kJ = 2;
-    auto tiles = [&](int mt, int count, const int (&col0)[kJ], const bool (&h)[kJ], V (&acc)[kJ]) {
-#pragma unroll
-        for (int t = 0; t < kJ; ++t) acc[t] = V{zero, zero, zero, zero};
+    // the residual rows of m tile mt: the g/d columns (h = false) or the h
+    // columns (h = true).  Column col0 + c is nonzero only in the two K
+    // entries of its own variable (the sin part and the cos part of [A B]), so
+    // the tile contracts the 2 x 16 entries of its columns' variables - four K
+    // steps over A, then four over B - and no other K step, whose products are
+    // all exact zeros.  The eight A-operand values are loaded before the first
+    // MFMA.  The lane's B-operand entry of its own column col0 + li lies in K
+    // step u_own of each half (4 u + lg = li); every other entry is zero.
+    const bool b_lane = ((li - lg) & 3) == 0;
+    const int u_own = (li - lg) >> 2;
+    auto tile = [&](int mt, int col0, bool h) {
         const int m_op = mt * 16 + li;      // A-operand row of this lane
-        for (int s = 0; s < nk; ++s) {
-            const int k = 4 * s + lg;
-            T aop = zero;
-            int j = -1;
-            if (k < 2 * n) {
-                j = k < n ? k : k - n;
-                if (m_op < n) aop = k < n ? fp_a<T>(a.fp, (size_t)m_op * n + k) : fp_b<T>(a.fp, (size_t)m_op * n + j);
-            }
-            const double sj = j >= 0 ? sh.s64[j] : 0.0, cj = j >= 0 ? sh.c64[j] : 0.0;
+        T aop[8];
 #pragma unroll
-            for (int t = 0; t < kJ; ++t) {
-                if (t < count) {
-                    const int var = col0[t] + li;   // B-operand column of this lane
-                    T b = zero;
-                    if (j == var) b = (T)(h[t] ? (k < n ? -sj : -cj) : (k < n ? cj : -sj));
-                    acc[t] = mfma16(aop, b, acc[t]);
-                }
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int kk = col0 + 4 * u + lg;   // variable of this K entry
+            const bool ok = m_op < n && kk < n;
+            const size_t idx = ok ? (size_t)m_op * n + kk : 0;
+            aop[u] = ok ? fp_a<T>(a.fp, idx) : zero;
+            aop[4 + u] = ok ? fp_b<T>(a.fp, idx) : zero;
         }
+        const int var = col0 + li;
+        const bool on = b_lane && var < n;
+        const double sj = sh.s64[on ? var : 0], cj = sh.c64[on ? var : 0];
+        const T b0 = on ? (T)(h ? -sj : cj) : zero;     // sin part
+        const T b1 = on ? (T)(h ? -cj : -sj) : zero;    // cos part
+        V acc = V{zero, zero, zero, zero};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc = mfma16(aop[s], (s & 3) == u_own ? (s < 4 ? b0 : b1) : zero, acc);
+        return acc;
     };
-    for (int mt = 0; mt < mtiles; ++mt) {
-        for (int kb = 0; kb < kblocks; ++kb) {
-            const int kbase = kb * kFpRowsKB;
-            const int kcount = n - kbase < kFpRowsKB ? n - kbase : kFpRowsKB;
-            const int ktiles = (kcount + 15) / 16;
-            const int rt_tasks = kb == 0 ? (gi_in_gk ? rtiles : 2 * rtiles) : 0;
-            const int ntasks = ktiles + rt_tasks;
-            // MFMA phase: the block's g columns, and (first block) the rows' h
-            // (and d) columns; the wave's tasks kJ at a time
+
+    for (int pass = 0; pass < npass; ++pass) {
+        const int jc0 = pass * cpp;                       // first chunk of the pass
+        const int ncp = nc - jc0 < cpp ? nc - jc0 : cpp;  // chunks in the pass
+        const int kbase = jc0 * C;                        // first variable of the pass
+        const int kcount = n - kbase < ncp * C ? n - kbase : ncp * C;
+        const int ktiles = (kcount + 15) / 16;
+        const int pcalls = nrows * ncp;
+
+        // the lane's calls of this pass: call cl -> chunk jc0 + cl / nrows, row r0 + cl % nrows
+        int ci[Q], ccs[Q], clo[Q];
+        bool cval[Q], cown[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int cl = threadIdx.x + q * (int)blockDim.x;
+            cval[q] = cl < pcalls;
+            const int jl = cval[q] ? cl / nrows : 0;
+            ci[q] = r0 + (cval[q] ? cl - jl * nrows : 0);
+            ccs[q] = (jc0 + jl) * C;
+            clo[q] = ci[q] - ccs[q];
+            cown[q] = cval[q] && clo[q] >= 0 && clo[q] < C;
+        }
+        RunSum<T> fh[Q][C];
+        RunSum<T> fo[Q];  // the row's own column (product rule in full)
+        RunSum<T> fd[Q];  // first-order component (row's first chunk, when asked for)
+
+        for (int mt = 0; mt < mtiles; ++mt) {
+            // MFMA phase: the pass's g columns, the rows' d columns (more than
+            // one pass) and the h columns of the rows whose own variable lies
+            // in the pass; one tile per wave at a time
+            const int gtasks = one_pass ? 0 : rtiles;
+            const int ntasks = ktiles + gtasks + rtiles;
             __syncthreads();  // the previous phase has finished reading LDS
-            for (int t0 = wave; t0 < ntasks; t0 += kFpRowsWaves * kJ) {
-                int col0[kJ], count = 0;
-                bool hcol[kJ];
-                T* dst[kJ];
-                int dcol[kJ];
-#pragma unroll
-                for (int u = 0; u < kJ; ++u) {
-                    const int t = t0 + u * kFpRowsWaves;
-                    col0[u] = 0;
-                    hcol[u] = false;
-                    dst[u] = nullptr;
-                    dcol[u] = 0;
-                    if (t < ntasks) {
-                        count = u + 1;
-                        if (t < ktiles) {
-                            col0[u] = kbase + 16 * t;
-                            dst[u] = &sh.gk[0][0];
-                            dcol[u] = 16 * t;
-                        } else {
-                            const int w = t - ktiles;
-                            hcol[u] = gi_in_gk || w >= rtiles;
-                            const int rt = w < rtiles ? w : w - rtiles;
-                            col0[u] = r0 + 16 * rt;
-                            dst[u] = hcol[u] ? &sh.hi[0][0] : &sh.gi[0][0];
-                            dcol[u] = 16 * rt;
-                        }
-                    }
+            for (int t = wave; t < ntasks; t += kFpRowsWaves) {
+                T* dst;
+                int col0, dcol, stride;
+                bool hcol = false;
+                if (t < ktiles) {
+                    col0 = kbase + 16 * t;
+                    dst = &sh.gk[0][0];
+                    dcol = 16 * t;
+                    stride = kFpRowsKB;
+                } else {
+                    const int w = t - ktiles;
+                    hcol = w >= gtasks;
+                    const int rt = hcol ? w - gtasks : w;
+                    col0 = r0 + 16 * rt;
+                    dst = hcol ? &sh.hi[0][0] : &sh.gi[0][0];
+                    dcol = 16 * rt;
+                    stride = kFpRowsMaxRows;
+                    if (hcol && (col0 + 16 <= kbase || col0 >= kbase + kcount)) continue;
                 }
-                V acc[kJ];
-                tiles(mt, count, col0, hcol, acc);
+                const V acc = tile(mt, col0, hcol);
 #pragma unroll
-                for (int u = 0; u < kJ; ++u) {
-                    if (u < count) {
-                        const int stride = dst[u] == &sh.gk[0][0] ? kFpRowsKB : kFpRowsMaxRows;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            dst[u][MfmaTile<T>::row(r, lg) * stride + dcol[u] + li] = -acc[u][r];
-                    }
-                }
+                for (int r = 0; r < 4; ++r) dst[MfmaTile<T>::row(r, lg) * stride + dcol + li] = -acc[r];
             }
             __syncthreads();
-            // vector phase: every call whose chunk lies in this block takes the
-            // second-order components of r_m * r_m for the tile's residuals
+            // vector phase: the second-order components of r_m * r_m for the
+            // tile's residuals
             const int mcount = n - mt * 16 < 16 ? n - mt * 16 : 16;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int i = ci[q], cs = ccs[q], il = i - r0;
-                if (cval[q] && cs / kFpRowsKB == kb) {
+                if (!cval[q]) continue;
+                const int i = ci[q], il = i - r0;
+                const int csl = ccs[q] - kbase;
                 for (int mm = 0; mm < mcount; ++mm) {
-                    const T rd = gi_in_gk ? sh.gk[mm][i - kbase] : sh.gi[mm][il];
-                    const T* gm = &sh.gk[mm][cs - kbase];
-                    if (want_grad && cs == 0) {
+                    const T rd = one_pass ? sh.gk[mm][i] : sh.gi[mm][il];
+                    const T* gm = &sh.gk[mm][csl];
+#pragma unroll
+                    for (int l = 0; l < C; ++l) {
+                        const T pr = rd * gm[l];
+                        fh[q][l].add(pr + pr);
+                    }
+                    if (cown[q]) {
+                        const T rv = (T)sh.rvs[mt * 16 + mm], rh = sh.hi[mm][il], rg = gm[clo[q]];
+                        fo[q].add(rv * rh + rd * rg + rd * rg + rv * rh);
+                    }
+                    if (want_grad && ccs[q] == 0) {
                         const T rv = (T)sh.rvs[mt * 16 + mm];
                         fd[q].add(rv * rd + rd * rv);
                     }
-#pragma unroll
-                    for (int l = 0; l < C; ++l) {
-                        if (cs + l < n) {
-                            const T rg = gm[l];
-                            if (cs + l == i) {
-                                const T rv = (T)sh.rvs[mt * 16 + mm], rh = sh.hi[mm][il];
-                                fh[q][l].add(rv * rh + rd * rg + rd * rg + rv * rh);
-                            } else {
-                                fh[q][l].add(rd * rg + rd * rg);
-                            }
-                        }
-                    }
-                }
                 }
             }
         }
-    }
 
-    // per call: store the Hessian chunk, or its dot with v
+        // per call: store the Hessian chunk, or its dot with v
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int i = ci[q], cs = ccs[q];
-        if (!cval[q]) {
-        } else if (kHess) {
-            double* row = a.out + p * n * n + (int64_t)i * n + cs;
+        for (int q = 0; q < Q; ++q) {
+            if (!cval[q]) continue;
+            const int i = ci[q], cs = ccs[q];
+            T hv[C];
 #pragma unroll
-            for (int l = 0; l < C; ++l)
-                if (cs + l < n) row[l] = (double)fh[q][l].value();
-        } else {
-            typename P::Dot dot;
+            for (int l = 0; l < C; ++l) hv[l] = cown[q] && l == clo[q] ? fo[q].value() : fh[q][l].value();
+            if (kHess) {
+                double* row = a.out + p * n * n + (int64_t)i * n + cs;
 #pragma unroll
-            for (int l = 0; l < C; ++l)
-                if (cs + l < n) dot.add(fh[q][l].value(), (T)sh.vv[cs + l]);
-            sh.dots[threadIdx.x + q * blockDim.x] = dot.get();
-            if (want_grad && cs == 0) a.grad[p * n + i] = (double)fd[q].value();
+                for (int l = 0; l < C; ++l)
+                    if (cs + l < n) row[l] = (double)hv[l];
+            } else {
+                typename P::Dot dot;
+#pragma unroll
+                for (int l = 0; l < C; ++l)
+                    if (cs + l < n) dot.add(hv[l], (T)sh.vv[cs + l]);
+                sh.dots[threadIdx.x + q * blockDim.x] = dot.get();
+                if (want_grad && cs == 0) a.grad[p * n + i] = (double)fd[q].value();
+            }
         }
-    }
-    if (!kHess) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < nrows; t += blockDim.x) {
-            double s = sh.dots[t * nc];
-            for (int jc = 1; jc < nc; ++jc) s += sh.dots[t * nc + jc];
-            a.out[p * n + r0 + t] = s;
+        if (!kHess) {
+            // row sums over the pass's chunks, in chunk order, continuing the
+            // previous passes' sums (the next pass writes dots only after
+            // two more barriers)
+            __syncthreads();
+            for (int t = threadIdx.x; t < nrows; t += blockDim.x) {
+                double s = pass == 0 ? sh.dots[t] : sh.rowsum[t];
+                for (int jl = pass == 0 ? 1 : 0; jl < ncp; ++jl) s += sh.dots[jl * nrows + t];
+                if (pass + 1 < npass)
+                    sh.rowsum[t] = s;
+                else
+                    a.out[p * n + r0 + t] = s;
+            }
         }
     }
 }
