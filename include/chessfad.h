@@ -209,7 +209,8 @@ const char* chessfad_strerror(int code);
  *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
  *                         plan's captured hipGraph; 0: it launches the same
  *                         kernels directly on the stream.
- *   CHESSFAD_OPT_MAPPING  the GPU mapping of chessfad_hvp (Sec. VI) where
+ *   CHESSFAD_OPT_MAPPING  the GPU mapping of chessfad_hvp and
+ *                         chessfad_hvp_mixed (Sec. VI) where
  *                         f runs on the vector ALUs (Rosenbrock, Ackley;
  *                         Fletcher-Powell with CHESSFAD_OPT_FP_MFMA = 0):
  *                         2 (default): L2, one lane per (point, row, chunk)
@@ -290,10 +291,10 @@ int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgro
  * needs its parameters registered for n.  Allocates and frees temporary
  * device memory and synchronises `stream`.  Returns the chosen chunk in
  * *best_chunk and its time per launch in *best_ms (either may be NULL).
- * For float64 H.v whose f runs on the vector ALUs it times the L1 mapping
- * beside L2 at every chunk and records the faster one too: chessfad_hvp with
- * chunk = 0 then runs that mapping (unless CHESSFAD_OPT_MAPPING is set to
- * 0 or 1).
+ * For H.v whose f runs on the vector ALUs it times the L1 mapping beside
+ * L2 at every chunk and records the faster one too, per precision:
+ * chessfad_hvp (precision 0) or chessfad_hvp_mixed (1) with chunk = 0 then
+ * runs that mapping (unless CHESSFAD_OPT_MAPPING is set to 0 or 1).
  */
 int chessfad_autotune(int func_id, int n, int precision, int64_t npts, void* stream, int* best_chunk,
                       float* best_ms);
@@ -309,7 +310,7 @@ int chessfad_autotune_sym(int func_id, int n, int precision, int64_t npts, void*
  * or a negative status for invalid arguments. */
 int chessfad_default_chunk(int func_id, int n);
 
-/* The GPU mapping chessfad_hvp uses for (func_id, n) with chunk = 0 when f
+/* The GPU mapping chessfad_hvp (float64) uses for (func_id, n) with chunk = 0 when f
  * runs on the vector ALUs: 0 (L0), 1 (L1) or 2 (L2); the option if set,
  * else 1 when the default chunk leaves one chunk per row, else the tuned
  * mapping, else 2.  Host only; a negative status for a bad func_id or n. */

@@ -327,8 +327,8 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
                            (int64_t)count, lo, -lo);
         err = hipGetLastError();
     }
-    // float64 H.v on the vector path: the L1 mapping is timed beside L2
-    const bool two_maps = !sym && precision == 0 && vector_path(func_id);
+    // H.v on the vector path: the L1 mapping is timed beside L2
+    const bool two_maps = !sym && vector_path(func_id);
     float times[kNumChunks];
     int maps[kNumChunks];
     int tried = 0;
@@ -388,7 +388,7 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
     if (err != hipSuccess) return hip_fail(err);
     if (!best) return CHESSFAD_E_CHUNK;
     record_tuned_chunk(func_id, n, precision, best, sym);
-    if (two_maps) record_tuned_mapping(func_id, n, best_map);
+    if (two_maps) record_tuned_mapping(func_id, n, precision, best_map);
     if (best_chunk) *best_chunk = best;
     if (best_ms) *best_ms = best_t;
     return CHESSFAD_OK;

@@ -20,7 +20,7 @@ namespace {
 thread_local std::string g_hip_error;
 std::mutex g_tune_mu;
 int g_tuned[2][3][2][CHESSFAD_MAX_N + 1];  // autotuned chunk per (form, func, precision, n); 0 = none
-int g_tuned_map[3][CHESSFAD_MAX_N + 1];    // autotuned mapping of float64 H.v (1 or 2); 0 = none
+int g_tuned_map[2][3][CHESSFAD_MAX_N + 1];  // autotuned mapping of H.v per precision (1 or 2); 0 = none
 int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
@@ -78,15 +78,15 @@ void record_tuned_chunk(int func_id, int n, int precision, int chunk, bool sym) 
     g_tuned[sym][func_id][precision][n] = chunk;
 }
 
-int tuned_mapping(int func_id, int n) {
+int tuned_mapping(int func_id, int n, int precision) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    const int t = g_tuned_map[func_id][n];
+    const int t = g_tuned_map[precision][func_id][n];
     return t ? t : 2;
 }
 
-void record_tuned_mapping(int func_id, int n, int level) {
+void record_tuned_mapping(int func_id, int n, int precision, int level) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned_map[func_id][n] = level;
+    g_tuned_map[precision][func_id][n] = level;
 }
 
 bool vector_path(int func_id) { return func_id != CHESSFAD_FLETCHER_POWELL || !g_opt_fp_mfma; }
@@ -218,11 +218,11 @@ PlainLaunch grad_table(int func_id, int C) {
     }
 }
 
-CoarseLaunch coarse_table(int func_id, int C, int level) {
+CoarseLaunch coarse_table(int func_id, int C, int level, bool mixed) {
     switch (func_id) {
-        case CHESSFAD_ROSENBROCK: return coarse_rosenbrock(C, level);
-        case CHESSFAD_ACKLEY: return coarse_ackley(C, level);
-        default: return coarse_fletcher_powell(C, level);
+        case CHESSFAD_ROSENBROCK: return mixed ? coarse_mixed_rosenbrock(C, level) : coarse_rosenbrock(C, level);
+        case CHESSFAD_ACKLEY: return mixed ? coarse_mixed_ackley(C, level) : coarse_ackley(C, level);
+        default: return mixed ? coarse_mixed_fletcher_powell(C, level) : coarse_fletcher_powell(C, level);
     }
 }
 
@@ -232,19 +232,21 @@ struct Geometry {
 };
 
 template <class F>
-size_t coarse_lds(int n, int ps) { return plain_lds_bytes<F64, F>(n, ps, 0, false); }
+size_t coarse_lds(int n, int ps, bool mixed) {
+    return mixed ? plain_lds_bytes<F32C, F>(n, ps, 0, false) : plain_lds_bytes<F64, F>(n, ps, 0, false);
+}
 
-size_t coarse_lds_for(int func_id, int n, int ps) {
+size_t coarse_lds_for(int func_id, int n, int ps, bool mixed) {
     switch (func_id) {
-        case CHESSFAD_ROSENBROCK: return coarse_lds<Rosenbrock>(n, ps);
-        case CHESSFAD_ACKLEY: return coarse_lds<Ackley>(n, ps);
-        default: return coarse_lds<FletcherPowell>(n, ps);
+        case CHESSFAD_ROSENBROCK: return coarse_lds<Rosenbrock>(n, ps, mixed);
+        case CHESSFAD_ACKLEY: return coarse_lds<Ackley>(n, ps, mixed);
+        default: return coarse_lds<FletcherPowell>(n, ps, mixed);
     }
 }
 
 // L1: 256 lanes, one per row task.  L0: one lane per point, up to 64 points
 // per workgroup (fewer when their staging would pass 48 KiB of LDS).
-Geometry coarse_geometry(int func_id, int n, int64_t npts, int C, int level, size_t& lds) {
+Geometry coarse_geometry(int func_id, int n, int64_t npts, int C, int level, bool mixed, size_t& lds) {
     Geometry g;
     g.nc = (n + C - 1) / C;
     if (level == 1) {
@@ -253,12 +255,12 @@ Geometry coarse_geometry(int func_id, int n, int64_t npts, int C, int level, siz
         g.pstride = (g.rows - 1) / n + 2;
     } else {
         int pts = 64;
-        while (pts > 1 && coarse_lds_for(func_id, n, pts | 1) > 48 * 1024) pts /= 2;
+        while (pts > 1 && coarse_lds_for(func_id, n, pts | 1, mixed) > 48 * 1024) pts /= 2;
         g.rows = pts * n;
         g.block = pts < 64 ? 64 : pts;
         g.pstride = pts | 1;
     }
-    lds = coarse_lds_for(func_id, n, g.pstride);
+    lds = coarse_lds_for(func_id, n, g.pstride, mixed);
     const int64_t nrows = npts * (int64_t)n;
     g.grid = (nrows + g.rows - 1) / g.rows;
     return g;
@@ -363,18 +365,18 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpRowsWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
-    // the mapping of float64 H.v: forced, asked for by the option, or the
-    // tuned one for chunk = 0; with one chunk per row L2 is L1, whose kernel
-    // needs fewer registers
+    // the mapping of H.v: forced, asked for by the option, or the tuned one
+    // for chunk = 0; with one chunk per row L2 is L1, whose kernel needs
+    // fewer registers
     int want = mapping >= 0 ? mapping : g_opt_mapping;
-    if (mapping < 0 && want == 2 && auto_chunk) want = tuned_mapping(func_id, n);
+    if (mapping < 0 && want == 2 && auto_chunk) want = tuned_mapping(func_id, n, mixed ? 1 : 0);
     const bool one_chunk = (n + chunk - 1) / chunk == 1;
-    if (!hess && !mixed && !grad && !fval && (want != 2 || one_chunk)) {
+    if (!hess && !grad && !fval && (want != 2 || one_chunk)) {
         const int level = want == 2 ? 1 : want;
         size_t lds = 0;
-        const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, lds);
+        const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, mixed, lds);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-        CoarseLaunch launch = coarse_table(func_id, chunk, level);
+        CoarseLaunch launch = coarse_table(func_id, chunk, level, mixed);
         if (!launch) return CHESSFAD_E_CHUNK;
         PlainArgs a{x, v, out, fp, npts, n, g.nc, g.rows, g.pstride};
         hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(g.block), lds, s);
@@ -508,7 +510,7 @@ int chessfad_default_mapping(int func_id, int n) {
     if (rc) return rc;
     if (g_opt_mapping != 2) return g_opt_mapping;
     const int c = resolve_chunk(func_id, n, 0, 16);
-    return (n + c - 1) / c == 1 ? 1 : tuned_mapping(func_id, n);
+    return (n + c - 1) / c == 1 ? 1 : tuned_mapping(func_id, n, 0);
 }
 
 }  // extern "C"

@@ -60,10 +60,13 @@ PlainLaunch grad_rosenbrock(int C);
 PlainLaunch grad_ackley(int C);
 PlainLaunch grad_fletcher_powell(int C);
 
-// The coarser L0 / L1 mappings (float64 H.v), one per function.
+// The coarser L0 / L1 mappings of H.v, one per function and precision.
 CoarseLaunch coarse_rosenbrock(int C, int level);
 CoarseLaunch coarse_ackley(int C, int level);
 CoarseLaunch coarse_fletcher_powell(int C, int level);
+CoarseLaunch coarse_mixed_rosenbrock(int C, int level);
+CoarseLaunch coarse_mixed_ackley(int C, int level);
+CoarseLaunch coarse_mixed_fletcher_powell(int C, int level);
 
 using FpMfmaLaunch = hipError_t (*)(const FpMfmaArgs&, dim3 grid, dim3 block, hipStream_t);
 

@@ -84,10 +84,12 @@ struct Rosenbrock {
         HD1<T, C> yk = pv.template y<C>(0);
         HD1<T, C> yk1 = pv.template y<C>(1);
         auto s = P::start(term<T, C>(yk, yk1));
+        // second-order component (i, cs + l) of term k is nonzero only when
+        // both i and cs + l are k or k + 1: at most two terms per component
         for (int k = 1; k + 1 < pv.n; ++k) {
             yk = yk1;
             yk1 = pv.template y<C>(k + 1);
-            P::add(s, term<T, C>(yk, yk1));
+            P::add_sparse(s, term<T, C>(yk, yk1));
         }
         return P::value(s);
     }
@@ -133,10 +135,12 @@ struct Ackley {
         HD1<T, C> y = pv.template y<C>(0);
         auto ss = P::start(y * y);
         auto cs = P::start(cos_term<T, C>(pv, 0));
+        // second-order component (i, cs + l) of a term in y_k is nonzero only
+        // for k = i = cs + l: at most one term per component
         for (int k = 1; k < pv.n; ++k) {
             y = pv.template y<C>(k);
-            P::add(ss, y * y);
-            P::add(cs, cos_term<T, C>(pv, k));
+            P::add_sparse(ss, y * y);
+            P::add_sparse(cs, cos_term<T, C>(pv, k));
         }
         const T inv_n = T(1.0 / pv.n);
         HD<T, C> t = inv_n * P::value(ss);

@@ -251,6 +251,8 @@ struct F64 {
     template <int C>
     static CF_DEV void add(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
     template <int C>
+    static CF_DEV void add_sparse(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
+    template <int C>
     static CF_DEV HD<T, C> value(const Acc<C>& a) { return a.x; }
     // chunk dot sum_l h[l] v[l]
     struct Dot {
@@ -289,6 +291,21 @@ struct F32C {
             two_sum(a.x.h[l], t.h[l], s, e);
             a.x.h[l] = s;
             a.lo[l] += e;
+        }
+    }
+    // A sum whose every Hessian-chunk component receives at most two nonzero
+    // terms (the others are exact zeros): a two-sum pair (s, e) of two terms
+    // has s + e = a + b exactly, so value() returns round(a + b) = s, which is
+    // what the rounded plain sum gives.  The low part is skipped; the adds are
+    // kept apart from the terms' products, as in two_sum.
+    template <int C>
+    static CF_DEV void add_sparse(Acc<C>& a, const HD<T, C>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
+#pragma unroll
+        for (int l = 0; l < C; ++l) {
+            a.x.g[l] += t.g[l];
+            a.x.h[l] = __fadd_rn(a.x.h[l], t.h[l]);
         }
     }
     template <int C>

@@ -1,10 +1,14 @@
-// Rosenbrock: float32 hDuals with compensated sums, every compiled chunk size, H.v and Hessian.
+// Rosenbrock: float32 hDuals with compensated sums, every compiled chunk size, H.v and Hessian; the L0 / L1 mappings of H.v.
 #include "dispatch.hpp"
 
 namespace chessfad {
 
 PlainLaunch mixed_rosenbrock(int C, bool hess) {
     return hess ? plain_entry<F32C, Rosenbrock, true>(C) : plain_entry<F32C, Rosenbrock, false>(C);
+}
+
+CoarseLaunch coarse_mixed_rosenbrock(int C, int level) {
+    return level == 0 ? coarse_entry<F32C, Rosenbrock, 0>(C) : coarse_entry<F32C, Rosenbrock, 1>(C);
 }
 
 }  // namespace chessfad

@@ -41,8 +41,8 @@ bool vector_path(int func_id);
 
 // GPU mapping (1 = L1, 2 = L2) chosen by the autotuner for float64 H.v of
 // (func_id, n) with chunk = 0; 2 when none was recorded.
-int tuned_mapping(int func_id, int n);
-void record_tuned_mapping(int func_id, int n, int level);
+int tuned_mapping(int func_id, int n, int precision);
+void record_tuned_mapping(int func_id, int n, int precision, int level);
 
 // Paper-model flops of one f call (Sec. V operation counts, chunk dot included).
 double model_flops_per_call(int func_id, int n, int C);

@@ -53,6 +53,35 @@ def test_mixed_against_oracle(gpu_lib, func, n, chunks):
         assert e_r > 0.0  # it really is a float32 computation
 
 
+@pytest.mark.parametrize("func", [R, A])
+def test_mixed_mappings(gpu_lib, func):
+    """The L0 / L1 mappings of chessfad_hvp_mixed compute the sums L2 does, in
+    the same order (float32 rounding may differ where the compiler contracts
+    multiply-adds differently); each stays within TOL32 of the oracle."""
+    prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 2)
+    try:
+        for n, npts in ((5, 70), (16, 300), (33, 9)):
+            w = inputs.make_workload(func, n, npts, inputs.rng_for(7300 + 10 * func + n))
+            x, v = _dev(w.x), _dev(w.v)
+            H_ref = cf.hessian(func, w.x, w.A, w.B, None)
+            hmax = np.abs(H_ref).max(axis=(1, 2))
+            r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, None)
+            scale = hmax * np.abs(w.v).max(axis=1)
+            for c in (1, 4, 16):
+                if c > n:
+                    continue
+                gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 2)
+                r2 = gpu_lib.chessfad_hvp_mixed(func, x, v, chunk=c).cpu().numpy()
+                for level in (1, 0):
+                    print(f"[case] mixed mapping L{level} func={func} n={n} C={c}", flush=True)
+                    gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, level)
+                    r = gpu_lib.chessfad_hvp_mixed(func, x, v, chunk=c).cpu().numpy()
+                    assert (np.abs(r - r2).max(axis=1) / scale).max() <= 1e-6
+                    assert (np.abs(r - r_ref).max(axis=1) / scale).max() <= TOL32
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev)
+
+
 @pytest.mark.parametrize("func", [R, A, FP])
 def test_mixed_full_size_sampled(gpu_lib, func):
     n, npts = 16, 1 << 20
