@@ -315,15 +315,17 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         // float64 H.v of the full form sums each lane's residual rows into the
         // chunk dots and adds the four lane groups once per row (the same
         // products, summed over m and the columns in another order); the
-        // Hessian, the symmetric form and float32 form every entry first
-        constexpr bool kLaneDot = !kHess && !kSym && sizeof(T) == sizeof(double);
+        // Hessian and the symmetric form form every entry first.  In float32
+        // the lane's four-row partial is a two-sum pair and its chunk dot is
+        // compensated (two-product, two-sum); the lanes' dots meet in float64.
+        constexpr bool kLaneDot = !kHess && !kSym;
         double lane_row = 0.0;
         // fixed trip counts (no early exit) so that rg is indexed statically
 #pragma unroll
         for (int jc = 0; jc < KCH; ++jc) {
             if (jc < nc && (!kSym || jc >= own)) {
                 const bool mirrored = kSym && jc > own;
-                typename P::Dot dot;
+                typename P::Dot dot;   // the row's chunk dot, or (float32 lane dots) the lane's
                 double lane_dot = 0.0;
 #pragma unroll
                 for (int l = 0; l < C; ++l) {
@@ -342,9 +344,21 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
                         }
-                        if constexpr (kLaneDot) {
+                        if constexpr (kLaneDot && sizeof(T) == sizeof(double)) {
                             const double tl = (t[0] + t[1]) + (t[2] + t[3]);
                             lane_dot += tl * (double)vw[li * kFpVStride + k];
+                        } else if constexpr (kLaneDot) {
+                            float hi = t[0], lo = 0.0f;
+#pragma unroll
+                            for (int r = 1; r < 4; ++r) {
+                                float s2, e2;
+                                two_sum(hi, t[r], s2, e2);
+                                hi = s2;
+                                lo += e2;
+                            }
+                            const T vk = vw[li * kFpVStride + k];
+                            dot.add(hi, vk);
+                            dot.lo += lo * vk;
                         } else {
                             // summed over all residual rows
                             const T h = row_sum4(t);
@@ -361,8 +375,10 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         }
                     }
                 }
-                if constexpr (kLaneDot)
+                if constexpr (kLaneDot && sizeof(T) == sizeof(double))
                     lane_row += lane_dot;
+                else if constexpr (kLaneDot)
+                    lane_row += dot.get();
                 else if (!kHess)
                     row += dot.get();
             }
