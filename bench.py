@@ -45,6 +45,11 @@ MEASURED_TRAFFIC = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0275e+08,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0275e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0313e+08,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0312e+08,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0310e+08,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0311e+08,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0310e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=2, H.v>": 4.0280e+08,
     "plain_kernel<ackley, C=4, H.v>": 4.0281e+08,
@@ -71,6 +76,11 @@ MEASURED_VALU_FLOPS = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 5.6858e+10,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 6.0314e+10,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 5.8754e+10,
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 1.8405e+10,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 1.7868e+10,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 1.7666e+10,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 1.7532e+10,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 1.7465e+10,
     "plain_kernel<ackley, C=1, H.v>": 9.7039e+10,
     "plain_kernel<ackley, C=2, H.v>": 6.7713e+10,
     "plain_kernel<ackley, C=4, H.v>": 5.7949e+10,
@@ -121,6 +131,9 @@ def parse():
     ap.add_argument("--batch-instances", type=int, default=8192)
     ap.add_argument("--large", action="store_true",
                     help="also time n=64 (2^18 points, float64 and mixed) and n=512 (1024 points) H.v")
+    ap.add_argument("--only", choices=("large", "batch"), default=None,
+                    help="only run the large-n timings or the batched workload and print their JSON "
+                         "(for profiling; not the benchmark line)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -215,7 +228,7 @@ def large_n(binding, inputs, cf, torch, flops):
         mf = flops.flops_per_hvp(f, n, c)
         res[f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"] = {
             "npts": npts, "chunk": c,
-            "mapping": "MFMA" if f == 2 else (f"L{binding.chessfad_default_mapping(f, n)}" if not prec and call_c == 0
+            "mapping": "MFMA" if f == 2 else (f"L{binding.chessfad_default_mapping(f, n, prec)}" if call_c == 0
                                               else "L2"),
             "kernel_ms": ms, "hvps_per_s": npts / (ms * 1e-3),
             "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
@@ -312,6 +325,12 @@ def main():
     from oracle import closed_form as cf
 
     binding.load()
+    if args.only == "large":
+        print(json.dumps({"large_n": large_n(binding, inputs, cf, torch, flops)}), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps({"batched": batched(args.batch_instances, binding, inputs, cf, torch)}), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     npts = args.npts
@@ -480,7 +499,8 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
-        mixed[NAMES[f]] = {"chunk": mc, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
+        mmap = "MFMA" if f == 2 and N <= 16 else f"L{binding.chessfad_default_mapping(f, N, 1)}" if not args.chunk else "L2"
+        mixed[NAMES[f]] = {"chunk": mc, "mapping": mmap, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                            "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
 
     # the paper's three GPU mappings of H.v (Sec. VI) for the vector-ALU

@@ -310,11 +310,12 @@ int chessfad_autotune_sym(int func_id, int n, int precision, int64_t npts, void*
  * or a negative status for invalid arguments. */
 int chessfad_default_chunk(int func_id, int n);
 
-/* The GPU mapping chessfad_hvp (float64) uses for (func_id, n) with chunk = 0 when f
- * runs on the vector ALUs: 0 (L0), 1 (L1) or 2 (L2); the option if set,
- * else 1 when the default chunk leaves one chunk per row, else the tuned
- * mapping, else 2.  Host only; a negative status for a bad func_id or n. */
-int chessfad_default_mapping(int func_id, int n);
+/* The GPU mapping chessfad_hvp (precision 0) or chessfad_hvp_mixed (1) uses
+ * for (func_id, n) with chunk = 0 when f runs on the vector ALUs: 0 (L0),
+ * 1 (L1) or 2 (L2); the option if set, else 1 when the chunk chunk = 0
+ * resolves to leaves one chunk per row, else the tuned mapping, else 2.
+ * Host only; a negative status for a bad func_id, n or precision. */
+int chessfad_default_mapping(int func_id, int n, int precision);
 
 #ifdef __cplusplus
 }

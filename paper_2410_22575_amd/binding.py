@@ -38,7 +38,7 @@ SIGNATURES = {
     "chessfad_fp_release": (_i, [_i]),
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
-    "chessfad_default_mapping": (_i, [_i, _i]),
+    "chessfad_default_mapping": (_i, [_i, _i, _i]),
     "chessfad_register_function": (_i, [_s, _pi]),
     "chessfad_release_function": (_i, [_i]),
     "chessfad_set_option": (_i, [_i, _i]),
@@ -206,8 +206,8 @@ def chessfad_release_function(func_id: int) -> None:
     _raise(load().chessfad_release_function(func_id), "chessfad_release_function")
 
 
-def chessfad_default_mapping(func_id: int, n: int) -> int:
-    return load().chessfad_default_mapping(func_id, n)
+def chessfad_default_mapping(func_id: int, n: int, precision: int = 0) -> int:
+    return load().chessfad_default_mapping(func_id, n, precision)
 
 
 def chessfad_default_chunk(func_id: int, n: int) -> int:

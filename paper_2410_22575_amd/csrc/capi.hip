@@ -505,12 +505,13 @@ int chessfad_default_chunk(int func_id, int n) {
     return rc ? rc : resolve_chunk(func_id, n, 0, 16);
 }
 
-int chessfad_default_mapping(int func_id, int n) {
+int chessfad_default_mapping(int func_id, int n, int precision) {
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
+    if (precision != 0 && precision != 1) return CHESSFAD_E_ARG;
     if (g_opt_mapping != 2) return g_opt_mapping;
-    const int c = resolve_chunk(func_id, n, 0, 16);
-    return (n + c - 1) / c == 1 ? 1 : tuned_mapping(func_id, n, 0);
+    const int c = resolve_chunk(func_id, n, precision, 16);
+    return (n + c - 1) / c == 1 ? 1 : tuned_mapping(func_id, n, precision);
 }
 
 }  // extern "C"

@@ -167,8 +167,10 @@ def test_options(lib):
 
 
 def test_default_chunk(lib):
-    assert lib.chessfad_default_mapping(R, 16) in (1, 2)
-    assert lib.chessfad_default_mapping(9, 16) == E_FUNC
+    assert lib.chessfad_default_mapping(R, 16, 0) in (1, 2)
+    assert lib.chessfad_default_mapping(A, 16, 1) in (1, 2)
+    assert lib.chessfad_default_mapping(9, 16, 0) == E_FUNC
+    assert lib.chessfad_default_mapping(R, 16, 2) == E_ARG
     assert lib.chessfad_default_chunk(R, 16) in (1, 2, 4, 8, 16)
     assert lib.chessfad_default_chunk(A, 1) == 1
     assert lib.chessfad_default_chunk(5, 16) == E_FUNC
