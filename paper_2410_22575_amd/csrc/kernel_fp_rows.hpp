@@ -31,12 +31,15 @@
 // sums over chunks in chunk order, pass after pass; Hessian: H[p][i][cs + l]
 // is stored.
 //
-// Calls are laid out chunk-major within a pass (consecutive lanes take
-// consecutive rows of one chunk), so the lanes of a wave read the same g
-// entries (LDS broadcast) and consecutive d and h entries.
+// Within a pass a lane takes kFpRowsCallsPerLane calls of one chunk (rows
+// t, t + slot, ...) and reads each g entry once for all of them; consecutive
+// lanes take consecutive rows, so the lanes of a wave read the same g entries
+// (LDS broadcast) and consecutive d and h entries.
 #pragma once
 
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "kernel_fp_mfma.hpp"
 
@@ -72,9 +75,13 @@ __host__ __device__ inline int fp_rows_pass_chunks(int n, int C) {
 // Rows per workgroup: as many as keep a pass's calls within kFpRowsMaxCalls,
 // at most kFpRowsMaxRows and n.
 __host__ __device__ inline int fp_rows_per_block(int n, int C) {
-    int r = kFpRowsMaxCalls / fp_rows_pass_chunks(n, C);
+    const int cpp = fp_rows_pass_chunks(n, C);
+    int r = kFpRowsMaxCalls / cpp;
     if (r > kFpRowsMaxRows) r = kFpRowsMaxRows;
     if (r > n) r = n;
+    // a lane takes kFpRowsCallsPerLane rows of one chunk: the chunks' row
+    // slots must fit the workgroup's lanes
+    while (r > 1 && cpp * ((r + kFpRowsCallsPerLane - 1) / kFpRowsCallsPerLane) > 64 * kFpRowsWaves) --r;
     return r < 1 ? 1 : r;
 }
 
@@ -208,17 +215,26 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
         const int ktiles = (kcount + 15) / 16;
         const int pcalls = nrows * ncp;
 
-        // the lane's calls of this pass: call cl -> chunk jc0 + cl / nrows, row r0 + cl % nrows
-        int ci[Q], ccs[Q], clo[Q];
+        // the lane's calls of this pass: one chunk jc0 + jl, and rows t, t + slot,
+        // ... of it, so that the lane reads each g entry once for all its
+        // calls; a lane takes as few calls as keep every call of the pass on
+        // some lane (slot = ceil(nrows / ceil(pcalls / lanes)))
+        const int per_lane = (pcalls + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int slot = (nrows + per_lane - 1) / per_lane;
+        const int lane_jl = threadIdx.x / slot;
+        const bool lane_on = lane_jl < ncp;
+        const int jl = lane_on ? lane_jl : 0;
+        const int t0 = threadIdx.x - lane_jl * slot;
+        const int cs_lane = (jc0 + jl) * C;
+        int ci[Q], clo[Q], cdi[Q];
         bool cval[Q], cown[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int cl = threadIdx.x + q * (int)blockDim.x;
-            cval[q] = cl < pcalls;
-            const int jl = cval[q] ? cl / nrows : 0;
-            ci[q] = r0 + (cval[q] ? cl - jl * nrows : 0);
-            ccs[q] = (jc0 + jl) * C;
-            clo[q] = ci[q] - ccs[q];
+            const int t = t0 + q * slot;
+            cval[q] = lane_on && t < nrows;
+            ci[q] = r0 + (cval[q] ? t : 0);
+            cdi[q] = jl * nrows + (cval[q] ? t : 0);   // the call's slot in dots, [chunk][row]
+            clo[q] = ci[q] - cs_lane;
             cown[q] = cval[q] && clo[q] >= 0 && clo[q] < C;
         }
         RunSum<T> fh[Q][C];
@@ -259,28 +275,43 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
             // vector phase: the second-order components of r_m * r_m for the
             // tile's residuals
             const int mcount = n - mt * 16 < 16 ? n - mt * 16 : 16;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                if (!cval[q]) continue;
-                const int i = ci[q], il = i - r0;
-                const int csl = ccs[q] - kbase;
+            // NQ calls per lane (NQ = per_lane, uniform over the workgroup)
+            auto valu = [&](auto nq) {
+                constexpr int NQ = decltype(nq)::value;
+                const int csl = cs_lane - kbase;
                 for (int mm = 0; mm < mcount; ++mm) {
-                    const T rd = one_pass ? sh.gk[mm][i] : sh.gi[mm][il];
                     const T* gm = &sh.gk[mm][csl];
+                    T rd[NQ];
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) rd[q] = one_pass ? sh.gk[mm][ci[q]] : sh.gi[mm][ci[q] - r0];
 #pragma unroll
                     for (int l = 0; l < C; ++l) {
-                        const T pr = rd * gm[l];
-                        fh[q][l].add(pr + pr);
+                        const T g = gm[l];
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            const T pr = rd[q] * g;
+                            fh[q][l].add(pr + pr);
+                        }
                     }
-                    if (cown[q]) {
-                        const T rv = (T)sh.rvs[mt * 16 + mm], rh = sh.hi[mm][il], rg = gm[clo[q]];
-                        fo[q].add(rv * rh + rd * rg + rd * rg + rv * rh);
-                    }
-                    if (want_grad && ccs[q] == 0) {
-                        const T rv = (T)sh.rvs[mt * 16 + mm];
-                        fd[q].add(rv * rd + rd * rv);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        if (cown[q]) {
+                            const T rv = (T)sh.rvs[mt * 16 + mm], rh = sh.hi[mm][ci[q] - r0], rg = gm[clo[q]];
+                            fo[q].add(rv * rh + rd[q] * rg + rd[q] * rg + rv * rh);
+                        }
+                        if (want_grad && cs_lane == 0 && cval[q]) {
+                            const T rv = (T)sh.rvs[mt * 16 + mm];
+                            fd[q].add(rv * rd[q] + rd[q] * rv);
+                        }
                     }
                 }
+            };
+            static_assert(Q == 2, "the vector phase takes one or two calls per lane");
+            if (lane_on) {
+                if (per_lane == 1)
+                    valu(std::integral_constant<int, 1>{});
+                else
+                    valu(std::integral_constant<int, 2>{});
             }
         }
 
@@ -288,7 +319,7 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if (!cval[q]) continue;
-            const int i = ci[q], cs = ccs[q];
+            const int i = ci[q], cs = cs_lane;
             T hv[C];
 #pragma unroll
             for (int l = 0; l < C; ++l) hv[l] = cown[q] && l == clo[q] ? fo[q].value() : fh[q][l].value();
@@ -302,7 +333,7 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
 #pragma unroll
                 for (int l = 0; l < C; ++l)
                     if (cs + l < n) dot.add(hv[l], (T)sh.vv[cs + l]);
-                sh.dots[threadIdx.x + q * blockDim.x] = dot.get();
+                sh.dots[cdi[q]] = dot.get();
                 if (want_grad && cs == 0) a.grad[p * n + i] = (double)fd[q].value();
             }
         }
