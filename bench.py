@@ -35,16 +35,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 4.0280e+08,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 4.0279e+08,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 4.0281e+08,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 4.0281e+08,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0284e+08,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.0274e+08,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.0274e+08,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0275e+08,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0275e+08,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
     "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0313e+08,
     "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0312e+08,
     "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0310e+08,
@@ -66,16 +56,6 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 7.5527e+10,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 5.8548e+10,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 5.4656e+10,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 5.1166e+10,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 4.9421e+10,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 7.9809e+10,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 6.5767e+10,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 5.6858e+10,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 6.0314e+10,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 5.8754e+10,
     "fp_mfma_kernel<C=1, NK=8, H.v>": 1.8405e+10,
     "fp_mfma_kernel<C=2, NK=8, H.v>": 1.7868e+10,
     "fp_mfma_kernel<C=4, NK=8, H.v>": 1.7666e+10,

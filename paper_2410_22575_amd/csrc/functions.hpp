@@ -78,20 +78,36 @@ struct Rosenbrock {
         return T(100) * (b * b) + e * e;
     }
 
-    template <class P, int C>
+    // kSplit: the terms k whose variables y_k, y_k+1 both lie outside the
+    // call's chunk [cs, cs + C) have seeds with no g part, so their g and h
+    // components are exact zeros; they run on HD<T, 0> (value and row
+    // derivative only), in the same order as the others.  For kernels whose
+    // lanes of a wave share cs.
+    template <class P, int C, bool kSplit = false>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        HD1<T, C> yk = pv.template y<C>(0);
-        HD1<T, C> yk1 = pv.template y<C>(1);
-        auto s = P::start(term<T, C>(yk, yk1));
-        // second-order component (i, cs + l) of term k is nonzero only when
-        // both i and cs + l are k or k + 1: at most two terms per component
-        for (int k = 1; k + 1 < pv.n; ++k) {
-            yk = yk1;
-            yk1 = pv.template y<C>(k + 1);
-            P::add_sparse(s, term<T, C>(yk, yk1));
+        if constexpr (!kSplit) {
+            HD1<T, C> yk = pv.template y<C>(0);
+            HD1<T, C> yk1 = pv.template y<C>(1);
+            auto s = P::start(term<T, C>(yk, yk1));
+            // second-order component (i, cs + l) of term k is nonzero only when
+            // both i and cs + l are k or k + 1: at most two terms per component
+            for (int k = 1; k + 1 < pv.n; ++k) {
+                yk = yk1;
+                yk1 = pv.template y<C>(k + 1);
+                P::add_sparse(s, term<T, C>(yk, yk1));
+            }
+            return P::value(s);
+        } else {
+            const int nt = pv.n - 1;                                 // terms
+            const int k0 = pv.cs > 0 ? pv.cs - 1 : 0;                // first term touching the chunk
+            const int k1 = pv.cs + C < nt ? pv.cs + C : nt;          // one past the last
+            auto s = P::start(zero_hd<T, C>());
+            for (int k = 0; k < k0; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
+            for (int k = k0; k < k1; ++k) P::add_sparse(s, term<T, C>(pv.template y<C>(k), pv.template y<C>(k + 1)));
+            for (int k = k1; k < nt; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
+            return P::value(s);
         }
-        return P::value(s);
     }
 };
 
@@ -129,18 +145,42 @@ struct Ackley {
         return chain(T(kTwoPi) * pv.template y<C>(k), c, -s, -c);
     }
 
-    template <class P, int C>
+    // kSplit: as for Rosenbrock, the terms of variables outside the chunk
+    // run on HD<T, 0>
+    template <class P, int C, bool kSplit = false>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        HD1<T, C> y = pv.template y<C>(0);
-        auto ss = P::start(y * y);
-        auto cs = P::start(cos_term<T, C>(pv, 0));
-        // second-order component (i, cs + l) of a term in y_k is nonzero only
-        // for k = i = cs + l: at most one term per component
-        for (int k = 1; k < pv.n; ++k) {
-            y = pv.template y<C>(k);
-            P::add_sparse(ss, y * y);
-            P::add_sparse(cs, cos_term<T, C>(pv, k));
+        typename P::template Acc<C> ss, cs;
+        if constexpr (!kSplit) {
+            HD1<T, C> y = pv.template y<C>(0);
+            ss = P::start(y * y);
+            cs = P::start(cos_term<T, C>(pv, 0));
+            // second-order component (i, cs + l) of a term in y_k is nonzero only
+            // for k = i = cs + l: at most one term per component
+            for (int k = 1; k < pv.n; ++k) {
+                y = pv.template y<C>(k);
+                P::add_sparse(ss, y * y);
+                P::add_sparse(cs, cos_term<T, C>(pv, k));
+            }
+        } else {
+            const int k0 = pv.cs, k1 = pv.cs + C < pv.n ? pv.cs + C : pv.n;
+            ss = P::start(zero_hd<T, C>());
+            cs = P::start(zero_hd<T, C>());
+            for (int k = 0; k < k0; ++k) {
+                const HD1<T, 0> y = pv.template y<0>(k);
+                P::add_light(ss, y * y);
+                P::add_light(cs, cos_term<T, 0>(pv, k));
+            }
+            for (int k = k0; k < k1; ++k) {
+                const HD1<T, C> y = pv.template y<C>(k);
+                P::add_sparse(ss, y * y);
+                P::add_sparse(cs, cos_term<T, C>(pv, k));
+            }
+            for (int k = k1; k < pv.n; ++k) {
+                const HD1<T, 0> y = pv.template y<0>(k);
+                P::add_light(ss, y * y);
+                P::add_light(cs, cos_term<T, 0>(pv, k));
+            }
         }
         const T inv_n = T(1.0 / pv.n);
         HD<T, C> t = inv_n * P::value(ss);
@@ -199,7 +239,7 @@ struct FletcherPowell {
         return r;
     }
 
-    template <class P, int C>
+    template <class P, int C, bool kSplit = false>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams& prm) {
         using T = typename P::T;
         HD<T, C> r = residual<T, C>(pv, prm, 0);

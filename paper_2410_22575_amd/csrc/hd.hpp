@@ -24,11 +24,28 @@ namespace chessfad {
 
 #define CF_DEV __device__ __forceinline__
 
+// HD<T, 0> (value and row derivative only) carries a term whose seeds have
+// no component in the call's chunk: its g and h parts are exact zeros.
 template <typename T, int C>
 struct HD {
     T v, d;
     T g[C], h[C];
 };
+template <typename T>
+struct HD<T, 0> {
+    T v, d;
+    T g[1], h[1];   // never read: every loop over the chunk has zero trips
+};
+
+template <typename T, int C>
+CF_DEV HD<T, C> zero_hd() {
+    HD<T, C> r;
+    r.v = T(0);
+    r.d = T(0);
+#pragma unroll
+    for (int l = 0; l < C; ++l) r.g[l] = r.h[l] = T(0);
+    return r;
+}
 
 template <typename T, int C>
 CF_DEV HD<T, C> operator+(const HD<T, C>& a, const HD<T, C>& b) {
@@ -130,6 +147,11 @@ template <typename T, int C>
 struct HD1 {
     T v, d;
     T g[C];
+};
+template <typename T>
+struct HD1<T, 0> {
+    T v, d;
+    T g[1];   // never read
 };
 
 // CHUNK-INIT for one variable: y_k = <x_k, [k = i], [k = cs + l], 0>.
@@ -252,6 +274,12 @@ struct F64 {
     static CF_DEV void add(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
     template <int C>
     static CF_DEV void add_sparse(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
+    // a term with no component in the chunk: value and row derivative only
+    template <int C>
+    static CF_DEV void add_light(Acc<C>& a, const HD<T, 0>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
+    }
     template <int C>
     static CF_DEV HD<T, C> value(const Acc<C>& a) { return a.x; }
     // chunk dot sum_l h[l] v[l]
@@ -307,6 +335,11 @@ struct F32C {
             a.x.g[l] += t.g[l];
             a.x.h[l] = __fadd_rn(a.x.h[l], t.h[l]);
         }
+    }
+    template <int C>
+    static CF_DEV void add_light(Acc<C>& a, const HD<T, 0>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
     }
     template <int C>
     static CF_DEV HD<T, C> value(const Acc<C>& a) {

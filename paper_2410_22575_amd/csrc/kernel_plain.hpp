@@ -15,7 +15,9 @@
 //      H.v: dots its Hessian chunk with v[p][cs .. cs + C), then the row's
 //      nc partial sums are added in chunk order in float64 (CHESS-VEC).
 // coarse_kernel runs the paper's coarser mappings L1 and L0 on the same
-// staging, for comparison.
+// staging.  There the lanes of a wave are at the same chunk, so the terms of
+// f whose variables lie outside the chunk run on HD<T, 0> (their g and h
+// components are exact zeros; see the functions' eval).
 #pragma once
 
 #include <stdint.h>
@@ -197,7 +199,8 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
         for (int j = 0; j < nc; ++j) {
             const int cs = j * C;
             PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
-            const HD<T, C> h = F::template eval<P, C>(pv, a.fp);
+            // the lanes of a wave are at the same chunk: terms outside it run light
+            const HD<T, C> h = F::template eval<P, C, true>(pv, a.fp);
             typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)
