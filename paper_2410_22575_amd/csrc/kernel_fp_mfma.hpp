@@ -191,6 +191,10 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     T g1[NK], g2[NK];
     double gv[NK];
     int jj[NK];
+    // n = 2 NK with NK even: the cos half's step s holds the coordinates of
+    // the sin half's step s - NK / 2, so their sin and cos are reused
+    const bool halves = NK % 2 == 0 && n == 2 * NK;
+    double ssv[NK], csv[NK];
 #pragma unroll
     for (int s = 0; s < NK; ++s) {
         const int k = 4 * s + lg;
@@ -199,7 +203,14 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         aop64[s] = (li < n && in) ? (k < n ? a.fp.A[li * n + k] : a.fp.B[li * n + j]) : 0.0;
         aop[s] = (T)aop64[s];
         double sj = 0.0, cj = 0.0;
-        if (in && live) sincos(xp[j], &sj, &cj);
+        if (halves && s >= NK / 2) {
+            sj = ssv[s >= NK / 2 ? s - NK / 2 : 0];
+            cj = csv[s >= NK / 2 ? s - NK / 2 : 0];
+        } else if (in && live) {
+            sincos(xp[j], &sj, &cj);
+        }
+        ssv[s] = sj;
+        csv[s] = cj;
         jj[s] = in ? j : -1;
         gv[s] = k < n ? sj : cj;          // value
         g1[s] = (T)(k < n ? cj : -sj);    // first-derivative factor
@@ -336,7 +347,12 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         // rows (independent terms: a chain through one
                         // accumulator is slower)
                         T t[4];
-                        if (k == i) {
+                        if (kLaneDot && sizeof(T) == sizeof(double)) {
+                            // every entry here, the row's own one too: its two
+                            // r.v r.h products are added after the chunk
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
+                        } else if (k == i) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
                                 t[r] = rv[r] * rh[r] + rd[r] * rg[k][r] + rd[r] * rg[k][r] + rv[r] * rh[r];
@@ -375,8 +391,16 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         }
                     }
                 }
-                if constexpr (kLaneDot && sizeof(T) == sizeof(double))
+                if constexpr (kLaneDot && sizeof(T) == sizeof(double)) {
+                    if (jc == own) {
+                        // the own entry's r.v r.h + ... + r.v r.h: its remaining products
+                        double o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = rv[r] * rh[r] + rv[r] * rh[r];
+                        lane_dot += ((o[0] + o[1]) + (o[2] + o[3])) * (double)vw[li * kFpVStride + i];
+                    }
                     lane_row += lane_dot;
+                }
                 else if constexpr (kLaneDot)
                     lane_row += dot.get();
                 else if (!kHess)
