@@ -13,9 +13,11 @@
 //
 // Work decomposition: a workgroup owns `ppb` whole points.  The calls of one
 // point are the pairs (b, cn), b <= cn < nc, times the C rows i = b C + ii of
-// row block b; one lane per (point, pair, ii), ii fastest, so the C lanes of
-// a pair are adjacent and aligned within a wave.  The workgroup loops over
-// its ppb * C * nc (nc + 1) / 2 calls in strides of blockDim.x.
+// row block b; one lane per (pair, point, ii), ii fastest and then points, so
+// the C lanes of a pair are adjacent and aligned within a wave, and the lanes
+// of a wave mostly share a pair (and its chunk cs: the terms of f outside the
+// chunk run light).  The workgroup loops over its ppb * C * nc (nc + 1) / 2
+// calls in strides of blockDim.x.
 //
 // H.v reductions, all in LDS and in a fixed order (bitwise reproducible):
 //   own(i, cn)  the lane's chunk dot (as in CHESS-VEC), one slot per call,
@@ -139,13 +141,18 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
     //    pair reductions always see all lanes of the wave
     const int total = npb * per_point;  // a multiple of C: pairs never straddle the end
     for (int base = 0; base < total; base += blockDim.x) {
+        // t -> (pair, point, ii), ii fastest and then points: the lanes of a
+        // wave share a pair (b, cn) across points, so they share the chunk
+        // cs and f's terms outside it run light
         const int t = base + threadIdx.x;
         const bool in_range = t < total;
         const int tt = in_range ? t : 0;
-        const int pl = tt / per_point;
-        const int local = tt - pl * per_point;
-        int pair = local / C;
         const int ii = tt % C;
+        const int rest = tt / C;
+        const int pair0 = rest / npb;
+        const int pl = rest - pair0 * npb;
+        const int local = pair0 * C + ii;
+        int pair = pair0;
         int b = 0;
         while (pair >= nc - b) {
             pair -= nc - b;
@@ -161,7 +168,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
         for (int l = 0; l < C; ++l) m[l] = 0.0;
         if (active) {
             PointView<T> pv{xs + pl, t0 + pl, t1 + pl, isl + pl, ps, n, i, cs};
-            const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
+            const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
             if (kHess) {
                 double* Hp = a.out + (p0 + pl) * (int64_t)n * n;
 #pragma unroll
