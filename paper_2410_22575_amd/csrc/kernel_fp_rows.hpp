@@ -24,9 +24,10 @@
 // residual m in order, the second-order components of r_m * r_m,
 //   2 r_m.d r_m.g[l], and on the row's own column
 //   r_m.v r_m.h + r_m.d r_m.g + r_m.d r_m.g + r_m.v r_m.h (the product rule),
-// added into the call's running sums (two-sum compensated in float32); the
-// own column runs in a sum of its own, which replaces entry l = i - cs at the
-// end.  The residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j are
+// added into the call's running sums (in float32 the 16 residuals of an m
+// tile are summed plainly and each tile's partial enters a two-sum
+// compensated running sum); the own column runs in a sum of its own (two-sum
+// per term in float32), which replaces entry l = i - cs at the end.  The residual values r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j are
 // float64 and computed once per point.  H.v: chunk dot with v, then the row
 // sums over chunks in chunk order, pass after pass; Hessian: H[p][i][cs + l]
 // is stored.
@@ -278,6 +279,15 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
             // NQ calls per lane (NQ = per_lane, uniform over the workgroup)
             auto valu = [&](auto nq) {
                 constexpr int NQ = decltype(nq)::value;
+                // float32: the tile's residuals are summed plainly and the
+                // tile's partial enters the compensated running sum (blocked
+                // compensation, one two-sum per 16 terms); float64: term by term
+                constexpr bool kTile = sizeof(T) == sizeof(float);
+                T part[NQ][C];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                    for (int l = 0; l < C; ++l) part[q][l] = zero;
                 const int csl = cs_lane - kbase;
                 for (int mm = 0; mm < mcount; ++mm) {
                     const T* gm = &sh.gk[mm][csl];
@@ -290,7 +300,10 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
 #pragma unroll
                         for (int q = 0; q < NQ; ++q) {
                             const T pr = rd[q] * g;
-                            fh[q][l].add(pr + pr);
+                            if constexpr (kTile)
+                                part[q][l] += pr + pr;
+                            else
+                                fh[q][l].add(pr + pr);
                         }
                     }
 #pragma unroll
@@ -304,6 +317,12 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
                             fd[q].add(rv * rd[q] + rd[q] * rv);
                         }
                     }
+                }
+                if constexpr (kTile) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                        for (int l = 0; l < C; ++l) fh[q][l].add(part[q][l]);
                 }
             };
             static_assert(Q == 2, "the vector phase takes one or two calls per lane");
