@@ -327,7 +327,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         // chunk dots and adds the four lane groups once per row (the same
         // products, summed over m and the columns in another order); the
         // Hessian and the symmetric form form every entry first.  In float32
-        // the lane's four-row partial is a two-sum pair and its chunk dot is
+        // the lane's four-row partial is a plain sum and its chunk dot is
         // compensated (two-product, two-sum); the lanes' dots meet in float64.
         constexpr bool kLaneDot = !kHess && !kSym;
         double lane_row = 0.0;
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         // rows (independent terms: a chain through one
                         // accumulator is slower)
                         T t[4];
-                        if (kLaneDot && sizeof(T) == sizeof(double)) {
+                        if (kLaneDot) {
                             // every entry here, the row's own one too: its two
                             // r.v r.h products are added after the chunk
 #pragma unroll
@@ -364,17 +364,10 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                             const double tl = (t[0] + t[1]) + (t[2] + t[3]);
                             lane_dot += tl * (double)vw[li * kFpVStride + k];
                         } else if constexpr (kLaneDot) {
-                            float hi = t[0], lo = 0.0f;
-#pragma unroll
-                            for (int r = 1; r < 4; ++r) {
-                                float s2, e2;
-                                two_sum(hi, t[r], s2, e2);
-                                hi = s2;
-                                lo += e2;
-                            }
-                            const T vk = vw[li * kFpVStride + k];
-                            dot.add(hi, vk);
-                            dot.lo += lo * vk;
+                            // the lane's four residuals summed plainly, the
+                            // chunk dot compensated (blocked compensation)
+                            const float tl = (t[0] + t[1]) + (t[2] + t[3]);
+                            dot.add(tl, vw[li * kFpVStride + k]);
                         } else {
                             // summed over all residual rows
                             const T h = row_sum4(t);
@@ -400,9 +393,15 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         lane_dot += ((o[0] + o[1]) + (o[2] + o[3])) * (double)vw[li * kFpVStride + i];
                     }
                     lane_row += lane_dot;
-                }
-                else if constexpr (kLaneDot)
+                } else if constexpr (kLaneDot) {
+                    if (jc == own) {
+                        T o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = rv[r] * rh[r] + rv[r] * rh[r];
+                        dot.add((o[0] + o[1]) + (o[2] + o[3]), vw[li * kFpVStride + i]);
+                    }
                     lane_row += dot.get();
+                }
                 else if (!kHess)
                     row += dot.get();
             }
