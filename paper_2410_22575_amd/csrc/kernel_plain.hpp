@@ -4,8 +4,7 @@
 // per (point p, row i, chunk j).  A workgroup owns `rows` consecutive row
 // tasks of the flattened (p, i) index q = p * n + i, so rows of one point may
 // span two workgroups and one workgroup may hold several points; its lanes
-// are ordered rows fastest for H.v (lane j * rows + r), chunks fastest for the
-// Hessian (lane r * nc + j).  Each workgroup:
+// are ordered rows fastest (lane j * rows + r).  Each workgroup:
 //   1. stages the coordinates of its points and, for H.v, their vectors into
 //      LDS as structure-of-arrays, with the function's per-coordinate
 //      transcendental tables (float64);
@@ -15,8 +14,8 @@
 //   4. Hessian: writes H[p][i][cs .. cs + C) (columns < n only, CHUNK-HESS);
 //      H.v: dots its Hessian chunk with v[p][cs .. cs + C), then the row's
 //      nc partial sums are added in chunk order in float64 (CHESS-VEC).
-//      For H.v the terms of f outside the chunk run light (HD<T, 0>), as in
-//      the coarse kernels: a wave's lanes share a chunk when rows >= 64.
+//      The terms of f outside the chunk run light (HD<T, 0>), as in the
+//      coarse kernels: a wave's lanes share a chunk when rows >= 64.
 // coarse_kernel runs the paper's coarser mappings L1 and L0 on the same
 // staging.  There the lanes of a wave are at the same chunk, so the terms of
 // f whose variables lie outside the chunk run on HD<T, 0> (their g and h
@@ -122,11 +121,10 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     // 1-2. staging and islands
     const PlainStage<T> st = plain_stage<P, F, kHess>(a, p0, npb, nthr, lds);
 
-    // H.v: rows fastest, so that the lanes of a wave share a chunk (and the
-    // terms of f outside it run light); Hessian: chunks fastest, so that a
-    // row's stores are contiguous
-    const int r = kHess ? threadIdx.x / nc : threadIdx.x % a.rows;
-    const int j = kHess ? threadIdx.x - r * nc : threadIdx.x / a.rows;
+    // rows fastest, so that the lanes of a wave share a chunk (and the terms
+    // of f outside it run light)
+    const int r = threadIdx.x % a.rows;
+    const int j = threadIdx.x / a.rows;
     const int64_t q = q0 + r;
     const bool active = threadIdx.x < nthr && q <= qlast;
     const int64_t p = q / n;
@@ -138,7 +136,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     if (active) {
         PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
         // 3. one f evaluation on hDual<C> seeds
-        const HD<T, C> res = F::template eval<P, C, !kHess>(pv, a.fp);
+        const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
         if (kHess) {
             // 4a. CHUNK-HESS: H[p][i][cs + l] = second-order component l
             double* row = a.out + q * n + cs;
