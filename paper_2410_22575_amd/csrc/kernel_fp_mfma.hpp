@@ -174,7 +174,9 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     using V = typename MfmaTile<T>::V;
     __shared__ T vs[kHess ? 1 : kFpWaves * kFpPointsPerWave * kFpVStride];
     // mirror sums of the symmetric H.v, one row of kFpVStride per point
-    __shared__ double msum[(kSym && !kHess) ? kFpWaves * kFpPointsPerWave * kFpVStride : 1];
+    // (float64: one array per lane group, which adds its four residuals' part)
+    constexpr int kMirGroups = sizeof(T) == sizeof(double) ? 4 : 1;
+    __shared__ double msum[(kSym && !kHess) ? kFpWaves * kMirGroups * kFpPointsPerWave * kFpVStride : 1];
 
     const int n = a.n, nc = a.nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -252,7 +254,9 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
     }
 
     T* vw = vs + wave * kFpPointsPerWave * kFpVStride;
-    double* mw = msum + ((kSym && !kHess) ? wave * kFpPointsPerWave * kFpVStride : 0);
+    double* mwave = msum + ((kSym && !kHess) ? wave * kMirGroups * kFpPointsPerWave * kFpVStride : 0);
+    // this lane's mirror array: its lane group's (float64) or the wave's
+    double* mw = mwave + (kMirGroups == 4 ? lg * kFpPointsPerWave * kFpVStride : 0);
     if (!kHess) {
         // stage the wave's 16 vectors (contiguous in global memory) in LDS
         const double* vg = a.v + pbase * n;
@@ -260,8 +264,9 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         for (int idx = lane; idx < kFpPointsPerWave * n; idx += 64) {
             const int pl = idx / n, k = idx - pl * n;
             vw[pl * kFpVStride + k] = (T)(idx < avail ? vg[idx] : 0.0);
-            if (kSym) mw[pl * kFpVStride + k] = 0.0;
         }
+        if (kSym)
+            for (int idx = lane; idx < kMirGroups * kFpPointsPerWave * kFpVStride; idx += 64) mwave[idx] = 0.0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -323,13 +328,14 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
 
         double row = 0.0;
         const int own = i / C;
-        // float64 H.v of the full form sums each lane's residual rows into the
-        // chunk dots and adds the four lane groups once per row (the same
-        // products, summed over m and the columns in another order); the
-        // Hessian and the symmetric form form every entry first.  In float32
+        // float64 H.v sums each lane's residual rows into the chunk dots and
+        // adds the four lane groups once per row (the same products, summed
+        // over m and the columns in another order); in the symmetric form
+        // each lane group also keeps its part of the mirror terms.  The
+        // Hessian and the float32 symmetric form form every entry first.  In float32
         // the lane's four-row partial is a plain sum and its chunk dot is
         // compensated (two-product, two-sum); the lanes' dots meet in float64.
-        constexpr bool kLaneDot = !kHess && !kSym;
+        constexpr bool kLaneDot = !kHess && (!kSym || sizeof(T) == sizeof(double));
         double lane_row = 0.0;
         // fixed trip counts (no early exit) so that rg is indexed statically
 #pragma unroll
@@ -363,6 +369,8 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         if constexpr (kLaneDot && sizeof(T) == sizeof(double)) {
                             const double tl = (t[0] + t[1]) + (t[2] + t[3]);
                             lane_dot += tl * (double)vw[li * kFpVStride + k];
+                            // symmetric form: the lane group's part of H(i, k) v[i] for r(k)
+                            if (mirrored) mw[li * kFpVStride + k] += tl * (double)vw[li * kFpVStride + i];
                         } else if constexpr (kLaneDot) {
                             // the lane's four residuals summed plainly, the
                             // chunk dot compensated (blocked compensation)
@@ -407,7 +415,13 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
             }
         }
         if constexpr (kLaneDot) row = pair_sum<32>(pair_sum<16>(lane_row));
-        if (kSym && !kHess) row += mw[li * kFpVStride + i];
+        if (kSym && !kHess) {
+            // r(i)'s mirror terms, from the rows of earlier row blocks (all done)
+            double mir = mwave[li * kFpVStride + i];
+#pragma unroll
+            for (int g = 1; g < kMirGroups; ++g) mir += mwave[(g * kFpPointsPerWave + li) * kFpVStride + i];
+            row += mir;
+        }
         if (!kHess && live && lg == 0) a.out[p * n + i] = row;
     }
 }
