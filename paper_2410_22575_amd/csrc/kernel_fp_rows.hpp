@@ -131,7 +131,6 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
     const int64_t p = blk / a.row_blocks;
     const int r0 = (int)(blk - p * a.row_blocks) * a.rows;
     const int nrows = (r0 + a.rows <= n ? a.rows : n - r0);
-    const int ncalls = nrows * nc;
     const double* xp = a.x + p * n;
 
     // per-point prologue (float64): sin/cos of the coordinates, the vector,
