@@ -108,10 +108,12 @@ int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* 
  * inputs and outputs stay float64).
  *   - every hDual component is carried in float32 (coordinates, v and the
  *     per-coordinate sin/cos tables are rounded to float32 where used);
- *   - the Hessian-chunk components of the sums inside f (Rosenbrock's sum of
- *     terms, Ackley's two sums, the Fletcher-Powell sum of squared
- *     residuals) accumulate with two-sum compensation; the chunk dot uses
- *     two-product and two-sum; the row sum over chunks is float64;
+ *   - the Hessian-chunk components of the Fletcher-Powell sum of squared
+ *     residuals accumulate with two-sum compensation (per term, or per
+ *     16-residual block for n > 16); Rosenbrock's and Ackley's sums, where
+ *     each component has at most two nonzero terms and compensation cannot
+ *     change the rounded result, are plain; the chunk dot uses two-product
+ *     and two-sum; the row sum over chunks is float64;
  *   - per-point float64 islands: Ackley's sqrt of the mean square and both
  *     exponentials (as g, g', g''), and the Fletcher-Powell residual values
  *     E_m - sum_j (A_mj sin x_j + B_mj cos x_j), which cancel.
