@@ -109,8 +109,9 @@ int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* 
  *   - every hDual component is carried in float32 (coordinates, v and the
  *     per-coordinate sin/cos tables are rounded to float32 where used);
  *   - the Hessian-chunk components of the Fletcher-Powell sum of squared
- *     residuals accumulate with two-sum compensation (per term, or per
- *     16-residual block for n > 16); Rosenbrock's and Ackley's sums, where
+ *     residuals accumulate with two-sum compensation over blocks of
+ *     residuals (four per lane for n <= 16, entering the compensated chunk
+ *     dot; sixteen for n > 16); Rosenbrock's and Ackley's sums, where
  *     each component has at most two nonzero terms and compensation cannot
  *     change the rounded result, are plain; the chunk dot uses two-product
  *     and two-sum; the row sum over chunks is float64;
