@@ -305,11 +305,12 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                 ah = mfma16(aop[s], jj[s] == i ? g2[s] : zero, ah);
             }
         }
-        T rd[4], rh[4];
+        T rd[4], rh[4], rd2[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             rd[r] = -dd[r];
             rh[r] = -ah[r];
+            rd2[r] = -(dd[r] + dd[r]);   // 2 r.d, exact: rd2 rg = rd rg + rd rg, one rounding each way
         }
         if (!kHess && !kSym && (a.grad || a.fval)) {
             // first-order (and, once, value) component of f = sum_m r_m * r_m
@@ -355,9 +356,11 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                         T t[4];
                         if (kLaneDot) {
                             // every entry here, the row's own one too: its two
-                            // r.v r.h products are added after the chunk
+                            // r.v r.h products are added after the chunk.
+                            // r.d r.g + r.d r.g = (2 r.d) r.g exactly (doubling
+                            // is exact), so one product forms both
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
+                            for (int r = 0; r < 4; ++r) t[r] = rd2[r] * rg[k][r];
                         } else if (k == i) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r)

@@ -290,19 +290,22 @@ __device__ __forceinline__ void fp_rows_block(const FpRowsArgs& a, int64_t blk, 
                 const int csl = cs_lane - kbase;
                 for (int mm = 0; mm < mcount; ++mm) {
                     const T* gm = &sh.gk[mm][csl];
-                    T rd[NQ];
+                    T rd[NQ], rd2[NQ];
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) rd[q] = one_pass ? sh.gk[mm][ci[q]] : sh.gi[mm][ci[q] - r0];
+                    for (int q = 0; q < NQ; ++q) {
+                        rd[q] = one_pass ? sh.gk[mm][ci[q]] : sh.gi[mm][ci[q] - r0];
+                        rd2[q] = rd[q] + rd[q];   // (2 r.d) r.g = r.d r.g + r.d r.g exactly
+                    }
 #pragma unroll
                     for (int l = 0; l < C; ++l) {
                         const T g = gm[l];
 #pragma unroll
                         for (int q = 0; q < NQ; ++q) {
-                            const T pr = rd[q] * g;
+                            const T pr2 = rd2[q] * g;
                             if constexpr (kTile)
-                                part[q][l] += pr + pr;
+                                part[q][l] += pr2;
                             else
-                                fh[q][l].add(pr + pr);
+                                fh[q][l].add(pr2);
                         }
                     }
 #pragma unroll
