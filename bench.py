@@ -45,6 +45,11 @@ MEASURED_TRAFFIC = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0273e+08,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0273e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0276e+08,
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0315e+08,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0314e+08,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0313e+08,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0312e+08,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0313e+08,
     "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=2, H.v>": 4.0281e+08,
     "plain_kernel<ackley, C=4, H.v>": 4.0282e+08,
@@ -71,6 +76,11 @@ MEASURED_VALU_FLOPS = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 2.0233e+10,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.4125e+10,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 6.2210e+10,
+    "fp_mfma_kernel<C=1, NK=8, H.v>": 1.2935e+10,
+    "fp_mfma_kernel<C=2, NK=8, H.v>": 1.2398e+10,
+    "fp_mfma_kernel<C=4, NK=8, H.v>": 1.2197e+10,
+    "fp_mfma_kernel<C=8, NK=8, H.v>": 1.2063e+10,
+    "fp_mfma_kernel<C=16, NK=8, H.v>": 1.1996e+10,
     "plain_kernel<ackley, C=1, H.v>": 5.4291e+10,
     "plain_kernel<ackley, C=2, H.v>": 3.1709e+10,
     "plain_kernel<ackley, C=4, H.v>": 2.1693e+10,

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
                                 t[r] = rv[r] * rh[r] + rd[r] * rg[k][r] + rd[r] * rg[k][r] + rv[r] * rh[r];
                         } else {
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) t[r] = rd[r] * rg[k][r] + rd[r] * rg[k][r];
+                            for (int r = 0; r < 4; ++r) t[r] = rd2[r] * rg[k][r];
                         }
                         if constexpr (kLaneDot && sizeof(T) == sizeof(double)) {
                             const double tl = (t[0] + t[1]) + (t[2] + t[3]);
