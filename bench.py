@@ -35,29 +35,11 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 4.0279e+08,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 4.0280e+08,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 4.0280e+08,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 4.0283e+08,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0288e+08,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.0273e+08,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.0272e+08,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0273e+08,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0273e+08,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0276e+08,
     "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0315e+08,
     "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0314e+08,
     "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0313e+08,
     "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0312e+08,
     "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0313e+08,
-    "plain_kernel<ackley, C=1, H.v>": 4.0281e+08,
-    "plain_kernel<ackley, C=2, H.v>": 4.0281e+08,
-    "plain_kernel<ackley, C=4, H.v>": 4.0282e+08,
-    "plain_kernel<ackley, C=8, H.v>": 4.0284e+08,
-    "plain_kernel<rosenbrock, C=1, H.v>": 4.0273e+08,
-    "plain_kernel<rosenbrock, C=2, H.v>": 4.0274e+08,
-    "plain_kernel<rosenbrock, C=4, H.v>": 4.0274e+08,
-    "plain_kernel<rosenbrock, C=8, H.v>": 4.0275e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -66,29 +48,11 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 3.2778e+10,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 2.2846e+10,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 1.8954e+10,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 2.6269e+10,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 3.9691e+10,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 1.0872e+10,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 1.3590e+10,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 2.0233e+10,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.4125e+10,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 6.2210e+10,
     "fp_mfma_kernel<C=1, NK=8, H.v>": 1.2935e+10,
     "fp_mfma_kernel<C=2, NK=8, H.v>": 1.2398e+10,
     "fp_mfma_kernel<C=4, NK=8, H.v>": 1.2197e+10,
     "fp_mfma_kernel<C=8, NK=8, H.v>": 1.2063e+10,
     "fp_mfma_kernel<C=16, NK=8, H.v>": 1.1996e+10,
-    "plain_kernel<ackley, C=1, H.v>": 5.4291e+10,
-    "plain_kernel<ackley, C=2, H.v>": 3.1709e+10,
-    "plain_kernel<ackley, C=4, H.v>": 2.1693e+10,
-    "plain_kernel<ackley, C=8, H.v>": 2.7171e+10,
-    "plain_kernel<rosenbrock, C=1, H.v>": 1.2281e+10,
-    "plain_kernel<rosenbrock, C=2, H.v>": 1.4865e+10,
-    "plain_kernel<rosenbrock, C=4, H.v>": 2.0217e+10,
-    "plain_kernel<rosenbrock, C=8, H.v>": 3.4108e+10,
 }
 
 

@@ -73,9 +73,9 @@ struct Rosenbrock {
 
     template <typename T, int C>
     static CF_DEV HD<T, C> term(const HD1<T, C>& yk, const HD1<T, C>& yk1) {
-        HD<T, C> b = yk1 - yk * yk;
+        HD<T, C> b = yk1 - sq(yk);
         HD1<T, C> e = T(1) - yk;
-        return T(100) * (b * b) + e * e;
+        return T(100) * sq(b) + sq(e);
     }
 
     // kSplit: the terms k whose variables y_k, y_k+1 both lie outside the
@@ -153,13 +153,13 @@ struct Ackley {
         typename P::template Acc<C> ss, cs;
         if constexpr (!kSplit) {
             HD1<T, C> y = pv.template y<C>(0);
-            ss = P::start(y * y);
+            ss = P::start(sq(y));
             cs = P::start(cos_term<T, C>(pv, 0));
             // second-order component (i, cs + l) of a term in y_k is nonzero only
             // for k = i = cs + l: at most one term per component
             for (int k = 1; k < pv.n; ++k) {
                 y = pv.template y<C>(k);
-                P::add_sparse(ss, y * y);
+                P::add_sparse(ss, sq(y));
                 P::add_sparse(cs, cos_term<T, C>(pv, k));
             }
         } else {
@@ -168,17 +168,17 @@ struct Ackley {
             cs = P::start(zero_hd<T, C>());
             for (int k = 0; k < k0; ++k) {
                 const HD1<T, 0> y = pv.template y<0>(k);
-                P::add_light(ss, y * y);
+                P::add_light(ss, sq(y));
                 P::add_light(cs, cos_term<T, 0>(pv, k));
             }
             for (int k = k0; k < k1; ++k) {
                 const HD1<T, C> y = pv.template y<C>(k);
-                P::add_sparse(ss, y * y);
+                P::add_sparse(ss, sq(y));
                 P::add_sparse(cs, cos_term<T, C>(pv, k));
             }
             for (int k = k1; k < pv.n; ++k) {
                 const HD1<T, 0> y = pv.template y<0>(k);
-                P::add_light(ss, y * y);
+                P::add_light(ss, sq(y));
                 P::add_light(cs, cos_term<T, 0>(pv, k));
             }
         }

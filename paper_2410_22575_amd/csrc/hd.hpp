@@ -213,6 +213,39 @@ CF_DEV HD<T, C> operator*(const HD1<T, C>& a, const HD1<T, C>& b) {
     return r;
 }
 
+// u * u for a first-order value: the product rule's pairs of equal products
+// (u.v u' + u' u.v, u.d u.g + u.g u.d) are each one product with a doubled
+// factor; doubling is exact, so the values are those of the two products added
+template <typename T, int C>
+CF_DEV HD<T, C> sq(const HD1<T, C>& a) {
+    HD<T, C> r;
+    const T v2 = a.v + a.v, d2 = a.d + a.d;
+    r.v = a.v * a.v;
+    r.d = v2 * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = v2 * a.g[l];
+        r.h[l] = d2 * a.g[l];
+    }
+    return r;
+}
+
+// u * u for a full value: as above, with the second-order part
+// (2 u.v) u.h + (2 u.d) u.g, the product rule's four terms paired the same way
+template <typename T, int C>
+CF_DEV HD<T, C> sq(const HD<T, C>& a) {
+    HD<T, C> r;
+    const T v2 = a.v + a.v, d2 = a.d + a.d;
+    r.v = a.v * a.v;
+    r.d = v2 * a.d;
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+        r.g[l] = v2 * a.g[l];
+        r.h[l] = v2 * a.h[l] + d2 * a.g[l];
+    }
+    return r;
+}
+
 // first-order minus full: the second-order part is the negated one of b
 template <typename T, int C>
 CF_DEV HD<T, C> operator-(const HD1<T, C>& a, const HD<T, C>& b) {
