@@ -36,6 +36,10 @@ struct PointView {
     CF_DEV T island(int q) const { return isl[q * stride]; }
     template <int C>
     CF_DEV HD1<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
+    // y_k restricted to the W chunk components m0 .. m0 + W - 1 (slots of that
+    // window outside [0, C) are never added to a sum)
+    template <int W>
+    CF_DEV HD1<T, W> y_at(int k, int m0) const { return seed<T, W>(x(k), k, i, cs + m0); }
 };
 
 struct FpParams {
@@ -104,7 +108,16 @@ struct Rosenbrock {
             const int k1 = pv.cs + C < nt ? pv.cs + C : nt;          // one past the last
             auto s = P::start(zero_hd<T, C>());
             for (int k = 0; k < k0; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
-            for (int k = k0; k < k1; ++k) P::add_sparse(s, term<T, C>(pv.template y<C>(k), pv.template y<C>(k + 1)));
+            // term k = cs - 1 + p has chunk components p - 1 and p only: it runs
+            // on that window of two and is added there (the other components
+            // of a full-width term are exact zeros)
+            static_for<C + 1>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                const int k = pv.cs - 1 + p;
+                if (k >= k0 && k < k1)
+                    P::template add_at<p - 1>(s, term<T, 2>(pv.template y_at<2>(k, p - 1),
+                                                            pv.template y_at<2>(k + 1, p - 1)));
+            });
             for (int k = k1; k < nt; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
             return P::value(s);
         }
@@ -117,10 +130,14 @@ struct Ackley {
     // t0 = cos(2 pi x), t1 = sin(2 pi x)
     static CF_DEV void tables(double x, double& t0, double& t1) { sincos(kTwoPi * x, &t1, &t0); }
     __host__ __device__ static int isl_tasks(int) { return 1; }
-    __host__ __device__ static int isl_size(int) { return 5; }
+    __host__ __device__ static int isl_size(int) { return 6; }
 
-    // float64 per-point values: sqrt(u) and its two derivatives at
-    // u = sum x^2 / n, exp(-0.2 sqrt(u)), exp(sum cos(2 pi x) / n)
+    // float64 per-point values of the two outer functions, each composed into
+    // one scalar function of its sum, with its first two derivatives there:
+    //   F(s) = -20 exp(-0.2 sqrt(s / n))  at s = sum x^2
+    //   G(c) = -exp(c / n)                at c = sum cos(2 pi x)
+    // With r = sqrt(s / n) and E = exp(-0.2 r): F' = 2E / (n r) and
+    // F'' = -E (0.2 + 1 / r) / (n r)^2; G' = G / n, G'' = G / n^2.
     template <typename T>
     static CF_DEV void island(int, int n, const double* xg, const double* t0, const double*, int stride,
                               const FpParams&, T* isl) {
@@ -130,19 +147,26 @@ struct Ackley {
             cs += t0[k * stride];
         }
         const double inv_n = 1.0 / n;
-        const double u = inv_n * ss;
-        const double rt = sqrt(u);
-        isl[0] = (T)rt;
-        isl[1 * stride] = (T)(0.5 / rt);
-        isl[2 * stride] = (T)(-0.25 / (rt * u));
-        isl[3 * stride] = (T)exp(-0.2 * rt);
-        isl[4 * stride] = (T)exp(inv_n * cs);
+        const double rt = sqrt(inv_n * ss);
+        const double e1 = exp(-0.2 * rt);
+        const double nr = n * rt;
+        isl[0] = (T)(-20.0 * e1);
+        isl[1 * stride] = (T)(2.0 * e1 / nr);
+        isl[2 * stride] = (T)(-e1 * (0.2 + 1.0 / rt) / (nr * nr));
+        const double g = -exp(inv_n * cs);
+        isl[3 * stride] = (T)g;
+        isl[4 * stride] = (T)(g * inv_n);
+        isl[5 * stride] = (T)(g * inv_n * inv_n);
     }
 
     template <typename T, int C>
     static CF_DEV HD<T, C> cos_term(const PointView<T>& pv, int k) {
+        return cos_of(pv, pv.template y<C>(k), k);
+    }
+    template <typename T, int W>
+    static CF_DEV HD<T, W> cos_of(const PointView<T>& pv, const HD1<T, W>& y, int k) {
         const T c = pv.tab0(k), s = pv.tab1(k);
-        return chain(T(kTwoPi) * pv.template y<C>(k), c, -s, -c);
+        return chain(T(kTwoPi) * y, c, -s, -c);
     }
 
     // kSplit: as for Rosenbrock, the terms of variables outside the chunk
@@ -171,27 +195,26 @@ struct Ackley {
                 P::add_light(ss, sq(y));
                 P::add_light(cs, cos_term<T, 0>(pv, k));
             }
-            for (int k = k0; k < k1; ++k) {
-                const HD1<T, C> y = pv.template y<C>(k);
-                P::add_sparse(ss, sq(y));
-                P::add_sparse(cs, cos_term<T, C>(pv, k));
-            }
+            // term k = cs + m has the one chunk component m: it runs on that
+            // component alone and is added there
+            static_for<C>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                const int k = k0 + m;
+                if (k < k1) {
+                    const HD1<T, 1> y = pv.template y_at<1>(k, m);
+                    P::template add_at<m>(ss, sq(y));
+                    P::template add_at<m>(cs, cos_of(pv, y, k));
+                }
+            });
             for (int k = k1; k < pv.n; ++k) {
                 const HD1<T, 0> y = pv.template y<0>(k);
                 P::add_light(ss, sq(y));
                 P::add_light(cs, cos_term<T, 0>(pv, k));
             }
         }
-        const T inv_n = T(1.0 / pv.n);
-        HD<T, C> t = inv_n * P::value(ss);
-        t = chain(t, pv.island(0), pv.island(1), pv.island(2));   // sqrt
-        t = T(-0.2) * t;
-        const T e1 = pv.island(3);
-        t = T(-20) * chain(t, e1, e1, e1);
-        HD<T, C> u = inv_n * P::value(cs);
-        const T e2 = pv.island(4);
-        t = t - chain(u, e2, e2, e2);
-        return t + T(20.0 + kE);
+        const HD<T, C> t = chain(P::value(ss), pv.island(0), pv.island(1), pv.island(2));   // F
+        const HD<T, C> u = chain(P::value(cs), pv.island(3), pv.island(4), pv.island(5));   // G
+        return (t + u) + T(20.0 + kE);
     }
 };
 

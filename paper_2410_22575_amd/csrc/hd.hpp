@@ -20,9 +20,23 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace chessfad {
 
 #define CF_DEV __device__ __forceinline__
+
+// fn(std::integral_constant<int, I>{}) for I = 0 .. N - 1, in order: a loop
+// whose index is a compile-time constant in the body
+template <class Fn, int... I>
+CF_DEV void static_for_impl(Fn&& fn, std::integer_sequence<int, I...>) {
+    (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class Fn>
+CF_DEV void static_for(Fn&& fn) {
+    static_for_impl(fn, std::make_integer_sequence<int, N>{});
+}
 
 // HD<T, 0> (value and row derivative only) carries a term whose seeds have
 // no component in the call's chunk: its g and h parts are exact zeros.
@@ -313,6 +327,19 @@ struct F64 {
         a.x.v += t.v;
         a.x.d += t.d;
     }
+    // a term whose chunk components other than M .. M + W - 1 are exact
+    // zeros, given as those W; slots outside [0, C) are skipped
+    template <int M, int C, int W>
+    static CF_DEV void add_at(Acc<C>& a, const HD<T, W>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (M + w >= 0 && M + w < C) {
+                a.x.g[M + w] += t.g[w];
+                a.x.h[M + w] += t.h[w];
+            }
+    }
     template <int C>
     static CF_DEV HD<T, C> value(const Acc<C>& a) { return a.x; }
     // chunk dot sum_l h[l] v[l]
@@ -373,6 +400,19 @@ struct F32C {
     static CF_DEV void add_light(Acc<C>& a, const HD<T, 0>& t) {
         a.x.v += t.v;
         a.x.d += t.d;
+    }
+    // add_sparse for a term given as its chunk components M .. M + W - 1
+    // (the others exact zeros); slots outside [0, C) are skipped
+    template <int M, int C, int W>
+    static CF_DEV void add_at(Acc<C>& a, const HD<T, W>& t) {
+        a.x.v += t.v;
+        a.x.d += t.d;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            if (M + w >= 0 && M + w < C) {
+                a.x.g[M + w] += t.g[w];
+                a.x.h[M + w] = __fadd_rn(a.x.h[M + w], t.h[w]);
+            }
     }
     template <int C>
     static CF_DEV HD<T, C> value(const Acc<C>& a) {
