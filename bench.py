@@ -35,11 +35,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 4.0315e+08,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 4.0314e+08,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 4.0313e+08,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 4.0312e+08,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 4.0313e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -48,11 +43,6 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
-    "fp_mfma_kernel<C=1, NK=8, H.v>": 1.2935e+10,
-    "fp_mfma_kernel<C=2, NK=8, H.v>": 1.2398e+10,
-    "fp_mfma_kernel<C=4, NK=8, H.v>": 1.2197e+10,
-    "fp_mfma_kernel<C=8, NK=8, H.v>": 1.2063e+10,
-    "fp_mfma_kernel<C=16, NK=8, H.v>": 1.1996e+10,
 }
 
 
@@ -62,22 +52,19 @@ def kernel_key(f, c, n=N, mapping=2):
     the L1 kernel when a row has a single chunk or L1 was chosen, else the
     L2 vector kernel."""
     if f == 2 and n <= 16:
-        return f"fp_mfma_kernel<C={c}, NK={min(8, max(1, (2 * n + 3) // 4))}, H.v>"
+        return f"fp_tile_kernel<NK={min(8, max(1, (2 * n + 3) // 4))}, H.v>"
     if c >= n or mapping == 1:
         return f"coarse_kernel<{NAMES[f]}, C={c}, L1, H.v>"
     return f"plain_kernel<{NAMES[f]}, C={c}, H.v>"
 
 
 def fp_mfma_flops(n, c, npts):
-    """MFMA flops the n <= 16 Fletcher-Powell kernel executes per launch: per
-    16-point wave, NK steps of 16x16x4 for the value column, and for the g
-    column of each variable and the d and h columns of each row the steps
-    that hold the variable's K entries k and n + k (two steps, one when both
-    fall in the same step); 2 x 16 x 16 x 4 flops per step.  The chunk size
-    does not change it."""
+    """MFMA flops the n <= 16 Fletcher-Powell float64 kernel executes per
+    launch: per 16-point wave, NK steps of 16x16x4 for the value column, and
+    per point ceil(n / 4) steps for its 16 x 16 tile J^T J; 2 x 16 x 16 x 4
+    flops per step.  The chunk size does not change it."""
     nk = min(8, max(1, (2 * n + 3) // 4))
-    band = sum(len({k // 4, (n + k) // 4}) for k in range(n))
-    steps = nk + band + 2 * band
+    steps = nk + 16 * ((n + 3) // 4)
     return steps * 2 * 16 * 16 * 4 * (npts / 16)
 
 
@@ -371,7 +358,7 @@ def main():
         # executed flops where known: MFMA from the tile schedule, vector
         # float64 from the counters taken for this kernel
         key = kernel_key(f, chunks[f], mapping=mapping[f])
-        ex = (fp_mfma_flops(N, chunks[f], npts) if key.startswith("fp_mfma") else 0.0)
+        ex = (fp_mfma_flops(N, chunks[f], npts) if key.startswith("fp_tile") else 0.0)
         valu = MEASURED_VALU_FLOPS.get(key)
         per_func[NAMES[f]]["executed_mfma_tflops"] = ex / (kernel_ms[f] * 1e-3) / 1e12 if ex else None
         per_func[NAMES[f]]["executed_valu_f64_tflops"] = valu / (kernel_ms[f] * 1e-3) / 1e12 if valu else None
@@ -380,7 +367,7 @@ def main():
     kname = kernel_key(dom, chunks[dom], mapping=mapping[dom])
     model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
     t_dom = kernel_ms[dom] * 1e-3
-    if kname.startswith("fp_mfma"):
+    if kname.startswith("fp_tile"):
         # the matrix cores: executed MFMA flops (fewer than the model counts)
         bound, work, basis = "mfma", fp_mfma_flops(N, chunks[dom], npts), "executed MFMA flops (tile schedule)"
     elif kname in MEASURED_VALU_FLOPS:

@@ -327,6 +327,10 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess, sym)
                                     : fp_mfma_entry(chunk, fp_mfma_steps(n), hess, sym);
         if (!launch) return CHESSFAD_E_CHUNK;
+        // float64: every call of a point is a block of the point's tile (the
+        // chunk size and the symmetric form give the same entries)
+        if (!mixed && g_opt_fp_mfma == 1) launch = fp_tile_entry(fp_mfma_steps(n), hess);
+        if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
         const int64_t grid = (npts + per_block - 1) / per_block;
@@ -493,7 +497,7 @@ int chessfad_set_option(int option, int value) {
     int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
               : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
               : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping : nullptr;
-    const int maxv = option == CHESSFAD_OPT_MAPPING ? 2 : 1;
+    const int maxv = option == CHESSFAD_OPT_MAPPING || option == CHESSFAD_OPT_FP_MFMA ? 2 : 1;
     if (!slot || value < 0 || value > maxv) return CHESSFAD_E_ARG;
     const int prev = *slot;
     *slot = value;

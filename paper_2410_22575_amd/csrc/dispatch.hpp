@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernel_fp_mfma.hpp"
+#include "kernel_fp_tile.hpp"
 #include "kernel_fp_rows.hpp"
 #include "kernel_plain.hpp"
 #include "kernel_sym.hpp"
@@ -95,6 +96,15 @@ inline int fp_mfma_steps(int n) {
 }
 
 FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess, bool sym);
+
+template <int NK, bool kHess>
+hipError_t launch_fp_tile(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((fp_tile_kernel<NK, kHess>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+// The float64 point-tile kernel (n <= 16) for a K-step count and output kind.
+FpMfmaLaunch fp_tile_entry(int nk, bool hess);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 

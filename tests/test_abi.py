@@ -158,7 +158,9 @@ def test_user_function_registration_host_only(lib):
 
 def test_options(lib):
     assert lib.chessfad_set_option(99, 0) == E_ARG
-    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 2) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 3) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 2) == 1   # the default is 1
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 1) == 2
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 3) == E_ARG
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, -1) == E_ARG
     prev = lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 0)
