@@ -45,7 +45,7 @@
 namespace chessfad {
 
 #ifndef CF_TILE_UNROLL
-#define CF_TILE_UNROLL 2
+#define CF_TILE_UNROLL 1
 #endif
 constexpr int kFpTileUnroll = CF_TILE_UNROLL;   // divides kFpPointsPerWave
 
@@ -60,7 +60,8 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
     __shared__ double vs[kHess ? 1 : kFpWaves * P * S];
 
     const int n = a.n;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index is the same in every lane: keep it (and the point loop) scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
     const int64_t pbase = ((int64_t)blockIdx.x * kFpWaves + wave) * P;
     const int64_t p = pbase + li;
