@@ -20,11 +20,12 @@ TOL64 = 1e-12
 CHUNKS = (1, 2, 4, 8, 16)
 
 
-FUNC_PATHS = [(R, None), (A, None), (FP, 1), (FP, 0)]  # (function, Fletcher-Powell MFMA option)
+FUNC_PATHS = [(R, None), (A, None), (FP, 1), (FP, 2), (FP, 0)]  # (function, Fletcher-Powell MFMA option)
 
 
 class fp_path:
-    """Select the Fletcher-Powell path (1 = MFMA contraction, 0 = vector ALUs)."""
+    """Select the Fletcher-Powell path (1 = MFMA point tile in float64, 2 = MFMA
+    contraction per call, 0 = vector ALUs)."""
 
     def __init__(self, lib, mfma):
         self.lib, self.mfma = lib, mfma
