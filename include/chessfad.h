@@ -205,13 +205,13 @@ const char* chessfad_strerror(int code);
  * Returns the previous value, or CHESSFAD_E_ARG for an unknown option or value.
  *   CHESSFAD_OPT_FP_MFMA  1 (default): for Fletcher-Powell with n <= 16 the
  *                         dense [A B] . [sin y; cos y] contraction over the
- *                         hDual components runs on float64 MFMA; in float64
- *                         the second-order components of all calls of a point
- *                         are formed as one 16 x 16 MFMA tile (the sum over
- *                         residuals of the product-rule terms, Sec. VII);
+ *                         hDual components runs on MFMA, and the second-order
+ *                         components of all calls of a point are formed as
+ *                         one 16 x 16 MFMA tile (the sum over residuals of
+ *                         the product-rule terms, Sec. VII; float32 MFMA in
+ *                         the mixed path);
  *                         2: the MFMA contraction per call, its second-order
- *                         components on the vector ALUs (float64; the mixed
- *                         path always runs this way);
+ *                         components on the vector ALUs;
  *                         0: every step runs on the vector ALUs.
  *                         All give the same derivative components; only the
  *                         order of the final sum over residuals differs.

@@ -327,9 +327,10 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess, sym)
                                     : fp_mfma_entry(chunk, fp_mfma_steps(n), hess, sym);
         if (!launch) return CHESSFAD_E_CHUNK;
-        // float64: every call of a point is a block of the point's tile (the
-        // chunk size and the symmetric form give the same entries)
-        if (!mixed && g_opt_fp_mfma == 1) launch = fp_tile_entry(fp_mfma_steps(n), hess);
+        // every call of a point is a block of the point's tile (the chunk
+        // size and the symmetric form give the same entries)
+        if (g_opt_fp_mfma == 1)
+            launch = mixed ? fp_tile_entry_mixed(fp_mfma_steps(n), hess) : fp_tile_entry(fp_mfma_steps(n), hess);
         if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;

@@ -97,14 +97,27 @@ inline int fp_mfma_steps(int n) {
 
 FpMfmaLaunch fp_mfma_entry(int C, int nk, bool hess, bool sym);
 
-template <int NK, bool kHess>
+template <class P, int NK, bool kHess>
 hipError_t launch_fp_tile(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((fp_tile_kernel<NK, kHess>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((fp_tile_kernel<P, NK, kHess>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-// The float64 point-tile kernel (n <= 16) for a K-step count and output kind.
+template <class P, bool kHess>
+FpMfmaLaunch fp_tile_by_steps(int nk) {
+    switch (nk) {
+        case 1: return &launch_fp_tile<P, 1, kHess>;
+        case 2: return &launch_fp_tile<P, 2, kHess>;
+        case 4: return &launch_fp_tile<P, 4, kHess>;
+        case 8: return &launch_fp_tile<P, 8, kHess>;
+        default: return nullptr;
+    }
+}
+
+// The point-tile kernel (n <= 16) for a K-step count and output kind, float64
+// and mixed (one translation unit each).
 FpMfmaLaunch fp_tile_entry(int nk, bool hess);
+FpMfmaLaunch fp_tile_entry_mixed(int nk, bool hess);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 

@@ -4,17 +4,8 @@
 
 namespace chessfad {
 
-template <bool kHess>
-static FpMfmaLaunch tile_by_steps(int nk) {
-    switch (nk) {
-        case 1: return &launch_fp_tile<1, kHess>;
-        case 2: return &launch_fp_tile<2, kHess>;
-        case 4: return &launch_fp_tile<4, kHess>;
-        case 8: return &launch_fp_tile<8, kHess>;
-        default: return nullptr;
-    }
+FpMfmaLaunch fp_tile_entry(int nk, bool hess) {
+    return hess ? fp_tile_by_steps<F64, true>(nk) : fp_tile_by_steps<F64, false>(nk);
 }
-
-FpMfmaLaunch fp_tile_entry(int nk, bool hess) { return hess ? tile_by_steps<true>(nk) : tile_by_steps<false>(nk); }
 
 }  // namespace chessfad

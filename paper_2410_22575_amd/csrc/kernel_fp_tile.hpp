@@ -1,5 +1,5 @@
-// Fletcher-Powell, n <= 16, float64: all second-order components of a point
-// as one 16 x 16 MFMA tile.
+// Fletcher-Powell, n <= 16: all second-order components of a point as one
+// 16 x 16 MFMA tile.
 //
 // The hDual evaluation of one call (point p, row i, chunk cs) has two layers
 // (Sec. VII): the residuals r_m = E_m - sum_j A_mj sin(y_j) + B_mj cos(y_j)
@@ -38,21 +38,24 @@
 //   D: lane l, element r holds D[4 r + l / 16][l % 16].
 // With A = B = J[4 s + lg][li] both operands are the same register: A[i][m] =
 // J[m][i] and B[m][k] = J[m][k].
+//
+// Precision policies: F64 runs everything in float64.  F32C rounds J to
+// float32 once and runs the tile on v_mfma_f32_16x16x4f32 (the sum over the
+// n <= 16 residuals is one plain float32 block, as in the rows kernel's
+// blocked compensation, whose blocks are 16 residuals); the value column, the
+// residual values, the own entries and the dot with v stay in float64.  The
+// f32 tile's D layout is row 4 lg + r in element r (MfmaTile<float>::row).
 #pragma once
 
 #include "kernel_fp_mfma.hpp"
 
 namespace chessfad {
 
-#ifndef CF_TILE_UNROLL
-#define CF_TILE_UNROLL 1
-#endif
-constexpr int kFpTileUnroll = CF_TILE_UNROLL;   // divides kFpPointsPerWave
-
-template <int NK, bool kHess>
+template <class Prec, int NK, bool kHess>
 __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
+    using T = typename Prec::T;
+    using V = typename MfmaTile<T>::V;
     constexpr int P = kFpPointsPerWave, S = kFpVStride;
-    constexpr int kU = kFpTileUnroll;
     // per wave: sin and cos of every (point, coordinate), r_m of every
     // (point, residual), v of every (point, coordinate); entries of index
     // n .. 15 are zero
@@ -145,56 +148,42 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
     }
     const int ms = (n + 3) >> 2;   // K steps that hold a residual
     const int np = a.npts - pbase < P ? (int)(a.npts - pbase) : P;
-    // kU points per trip, their MFMA chains interleaved (the LDS rows of
-    // points past np hold zeros or finite values; only their stores are skipped)
-    for (int pt0 = 0; pt0 < np; pt0 += kU) {
-        double jv[kU][4], sj[kU], cj[kU];
-        f64x4 d[kU];
+    for (int pt = 0; pt < np; ++pt) {
+        const double sj = sw[pt * S + li], cj = cw[pt * S + li];
+        double jv[4];
+        V d = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            sj[u] = sw[(pt0 + u) * S + li];
-            cj[u] = cw[(pt0 + u) * S + li];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) jv[u][s] = bm[s] * sj[u] - am[s] * cj[u];
-            d[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < 4; ++s) {
+            jv[s] = bm[s] * sj - am[s] * cj;
+            // float32 policy: J rounded once from float64
+            if (s < ms) d = mfma16((T)jv[s], (T)jv[s], d);
         }
+        // own entry: sum over this lane's residuals of r_m.v r_m.h(li)
+        double o = 0.0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (s < ms) {
+        for (int s = 0; s < 4; ++s) o += rw[pt * S + 4 * s + lg] * (am[s] * sj + bm[s] * cj);
+        const int64_t q = pbase + pt;
+        if constexpr (kHess) {
+            o = pair_sum<32>(pair_sum<16>(o));
 #pragma unroll
-                for (int u = 0; u < kU; ++u) d[u] = mfma16(jv[u][s], jv[u][s], d[u]);
+            for (int r = 0; r < 4; ++r) {
+                const int i = MfmaTile<T>::row(r, lg);
+                const double h = i == li ? (double)d[r] + o : (double)d[r];
+                if (i < n && li < n) a.out[(q * n + i) * n + li] = h + h;
             }
+        } else {
+            double part = o * vw[pt * S + li];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int pt = pt0 + u;
-            // own entry: sum over this lane's residuals of r_m.v r_m.h(li)
-            double o = 0.0;
+            for (int r = 0; r < 4; ++r) part += (double)d[r] * vw[pt * S + MfmaTile<T>::row(r, lg)];
+            const double row = pair_sum<32>(pair_sum<16>(part));
+            if (lg == 0 && li < n) a.out[q * n + li] = row + row;
+            if (a.grad) {
+                // first-order component: sum_m 2 r_m.v r_m.d
+                double g = 0.0;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) o += rw[pt * S + 4 * s + lg] * (am[s] * sj[u] + bm[s] * cj[u]);
-            const int64_t q = pbase + pt;
-            const bool st = pt < np;
-            if constexpr (kHess) {
-                o = pair_sum<32>(pair_sum<16>(o));
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = 4 * r + lg;
-                    const double h = i == li ? d[u][r] + o : d[u][r];
-                    if (st && i < n && li < n) a.out[(q * n + i) * n + li] = h + h;
-                }
-            } else {
-                double part = o * vw[pt * S + li];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) part += d[u][r] * vw[pt * S + 4 * r + lg];
-                const double row = pair_sum<32>(pair_sum<16>(part));
-                if (st && lg == 0 && li < n) a.out[q * n + li] = row + row;
-                if (a.grad) {
-                    // first-order component: sum_m 2 r_m.v r_m.d
-                    double g = 0.0;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) g += rw[pt * S + 4 * s + lg] * jv[u][s];
-                    g = pair_sum<32>(pair_sum<16>(g));
-                    if (st && lg == 0 && li < n) a.grad[q * n + li] = g + g;
-                }
+                for (int s = 0; s < 4; ++s) g += rw[pt * S + 4 * s + lg] * jv[s];
+                g = pair_sum<32>(pair_sum<16>(g));
+                if (lg == 0 && li < n) a.grad[q * n + li] = g + g;
             }
         }
     }
