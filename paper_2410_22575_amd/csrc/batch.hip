@@ -332,12 +332,15 @@ int autotune(int func_id, int n, int precision, int64_t npts, void* stream, int*
     float times[kNumChunks];
     int maps[kNumChunks];
     int tried = 0;
+    // the point tile runs the same launch for every chunk: time the largest only
+    const bool tile = fp_tile_path(func_id, n);
     for (int k = 0; k < kNumChunks && err == hipSuccess && rc == CHESSFAD_OK; ++k) {
         const int C = kChunks[k];
         if (C > n) break;
         times[k] = -1.0f;
         maps[k] = 2;
         tried = k + 1;
+        if (tile && k + 1 < kNumChunks && kChunks[k + 1] <= n) continue;
         const bool both = two_maps && (n + C - 1) / C > 1;
         for (int level = 2; level >= (both ? 1 : 2) && err == hipSuccess && rc == CHESSFAD_OK; --level) {
             const int map = sym ? -1 : level;

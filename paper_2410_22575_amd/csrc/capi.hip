@@ -90,6 +90,9 @@ void record_tuned_mapping(int func_id, int n, int precision, int level) {
 }
 
 bool vector_path(int func_id) { return func_id != CHESSFAD_FLETCHER_POWELL || !g_opt_fp_mfma; }
+bool fp_tile_path(int func_id, int n) {
+    return func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma == 1;
+}
 
 double model_flops_per_call(int func_id, int n, int C) {
     const double hadd = 2.0 * C + 2, hmul = 10.0 * C + 4, scal = 2.0 * C + 2, unary = 4.0 * C + 2, dot = 2.0 * C;

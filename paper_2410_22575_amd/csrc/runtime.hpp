@@ -38,6 +38,8 @@ int run_user(int func_id, int n, int64_t npts, const double* x, const double* v,
 
 // Float64 H.v of func_id runs its f on the vector ALUs (not on MFMA).
 bool vector_path(int func_id);
+// Fletcher-Powell at n <= 16 on the point tile: every chunk gives the same launch
+bool fp_tile_path(int func_id, int n);
 
 // GPU mapping (1 = L1, 2 = L2) chosen by the autotuner for float64 H.v of
 // (func_id, n) with chunk = 0; 2 when none was recorded.
