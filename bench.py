@@ -35,17 +35,6 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 4.0275e+08,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 4.0276e+08,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 4.0277e+08,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 4.0279e+08,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0281e+08,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.0269e+08,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.0271e+08,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0273e+08,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0277e+08,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0278e+08,
-    "fp_tile_kernel<NK=8, H.v>": 4.0287e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -54,17 +43,6 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 2.8605e+10,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 1.7465e+10,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 1.1895e+10,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 9.1100e+09,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 7.7175e+09,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 8.8416e+09,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 7.6336e+09,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 7.0464e+09,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 6.7444e+09,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 6.5934e+09,
-    "fp_tile_kernel<NK=8, H.v>": 3.9426e+09,
 }
 
 

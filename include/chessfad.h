@@ -26,6 +26,10 @@
  *     (func_id, n).  Compiled sizes: 1, 2, 4, 8, 16.  chunk may not exceed
  *     n; when n is not a multiple of chunk the last chunk of every row is
  *     ragged (it seeds only the columns < n; Sec. III.B assumes csize | n).
+ *   - x, v and the Fletcher-Powell parameters must be finite, and so must f
+ *     and its derivatives at x: the kernels are built assuming finite values
+ *     (non-finite inputs give unspecified results, not an error), and a
+ *     zero result may come out as -0.0 or +0.0.
  *   - Calls on different streams are independent.  chessfad_fp_set_params
  *     and chessfad_fp_release must not race with compute calls that read
  *     the same n.

@@ -26,6 +26,12 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-command-line-argument",
+    # the CHUNK-INIT seeds are constants 0 and 1 in most components: with
+    # finite values and no signed zeros the compiler folds the products with
+    # a zero seed (x * 0 = 0) and the sums of exact zeros (x + 0 = x), as the
+    # hDual rules do by hand elsewhere; inputs must be finite, and the sign of
+    # a zero result is not kept
+    "-fno-signed-zeros", "-ffinite-math-only",
     # keep MFMA sources and results in VGPRs: otherwise accumulators carried
     # across runtime-length K loops are copied between AGPRs and VGPRs on
     # every iteration
