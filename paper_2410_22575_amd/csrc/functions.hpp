@@ -20,20 +20,24 @@
 
 namespace chessfad {
 
-// One work item's view of its point, staged in LDS in structure-of-arrays
-// form: entry k of the point lives at base[k * stride].
+// Per-point rows of the LDS staging: a point's m entries of one array are
+// contiguous, rows padded to an odd length so that the rows of different
+// points start in different banks; offsets within a row are then immediates.
+__host__ __device__ inline int aos_stride(int m) { return m | 1; }
+
+// One work item's view of its point, staged in LDS: entry k of the point
+// lives at base[k].
 template <typename T>
 struct PointView {
     const T* xs;          // coordinates (hDual precision)
     const double* t0;     // tables (float64)
     const double* t1;
     const T* isl;         // per-point island values (hDual precision)
-    int stride;
     int n, i, cs;
-    CF_DEV T x(int k) const { return xs[k * stride]; }
-    CF_DEV T tab0(int k) const { return (T)t0[k * stride]; }
-    CF_DEV T tab1(int k) const { return (T)t1[k * stride]; }
-    CF_DEV T island(int q) const { return isl[q * stride]; }
+    CF_DEV T x(int k) const { return xs[k]; }
+    CF_DEV T tab0(int k) const { return (T)t0[k]; }
+    CF_DEV T tab1(int k) const { return (T)t1[k]; }
+    CF_DEV T island(int q) const { return isl[q]; }
     template <int C>
     CF_DEV HD1<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
     // y_k restricted to the W chunk components m0 .. m0 + W - 1 (slots of that

@@ -37,7 +37,7 @@ struct PlainArgs {
     int n;              // variables
     int nc;             // chunks per row, ceil(n / C)
     int rows;           // row tasks per workgroup; blockDim.x == rows * nc
-    int pstride;        // LDS stride between entries of one point (>= points per workgroup)
+    int pstride;        // LDS rows per staged array (>= points per workgroup)
     double* grad = nullptr;  // kGrad kernels: [npts][n] gradient (row i's d component)
     double* fval = nullptr;  // kGrad kernels, optional: [npts] f (the value component)
 };
@@ -45,12 +45,14 @@ struct PlainArgs {
 constexpr int kMaxBlock = 512;
 
 // LDS bytes for one workgroup (host and device agree on this layout):
-// doubles: red[block], t0, t1 [n][pstride]; T: xs, vs [n][pstride], isl [isl][pstride]
+// doubles: red[block], t0, t1 [pstride][ks]; T: xs, vs [pstride][ks],
+// isl [pstride][ki], with ks = aos_stride(n) and ki = aos_stride(isl_size(n))
 template <class P, class F>
 __host__ __device__ inline size_t plain_lds_bytes(int n, int pstride, int block, bool hess) {
     using T = typename P::T;
-    const size_t dbl = (size_t)block + (F::kTables ? 2 * (size_t)n * pstride : 0);
-    const size_t tt = (size_t)n * pstride * (hess ? 1 : 2) + (size_t)F::isl_size(n) * pstride;
+    const size_t ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
+    const size_t dbl = (size_t)block + (F::kTables ? 2 * ks * pstride : 0);
+    const size_t tt = ks * pstride * (hess ? 1 : 2) + ki * pstride;
     return dbl * sizeof(double) + tt * sizeof(T);
 }
 
@@ -63,10 +65,11 @@ struct PlainStage {
     T* xs;
     T* vs;
     T* isl;
+    int ks, ki;   // row lengths: coordinate arrays, islands
 };
 
 // Steps 1 and 2 for the points p0 .. p0 + npb - 1: coordinates (and vectors)
-// as structure-of-arrays with the per-coordinate tables, then the per-point
+// in per-point rows with the per-coordinate tables, then the per-point
 // float64 islands.  `nthr` doubles of reduction space come first.
 template <class P, class F, bool kHess>
 __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs& a, int64_t p0, int npb, int nthr,
@@ -74,28 +77,31 @@ __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs
     using T = typename P::T;
     const int n = a.n, ps = a.pstride;
     PlainStage<T> st;
+    const int ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
+    st.ks = ks;
+    st.ki = ki;
     st.red = lds;
     st.t0 = st.red + nthr;
-    st.t1 = st.t0 + (F::kTables ? n * ps : 0);
-    st.xs = reinterpret_cast<T*>(st.t1 + (F::kTables ? n * ps : 0));
-    st.vs = st.xs + n * ps;
-    st.isl = st.vs + (kHess ? 0 : n * ps);
+    st.t1 = st.t0 + (F::kTables ? ks * ps : 0);
+    st.xs = reinterpret_cast<T*>(st.t1 + (F::kTables ? ks * ps : 0));
+    st.vs = st.xs + ks * ps;
+    st.isl = st.vs + (kHess ? 0 : ks * ps);
 
     const double* xg = a.x + p0 * n;
     const double* vg = a.v + p0 * n;
     for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
         const int pl = idx / n, k = idx - pl * n;
         const double xv = xg[idx];
-        st.xs[k * ps + pl] = (T)xv;
-        if (!kHess) st.vs[k * ps + pl] = (T)vg[idx];
-        if (F::kTables) F::tables(xv, st.t0[k * ps + pl], st.t1[k * ps + pl]);
+        st.xs[pl * ks + k] = (T)xv;
+        if (!kHess) st.vs[pl * ks + k] = (T)vg[idx];
+        if (F::kTables) F::tables(xv, st.t0[pl * ks + k], st.t1[pl * ks + k]);
     }
     __syncthreads();
     const int tasks = F::isl_tasks(n);
     if (tasks) {
         for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
             const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl, st.t1 + pl, ps, a.fp, st.isl + pl);
+            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
         }
         __syncthreads();
     }
@@ -110,7 +116,7 @@ __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs
 template <class P, class F, int C, bool kHess, bool kGrad = false>
 __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, double* lds) {
     using T = typename P::T;
-    const int n = a.n, nc = a.nc, ps = a.pstride;
+    const int n = a.n, nc = a.nc;
     const int nthr = a.rows * nc;
     const int64_t nrows = a.npts * (int64_t)n;
     const int64_t q0 = blk * a.rows;
@@ -134,7 +140,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
 
     double dot = 0.0;
     if (active) {
-        PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
+        PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
         // 3. one f evaluation on hDual<C> seeds
         const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
         if (kHess) {
@@ -148,7 +154,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
             typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)
-                if (cs + l < n) acc.add(res.h[l], st.vs[(cs + l) * ps + pl]);
+                if (cs + l < n) acc.add(res.h[l], st.vs[pl * st.ks + cs + l]);
             dot = acc.get();
             // the first-order and value components of the same call
             if (kGrad && j == 0) {
@@ -183,7 +189,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
 template <class P, class F, int C, int kLevel>
 __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, double* lds) {
     using T = typename P::T;
-    const int n = a.n, nc = a.nc, ps = a.pstride;
+    const int n = a.n, nc = a.nc;
     const int64_t nrows = a.npts * (int64_t)n;
     const int64_t q0 = blk * a.rows;
     const int64_t qlast = (q0 + a.rows < nrows ? q0 + a.rows : nrows) - 1;
@@ -202,21 +208,27 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
         double res = 0.0;
         for (int j = 0; j < nc; ++j) {
             const int cs = j * C;
-            PointView<T> pv{st.xs + pl, st.t0 + pl, st.t1 + pl, st.isl + pl, ps, n, i, cs};
+            PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
             // the lanes of a wave are at the same chunk: terms outside it run light
             const HD<T, C> h = F::template eval<P, C, true>(pv, a.fp);
             typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)
-                if (cs + l < n) acc.add(h.h[l], st.vs[(cs + l) * ps + pl]);
+                if (cs + l < n) acc.add(h.h[l], st.vs[pl * st.ks + cs + l]);
             res += acc.get();
         }
         a.out[q] = res;
     }
 }
 
+// At C = 8 the float64 L1/L0 kernels sit a few registers above 96, where the
+// occupancy drops from five waves per SIMD to four; ask for five there.
+template <int C>
+constexpr int coarse_waves_per_eu() { return C == 8 ? 5 : 1; }
+
 template <class P, class F, int C, int kLevel>
-__global__ __launch_bounds__(kMaxBlock) void coarse_kernel(PlainArgs a) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(coarse_waves_per_eu<C>())))
+void coarse_kernel(PlainArgs a) {
     extern __shared__ double lds[];
     coarse_block<P, F, C, kLevel>(a, blockIdx.x, lds);
 }

@@ -46,7 +46,7 @@ struct SymArgs {
     int n;
     int nc;             // ceil(n / C)
     int ppb;            // points per workgroup
-    int pstride;        // LDS stride between entries of one point (>= ppb)
+    int pstride;        // LDS rows per staged array (>= ppb)
 };
 
 constexpr int kSymThreads = 256;
@@ -68,15 +68,16 @@ __host__ __device__ inline int sym_mir_off(int s) {
 }
 
 // LDS bytes (host and device agree on this layout):
-// doubles: partial sums [ppb][C nc^2] (H.v), t0, t1 [n][pstride];
-// T: xs, vs [n][pstride], isl [isl][pstride]
+// doubles: partial sums [ppb][C nc^2] (H.v), t0, t1 [pstride][ks];
+// T: xs, vs [pstride][ks], isl [pstride][ki] (per-point rows, aos_stride)
 template <class P, class F>
 __host__ __device__ inline size_t sym_lds_bytes(int n, int C, int ppb, int pstride, bool hess) {
     using T = typename P::T;
     const int nc = (n + C - 1) / C;
     const size_t red = hess ? 0 : (size_t)ppb * C * nc * nc;
-    const size_t dbl = red + (F::kTables ? 2 * (size_t)n * pstride : 0);
-    const size_t tt = (size_t)n * pstride * (hess ? 1 : 2) + (size_t)F::isl_size(n) * pstride;
+    const size_t ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
+    const size_t dbl = red + (F::kTables ? 2 * ks * pstride : 0);
+    const size_t tt = ks * pstride * (hess ? 1 : 2) + ki * pstride;
     return dbl * sizeof(double) + tt * sizeof(T);
 }
 
@@ -110,21 +111,22 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
 
     double* red = lds;  // per point: own sums [per_point], then mirror sums
     double* t0 = red + (kHess ? 0 : (size_t)ppb * slots);
-    double* t1 = t0 + (F::kTables ? n * ps : 0);
-    T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? n * ps : 0));
-    T* vs = xs + n * ps;
-    T* isl = vs + (kHess ? 0 : n * ps);
+    const int ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
+    double* t1 = t0 + (F::kTables ? ks * ps : 0);
+    T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? ks * ps : 0));
+    T* vs = xs + ks * ps;
+    T* isl = vs + (kHess ? 0 : ks * ps);
 
-    // 1. stage coordinates (and vectors) as structure-of-arrays, with the
+    // 1. stage coordinates (and vectors) in per-point rows, with the
     //    per-coordinate tables
     const double* xg = a.x + p0 * n;
     const double* vg = a.v + p0 * n;
     for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
         const int pl = idx / n, k = idx - pl * n;
         const double xv = xg[idx];
-        xs[k * ps + pl] = (T)xv;
-        if (!kHess) vs[k * ps + pl] = (T)vg[idx];
-        if (F::kTables) F::tables(xv, t0[k * ps + pl], t1[k * ps + pl]);
+        xs[pl * ks + k] = (T)xv;
+        if (!kHess) vs[pl * ks + k] = (T)vg[idx];
+        if (F::kTables) F::tables(xv, t0[pl * ks + k], t1[pl * ks + k]);
     }
     __syncthreads();
     // 2. per-point float64 island values
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
     if (tasks) {
         for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
             const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, t0 + pl, t1 + pl, ps, a.fp, isl + pl);
+            F::island(task, n, xg + (size_t)pl * n, t0 + pl * ks, t1 + pl * ks, 1, a.fp, isl + pl * ki);
         }
         __syncthreads();
     }
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
 #pragma unroll
         for (int l = 0; l < C; ++l) m[l] = 0.0;
         if (active) {
-            PointView<T> pv{xs + pl, t0 + pl, t1 + pl, isl + pl, ps, n, i, cs};
+            PointView<T> pv{xs + pl * ks, t0 + pl * ks, t1 + pl * ks, isl + pl * ki, n, i, cs};
             const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
             if (kHess) {
                 double* Hp = a.out + (p0 + pl) * (int64_t)n * n;
@@ -182,10 +184,10 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
                 typename P::Dot acc;
 #pragma unroll
                 for (int l = 0; l < C; ++l)
-                    if (cs + l < n) acc.add(res.h[l], vs[(cs + l) * ps + pl]);
+                    if (cs + l < n) acc.add(res.h[l], vs[pl * ks + cs + l]);
                 red[(size_t)pl * slots + local] = acc.get();
                 if (mirrored) {
-                    const double vi = (double)vs[i * ps + pl];
+                    const double vi = (double)vs[pl * ks + i];
 #pragma unroll
                     for (int l = 0; l < C; ++l) m[l] = cs + l < n ? (double)res.h[l] * vi : 0.0;
                 }
