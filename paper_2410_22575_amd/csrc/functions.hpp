@@ -174,12 +174,18 @@ struct Ackley {
     }
 
     // kSplit: as for Rosenbrock, the terms of variables outside the chunk
-    // run on HD<T, 0>
+    // carry no chunk components, and term k = cs + m has the one chunk
+    // component m.  So each sum's component m is complete once its one window
+    // term is added (to zero, exactly), and F's and G's chain rule is applied
+    // to it right there; the sums' row-derivative components, to which every
+    // term contributes, are formed first, in order of k.  The values are those
+    // of the accumulated sums, and only the result's components stay live.
+    // (The sums' value components are never read: the chain takes F and G.)
     template <class P, int C, bool kSplit = false>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        typename P::template Acc<C> ss, cs;
         if constexpr (!kSplit) {
+            typename P::template Acc<C> ss, cs;
             HD1<T, C> y = pv.template y<C>(0);
             ss = P::start(sq(y));
             cs = P::start(cos_term<T, C>(pv, 0));
@@ -190,35 +196,38 @@ struct Ackley {
                 P::add_sparse(ss, sq(y));
                 P::add_sparse(cs, cos_term<T, C>(pv, k));
             }
+            const HD<T, C> t = chain(P::value(ss), pv.island(0), pv.island(1), pv.island(2));   // F
+            const HD<T, C> u = chain(P::value(cs), pv.island(3), pv.island(4), pv.island(5));   // G
+            return (t + u) + T(20.0 + kE);
         } else {
-            const int k0 = pv.cs, k1 = pv.cs + C < pv.n ? pv.cs + C : pv.n;
-            ss = P::start(zero_hd<T, C>());
-            cs = P::start(zero_hd<T, C>());
-            for (int k = 0; k < k0; ++k) {
+            T ssd = T(0), csd = T(0);
+            for (int k = 0; k < pv.n; ++k) {
                 const HD1<T, 0> y = pv.template y<0>(k);
-                P::add_light(ss, sq(y));
-                P::add_light(cs, cos_term<T, 0>(pv, k));
+                ssd += sq(y).d;
+                csd += cos_term<T, 0>(pv, k).d;
             }
-            // term k = cs + m has the one chunk component m: it runs on that
-            // component alone and is added there
+            // chain(a, g, g', g''): r.d = g' a.d, r.g = g' a.g, r.h = g' a.h + (g'' a.d) a.g
+            const T f1 = pv.island(1), f2d = pv.island(2) * ssd;
+            const T g1 = pv.island(4), g2d = pv.island(5) * csd;
+            HD<T, C> r;
+            r.v = (pv.island(0) + pv.island(3)) + T(20.0 + kE);
+            r.d = f1 * ssd + g1 * csd;
+            const int k0 = pv.cs, k1 = pv.cs + C < pv.n ? pv.cs + C : pv.n;
             static_for<C>([&](auto mc) {
                 constexpr int m = decltype(mc)::value;
                 const int k = k0 + m;
                 if (k < k1) {
                     const HD1<T, 1> y = pv.template y_at<1>(k, m);
-                    P::template add_at<m>(ss, sq(y));
-                    P::template add_at<m>(cs, cos_of(pv, y, k));
+                    const HD<T, 1> st = sq(y), ct = cos_of(pv, y, k);
+                    r.g[m] = f1 * st.g[0] + g1 * ct.g[0];
+                    r.h[m] = (f1 * st.h[0] + f2d * st.g[0]) + (g1 * ct.h[0] + g2d * ct.g[0]);
+                } else {
+                    r.g[m] = T(0);
+                    r.h[m] = T(0);
                 }
             });
-            for (int k = k1; k < pv.n; ++k) {
-                const HD1<T, 0> y = pv.template y<0>(k);
-                P::add_light(ss, sq(y));
-                P::add_light(cs, cos_term<T, 0>(pv, k));
-            }
+            return r;
         }
-        const HD<T, C> t = chain(P::value(ss), pv.island(0), pv.island(1), pv.island(2));   // F
-        const HD<T, C> u = chain(P::value(cs), pv.island(3), pv.island(4), pv.island(5));   // G
-        return (t + u) + T(20.0 + kE);
     }
 };
 

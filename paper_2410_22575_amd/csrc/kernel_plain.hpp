@@ -221,14 +221,8 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
     }
 }
 
-// At C = 8 the float64 L1/L0 kernels sit a few registers above 96, where the
-// occupancy drops from five waves per SIMD to four; ask for five there.
-template <int C>
-constexpr int coarse_waves_per_eu() { return C == 8 ? 5 : 1; }
-
 template <class P, class F, int C, int kLevel>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(coarse_waves_per_eu<C>())))
-void coarse_kernel(PlainArgs a) {
+__global__ __launch_bounds__(kMaxBlock) void coarse_kernel(PlainArgs a) {
     extern __shared__ double lds[];
     coarse_block<P, F, C, kLevel>(a, blockIdx.x, lds);
 }
