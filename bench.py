@@ -35,6 +35,17 @@ METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at state
 # copy-kernel calibration), keyed by the kernel as it stood when the counters
 # were taken; a kernel absent here reports traffic null.
 MEASURED_TRAFFIC = {
+    "coarse_kernel<ackley, C=1, L1, H.v>": 4.0275e+08,
+    "coarse_kernel<ackley, C=2, L1, H.v>": 4.0276e+08,
+    "coarse_kernel<ackley, C=4, L1, H.v>": 4.0276e+08,
+    "coarse_kernel<ackley, C=8, L1, H.v>": 4.0277e+08,
+    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0280e+08,
+    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.0271e+08,
+    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.0270e+08,
+    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0271e+08,
+    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0274e+08,
+    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
+    "fp_tile_kernel<NK=8, H.v>": 4.0288e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -43,6 +54,17 @@ MEASURED_TRAFFIC = {
 # than the paper's operation model counts: first-order seeds carry no
 # second-order part and the compiler folds the constant seed components.
 MEASURED_VALU_FLOPS = {
+    "coarse_kernel<ackley, C=1, L1, H.v>": 2.2951e+10,
+    "coarse_kernel<ackley, C=2, L1, H.v>": 1.4093e+10,
+    "coarse_kernel<ackley, C=4, L1, H.v>": 9.6637e+09,
+    "coarse_kernel<ackley, C=8, L1, H.v>": 7.4491e+09,
+    "coarse_kernel<ackley, C=16, L1, H.v>": 6.3418e+09,
+    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.5298e+09,
+    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.1272e+09,
+    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 3.9259e+09,
+    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.8252e+09,
+    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 3.7749e+09,
+    "fp_tile_kernel<NK=8, H.v>": 3.8588e+09,
 }
 
 
