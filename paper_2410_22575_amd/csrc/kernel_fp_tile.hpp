@@ -75,9 +75,41 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
     double* rw = rvs + wave * P * S;
     double* vw = vs + (kHess ? 0 : wave * P * S);
 
+    // every global load of the prologue is issued first, so that their
+    // latencies overlap: this lane's coordinates, the [A B] operands of the
+    // value column, its four vector entries, and its column of A and B
+    const bool halves = NK % 2 == 0 && n == 2 * NK;
+    double xv[NK], aop[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+        const int k = 4 * s + lg;
+        const bool in = k < 2 * n;
+        const int j = k < n ? k : k - n;
+        aop[s] = (li < n && in) ? (k < n ? a.fp.A[li * n + k] : a.fp.B[li * n + j]) : 0.0;
+        xv[s] = (in && live && !(halves && s >= NK / 2)) ? xp[j] : 0.0;
+    }
+    double vreg[4];
+    if (!kHess) {
+        // the wave's 16 vectors are contiguous in global memory
+        const double* vg = a.v + pbase * n;
+        const int64_t avail = (a.npts - pbase) * n;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int idx = lane + 64 * t;
+            vreg[t] = (idx < P * n && idx < avail) ? vg[idx] : 0.0;
+        }
+    }
+    double am[4], bm[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int m = 4 * s + lg;
+        const bool in = m < n && li < n;
+        am[s] = in ? a.fp.A[m * n + li] : 0.0;
+        bm[s] = in ? a.fp.B[m * n + li] : 0.0;
+    }
+
     // 1. value column: lane (point li) contracts its sin/cos values
     {
-        const bool halves = NK % 2 == 0 && n == 2 * NK;
         double ssv[NK], csv[NK];
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -85,17 +117,16 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
             const int k = 4 * s + lg;
             const bool in = k < 2 * n;
             const int j = k < n ? k : k - n;
-            const double aop = (li < n && in) ? (k < n ? a.fp.A[li * n + k] : a.fp.B[li * n + j]) : 0.0;
             double sj = 0.0, cj = 0.0;
             if (halves && s >= NK / 2) {
                 sj = ssv[s >= NK / 2 ? s - NK / 2 : 0];
                 cj = csv[s >= NK / 2 ? s - NK / 2 : 0];
             } else if (in && live) {
-                sincos(xp[j], &sj, &cj);
+                sincos(xv[s], &sj, &cj);
             }
             ssv[s] = sj;
             csv[s] = cj;
-            acc = mfma16(aop, k < n ? sj : cj, acc);
+            acc = mfma16(aop[s], k < n ? sj : cj, acc);
             // the lane of sin row k = j stores coordinate j's pair
             if (k < n) {
                 sw[li * S + j] = sj;
@@ -121,12 +152,14 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
         }
     }
     if (!kHess) {
-        // the wave's 16 vectors (contiguous in global memory), zero-padded
-        const double* vg = a.v + pbase * n;
-        const int64_t avail = (a.npts - pbase) * n;
-        for (int idx = lane; idx < P * n; idx += 64) {
-            const int pl = idx / n, k = idx - pl * n;
-            vw[pl * S + k] = idx < avail ? vg[idx] : 0.0;
+        // v in LDS, zero-padded to 16 entries per point
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < P * n) {
+                const int pl = idx / n, k = idx - pl * n;
+                vw[pl * S + k] = vreg[t];
+            }
         }
         for (int idx = lane; idx < P * (P - n); idx += 64) {
             const int pl = idx / (P - n), k = n + idx - pl * (P - n);
@@ -137,15 +170,8 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_tile_kernel(FpMfmaArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // 2. this lane's entries of A and B: column li, rows m = 4 s + lg
-    double am[4], bm[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int m = 4 * s + lg;
-        const bool in = m < n && li < n;
-        am[s] = in ? a.fp.A[m * n + li] : 0.0;
-        bm[s] = in ? a.fp.B[m * n + li] : 0.0;
-    }
+    // 2. the point loop; am, bm: this lane's entries of A and B (column li,
+    // rows m = 4 s + lg)
     const int ms = (n + 3) >> 2;   // K steps that hold a residual
     const int np = a.npts - pbase < P ? (int)(a.npts - pbase) : P;
     for (int pt = 0; pt < np; ++pt) {
