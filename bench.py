@@ -45,7 +45,6 @@ MEASURED_TRAFFIC = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0271e+08,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0274e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
-    "fp_tile_kernel<NK=8, H.v>": 4.0288e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -64,7 +63,13 @@ MEASURED_VALU_FLOPS = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 3.9259e+09,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.8252e+09,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 3.7749e+09,
-    "fp_tile_kernel<NK=8, H.v>": 3.8588e+09,
+}
+
+# VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, MFMA included),
+# same keying and rule as MEASURED_TRAFFIC.  A CU issues at most one vector
+# wave-instruction per clock (four SIMDs, four clocks per wave64 instruction),
+# so count / (256 CUs x 2.4 GHz) is the launch's minimum issue time.
+MEASURED_VALU_INSTS = {
 }
 
 
@@ -409,6 +414,9 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": MEASURED_TRAFFIC.get(kname),
                 "flops_per_launch": work, "basis": basis, "model_flops_per_launch": model_launch,
                 "model_tflops": model_launch / t_dom / 1e12}
+    insts = MEASURED_VALU_INSTS.get(kname)
+    # share of the launch the vector issue alone would take (1.0 = issue-bound)
+    roofline["valu_issue_frac"] = insts / (256 * 2.4e9) / t_dom if insts else None
     if bound == "mfma":
         roofline["measured_mfma_f64_peak"] = 72.8
         valu = MEASURED_VALU_FLOPS.get(kname)
