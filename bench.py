@@ -45,6 +45,7 @@ MEASURED_TRAFFIC = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0271e+08,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0274e+08,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
+    "fp_tile_kernel<NK=8, H.v>": 4.0292e+08,
 }
 
 # float64 flops the vector ALUs execute per launch (rocprofv3
@@ -63,6 +64,7 @@ MEASURED_VALU_FLOPS = {
     "coarse_kernel<rosenbrock, C=4, L1, H.v>": 3.9259e+09,
     "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.8252e+09,
     "coarse_kernel<rosenbrock, C=16, L1, H.v>": 3.7749e+09,
+    "fp_tile_kernel<NK=8, H.v>": 3.8588e+09,
 }
 
 # VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, MFMA included),
@@ -70,6 +72,17 @@ MEASURED_VALU_FLOPS = {
 # wave-instruction per clock (four SIMDs, four clocks per wave64 instruction),
 # so count / (256 CUs x 2.4 GHz) is the launch's minimum issue time.
 MEASURED_VALU_INSTS = {
+    "coarse_kernel<ackley, C=1, L1, H.v>": 7.3374e+08,
+    "coarse_kernel<ackley, C=2, L1, H.v>": 4.3988e+08,
+    "coarse_kernel<ackley, C=4, L1, H.v>": 2.8888e+08,
+    "coarse_kernel<ackley, C=8, L1, H.v>": 2.1339e+08,
+    "coarse_kernel<ackley, C=16, L1, H.v>": 1.7564e+08,
+    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 1.4523e+08,
+    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 1.2321e+08,
+    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 1.1141e+08,
+    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 1.0774e+08,
+    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 1.0302e+08,
+    "fp_tile_kernel<NK=8, H.v>": 9.3979e+07,
 }
 
 
