@@ -113,14 +113,15 @@ int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* 
  *   - every hDual component is carried in float32 (coordinates, v and the
  *     per-coordinate sin/cos tables are rounded to float32 where used);
  *   - the Hessian-chunk components of the Fletcher-Powell sum of squared
- *     residuals accumulate with two-sum compensation over blocks of
- *     residuals (four per lane for n <= 16, entering the compensated chunk
- *     dot; sixteen for n > 16); Rosenbrock's and Ackley's sums, where
- *     each component has at most two nonzero terms and compensation cannot
- *     change the rounded result, are plain; the chunk dot uses two-product
- *     and two-sum; the row sum over chunks is float64;
- *   - per-point float64 islands: Ackley's sqrt of the mean square and both
- *     exponentials (as g, g', g''), and the Fletcher-Powell residual values
+ *     residuals: for n <= 16 one float32 MFMA block over the residuals; for
+ *     n > 16 plain float32 blocks of sixteen residuals entering a two-sum
+ *     compensated running sum; Rosenbrock's and Ackley's sums, where each
+ *     component has at most two nonzero terms and compensation cannot
+ *     change the rounded result, are plain;
+ *   - the chunk dot with v and the row sum over chunks are float64 (a
+ *     float32 x float32 product is exact in float64);
+ *   - per-point float64 islands: Ackley's two outer functions with their
+ *     first two derivatives, and the Fletcher-Powell residual values
  *     E_m - sum_j (A_mj sin x_j + B_mj cos x_j), which cancel.
  * The error is bounded by float32 rounding of the inputs and of the hDual
  * arithmetic: normwise relative errors of a few 1e-7 on the test inputs.

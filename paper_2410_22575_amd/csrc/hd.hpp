@@ -294,18 +294,13 @@ CF_DEV HD<T, C> chain(const HD1<T, C>& a, T g0, T g1, T g2) {
 namespace chessfad {
 
 // ---------------------------------------------------------------- precision
-// Error-free transformations (Knuth's two-sum; the fma form of two-product).
+// Error-free transformation: Knuth's two-sum.
 // The _rn intrinsics keep the compiler from contracting a neighbouring
 // multiply into these additions, which would break the exact error terms.
 CF_DEV void two_sum(float a, float b, float& s, float& e) {
     s = __fadd_rn(a, b);
     const float bb = __fsub_rn(s, a);
     e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, bb)), __fsub_rn(b, bb));
-}
-
-CF_DEV void two_prod(float a, float b, float& p, float& e) {
-    p = __fmul_rn(a, b);
-    e = fmaf(a, b, -p);
 }
 
 // Plain float64 hDuals: accumulations are ordinary hDual sums.
@@ -351,8 +346,8 @@ struct F64 {
 };
 
 // float32 hDuals whose Hessian-chunk components are accumulated with
-// two-sum compensation (a running low part per component); the chunk dot
-// uses two-product and two-sum and is returned in float64.
+// two-sum compensation (a running low part per component); the chunk dot is
+// float64.
 struct F32C {
     using T = float;
     template <int C>
@@ -421,16 +416,12 @@ struct F32C {
         for (int l = 0; l < C; ++l) r.h[l] = a.x.h[l] + a.lo[l];
         return r;
     }
+    // the chunk dot in float64: a float32 x float32 product is exact in
+    // float64, so each term is exact and only the float64 sum rounds
     struct Dot {
-        float hi = 0.0f, lo = 0.0f;
-        CF_DEV void add(T a, T b) {
-            float p, pe, s, e;
-            two_prod(a, b, p, pe);
-            two_sum(hi, p, s, e);
-            hi = s;
-            lo += e + pe;
-        }
-        CF_DEV double get() const { return (double)hi + (double)lo; }
+        double s = 0.0;
+        CF_DEV void add(T a, T b) { s += (double)a * (double)b; }
+        CF_DEV double get() const { return s; }
     };
 };
 

@@ -50,8 +50,8 @@
 // Precision policies: F64 runs every step in float64 (v_mfma_f64_16x16x4f64);
 // F32C runs the derivative columns on v_mfma_f32_16x16x4f32 with float32
 // seeded factors and [A B], keeps the value column and the residual values
-// r_m in float64 (their difference E_m - inner_m cancels), and accumulates
-// the sum over m and the chunk dot with two-sum / two-product compensation.
+// r_m in float64 (their difference E_m - inner_m cancels), sums each lane's
+// four residuals in float32 and forms the chunk dot in float64.
 //
 // Operand layouts (lane l = 0..63), both instructions:
 //   A: lane l holds A[l % 16][l / 16];   B: lane l holds B[l / 16][l % 16];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_mfma_kernel(FpMfmaArgs a) {
         // each lane group also keeps its part of the mirror terms.  The
         // Hessian and the float32 symmetric form form every entry first.  In float32
         // the lane's four-row partial is a plain sum and its chunk dot is
-        // compensated (two-product, two-sum); the lanes' dots meet in float64.
+        // float64; the lanes' dots meet in float64.
         constexpr bool kLaneDot = !kHess && (!kSym || sizeof(T) == sizeof(double));
         double lane_row = 0.0;
         // fixed trip counts (no early exit) so that rg is indexed statically
