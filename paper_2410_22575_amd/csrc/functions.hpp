@@ -86,45 +86,32 @@ struct Rosenbrock {
         return T(100) * sq(b) + sq(e);
     }
 
-    // kSplit: the terms k whose variables y_k, y_k+1 both lie outside the
-    // call's chunk [cs, cs + C) have seeds with no g part, so their g and h
+    // The terms k whose variables y_k, y_k+1 both lie outside the call's
+    // chunk [cs, cs + C) have seeds with no g part, so their g and h
     // components are exact zeros; they run on HD<T, 0> (value and row
-    // derivative only), in the same order as the others.  For kernels whose
-    // lanes of a wave share cs.
-    template <class P, int C, bool kSplit = false>
+    // derivative only), in order of k with the others.  Second-order
+    // component (i, cs + l) receives at most two nonzero terms.  For kernels
+    // whose lanes of a wave share cs.
+    template <class P, int C>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        if constexpr (!kSplit) {
-            HD1<T, C> yk = pv.template y<C>(0);
-            HD1<T, C> yk1 = pv.template y<C>(1);
-            auto s = P::start(term<T, C>(yk, yk1));
-            // second-order component (i, cs + l) of term k is nonzero only when
-            // both i and cs + l are k or k + 1: at most two terms per component
-            for (int k = 1; k + 1 < pv.n; ++k) {
-                yk = yk1;
-                yk1 = pv.template y<C>(k + 1);
-                P::add_sparse(s, term<T, C>(yk, yk1));
-            }
-            return P::value(s);
-        } else {
-            const int nt = pv.n - 1;                                 // terms
-            const int k0 = pv.cs > 0 ? pv.cs - 1 : 0;                // first term touching the chunk
-            const int k1 = pv.cs + C < nt ? pv.cs + C : nt;          // one past the last
-            auto s = P::start(zero_hd<T, C>());
-            for (int k = 0; k < k0; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
-            // term k = cs - 1 + p has chunk components p - 1 and p only: it runs
-            // on that window of two and is added there (the other components
-            // of a full-width term are exact zeros)
-            static_for<C + 1>([&](auto pc) {
-                constexpr int p = decltype(pc)::value;
-                const int k = pv.cs - 1 + p;
-                if (k >= k0 && k < k1)
-                    P::template add_at<p - 1>(s, term<T, 2>(pv.template y_at<2>(k, p - 1),
-                                                            pv.template y_at<2>(k + 1, p - 1)));
-            });
-            for (int k = k1; k < nt; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
-            return P::value(s);
-        }
+        const int nt = pv.n - 1;                                 // terms
+        const int k0 = pv.cs > 0 ? pv.cs - 1 : 0;                // first term touching the chunk
+        const int k1 = pv.cs + C < nt ? pv.cs + C : nt;          // one past the last
+        auto s = P::start(zero_hd<T, C>());
+        for (int k = 0; k < k0; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
+        // term k = cs - 1 + p has chunk components p - 1 and p only: it runs
+        // on that window of two and is added there (the other components
+        // of a full-width term are exact zeros)
+        static_for<C + 1>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            const int k = pv.cs - 1 + p;
+            if (k >= k0 && k < k1)
+                P::template add_at<p - 1>(s, term<T, 2>(pv.template y_at<2>(k, p - 1),
+                                                        pv.template y_at<2>(k + 1, p - 1)));
+        });
+        for (int k = k1; k < nt; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
+        return P::value(s);
     }
 };
 
@@ -173,61 +160,44 @@ struct Ackley {
         return chain(T(kTwoPi) * y, c, -s, -c);
     }
 
-    // kSplit: as for Rosenbrock, the terms of variables outside the chunk
-    // carry no chunk components, and term k = cs + m has the one chunk
-    // component m.  So each sum's component m is complete once its one window
-    // term is added (to zero, exactly), and F's and G's chain rule is applied
-    // to it right there; the sums' row-derivative components, to which every
-    // term contributes, are formed first, in order of k.  The values are those
-    // of the accumulated sums, and only the result's components stay live.
-    // (The sums' value components are never read: the chain takes F and G.)
-    template <class P, int C, bool kSplit = false>
+    // As for Rosenbrock, the terms of variables outside the chunk carry no
+    // chunk components, and term k = cs + m has the one chunk component m.
+    // So each sum's component m is complete once its one window term is
+    // added (to zero, exactly), and F's and G's chain rule is applied to it
+    // right there; the sums' row-derivative components, to which every term
+    // contributes, are formed first, in order of k.  The values are those of
+    // the accumulated sums, and only the result's components stay live.  (The
+    // sums' value components are never read: the chain takes F and G.)
+    template <class P, int C>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams&) {
         using T = typename P::T;
-        if constexpr (!kSplit) {
-            typename P::template Acc<C> ss, cs;
-            HD1<T, C> y = pv.template y<C>(0);
-            ss = P::start(sq(y));
-            cs = P::start(cos_term<T, C>(pv, 0));
-            // second-order component (i, cs + l) of a term in y_k is nonzero only
-            // for k = i = cs + l: at most one term per component
-            for (int k = 1; k < pv.n; ++k) {
-                y = pv.template y<C>(k);
-                P::add_sparse(ss, sq(y));
-                P::add_sparse(cs, cos_term<T, C>(pv, k));
-            }
-            const HD<T, C> t = chain(P::value(ss), pv.island(0), pv.island(1), pv.island(2));   // F
-            const HD<T, C> u = chain(P::value(cs), pv.island(3), pv.island(4), pv.island(5));   // G
-            return (t + u) + T(20.0 + kE);
-        } else {
-            T ssd = T(0), csd = T(0);
-            for (int k = 0; k < pv.n; ++k) {
-                const HD1<T, 0> y = pv.template y<0>(k);
-                ssd += sq(y).d;
-                csd += cos_term<T, 0>(pv, k).d;
-            }
-            // chain(a, g, g', g''): r.d = g' a.d, r.g = g' a.g, r.h = g' a.h + (g'' a.d) a.g
-            const T f1 = pv.island(1), f2d = pv.island(2) * ssd;
-            const T g1 = pv.island(4), g2d = pv.island(5) * csd;
-            HD<T, C> r;
-            r.v = (pv.island(0) + pv.island(3)) + T(20.0 + kE);
-            r.d = f1 * ssd + g1 * csd;
-            const int k0 = pv.cs, k1 = pv.cs + C < pv.n ? pv.cs + C : pv.n;
-            static_for<C>([&](auto mc) {
-                constexpr int m = decltype(mc)::value;
-                const int k = k0 + m;
-                if (k < k1) {
-                    const HD1<T, 1> y = pv.template y_at<1>(k, m);
-                    const HD<T, 1> st = sq(y), ct = cos_of(pv, y, k);
-                    r.g[m] = f1 * st.g[0] + g1 * ct.g[0];
-                    r.h[m] = (f1 * st.h[0] + f2d * st.g[0]) + (g1 * ct.h[0] + g2d * ct.g[0]);
-                } else {
-                    r.g[m] = T(0);
-                    r.h[m] = T(0);
-                }
-            });
-            return r;
+        T ssd = T(0), csd = T(0);
+        for (int k = 0; k < pv.n; ++k) {
+            const HD1<T, 0> y = pv.template y<0>(k);
+            ssd += sq(y).d;
+            csd += cos_term<T, 0>(pv, k).d;
         }
+        // chain(a, g, g', g''): r.d = g' a.d, r.g = g' a.g, r.h = g' a.h + (g'' a.d) a.g
+        const T f1 = pv.island(1), f2d = pv.island(2) * ssd;
+        const T g1 = pv.island(4), g2d = pv.island(5) * csd;
+        HD<T, C> r;
+        r.v = (pv.island(0) + pv.island(3)) + T(20.0 + kE);
+        r.d = f1 * ssd + g1 * csd;
+        const int k0 = pv.cs, k1 = pv.cs + C < pv.n ? pv.cs + C : pv.n;
+        static_for<C>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int k = k0 + m;
+            if (k < k1) {
+                const HD1<T, 1> y = pv.template y_at<1>(k, m);
+                const HD<T, 1> st = sq(y), ct = cos_of(pv, y, k);
+                r.g[m] = f1 * st.g[0] + g1 * ct.g[0];
+                r.h[m] = (f1 * st.h[0] + f2d * st.g[0]) + (g1 * ct.h[0] + g2d * ct.g[0]);
+            } else {
+                r.g[m] = T(0);
+                r.h[m] = T(0);
+            }
+        });
+        return r;
     }
 };
 
@@ -275,7 +245,7 @@ struct FletcherPowell {
         return r;
     }
 
-    template <class P, int C, bool kSplit = false>
+    template <class P, int C>
     static CF_DEV HD<typename P::T, C> eval(const PointView<typename P::T>& pv, const FpParams& prm) {
         using T = typename P::T;
         HD<T, C> r = residual<T, C>(pv, prm, 0);

@@ -314,8 +314,6 @@ struct F64 {
     static CF_DEV Acc<C> start(const HD<T, C>& t) { return Acc<C>{t}; }
     template <int C>
     static CF_DEV void add(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
-    template <int C>
-    static CF_DEV void add_sparse(Acc<C>& a, const HD<T, C>& t) { a.x = a.x + t; }
     // a term with no component in the chunk: value and row derivative only
     template <int C>
     static CF_DEV void add_light(Acc<C>& a, const HD<T, 0>& t) {
@@ -376,28 +374,18 @@ struct F32C {
             a.lo[l] += e;
         }
     }
-    // A sum whose every Hessian-chunk component receives at most two nonzero
-    // terms (the others are exact zeros): a two-sum pair (s, e) of two terms
-    // has s + e = a + b exactly, so value() returns round(a + b) = s, which is
-    // what the rounded plain sum gives.  The low part is skipped; the adds are
-    // kept apart from the terms' products, as in two_sum.
-    template <int C>
-    static CF_DEV void add_sparse(Acc<C>& a, const HD<T, C>& t) {
-        a.x.v += t.v;
-        a.x.d += t.d;
-#pragma unroll
-        for (int l = 0; l < C; ++l) {
-            a.x.g[l] += t.g[l];
-            a.x.h[l] = __fadd_rn(a.x.h[l], t.h[l]);
-        }
-    }
     template <int C>
     static CF_DEV void add_light(Acc<C>& a, const HD<T, 0>& t) {
         a.x.v += t.v;
         a.x.d += t.d;
     }
-    // add_sparse for a term given as its chunk components M .. M + W - 1
-    // (the others exact zeros); slots outside [0, C) are skipped
+    // A term given as its chunk components M .. M + W - 1 (the others exact
+    // zeros; slots outside [0, C) are skipped), into a sum whose every
+    // Hessian-chunk component receives at most two nonzero terms: a two-sum
+    // pair (s, e) of two terms has s + e = a + b exactly, so value() returns
+    // round(a + b) = s, which is what the rounded plain sum gives.  The low
+    // part is skipped; the adds are kept apart from the terms' products, as
+    // in two_sum.
     template <int M, int C, int W>
     static CF_DEV void add_at(Acc<C>& a, const HD<T, W>& t) {
         a.x.v += t.v;

@@ -142,7 +142,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     if (active) {
         PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
         // 3. one f evaluation on hDual<C> seeds
-        const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
+        const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
         if (kHess) {
             // 4a. CHUNK-HESS: H[p][i][cs + l] = second-order component l
             double* row = a.out + q * n + cs;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
             const int cs = j * C;
             PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
             // the lanes of a wave are at the same chunk: terms outside it run light
-            const HD<T, C> h = F::template eval<P, C, true>(pv, a.fp);
+            const HD<T, C> h = F::template eval<P, C>(pv, a.fp);
             typename P::Dot acc;
 #pragma unroll
             for (int l = 0; l < C; ++l)

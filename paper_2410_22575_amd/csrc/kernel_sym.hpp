@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
         for (int l = 0; l < C; ++l) m[l] = 0.0;
         if (active) {
             PointView<T> pv{xs + pl * ks, t0 + pl * ks, t1 + pl * ks, isl + pl * ki, n, i, cs};
-            const HD<T, C> res = F::template eval<P, C, true>(pv, a.fp);
+            const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
             if (kHess) {
                 double* Hp = a.out + (p0 + pl) * (int64_t)n * n;
 #pragma unroll
