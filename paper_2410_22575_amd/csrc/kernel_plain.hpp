@@ -146,9 +146,17 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
         if (kHess) {
             // 4a. CHUNK-HESS: H[p][i][cs + l] = second-order component l
             double* row = a.out + q * n + cs;
+            if (C % 2 == 0 && cs + C <= n && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+                // a whole chunk on a 16-byte boundary: 16-byte stores
+                double2* row2 = reinterpret_cast<double2*>(row);
 #pragma unroll
-            for (int l = 0; l < C; ++l)
-                if (cs + l < n) row[l] = (double)res.h[l];
+                for (int l = 0; l < C / 2; ++l)
+                    row2[l] = make_double2((double)res.h[2 * l], (double)res.h[2 * l + 1]);
+            } else {
+#pragma unroll
+                for (int l = 0; l < C; ++l)
+                    if (cs + l < n) row[l] = (double)res.h[l];
+            }
         } else {
             // 4b. chunk dot with v[p][cs .. cs + C)
             typename P::Dot acc;
