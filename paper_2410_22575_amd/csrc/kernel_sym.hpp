@@ -173,12 +173,22 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
             const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
             if (kHess) {
                 double* Hp = a.out + (p0 + pl) * (int64_t)n * n;
+                double* row = Hp + (int64_t)i * n + cs;
+                if (C % 2 == 0 && cs + C <= n && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+                    // a whole chunk on a 16-byte boundary: 16-byte stores
+                    double2* row2 = reinterpret_cast<double2*>(row);
 #pragma unroll
-                for (int l = 0; l < C; ++l) {
-                    if (cs + l >= n) break;
-                    const double h = (double)res.h[l];
-                    Hp[(int64_t)i * n + cs + l] = h;
-                    if (mirrored) Hp[(int64_t)(cs + l) * n + i] = h;
+                    for (int l = 0; l < C / 2; ++l)
+                        row2[l] = make_double2((double)res.h[2 * l], (double)res.h[2 * l + 1]);
+                } else {
+#pragma unroll
+                    for (int l = 0; l < C; ++l)
+                        if (cs + l < n) row[l] = (double)res.h[l];
+                }
+                if (mirrored) {
+#pragma unroll
+                    for (int l = 0; l < C; ++l)
+                        if (cs + l < n) Hp[(int64_t)(cs + l) * n + i] = (double)res.h[l];
                 }
             } else {
                 typename P::Dot acc;
