@@ -2,110 +2,97 @@
 
 One step = one pass of the whole hot path over one batch: float64 chunked
 H.v for Rosenbrock, Ackley and Fletcher-Powell, each at n = 16 over 2^20
-resident points (seeded synthetic inputs), three launches through the C ABI.
+resident points (seeded synthetic inputs), three launches through the C ABI
+at the autotuned chunk (and mapping) of each function.  Every launch runs the
+chunked method: f is evaluated per (point, row, chunk) call on CHUNK-INIT
+seeds (Fletcher-Powell on the per-call kernel, CHESSFAD_OPT_FP_MFMA = 1).
 `value` is the total HVPs of a step divided by the step time.
 
-Also reported:
-  roofline      the dominant kernel's paper-model flops per launch divided by
-                its average launch time (HIP events around each launch inside
-                the timed region), against the float64 vector peak;
-  cpu_baseline  the CPU oracle's chunked method (plain C, OpenMP over points,
-                all host cores) timed on a bounded sample of the same inputs.
+Also reported, outside the timed region:
+  roofline        the dominant kernel's executed flops per launch (rocprofv3
+                  counters taken on the same kernel source; `stale` when the
+                  source has changed since) divided by its average launch time
+                  (HIP events on the launch stream inside the timed region);
+  cpu_baseline    the CPU oracle's chunked method (plain C, OpenMP over
+                  points, all host cores) on a bounded sample of the same
+                  inputs, with a one-thread run and the closed-form H.v
+                  beside it;
+  fp_engines      Fletcher-Powell at n = 16 on every engine and chunk: the
+                  per-call kernels (the method) and the closed-form J^T J
+                  tile (`fp_closed_form_tile`, not the method);
+  generic_method  the three functions written once as user functions over
+                  the generic hDual type (every operation of f in every call);
+  mixed_f32, hessian_f64, symmetric_f64, mappings_f64, batched, large_n,
+  cfg1_cpu_seconds.
 
-    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-cpu] [--no-batch] [--no-large]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 FUNCS = (0, 1, 2)
 NAMES = {0: "rosenbrock", 1: "ackley", 2: "fletcher_powell"}
 N = 16
 NPTS = 1 << 20
 PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (FMA = 2), vector and MFMA
+VALU_ISSUE_PER_S = 256 * 2.4e9   # vector wave-instructions per second (one per CU-clock)
 METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at stated error"
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0,
-# copy-kernel calibration), keyed by the kernel as it stood when the counters
-# were taken; a kernel absent here reports traffic null.
-MEASURED_TRAFFIC = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 4.0275e+08,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 4.0276e+08,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 4.0276e+08,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 4.0277e+08,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 4.0280e+08,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.0271e+08,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.0270e+08,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 4.0271e+08,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 4.0274e+08,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 4.0277e+08,
-    "fp_tile_kernel<NK=8, H.v>": 4.0292e+08,
-}
+# ---------------------------------------------------------------- counters
+# Per-launch figures from rocprofv3 --pmc runs of `bench.py --only step`
+# (profiles/hvp_n16_step_counters.md), keyed by kernel.  They hold for the
+# kernel source they were taken on: COUNTER_SOURCE_SHA is source_sha() at that
+# time, and a run whose source differs reports them with "stale": true.
+#   traffic     HBM bytes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, copy-kernel
+#               calibration; each x 1024)
+#   valu_flops  SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes (FMA = 2)
+#   valu_insts  SQ_INSTS_VALU wave-instructions (MFMA included)
+#   mfma_flops  SQ_INSTS_VALU_MFMA_MOPS_F64 x 512
+COUNTER_SOURCE_SHA = None
+COUNTERS = {}
 
-# float64 flops the vector ALUs execute per launch (rocprofv3
-# SQ_INSTS_VALU_FLOPS_FP64, which counts per wavefront, x 64 lanes; FMA = 2),
-# same keying and rule as MEASURED_TRAFFIC.  The kernels execute fewer flops
-# than the paper's operation model counts: first-order seeds carry no
-# second-order part and the compiler folds the constant seed components.
-MEASURED_VALU_FLOPS = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 2.2951e+10,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 1.4093e+10,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 9.6637e+09,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 7.4491e+09,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 6.3418e+09,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 4.5298e+09,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 4.1272e+09,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 3.9259e+09,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 3.8252e+09,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 3.7749e+09,
-    "fp_tile_kernel<NK=8, H.v>": 3.8588e+09,
-}
 
-# VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU, MFMA included),
-# same keying and rule as MEASURED_TRAFFIC.  A CU issues at most one vector
-# wave-instruction per clock (four SIMDs, four clocks per wave64 instruction),
-# so count / (256 CUs x 2.4 GHz) is the launch's minimum issue time.
-MEASURED_VALU_INSTS = {
-    "coarse_kernel<ackley, C=1, L1, H.v>": 7.3374e+08,
-    "coarse_kernel<ackley, C=2, L1, H.v>": 4.3988e+08,
-    "coarse_kernel<ackley, C=4, L1, H.v>": 2.8888e+08,
-    "coarse_kernel<ackley, C=8, L1, H.v>": 2.1339e+08,
-    "coarse_kernel<ackley, C=16, L1, H.v>": 1.7564e+08,
-    "coarse_kernel<rosenbrock, C=1, L1, H.v>": 1.4523e+08,
-    "coarse_kernel<rosenbrock, C=2, L1, H.v>": 1.2321e+08,
-    "coarse_kernel<rosenbrock, C=4, L1, H.v>": 1.1141e+08,
-    "coarse_kernel<rosenbrock, C=8, L1, H.v>": 1.0774e+08,
-    "coarse_kernel<rosenbrock, C=16, L1, H.v>": 1.0302e+08,
-    "fp_tile_kernel<NK=8, H.v>": 9.3979e+07,
-}
+def source_sha() -> str:
+    """sha256 over the library's sources and build flags (the kernels the
+    counters describe)."""
+    h = hashlib.sha256()
+    paths = [os.path.join(ROOT, "paper_2410_22575_amd", "build.py")]
+    for d in (os.path.join(ROOT, "paper_2410_22575_amd", "csrc"), os.path.join(ROOT, "include")):
+        paths += [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith((".hip", ".hpp", ".h"))]
+    for p in paths:
+        h.update(os.path.relpath(p, ROOT).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_key(f, c, n=N, mapping=2):
     """The kernel chessfad_hvp runs for (function, chunk, mapping) at n, as
-    keyed in the measured tables: the n <= 16 Fletcher-Powell MFMA kernel,
-    the L1 kernel when a row has a single chunk or L1 was chosen, else the
-    L2 vector kernel."""
+    keyed in COUNTERS."""
     if f == 2 and n <= 16:
-        return f"fp_tile_kernel<NK={min(8, max(1, (2 * n + 3) // 4))}, H.v>"
+        return f"fp_call_kernel<NK={min(8, max(1, (2 * n + 3) // 4))}, C={c}, H.v>"
+    if f == 2:
+        return f"fp_rows_kernel<C={c}, H.v>"
     if c >= n or mapping == 1:
         return f"coarse_kernel<{NAMES[f]}, C={c}, L1, H.v>"
     return f"plain_kernel<{NAMES[f]}, C={c}, H.v>"
 
 
-def fp_mfma_flops(n, c, npts):
-    """MFMA flops the n <= 16 Fletcher-Powell float64 kernel executes per
-    launch: per 16-point wave, NK steps of 16x16x4 for the value column, and
-    per point ceil(n / 4) steps for its 16 x 16 tile J^T J; 2 x 16 x 16 x 4
-    flops per step.  The chunk size does not change it."""
+def fp_value_column_mfma_flops(n, npts):
+    """MFMA flops of the per-call kernel's value column: per 16-point wave,
+    NK steps of 16x16x4 (2 x 16 x 16 x 4 flops each), whatever the chunk."""
     nk = min(8, max(1, (2 * n + 3) // 4))
-    steps = nk + 16 * ((n + 3) // 4)
-    return steps * 2 * 16 * 16 * 4 * (npts / 16)
+    return nk * 2 * 16 * 16 * 4 * (npts / 16)
 
 
 def parse():
@@ -113,18 +100,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chunk", type=int, default=0, help="0 = library default per function")
+    ap.add_argument("--chunk", type=int, default=0, help="0 = the autotuned chunk per function")
     ap.add_argument("--npts", type=int, default=NPTS)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baselines and cfg1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="use the default chunk instead of autotuning it")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance workload")
     ap.add_argument("--batch-instances", type=int, default=8192)
-    ap.add_argument("--large", action="store_true",
-                    help="also time n=64 (2^18 points, float64 and mixed) and n=512 (1024 points) H.v")
-    ap.add_argument("--only", choices=("large", "batch"), default=None,
-                    help="only run the large-n timings or the batched workload and print their JSON "
-                         "(for profiling; not the benchmark line)")
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 64 and n = 512 workloads")
+    ap.add_argument("--only", choices=("step", "large", "batch", "fp"), default=None,
+                    help="only run one part and print its JSON (for profiling; not the benchmark line)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -145,117 +130,196 @@ def copy_probe(mib, reps=3):
     print(json.dumps({"copy_probe_mib": mib, "reps": reps, "kib_per_launch_each_way": mib * 1024}), flush=True)
 
 
-def cpu_baseline(workloads, E, chunks, budget_s):
-    """Time the oracle's chunked CHESS-VEC (C, OpenMP) on a bounded sample."""
-    from oracle import chunked
+class Ctx:
+    """Library, inputs and helpers shared by the parts of the benchmark."""
 
-    chunked.build()
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    # calibrate on a small sample, then size the sample to the budget
-    sample = 64
-    while True:
-        t0 = time.perf_counter()
-        for f in FUNCS:
-            w = workloads[f]
-            chunked.hvp(f, w.x[:sample], w.v[:sample], chunks[f], w.A, w.B, E[f], nthreads=threads)
-        dt = time.perf_counter() - t0
-        if dt > 0.5 or sample >= 1 << 16:
-            break
-        sample *= 2
-    sample = int(min(NPTS, max(sample, sample * budget_s / max(dt, 1e-9))))
-    t0 = time.perf_counter()
-    per = {}
-    for f in FUNCS:
-        w = workloads[f]
-        t1 = time.perf_counter()
-        chunked.hvp(f, w.x[:sample], w.v[:sample], chunks[f], w.A, w.B, E[f], nthreads=threads)
-        per[NAMES[f]] = sample / (time.perf_counter() - t1)
-    dt = time.perf_counter() - t0
-    return {"value": 3 * sample / dt, "unit": "HVP/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of the {NPTS} points of each function (n=16, same chunk sizes), "
-                      f"oracle/chunked.c CHESS-VEC with OpenMP over points",
-            "per_function": per}
+    def __init__(self, npts):
+        import torch
 
+        from oracle import closed_form as cf
+        from paper_2410_22575_amd import binding, flops, inputs
 
-def large_n(binding, inputs, cf, torch, flops):
-    """n = 64 over 2^18 points (all three functions, float64 and mixed) and
-    n = 512 over 1024 points (Fletcher-Powell float64 and mixed, Rosenbrock
-    float64): kernel time, HVP/s, paper-model TFLOP/s and the max error on
-    sampled points."""
-    dev = torch.device("cuda:0")
-    res = {}
-    cases = [(f, 64, 1 << 18, prec) for f in FUNCS for prec in (0, 1)]
-    cases += [(2, 512, 1024, 1), (2, 512, 1024, 0), (0, 512, 1024, 0)]
-    for f, n, npts, prec in cases:
-        w = inputs.make_workload(f, n, npts, inputs.rng_for(100 + n))
-        x, v = torch.from_numpy(w.x).to(dev), torch.from_numpy(w.v).to(dev)
-        E = None
-        if f == 2:
-            binding.chessfad_fp_set_params(*(torch.from_numpy(a).to(dev) for a in (w.A, w.B, w.alpha)))
-            E = cf.fp_offsets(w.A, w.B, w.alpha)
-        # autotuned chunk (and mapping) except for Fletcher-Powell at n = 512,
-        # where one launch per chunk takes about a second: C = 16 there
-        if f == 2 and n == 512:
-            c = call_c = 16
-        else:
-            c, _ = binding.chessfad_autotune(f, n, prec, npts=min(npts, 1 << 16))
-            call_c = 0  # the tuned chunk and, for float64 on the vector ALUs, mapping
-        fn = binding.chessfad_hvp_mixed if prec else binding.chessfad_hvp
-        out = fn(f, x, v, chunk=call_c)
-        torch.cuda.synchronize()
-        reps = 1 if n == 512 and f == 2 else 3
+        self.torch, self.cf, self.binding, self.flops, self.inputs = torch, cf, binding, flops, inputs
+        binding.load()
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+        self.npts = npts
+
+    def dev_array(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
+
+    def set_fp(self, w):
+        self.binding.chessfad_fp_set_params(self.dev_array(w.A), self.dev_array(w.B), self.dev_array(w.alpha))
+        return self.cf.fp_offsets(w.A, w.B, w.alpha)
+
+    def time_ms(self, fn, reps=3, warm=1):
+        """Average time of fn() from HIP events on the current stream."""
+        torch = self.torch
+        for _ in range(warm):
+            fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            fn(f, x, v, out, chunk=call_c)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        idx = np.random.default_rng(2).choice(npts, min(64, npts), replace=False)
-        H = cf.hessian(f, w.x[idx], w.A, w.B, E)
-        ref = np.einsum("pij,pj->pi", H, w.v[idx])
-        got = out.cpu().numpy()[idx]
-        err = float((np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))).max())
-        mf = flops.flops_per_hvp(f, n, c)
-        res[f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"] = {
-            "npts": npts, "chunk": c,
-            "mapping": "MFMA" if f == 2 else (f"L{binding.chessfad_default_mapping(f, n, prec)}" if call_c == 0
-                                              else "L2"),
-            "kernel_ms": ms, "hvps_per_s": npts / (ms * 1e-3),
-            "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
-        print(f"  large: {NAMES[f]} n={n} {'mixed' if prec else 'f64'} {ms:.2f} ms err {err:.2e}", file=sys.stderr, flush=True)
-    return res
-
-
-def batched(ninst, binding, inputs, cf, torch):
-    """Mixed-function batch: `ninst` single-point instances, function uniform
-    over the three, n log-uniform in [8, 256], each Fletcher-Powell instance
-    with its own parameters.  Times one replay of the plan's hipGraph in
-    float32-mixed and in float64, and the same instances as separate
-    float64 chessfad_hvp launches (kernel time only, summed)."""
-    ws = inputs.mixed_instances(ninst, inputs.rng_for(4), 8, 256, npts=1)
-    dev = torch.device("cuda:0")
-    insts = []
-    for w in ws:
-        d = {"func_id": w.func, "x": torch.from_numpy(w.x).to(dev), "v": torch.from_numpy(w.v).to(dev),
-             "out": torch.empty((w.npts, w.n), dtype=torch.float64, device=dev)}
-        if w.func == 2:
-            d.update(A=torch.from_numpy(w.A).to(dev), B=torch.from_numpy(w.B).to(dev),
-                     alpha=torch.from_numpy(w.alpha).to(dev))
-        insts.append(d)
-    torch.cuda.synchronize()
-
-    def timed(plan, reps=3):
-        plan.run()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            plan.run()
+            fn()
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    def hvp_err(self, w, E, out, idx=None):
+        """Max over sampled points of max|r - r*| / (max|H*| max|v|)."""
+        if idx is None:
+            idx = np.arange(0, w.npts, max(1, w.npts // 64))
+        H = self.cf.hessian(w.func, w.x[idx], w.A, w.B, E)
+        ref = np.einsum("pij,pj->pi", H, w.v[idx])
+        got = out.cpu().numpy()[idx] if hasattr(out, "cpu") else out[idx]
+        scale = np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1)
+        return float((np.abs(got - ref).max(axis=1) / scale).max())
+
+
+# ------------------------------------------------------------------ parts
+def fp_engines(ctx, w, E, x, v):
+    """Fletcher-Powell H.v at n = 16 over all points on every engine and
+    chunk size.  Engines 1 and 2 run the chunked method (one evaluation per
+    call); engine 3 is the closed form 2 (J^T J + diag(D^T r)) as one MFMA tile
+    per point, whose result does not depend on the chunk."""
+    b = ctx.binding
+    out = ctx.torch.empty_like(x)
+    res = {}
+    labels = {1: "per_call_dpp", 2: "per_call_mfma", 3: "fp_closed_form_tile", 0: "vector_alu"}
+    for eng in (1, 2, 3, 0):
+        prev = b.chessfad_set_option(b.CHESSFAD_OPT_FP_MFMA, eng)
+        try:
+            row = {}
+            chunks = (1, 2, 4, 8, 16) if eng in (1, 2) else (16,)
+            for c in chunks:
+                ms = ctx.time_ms(lambda: b.chessfad_hvp(2, x, v, out, chunk=c), reps=3 if eng else 1)
+                row[f"C{c}"] = {"kernel_ms": round(ms, 4), "hvps_per_s": w.npts / (ms * 1e-3),
+                                "max_rel_err_sampled": ctx.hvp_err(w, E, out)}
+        finally:
+            b.chessfad_set_option(b.CHESSFAD_OPT_FP_MFMA, prev)
+        res[labels[eng]] = row
+    res["fp_closed_form_tile"]["note"] = ("closed form, not the chunked method: all second-order components of a "
+                                          "point as one MFMA tile 2 (J^T J + diag(D^T r)); the chunk does not enter")
+    res["vector_alu"]["note"] = "every hDual operation of f in every call on the vector ALUs (L2 mapping)"
+    return res
+
+
+def generic_method(ctx, ws, Es, xs, vs):
+    """The three functions registered as user functions (f written once over
+    the generic hDual type) and run by chessfad_hvp on the same inputs: the
+    general method, with no per-function specialisation."""
+    from paper_2410_22575_amd import user_sources
+
+    b = ctx.binding
+    res = {}
+    for f in FUNCS:
+        w = ws[f]
+        if f == 0:
+            src = user_sources.ROSENBROCK_HIP
+        elif f == 1:
+            src = user_sources.ACKLEY_HIP
+        else:
+            src = user_sources.fletcher_powell_hip(w.A, w.B, Es[f])
+        fid = b.chessfad_register_function(src)
+        try:
+            out = ctx.torch.empty_like(xs[f])
+            row = {}
+            for c in (4, 16):
+                ms = ctx.time_ms(lambda: b.chessfad_hvp(fid, xs[f], vs[f], out, chunk=c), reps=1)
+                row[f"C{c}"] = {"kernel_ms": round(ms, 3), "hvps_per_s": w.npts / (ms * 1e-3),
+                                "max_rel_err_sampled": ctx.hvp_err(w, Es[f], out)}
+            res[NAMES[f]] = row
+        finally:
+            b.chessfad_release_function(fid)
+    res["mapping"] = "L1 (one lane per (point, row), walking its chunks), float64, every hDual operation evaluated"
+    return res
+
+
+def large_n(ctx):
+    """cfg3: n = 64 over 2^18 points, all three functions, float64 and mixed,
+    at the autotuned chunk.  cfg5: Fletcher-Powell n = 512 over 1024 points
+    (float32 MFMA contraction in the mixed path, float64), Rosenbrock n = 512
+    H.v.  Kernel time, HVP/s, paper-model TFLOP/s, and the max error against
+    the oracle on 64 sampled points."""
+    b, torch = ctx.binding, ctx.torch
+    res = {}
+    cases = [(f, 64, 1 << 18, prec) for f in FUNCS for prec in (0, 1)]
+    cases += [(2, 512, 1024, 1), (2, 512, 1024, 0), (0, 512, 1024, 0)]
+    for f, n, npts, prec in cases:
+        w = ctx.inputs.make_workload(f, n, npts, ctx.inputs.rng_for(100 + n))
+        x, v = ctx.dev_array(w.x), ctx.dev_array(w.v)
+        E = ctx.set_fp(w) if f == 2 else None
+        # autotuned chunk (and mapping) except for Fletcher-Powell at n = 512,
+        # where a launch per chunk takes several milliseconds: C = 16 there
+        if f == 2 and n == 512:
+            c = call_c = 16
+        else:
+            c, _ = b.chessfad_autotune(f, n, prec, npts=min(npts, 1 << 16))
+            call_c = 0
+        fn = b.chessfad_hvp_mixed if prec else b.chessfad_hvp
+        out = torch.empty_like(x)
+        ms = ctx.time_ms(lambda: fn(f, x, v, out, chunk=call_c), reps=3)
+        idx = np.random.default_rng(2).choice(npts, min(64, npts), replace=False)
+        err = ctx.hvp_err(w, E, out, idx)
+        mf = ctx.flops.flops_per_hvp(f, n, c)
+        name = f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"
+        res[name] = {"npts": npts, "chunk": c,
+                     "mapping": "MFMA rows" if f == 2 else f"L{b.chessfad_default_mapping(f, n, prec)}",
+                     "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
+                     "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
+        print(f"  large: {name} C={c} {ms:.3f} ms err {err:.2e}", file=sys.stderr, flush=True)
+    for f in FUNCS:
+        a, m = res[f"{NAMES[f]}_n64_f64"], res[f"{NAMES[f]}_n64_mixed"]
+        m["speedup_vs_f64"] = a["kernel_ms"] / m["kernel_ms"]
+    res["fletcher_powell_n512_mixed"]["speedup_vs_f64"] = (res["fletcher_powell_n512_f64"]["kernel_ms"]
+                                                           / res["fletcher_powell_n512_mixed"]["kernel_ms"])
+    return res
+
+
+def symmetric_large_n(ctx):
+    """SC-HESS-VEC against CHESS-VEC (float64) where symmetry has calls to
+    save (C < n): Rosenbrock and Ackley at n = 64 and 128 over 2^16 points,
+    Fletcher-Powell at n = 64 over 2^12 points, C = 4, 8, 16."""
+    b, torch = ctx.binding, ctx.torch
+    res = {}
+    for f, n, npts in ((0, 64, 1 << 16), (0, 128, 1 << 16), (1, 64, 1 << 16), (1, 128, 1 << 16), (2, 64, 1 << 12)):
+        w = ctx.inputs.make_workload(f, n, npts, ctx.inputs.rng_for(700 + n))
+        x, v = ctx.dev_array(w.x), ctx.dev_array(w.v)
+        E = ctx.set_fp(w) if f == 2 else None
+        out = torch.empty_like(x)
+        for c in (4, 8, 16):
+            full = ctx.time_ms(lambda: b.chessfad_hvp(f, x, v, out, chunk=c))
+            try:
+                sym = ctx.time_ms(lambda: b.chessfad_hvp_sym(f, x, v, out, chunk=c))
+            except b.ChessfadError as e:
+                res[f"{NAMES[f]}_n{n}_C{c}"] = {"full_ms": round(full, 4), "sym": f"not run: {e}"}
+                continue
+            err = ctx.hvp_err(w, E, out)
+            res[f"{NAMES[f]}_n{n}_C{c}"] = {
+                "npts": npts, "full_ms": round(full, 4), "sym_ms": round(sym, 4), "speedup_sym_vs_full": full / sym,
+                "calls_full": ctx.flops.calls_per_point(n, c), "calls_sym": ctx.flops.calls_per_point_sym(n, c),
+                "max_rel_err_sampled": err}
+    return res
+
+
+def batched(ctx, ninst):
+    """Mixed-function batch: `ninst` single-point instances, function uniform
+    over the three, n log-uniform in [8, 256], each Fletcher-Powell instance
+    with its own parameters.  One replay of the plan's hipGraph, mixed and
+    float64; the float64 baseline as plain launches grouped per (function,
+    n) - Rosenbrock and Ackley instances of one n as one launch over their
+    points, each Fletcher-Powell instance (its own parameters) as its own
+    launch - kernel time only, summed."""
+    b, torch = ctx.binding, ctx.torch
+    ws = ctx.inputs.mixed_instances(ninst, ctx.inputs.rng_for(4), 8, 256, npts=1)
+    insts = []
+    for w in ws:
+        d = {"func_id": w.func, "x": ctx.dev_array(w.x), "v": ctx.dev_array(w.v),
+             "out": torch.empty((w.npts, w.n), dtype=torch.float64, device=ctx.dev)}
+        if w.func == 2:
+            d.update(A=ctx.dev_array(w.A), B=ctx.dev_array(w.B), alpha=ctx.dev_array(w.alpha))
+        insts.append(d)
+    torch.cuda.synchronize()
     res = {"workload": f"{ninst} single-point instances, function uniform over Rosenbrock/Ackley/Fletcher-Powell, "
                        "n log-uniform in [8, 256], own Fletcher-Powell parameters each; chunk per (function, n) "
                        "from the autotuned table or the default"}
@@ -263,114 +327,211 @@ def batched(ninst, binding, inputs, cf, torch):
     for prec, name in ((1, "mixed_f32"), (0, "f64")):
         for d in insts:
             d["precision"] = prec
-        plan = binding.chessfad_batch_create(insts)
-        ms = timed(plan)
+        plan = b.chessfad_batch_create(insts)
+        ms = ctx.time_ms(plan.run)
         info = plan.info()
-        res[name] = {"graph_ms": ms, "hvps_per_s": ninst / (ms * 1e-3), "model_tflops": info["model_flops"] / (ms * 1e-3) / 1e12,
+        res[name] = {"graph_ms": round(ms, 4), "hvps_per_s": ninst / (ms * 1e-3),
+                     "model_tflops": info["model_flops"] / (ms * 1e-3) / 1e12,
                      "items": info["items"], "workgroups": info["workgroups"]}
         outs[name] = [d["out"].clone() for d in insts]
         plan.destroy()
-    # the same instances one launch each (float64), kernel time only
-    total = 0.0
+    # the grouped float64 baseline
+    groups = {}
+    for k, w in enumerate(ws):
+        groups.setdefault((w.func, w.n) if w.func != 2 else (2, w.n, k), []).append(k)
+    total, launches = 0.0, 0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for d, w in zip(insts, ws):
-        if w.func == 2:
-            binding.chessfad_fp_set_params(d["A"], d["B"], d["alpha"])
+    for key, ks in groups.items():
+        f = key[0]
+        x = torch.cat([insts[k]["x"] for k in ks])
+        v = torch.cat([insts[k]["v"] for k in ks])
+        out = torch.empty_like(x)
+        if f == 2:
+            d = insts[ks[0]]
+            b.chessfad_fp_set_params(d["A"], d["B"], d["alpha"])
         e0.record()
-        binding.chessfad_hvp(w.func, d["x"], d["v"], d["out"], chunk=min(4, w.n))
+        b.chessfad_hvp(f, x, v, out, chunk=0)
         e1.record()
         e1.synchronize()
         total += e0.elapsed_time(e1)
-    res["per_instance_f64_kernel_ms_sum"] = total
-    res["speedup_mixed_batched_vs_per_instance_f64"] = total / res["mixed_f32"]["graph_ms"]
+        launches += 1
+    res["grouped_f64_launches"] = launches
+    res["grouped_f64_kernel_ms_sum"] = round(total, 3)
+    res["speedup_mixed_batched_vs_grouped_f64"] = total / res["mixed_f32"]["graph_ms"]
+    res["speedup_f64_batched_vs_grouped_f64"] = total / res["f64"]["graph_ms"]
     res["speedup_mixed_batched_vs_f64_batched"] = res["f64"]["graph_ms"] / res["mixed_f32"]["graph_ms"]
-    # accuracy on a sample of instances
     idx = np.random.default_rng(11).choice(ninst, min(64, ninst), replace=False)
     for name in ("mixed_f32", "f64"):
         worst = 0.0
         for k in idx:
             w = ws[k]
-            E = cf.fp_offsets(w.A, w.B, w.alpha) if w.func == 2 else None
-            H = cf.hessian(w.func, w.x, w.A, w.B, E)
-            ref = np.einsum("pij,pj->pi", H, w.v)
-            got = outs[name][k].cpu().numpy()
-            worst = max(worst, float((np.abs(got - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v).max(axis=1))).max()))
+            E = ctx.cf.fp_offsets(w.A, w.B, w.alpha) if w.func == 2 else None
+            worst = max(worst, ctx.hvp_err(w, E, outs[name][k], np.arange(w.npts)))
         res[name]["max_rel_err_sampled"] = worst
     return res
 
 
+# -------------------------------------------------------------------- CPU
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def host_threads():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def cpu_baseline(ws, Es, chunks, budget_s, npts):
+    """The oracle timed on the host: the C chunked method (CHESS-VEC, OpenMP
+    over points) on every host thread and on one thread, each on a bounded
+    sample of the benchmark's points, and the numpy closed-form H.v (the
+    plain definition) on one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import chunked
+    from oracle import closed_form as cf
+
+    chunked.build()
+    threads = host_threads()
+
+    def run(sample, nthreads):
+        t0 = time.perf_counter()
+        per = {}
+        for f in FUNCS:
+            w = ws[f]
+            t1 = time.perf_counter()
+            chunked.hvp(f, w.x[:sample], w.v[:sample], chunks[f], w.A, w.B, Es[f], nthreads=nthreads)
+            per[NAMES[f]] = sample / (time.perf_counter() - t1)
+        return time.perf_counter() - t0, per
+
+    def sized(nthreads, budget):
+        sample, dt = 64, 0.0
+        while sample < npts:
+            dt, _ = run(sample, nthreads)
+            if dt > 0.3:
+                break
+            sample *= 2
+        return int(min(npts, max(sample, sample * budget / max(dt, 1e-9))))
+
+    sample = sized(threads, budget_s)
+    dt, per = run(sample, threads)
+    s1 = sized(1, budget_s / 3)
+    dt1, per1 = run(s1, 1)
+    # closed form, one BLAS thread, on up to 2^17 points of each function
+    cs = min(npts, 1 << 17)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        per_cf = {}
+        for f in FUNCS:
+            w = ws[f]
+            t1 = time.perf_counter()
+            cf.hvp(f, w.x[:cs], w.v[:cs], w.A, w.B, Es[f])
+            per_cf[NAMES[f]] = cs / (time.perf_counter() - t1)
+        dtc = time.perf_counter() - t0
+    return {"value": 3 * sample / dt, "unit": "HVP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of the {npts} points of each function (n=16, the step's chunk sizes), "
+                      f"oracle/chunked.c CHESS-VEC with OpenMP over points on {threads} threads",
+            "cpu_model": cpu_model(), "per_function": per,
+            "one_thread": {"value": 3 * s1 / dt1, "unit": "HVP/s", "sample": f"first {s1} points of each function",
+                           "per_function": per1},
+            "closed_form_one_thread": {"value": 3 * cs / dtc, "unit": "HVP/s",
+                                       "sample": f"first {cs} points of each function, numpy closed-form H.v "
+                                                 "(oracle/closed_form.py), one BLAS thread",
+                                       "per_function": per_cf},
+            "note": "the chunked C oracle evaluates every hDual component of every call (structural zeros "
+                    "included); the closed form is the plain definition"}
+
+
+def cfg1_cpu_seconds():
+    """cfg1: Rosenbrock, n = 8, 1024 points, x ~ U[-2, 2], v ~ N(0, 1),
+    C = 4: the full Hessian and H.v of every point by the oracle's chunked
+    method (CHUNK-HESS + CHESS-VEC), on one thread and on every host thread."""
+    from oracle import chunked
+    from paper_2410_22575_amd import inputs
+
+    w = inputs.make_workload(0, 8, 1024, inputs.rng_for(1))
+    res = {"workload": "Rosenbrock n=8, 1024 points, chunk 4, full Hessian + H.v per point (oracle/chunked.c)"}
+    for label, nt in (("one_thread", 1), ("all_threads", host_threads())):
+        best = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            chunked.hessian(0, w.x, 4, nthreads=nt)
+            chunked.hvp(0, w.x, w.v, 4, nthreads=nt)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[label] = {"seconds": best, "threads": nt}
+    return res
+
+
+# ------------------------------------------------------------------- main
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               f"(points shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
 
-    import torch
-
-    from paper_2410_22575_amd import binding, flops, inputs
-    from oracle import closed_form as cf
-
-    binding.load()
+    ctx = Ctx(args.npts)
+    b, torch, cf, flops, inputs = ctx.binding, ctx.torch, ctx.cf, ctx.flops, ctx.inputs
     if args.only == "large":
-        print(json.dumps({"large_n": large_n(binding, inputs, cf, torch, flops)}), flush=True)
+        print(json.dumps({"large_n": large_n(ctx)}), flush=True)
         return
     if args.only == "batch":
-        print(json.dumps({"batched": batched(args.batch_instances, binding, inputs, cf, torch)}), flush=True)
+        print(json.dumps({"batched": batched(ctx, args.batch_instances)}), flush=True)
         return
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     npts = args.npts
 
     # seeded synthetic inputs, resident in HBM before timing
-    workloads, E, xs, vs, outs, chunks = {}, {}, {}, {}, {}, {}
+    ws, Es, xs, vs, outs = {}, {}, {}, {}, {}
     for f in FUNCS:
         w = inputs.make_workload(f, N, npts, inputs.rng_for(1))
-        workloads[f] = w
-        xs[f] = torch.from_numpy(w.x).to(dev)
-        vs[f] = torch.from_numpy(w.v).to(dev)
+        ws[f] = w
+        xs[f], vs[f] = ctx.dev_array(w.x), ctx.dev_array(w.v)
         outs[f] = torch.empty_like(xs[f])
-        E[f] = None
-        if f == 2:
-            binding.chessfad_fp_set_params(torch.from_numpy(w.A).to(dev), torch.from_numpy(w.B).to(dev),
-                                           torch.from_numpy(w.alpha).to(dev))
-            E[f] = cf.fp_offsets(w.A, w.B, w.alpha)
+        Es[f] = ctx.set_fp(w) if f == 2 else None
     torch.cuda.synchronize()
+    if args.only == "fp":
+        print(json.dumps({"fp_engines": fp_engines(ctx, ws[2], Es[2], xs[2], vs[2])}), flush=True)
+        return
+
     # chunk per function: explicit, autotuned (outside the timed region), or default
-    tuned, mchunks, schunks = {}, {}, {}
+    chunks, mchunks, schunks, tuned = {}, {}, {}, {}
     for f in FUNCS:
         if args.chunk:
             chunks[f] = mchunks[f] = schunks[f] = args.chunk
         elif not args.no_tune:
-            chunks[f], tuned[NAMES[f]] = binding.chessfad_autotune(f, N, 0, npts=npts)
-            mchunks[f], _ = binding.chessfad_autotune(f, N, 1, npts=npts)
-            schunks[f], _ = binding.chessfad_autotune_sym(f, N, 0, npts=npts)
+            chunks[f], tuned[NAMES[f]] = b.chessfad_autotune(f, N, 0, npts=npts)
+            mchunks[f], _ = b.chessfad_autotune(f, N, 1, npts=npts)
+            schunks[f], _ = b.chessfad_autotune_sym(f, N, 0, npts=npts)
         else:
-            chunks[f] = mchunks[f] = binding.chessfad_default_chunk(f, N)
+            chunks[f] = mchunks[f] = b.chessfad_default_chunk(f, N)
             schunks[f] = 0
     torch.cuda.synchronize()
-
     # the step passes chunk 0 unless a chunk was forced: the library then runs
     # the tuned chunk and mapping
     step_chunk = {f: (args.chunk or 0) for f in FUNCS}
-    mapping = {f: (args.chunk and 2) or binding.chessfad_default_mapping(f, N) for f in FUNCS}
+    mapping = {f: (args.chunk and 2) or b.chessfad_default_mapping(f, N) for f in FUNCS}
 
     def step(events=None):
         for f in FUNCS:
             if events is not None:
                 events[f][0].record()
-            binding.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=step_chunk[f])
+            b.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=step_chunk[f])
             if events is not None:
                 events[f][1].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
     evs = [{f: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for f in FUNCS}
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -379,204 +540,107 @@ def main():
         step(evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-
     kernel_ms = {f: float(np.mean([e[f][0].elapsed_time(e[f][1]) for e in evs])) for f in FUNCS}
     ms_per_step = 1e3 * elapsed / args.steps
     value = len(FUNCS) * npts / (elapsed / args.steps)
+    max_err = {NAMES[f]: ctx.hvp_err(ws[f], Es[f], outs[f]) for f in FUNCS}
+    if args.only == "step":
+        print(json.dumps({"kernel_ms": {NAMES[f]: kernel_ms[f] for f in FUNCS}, "ms_per_step": ms_per_step,
+                          "max_rel_err_sampled": max_err}), flush=True)
+        return
 
+    # ---- roofline of the dominant kernel, on the executed-flop basis
+    sha = source_sha()
+    stale = COUNTER_SOURCE_SHA != sha
     per_func = {}
     for f in FUNCS:
         mf = flops.flops_per_hvp(f, N, chunks[f])
-        per_func[NAMES[f]] = {
-            "chunk": chunks[f], "mapping": f"L{mapping[f]}" if f != 2 or N > 16 else "MFMA",
-            "kernel_ms": round(kernel_ms[f], 4),
-            "hvps_per_s": npts / (kernel_ms[f] * 1e-3),
-            "model_tflops": mf * npts / (kernel_ms[f] * 1e-3) / 1e12,
-            "model_flops_per_hvp": mf,
-        }
-    for f in FUNCS:
-        # executed flops where known: MFMA from the tile schedule, vector
-        # float64 from the counters taken for this kernel
         key = kernel_key(f, chunks[f], mapping=mapping[f])
-        ex = (fp_mfma_flops(N, chunks[f], npts) if key.startswith("fp_tile") else 0.0)
-        valu = MEASURED_VALU_FLOPS.get(key)
-        per_func[NAMES[f]]["executed_mfma_tflops"] = ex / (kernel_ms[f] * 1e-3) / 1e12 if ex else None
-        per_func[NAMES[f]]["executed_valu_f64_tflops"] = valu / (kernel_ms[f] * 1e-3) / 1e12 if valu else None
-    fp_mfma = N <= 16
+        cnt = COUNTERS.get(key, {})
+        t = kernel_ms[f] * 1e-3
+        executed = cnt.get("valu_flops", 0.0) + cnt.get("mfma_flops", 0.0) if cnt else None
+        per_func[NAMES[f]] = {
+            "kernel": key, "chunk": chunks[f],
+            "method": ("per-call chunked evaluation (value column on MFMA, per-call product rule on the vector "
+                       "ALUs with DPP lane broadcasts)" if f == 2 else
+                       f"per-call chunked evaluation on the vector ALUs, L{mapping[f]} mapping"),
+            "kernel_ms": round(kernel_ms[f], 4), "hvps_per_s": npts / t,
+            "model_flops_per_hvp": mf, "model_tflops": mf * npts / t / 1e12,
+            "executed_tflops": executed / t / 1e12 if executed else None,
+            "valu_issue_frac": cnt["valu_insts"] / VALU_ISSUE_PER_S / t if cnt.get("valu_insts") else None,
+        }
     dom = max(FUNCS, key=lambda f: kernel_ms[f])
-    kname = kernel_key(dom, chunks[dom], mapping=mapping[dom])
-    model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
+    kname = per_func[NAMES[dom]]["kernel"]
     t_dom = kernel_ms[dom] * 1e-3
-    if kname.startswith("fp_tile"):
-        # executed MFMA flops (fewer than the model counts); float64 MFMA and
-        # float64 VALU work do not overlap on MI355X (one float64 datapath,
-        # measured), so the kernel's vector float64 flops count against the
-        # same peak when their counters are known
-        bound, work, basis = "mfma", fp_mfma_flops(N, chunks[dom], npts), "executed MFMA flops (tile schedule)"
-        if kname in MEASURED_VALU_FLOPS:
-            work += MEASURED_VALU_FLOPS[kname]
-            basis += " + executed float64 VALU flops (counters)"
-    elif kname in MEASURED_VALU_FLOPS:
-        bound, work, basis = "alu", MEASURED_VALU_FLOPS[kname], "executed float64 VALU flops (counters)"
+    model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
+    cnt = COUNTERS.get(kname)
+    if cnt:
+        work = cnt.get("valu_flops", 0.0) + cnt.get("mfma_flops", 0.0)
+        basis = "executed float64 flops (rocprofv3 counters: VALU FLOPS_FP64 x 64" + (
+            " + MFMA MOPS_F64 x 512)" if cnt.get("mfma_flops") else ")")
+        bound = "alu"
     else:
-        bound, work, basis = "alu", model_launch, "paper-model flops"
+        work, basis, bound = model_launch, "paper-model flops (no counters for this kernel)", "alu"
     if work > model_launch:
         work, basis = model_launch, "paper-model flops (below the executed count)"
     achieved = work / t_dom / 1e12
     roofline = {"bound": bound, "kernel": kname, "achieved": achieved, "peak": PEAK_F64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": MEASURED_TRAFFIC.get(kname),
-                "flops_per_launch": work, "basis": basis, "model_flops_per_launch": model_launch,
-                "model_tflops": model_launch / t_dom / 1e12}
-    insts = MEASURED_VALU_INSTS.get(kname)
-    # share of the launch the vector issue alone would take (1.0 = issue-bound)
-    roofline["valu_issue_frac"] = insts / (256 * 2.4e9) / t_dom if insts else None
-    if bound == "mfma":
-        roofline["measured_mfma_f64_peak"] = 72.8
-        valu = MEASURED_VALU_FLOPS.get(kname)
-        roofline["executed_valu_f64_tflops"] = valu / t_dom / 1e12 if valu else None
+                "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS,
+                "traffic": (cnt or {}).get("traffic"), "flops_per_launch": work, "basis": basis,
+                "model_flops_per_launch": model_launch, "model_tflops": model_launch / t_dom / 1e12,
+                "valu_issue_frac": per_func[NAMES[dom]]["valu_issue_frac"],
+                "counters_source_sha": COUNTER_SOURCE_SHA, "source_sha": sha, "stale": stale}
 
-    # the Fletcher-Powell vector-ALU path, for comparison (outside the timed region)
-    fp_vector_ms = None
-    if fp_mfma:
-        # the vector path at its own best chunk (the MFMA tile ignores the chunk)
-        vec_c = min(16, N)
-        prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=vec_c)
-        e0.record()
-        for _ in range(3):
-            binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=vec_c)
-        e1.record()
-        torch.cuda.synchronize()
-        fp_vector_ms = e0.elapsed_time(e1) / 3
-        binding.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, prev)
-        binding.chessfad_hvp(2, xs[2], vs[2], outs[2], chunk=vec_c)
-        torch.cuda.synchronize()
+    # ---- comparisons outside the timed region
+    fp_eng = fp_engines(ctx, ws[2], Es[2], xs[2], vs[2])
+    gen = generic_method(ctx, ws, Es, xs, vs)
 
-    # quick sanity check of the last outputs on a few points (oracle on CPU)
-    idx = np.arange(0, npts, max(1, npts // 64))
-    refs = {}
-    for f in FUNCS:
-        w = workloads[f]
-        H = cf.hessian(f, w.x[idx], w.A, w.B, E[f])
-        refs[f] = (np.einsum("pij,pj->pi", H, w.v[idx]), np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
-
-    def rel_err(f, out):
-        ref, scale = refs[f]
-        return float((np.abs(out.cpu().numpy()[idx] - ref).max(axis=1) / scale).max())
-
-    max_err = {NAMES[f]: rel_err(f, outs[f]) for f in FUNCS}
-
-    # full Hessians on the same points (outside the timed region): 8 n^2
-    # bytes per point written on top of the H.v path's 16 n read
     hess = {}
     for f in FUNCS:
         sub = min(npts, 1 << 19)
-        Hbuf = torch.empty((sub, N, N), dtype=torch.float64, device=dev)
-        binding.chessfad_hessian(f, xs[f][:sub], Hbuf, chunk=chunks[f])
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            binding.chessfad_hessian(f, xs[f][:sub], Hbuf, chunk=chunks[f])
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 3
-        hess[NAMES[f]] = {"npts": sub, "kernel_ms": round(ms, 4), "hessians_per_s": sub / (ms * 1e-3),
+        Hbuf = torch.empty((sub, N, N), dtype=torch.float64, device=ctx.dev)
+        ms = ctx.time_ms(lambda: b.chessfad_hessian(f, xs[f][:sub], Hbuf, chunk=chunks[f]))
+        hess[NAMES[f]] = {"npts": sub, "chunk": chunks[f], "kernel_ms": round(ms, 4),
+                          "hessians_per_s": sub / (ms * 1e-3),
                           "hbm_gb_per_s": sub * (8 * N * N + 8 * N) / (ms * 1e-3) / 1e9}
         del Hbuf
-    torch.cuda.synchronize()
 
-    # the mixed-precision path on the same inputs (outside the timed region)
     mixed = {}
     for f in FUNCS:
         mo = torch.empty_like(xs[f])
-        mc = mchunks[f]   # the mixed path's own tuned chunk
-        # chunk 0 runs the tuned chunk and mapping (as the float64 step does)
         call_c = args.chunk or 0
-        binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=call_c)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            binding.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=call_c)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
-        mmap = "MFMA" if f == 2 and N <= 16 else f"L{binding.chessfad_default_mapping(f, N, 1)}" if not args.chunk else "L2"
-        mixed[NAMES[f]] = {"chunk": mc, "mapping": mmap, "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
-                           "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": rel_err(f, mo)}
+        ms = ctx.time_ms(lambda: b.chessfad_hvp_mixed(f, xs[f], vs[f], mo, chunk=call_c), reps=5)
+        mixed[NAMES[f]] = {"chunk": mchunks[f], "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
+                           "speedup_vs_f64": kernel_ms[f] / ms, "max_rel_err_sampled": ctx.hvp_err(ws[f], Es[f], mo)}
+    mixed_ms = sum(v["kernel_ms"] for v in mixed.values())
+    mixed["all_three"] = {"kernel_ms_sum": round(mixed_ms, 4), "hvps_per_s": 3 * npts / (mixed_ms * 1e-3),
+                          "speedup_vs_f64": sum(kernel_ms.values()) / mixed_ms}
 
-    # the paper's three GPU mappings of H.v (Sec. VI) for the vector-ALU
-    # functions, outside the timed region: L0 one lane per point, L1 per
-    # row, L2 per (row, chunk) - the same sums in every case
     mappings = {}
     for f in (0, 1):
         mo = torch.empty_like(xs[f])
-        res = {}
+        row = {}
         for level in (0, 1, 2):
-            prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, level)
+            prev = b.chessfad_set_option(b.CHESSFAD_OPT_MAPPING, level)
             try:
-                binding.chessfad_hvp(f, xs[f], vs[f], mo, chunk=chunks[f])
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for _ in range(3):
-                    binding.chessfad_hvp(f, xs[f], vs[f], mo, chunk=chunks[f])
-                e1.record()
-                torch.cuda.synchronize()
+                ms = ctx.time_ms(lambda: b.chessfad_hvp(f, xs[f], vs[f], mo, chunk=chunks[f]))
             finally:
-                binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev)
-            ms = e0.elapsed_time(e1) / 3
-            res[f"L{level}"] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3)}
-        mappings[NAMES[f]] = {"chunk": chunks[f], **res}
+                b.chessfad_set_option(b.CHESSFAD_OPT_MAPPING, prev)
+            row[f"L{level}"] = {"kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3)}
+        mappings[NAMES[f]] = {"chunk": chunks[f], **row}
 
-    # the same comparison across n (the shape of the paper's mapping figures):
-    # Rosenbrock and Ackley, C = 4, 2^17 points per n
-    sweep = {}
-    for f in (0, 1):
-        for nn in (4, 8, 16, 32, 64):
-            w = inputs.make_workload(f, nn, 1 << 17, inputs.rng_for(300 + nn))
-            xw, vw = torch.from_numpy(w.x).to(dev), torch.from_numpy(w.v).to(dev)
-            mo = torch.empty_like(xw)
-            row = {}
-            for level in (0, 1, 2):
-                prev = binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, level)
-                try:
-                    binding.chessfad_hvp(f, xw, vw, mo, chunk=4)
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    for _ in range(3):
-                        binding.chessfad_hvp(f, xw, vw, mo, chunk=4)
-                    e1.record()
-                    torch.cuda.synchronize()
-                finally:
-                    binding.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev)
-                row[f"L{level}_ms"] = round(e0.elapsed_time(e1) / 3, 4)
-            sweep[f"{NAMES[f]}_n{nn}"] = row
-        del xw, vw, mo
-
-    # the symmetric form (SC-HESS-VEC) on the same inputs, outside the timed
-    # region: fewer f calls per point, the same H.v
     sym = {}
     for f in FUNCS:
         so = torch.empty_like(xs[f])
         sc = schunks[f]
-        binding.chessfad_hvp_sym(f, xs[f], vs[f], so, chunk=sc)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            binding.chessfad_hvp_sym(f, xs[f], vs[f], so, chunk=sc)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
+        ms = ctx.time_ms(lambda: b.chessfad_hvp_sym(f, xs[f], vs[f], so, chunk=sc), reps=5)
         sym[NAMES[f]] = {"chunk": sc or "library default", "kernel_ms": round(ms, 4),
                          "hvps_per_s": npts / (ms * 1e-3), "speedup_vs_full_f64": kernel_ms[f] / ms,
                          "calls_per_point": flops.calls_per_point_sym(N, sc) if sc else None,
-                         "max_rel_err_sampled": rel_err(f, so)}
+                         "max_rel_err_sampled": ctx.hvp_err(ws[f], Es[f], so)}
     sym_step = sum(v["kernel_ms"] for v in sym.values())
-    sym_total = {"kernel_ms_sum": round(sym_step, 4), "hvps_per_s": len(FUNCS) * npts / (sym_step * 1e-3)}
 
-    # Sec. V's chunk-size analysis against the autotuner: the multiplication
-    # count (6 + 3/c) n^2 M falls with c for the full form; the symmetric
-    # form's (3/2) n (2n + 2c + n/c + 1) M is smallest near sqrt(n / 2)
+    # Sec. V's chunk-size analysis against the autotuner
     def sym_model_chunk(n):
         best, bc = None, 1
         for c in (1, 2, 4, 8, 16):
@@ -600,27 +664,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 H.v: Rosenbrock, Ackley, Fletcher-Powell; n=16; "
-                               f"{npts} points each; chunk per function",
+        "config": {"workload": "plain FP64 chunked H.v (CHESS-VEC): Rosenbrock, Ackley, Fletcher-Powell; n=16; "
+                               f"{npts} points each; autotuned chunk per function",
                    "n": N, "npts": npts, "chunks": {NAMES[f]: chunks[f] for f in FUNCS}},
         "roofline": roofline,
         "per_function": per_func,
         "max_rel_err_sampled": max_err,
-        "fp_vector_path_ms": fp_vector_ms,
+        "fp_engines": fp_eng,
+        "generic_method": gen,
         "mixed_f32": mixed,
         "hessian_f64": hess,
-        "symmetric_f64": {"per_function": sym, "all_three": sym_total},
+        "symmetric_f64": {"per_function": sym, "all_three": {"kernel_ms_sum": round(sym_step, 4),
+                                                            "hvps_per_s": 3 * npts / (sym_step * 1e-3)}},
         "mappings_f64": mappings,
-        "mappings_f64_by_n": {"chunk": 4, "npts": 1 << 17, "kernel_ms": sweep},
         "chunk_model_vs_tuned": chunk_model,
+        "autotuned_ms": tuned or None,
     }
-    result["autotuned_ms"] = tuned or None
+    if not args.no_large:
+        result["large_n"] = large_n(ctx)
+        result["symmetric_large_n"] = symmetric_large_n(ctx)
     if not args.no_batch:
-        result["batched"] = batched(args.batch_instances, binding, inputs, cf, torch)
-    if args.large:
-        result["large_n"] = large_n(binding, inputs, cf, torch, flops)
+        result["batched"] = batched(ctx, args.batch_instances)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(workloads, E, chunks, args.cpu_seconds)
+        result["cfg1_cpu_seconds"] = cfg1_cpu_seconds()
+        result["cpu_baseline"] = cpu_baseline(ws, Es, chunks, args.cpu_seconds, npts)
     print(json.dumps(result), flush=True)
 
 

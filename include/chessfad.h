@@ -30,9 +30,11 @@
  *     and its derivatives at x: the kernels are built assuming finite values
  *     (non-finite inputs give unspecified results, not an error), and a
  *     zero result may come out as -0.0 or +0.0.
- *   - Calls on different streams are independent.  chessfad_fp_set_params
- *     and chessfad_fp_release must not race with compute calls that read
- *     the same n.
+ *   - Calls on different streams are independent.  A Fletcher-Powell
+ *     parameter set is complete on the device when chessfad_fp_set_params
+ *     returns; replacing or releasing it waits for the work already enqueued
+ *     on the device (hipFree), and compute calls made while it is replaced
+ *     or released see the old set, the new one or CHESSFAD_E_PARAMS.
  */
 #ifndef CHESSFAD_H
 #define CHESSFAD_H
@@ -132,7 +134,7 @@ int chessfad_hessian_mixed(int func_id, int n, int64_t npts, const double* x, do
                            int chunk, void* stream);
 
 /*
- * Symmetric forms (SCHUNK-HESS, Sec. IV; SC-HESS-VEC, Sec. VI; count in
+ * Symmetric forms (SCHUNK-HESS, Sec. III.B; SC-HESS-VEC, Sec. VI; count in
  * Sec. V).  Row i evaluates f only for its own chunk i / chunk and the
  * chunks after it: n (n / chunk + 1) / 2 calls per point when chunk divides
  * n, instead of n * ceil(n / chunk).  An entry H(i, s) of a later chunk
@@ -190,7 +192,9 @@ int chessfad_release_function(int func_id);
  *   A, B   [n][n] device arrays (row-major), alpha [n] device array.
  * The library copies them into memory it owns, computes
  * E_m = sum_j A_mj sin(alpha_j) + B_mj cos(alpha_j) in float64 on `stream`,
- * and keeps the set until chessfad_fp_release(n) or a new set for n.
+ * synchronises `stream` (so compute calls on any stream may read the set
+ * once this returns), and keeps the set until chessfad_fp_release(n) or a
+ * new set for n.
  * Returns CHESSFAD_E_N for a bad n, CHESSFAD_E_NULL for a NULL array,
  * CHESSFAD_E_HIP if allocation or the copy fails.
  */
@@ -198,7 +202,8 @@ int chessfad_fp_set_params(int n, const double* A, const double* B, const double
                            void* stream);
 
 /* Frees the Fletcher-Powell parameter set of size n (no-op if none).  The
- * caller must ensure no enqueued work still reads it. */
+ * free waits for the work enqueued on the device (hipFree synchronises), and
+ * it is serialised against the lookup and enqueue of compute calls. */
 int chessfad_fp_release(int n);
 
 /* Static description of a status code (for CHESSFAD_E_HIP, the text of the
@@ -208,18 +213,29 @@ const char* chessfad_strerror(int code);
 /*
  * Process-wide options (not thread-safe against concurrent compute calls).
  * Returns the previous value, or CHESSFAD_E_ARG for an unknown option or value.
- *   CHESSFAD_OPT_FP_MFMA  1 (default): for Fletcher-Powell with n <= 16 the
- *                         dense [A B] . [sin y; cos y] contraction over the
- *                         hDual components runs on MFMA, and the second-order
- *                         components of all calls of a point are formed as
- *                         one 16 x 16 MFMA tile (the sum over residuals of
- *                         the product-rule terms, Sec. VII; float32 MFMA in
- *                         the mixed path);
- *                         2: the MFMA contraction per call, its second-order
- *                         components on the vector ALUs;
- *                         0: every step runs on the vector ALUs.
+ *   CHESSFAD_OPT_FP_MFMA  the Fletcher-Powell engine for n <= 16:
+ *                         1 (default): the per-call kernel: the dense value
+ *                         contraction [A B] . [sin x; cos x] of every point on
+ *                         MFMA, then per (point, row, chunk) call the
+ *                         residuals' chunk components and the product rule
+ *                         of their squares on the vector ALUs, each lane of a
+ *                         point's 16-lane row holding one variable's column
+ *                         and the call's chunk columns read from the other
+ *                         lanes by DPP broadcasts (float32 products in the
+ *                         mixed path); the symmetric form runs on engine 2;
+ *                         2: the per-call kernel whose contractions of every
+ *                         hDual component run on MFMA, the rest of each call
+ *                         on the vector ALUs (full and symmetric form);
+ *                         3: the closed form, not the chunked method: the
+ *                         second-order components of all calls of a point as
+ *                         one 16 x 16 MFMA tile 2 (J^T J + diag(D^T r)) whose
+ *                         blocks the calls are (float32 MFMA in the mixed
+ *                         path); for comparison;
+ *                         0: every step of f on the vector ALUs.
  *                         All give the same derivative components; only the
  *                         order of the final sum over residuals differs.
+ *                         Fletcher-Powell with n > 16 runs its row-block
+ *                         kernel for every value but 0.
  *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
  *                         plan's captured hipGraph; 0: it launches the same
  *                         kernels directly on the stream.

@@ -17,7 +17,7 @@
  * chunk_hess  : CHUNK-HESS (Sec. III.B) - n * ceil(n/csize) calls of f.
  * chess_vec   : CHESS-VEC (Sec. VI) - the same calls, each chunk dotted with
  *               the input vector and summed per row; H is never stored.
- * schunk_hess : SCHUNK-HESS (Sec. IV) - only the chunks that reach the
+ * schunk_hess : SCHUNK-HESS (Sec. III.B) - only the chunks that reach the
  *               diagonal or lie right of it are evaluated; the entries left
  *               of a row's own chunk are copied from their mirror images.
  * sc_hess_vec : SC-HESS-VEC (Sec. VI) - the same calls; a computed entry

@@ -258,10 +258,8 @@ class BatchPlan:
             pass
 
 
-def chessfad_batch_create(instances, stream=None) -> BatchPlan:
-    """instances: list of dicts with func_id, x, v, out (float64 CUDA tensors
-    [npts, n]), optional chunk (0), precision (0 or 1) and, for
-    Fletcher-Powell, A, B, alpha (float64 CUDA tensors)."""
+def _instances(instances):
+    """ctypes array of chessfad_instance, and the tensors it points into."""
     arr = (Instance * max(1, len(instances)))()
     keep = []
     for k, d in enumerate(instances):
@@ -277,6 +275,14 @@ def chessfad_batch_create(instances, stream=None) -> BatchPlan:
         arr[k] = Instance(d["func_id"], n, d.get("chunk", 0), d.get("precision", 0), npts, _ptr(x), _ptr(v),
                           _ptr(out), _ptr(A), _ptr(B), _ptr(alpha))
         keep += [t for t in (x, v, out, A, B, alpha) if t is not None]
+    return arr, keep
+
+
+def chessfad_batch_create(instances, stream=None) -> BatchPlan:
+    """instances: list of dicts with func_id, x, v, out (float64 CUDA tensors
+    [npts, n]), optional chunk (0), precision (0 or 1) and, for
+    Fletcher-Powell, A, B, alpha (float64 CUDA tensors)."""
+    arr, keep = _instances(instances)
     h = ctypes.c_void_p()
     bad = ctypes.c_int(-1)
     rc = load().chessfad_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(instances), _stream(stream),

@@ -65,16 +65,6 @@ BatchKernel batch_kernel_for(int list) {
     }
 }
 
-hipError_t launch_all(chessfad_batch* b, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b->counters, 4);
-    hipError_t e = hipGetLastError();
-    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
-        if (!b->args[l].nitems) continue;
-        hipLaunchKernelGGL(batch_kernel_for(l), dim3(b->grid[l]), dim3(kBatchThreads), b->lds[l], s, b->args[l]);
-        e = hipGetLastError();
-    }
-    return e;
-}
 
 void destroy(chessfad_batch* b) {
     if (!b) return;
@@ -100,17 +90,32 @@ __global__ void tune_fill_kernel(double* x, double* v, int64_t count, double lo,
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream, chessfad_batch** plan,
-                          int* bad_index) {
-    if (bad_index) *bad_index = -1;
-    if (!plan || (ninst > 0 && !inst) || ninst < 0) return CHESSFAD_E_ARG;
-    *plan = nullptr;
+// ------------------------------------------------------------ planning
+// Everything a plan needs that does not depend on where its device memory
+// lives: the validated instances, the sorted work lists, the byte layout of
+// the plan's device memory, and the persistent grids.
+struct PlanLayout {
     std::vector<PlanEntry> entries;
-    entries.reserve(ninst);
+    std::vector<size_t> ws_off;  // per instance: offset of its Fletcher-Powell workspace
+    std::vector<BatchDesc> descs[4];
+    std::vector<BatchItem> flat[4];
+    size_t off_desc[4] = {}, off_items[4] = {}, lds[4] = {};
+    size_t off_counters = 0, off_ws = 0, total = 0;
+    int grid[4] = {0, 0, 0, 0};
+    int64_t items = 0;
+    double flops = 0.0;
+};
+
+// Validates the instances and builds the work lists (host only; nothing is
+// enqueued).  On failure *bad_index names the instance.
+int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, PlanLayout& L) {
+    if (bad_index) *bad_index = -1;
+    if ((ninst > 0 && !inst) || ninst < 0) return CHESSFAD_E_ARG;
+    L.entries.reserve(ninst);
+    L.ws_off.assign(ninst, 0);
     size_t ws_bytes = 0;  // Fletcher-Powell workspace
-    std::vector<size_t> ws_off(ninst, 0);
     for (int k = 0; k < ninst; ++k) {
         const chessfad_instance& c = inst[k];
         auto bad = [&](int rc) {
@@ -153,7 +158,7 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
             e.d.row_blocks = (c.n + e.d.rows - 1) / e.d.rows;
             e.d.pstride = 0;
             e.blocks = c.npts * e.d.row_blocks;
-            ws_off[k] = ws_bytes;
+            L.ws_off[k] = ws_bytes;
             ws_bytes += align_up(sizeof(double) * c.n, 256) + 2 * align_up(sizeof(float) * (size_t)c.n * c.n, 256);
         } else {
             e.d.kind = 0;
@@ -164,59 +169,34 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
         }
         if (e.blocks > 0x7fffffffLL) return bad(CHESSFAD_E_ARG);
         e.cost_per_block = model_flops_per_call(c.func_id, c.n, C) * e.d.rows * nc;
-        entries.push_back(e);
+        L.entries.push_back(e);
     }
 
-    // one device allocation: descriptors, items, counters, Fletcher-Powell workspace
+    // the byte layout: descriptors, items, counters, Fletcher-Powell workspace
     size_t nitems[4] = {0, 0, 0, 0}, ndesc[4] = {0, 0, 0, 0};
-    for (const PlanEntry& e : entries) {
+    for (const PlanEntry& e : L.entries) {
         nitems[2 * e.prec + e.d.kind] += (size_t)e.blocks;
         ndesc[2 * e.prec + e.d.kind] += 1;
     }
-    size_t off_desc[4], off_items[4], total = 0;
+    size_t total = 0;
     for (int l = 0; l < 4; ++l) {
-        off_desc[l] = total;
+        L.off_desc[l] = total;
         total = align_up(total + sizeof(BatchDesc) * ndesc[l], 256);
-        off_items[l] = total;
+        L.off_items[l] = total;
         total = align_up(total + sizeof(BatchItem) * nitems[l], 256);
     }
-    const size_t off_counters = total;
+    L.off_counters = total;
     total = align_up(total + 4 * sizeof(unsigned), 256);
-    const size_t off_ws = total;
-    total += ws_bytes;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    chessfad_batch* b = new chessfad_batch;
-    hipError_t err = hipGetDevice(&b->device);
-    if (err == hipSuccess) err = hipMalloc(&b->dmem, std::max<size_t>(total, 256));
-    if (err != hipSuccess) {
-        destroy(b);
-        return hip_fail(err);
-    }
-    b->counters = reinterpret_cast<unsigned*>(b->dmem + off_counters);
+    L.off_ws = total;
+    L.total = total + ws_bytes;
 
-    // Fletcher-Powell offsets and float32 copies, per instance
-    for (PlanEntry& e : entries) {
-        if (e.d.kind != 1 || err != hipSuccess) continue;
-        const chessfad_instance& c = inst[e.src];
-        char* w = b->dmem + off_ws + ws_off[e.src];
-        double* E = reinterpret_cast<double*>(w);
-        float* A32 = reinterpret_cast<float*>(w + align_up(sizeof(double) * c.n, 256));
-        float* B32 = reinterpret_cast<float*>(reinterpret_cast<char*>(A32) + align_up(sizeof(float) * (size_t)c.n * c.n, 256));
-        hipLaunchKernelGGL(fp_offsets_kernel, dim3((c.n + 63) / 64), dim3(64), 0, s, c.n, c.A, c.B, c.alpha, E);
-        err = hipGetLastError();
-        if (err != hipSuccess) break;
-        const int count = c.n * c.n;
-        hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, c.A, c.B, A32, B32);
-        err = hipGetLastError();
-        e.d.fp = FpParams{c.A, c.B, E, A32, B32};
-    }
-    // work lists per (precision, kind), largest model cost first
-    std::vector<BatchDesc> descs[4];
+    // work lists per (precision, kind), largest model cost first; a
+    // descriptor's index in its list is its position among the list's entries
     std::vector<std::pair<double, BatchItem>> items[4];
-    for (const PlanEntry& e : entries) {
+    int ndescs[4] = {0, 0, 0, 0};
+    for (const PlanEntry& e : L.entries) {
         const int list = 2 * e.prec + e.d.kind;
-        const int di = (int)descs[list].size();
-        descs[list].push_back(e.d);
+        const int di = ndescs[list]++;
         for (int64_t blk = 0; blk < e.blocks; ++blk) {
             double cost = e.cost_per_block;
             if (e.d.kind == 0) {
@@ -227,43 +207,128 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
                 cost = cost * (double)std::min(e.d.rows, e.d.n - r0) / e.d.rows;
             }
             items[list].push_back({cost, BatchItem{di, (int)blk}});
-            b->flops += cost;
+            L.flops += cost;
         }
     }
-    for (auto& it : items)
-        std::stable_sort(it.begin(), it.end(), [](const auto& l, const auto& r) { return l.first > r.first; });
-
-    // upload descriptors and sorted work lists; size the persistent grids
-    int cus = 0;
-    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    for (int l = 0; l < 4 && err == hipSuccess; ++l) {
+    for (int l = 0; l < 4; ++l) {
+        std::stable_sort(items[l].begin(), items[l].end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        L.flat[l].reserve(items[l].size());
+        for (const auto& it : items[l]) L.flat[l].push_back(it.second);
+        L.items += (int64_t)L.flat[l].size();
         const int pr = l / 2;
-        std::vector<BatchItem> flat;
-        flat.reserve(items[l].size());
-        size_t lds = 0;
-        for (const auto& it : items[l]) flat.push_back(it.second);
-        for (const BatchDesc& d : descs[l]) {
-            const size_t need = d.kind == 1 ? (pr ? sizeof(FpRowsShared<float>) : sizeof(FpRowsShared<double>))
-                                            : (pr ? plain_lds_for<F32C>(d) : plain_lds_for<F64>(d));
-            lds = std::max(lds, need);
-        }
-        BatchDesc* dd = reinterpret_cast<BatchDesc*>(b->dmem + off_desc[l]);
-        BatchItem* di = reinterpret_cast<BatchItem*>(b->dmem + off_items[l]);
-        if (!descs[l].empty()) err = hipMemcpyAsync(dd, descs[l].data(), sizeof(BatchDesc) * descs[l].size(), hipMemcpyHostToDevice, s);
-        if (err == hipSuccess && !flat.empty())
-            err = hipMemcpyAsync(di, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
-        b->args[l] = BatchArgs{dd, di, (int)flat.size(), b->counters + l};
-        b->lds[l] = lds;
-        b->items += (int64_t)flat.size();
-        if (err == hipSuccess && !flat.empty()) {
-            int per_cu = 0;
-            err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(l), kBatchThreads, lds);
-            b->grid[l] = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, (int64_t)flat.size());
+        for (const PlanEntry& e : L.entries) {
+            if (2 * e.prec + e.d.kind != l) continue;
+            const size_t need = e.d.kind == 1 ? (pr ? sizeof(FpRowsShared<float>) : sizeof(FpRowsShared<double>))
+                                              : (pr ? plain_lds_for<F32C>(e.d) : plain_lds_for<F64>(e.d));
+            L.lds[l] = std::max(L.lds[l], need);
         }
     }
+    return CHESSFAD_OK;
+}
+
+// Sizes the persistent grids for `device` (occupancy x compute units, at
+// most one workgroup per item).
+hipError_t size_grids(PlanLayout& L, int device) {
+    int cus = 0;
+    hipError_t err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    for (int l = 0; l < 4 && err == hipSuccess; ++l) {
+        L.grid[l] = 0;
+        if (L.flat[l].empty()) continue;
+        int per_cu = 0;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(l), kBatchThreads, L.lds[l]);
+        L.grid[l] = (int)std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, (int64_t)L.flat[l].size());
+    }
+    return err;
+}
+
+// Places the plan in the device memory at `base` (L.total bytes): enqueues
+// the Fletcher-Powell offsets and float32 copies and the uploads of the
+// descriptors and work lists on `s`, and fills args.  The host arrays are
+// read by the copies, so the caller keeps L alive until `s` has passed them.
+hipError_t materialize(PlanLayout& L, const chessfad_instance* inst, char* base, hipStream_t s, BatchArgs args[4],
+                       unsigned*& counters) {
+    hipError_t err = hipSuccess;
+    counters = reinterpret_cast<unsigned*>(base + L.off_counters);
+    for (int l = 0; l < 4; ++l) L.descs[l].clear();
+    for (PlanEntry& e : L.entries) {
+        if (e.d.kind == 1 && err == hipSuccess) {
+            const chessfad_instance& c = inst[e.src];
+            char* w = base + L.off_ws + L.ws_off[e.src];
+            double* E = reinterpret_cast<double*>(w);
+            float* A32 = reinterpret_cast<float*>(w + align_up(sizeof(double) * c.n, 256));
+            float* B32 = reinterpret_cast<float*>(reinterpret_cast<char*>(A32) +
+                                                  align_up(sizeof(float) * (size_t)c.n * c.n, 256));
+            hipLaunchKernelGGL(fp_offsets_kernel, dim3((c.n + 63) / 64), dim3(64), 0, s, c.n, c.A, c.B, c.alpha, E);
+            err = hipGetLastError();
+            if (err == hipSuccess) {
+                const int count = c.n * c.n;
+                hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, c.A, c.B,
+                                   A32, B32);
+                err = hipGetLastError();
+            }
+            e.d.fp = FpParams{c.A, c.B, E, A32, B32};
+        }
+        L.descs[2 * e.prec + e.d.kind].push_back(e.d);
+    }
+    for (int l = 0; l < 4 && err == hipSuccess; ++l) {
+        BatchDesc* dd = reinterpret_cast<BatchDesc*>(base + L.off_desc[l]);
+        BatchItem* di = reinterpret_cast<BatchItem*>(base + L.off_items[l]);
+        if (!L.descs[l].empty())
+            err = hipMemcpyAsync(dd, L.descs[l].data(), sizeof(BatchDesc) * L.descs[l].size(), hipMemcpyHostToDevice, s);
+        if (err == hipSuccess && !L.flat[l].empty())
+            err = hipMemcpyAsync(di, L.flat[l].data(), sizeof(BatchItem) * L.flat[l].size(), hipMemcpyHostToDevice, s);
+        args[l] = BatchArgs{dd, di, (int)L.flat[l].size(), counters + l};
+    }
+    return err;
+}
+
+hipError_t launch_lists(const BatchArgs args[4], const int grid[4], const size_t lds[4], unsigned* counters,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, counters, 4);
+    hipError_t e = hipGetLastError();
+    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+        if (!args[l].nitems) continue;
+        hipLaunchKernelGGL(batch_kernel_for(l), dim3(grid[l]), dim3(kBatchThreads), lds[l], s, args[l]);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_all(chessfad_batch* b, hipStream_t s) { return launch_lists(b->args, b->grid, b->lds, b->counters, s); }
+
+}  // namespace
+
+extern "C" {
+
+int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream, chessfad_batch** plan,
+                          int* bad_index) {
+    if (bad_index) *bad_index = -1;
+    if (!plan) return CHESSFAD_E_ARG;
+    *plan = nullptr;
+    PlanLayout L;
+    const int rc = plan_instances(inst, ninst, bad_index, L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    chessfad_batch* b = new chessfad_batch;
+    hipError_t err = hipGetDevice(&b->device);
+    if (err == hipSuccess) err = hipMalloc(&b->dmem, std::max<size_t>(L.total, 256));
+    if (err == hipSuccess) err = size_grids(L, b->device);
+    if (err == hipSuccess) err = materialize(L, inst, b->dmem, s, b->args, b->counters);
+    // the uploads read L's host arrays
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        destroy(b);
+        return hip_fail(err);
+    }
+    for (int l = 0; l < 4; ++l) {
+        b->grid[l] = L.grid[l];
+        b->lds[l] = L.lds[l];
+    }
+    b->items = L.items;
+    b->flops = L.flops;
     // capture reset + persistent kernels in one graph
-    if (err == hipSuccess) err = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    err = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     if (err == hipSuccess) {
         hipError_t le = launch_all(b, b->capture);

@@ -91,7 +91,7 @@ void record_tuned_mapping(int func_id, int n, int precision, int level) {
 
 bool vector_path(int func_id) { return func_id != CHESSFAD_FLETCHER_POWELL || !g_opt_fp_mfma; }
 bool fp_tile_path(int func_id, int n) {
-    return func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma == 1;
+    return func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma == 3;
 }
 
 double model_flops_per_call(int func_id, int n, int C) {
@@ -141,8 +141,10 @@ void fp_free(FpSet& s) {
     s = FpSet{};
 }
 
-int fp_lookup(int n, FpParams& out) {
-    std::lock_guard<std::mutex> lk(g_fp_mu);
+// The caller holds g_fp_mu until it has enqueued the work that reads the set,
+// so a concurrent chessfad_fp_release (whose hipFree waits for the device)
+// frees it only before the lookup or after that work.
+int fp_lookup_locked(int n, FpParams& out) {
     const FpSet& s = g_fp[n];
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return CHESSFAD_E_HIP;
@@ -321,19 +323,29 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
                  overlaps(fval, f_bytes, out, out_bytes) || (grad && overlaps(fval, f_bytes, grad, in_bytes))))
         return CHESSFAD_E_OVERLAP;
     FpParams fp{nullptr, nullptr, nullptr};
+    std::unique_lock<std::mutex> fp_lock;
     if (func_id == CHESSFAD_FLETCHER_POWELL) {
-        rc = fp_lookup(n, fp);
+        fp_lock = std::unique_lock<std::mutex>(g_fp_mu);
+        rc = fp_lookup_locked(n, fp);
         if (rc) return rc;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (func_id == CHESSFAD_FLETCHER_POWELL && n <= kFpMaxN && g_opt_fp_mfma) {
-        FpMfmaLaunch launch = mixed ? fp_mfma_entry_mixed(chunk, fp_mfma_steps(n), hess, sym)
-                                    : fp_mfma_entry(chunk, fp_mfma_steps(n), hess, sym);
-        if (!launch) return CHESSFAD_E_CHUNK;
-        // every call of a point is a block of the point's tile (the chunk
-        // size and the symmetric form give the same entries)
-        if (g_opt_fp_mfma == 1)
-            launch = mixed ? fp_tile_entry_mixed(fp_mfma_steps(n), hess) : fp_tile_entry(fp_mfma_steps(n), hess);
+        const int nk = fp_mfma_steps(n);
+        FpMfmaLaunch launch = nullptr;
+        if (g_opt_fp_mfma == 1 && !sym) {
+            // the per-call kernel (DPP lane broadcasts)
+            launch = mixed ? fp_call_entry_mixed(chunk, nk, hess)
+                           : (grad || fval) ? fp_call_entry_grad(chunk, nk) : fp_call_entry(chunk, nk, hess);
+        } else if (g_opt_fp_mfma == 3) {
+            // the closed-form point tile: every call of a point is a block of
+            // its J^T J tile (the chunk size and the symmetric form give the
+            // same entries)
+            launch = mixed ? fp_tile_entry_mixed(nk, hess) : fp_tile_entry(nk, hess);
+        } else {
+            // the per-call kernel with MFMA contractions (also the symmetric form)
+            launch = mixed ? fp_mfma_entry_mixed(chunk, nk, hess, sym) : fp_mfma_entry(chunk, nk, hess, sym);
+        }
         if (!launch) return CHESSFAD_E_CHUNK;
         const int nc = (n + chunk - 1) / chunk;
         const int64_t per_block = (int64_t)kFpWaves * kFpPointsPerWave;
@@ -464,6 +476,8 @@ int chessfad_fp_set_params(int n, const double* A, const double* B, const double
                            set.A32, set.B32);
         e = hipGetLastError();
     }
+    // the set is complete on the device before any stream can read it
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         fp_free(set);
         return hip_fail(e);
@@ -501,7 +515,7 @@ int chessfad_set_option(int option, int value) {
     int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
               : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
               : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping : nullptr;
-    const int maxv = option == CHESSFAD_OPT_MAPPING || option == CHESSFAD_OPT_FP_MFMA ? 2 : 1;
+    const int maxv = option == CHESSFAD_OPT_FP_MFMA ? 3 : option == CHESSFAD_OPT_MAPPING ? 2 : 1;
     if (!slot || value < 0 || value > maxv) return CHESSFAD_E_ARG;
     const int prev = *slot;
     *slot = value;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kernel_fp_call.hpp"
 #include "kernel_fp_mfma.hpp"
 #include "kernel_fp_tile.hpp"
 #include "kernel_fp_rows.hpp"
@@ -118,6 +119,42 @@ FpMfmaLaunch fp_tile_by_steps(int nk) {
 // and mixed (one translation unit each).
 FpMfmaLaunch fp_tile_entry(int nk, bool hess);
 FpMfmaLaunch fp_tile_entry_mixed(int nk, bool hess);
+
+template <class P, int NK, int C, bool kHess, bool kGrad>
+hipError_t launch_fp_call(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    hipLaunchKernelGGL((fp_call_kernel<P, NK, C, kHess, kGrad>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <class P, int NK, bool kHess, bool kGrad>
+FpMfmaLaunch fp_call_entry_c(int C) {
+    switch (C) {
+        case 1: return &launch_fp_call<P, NK, 1, kHess, kGrad>;
+        case 2: return &launch_fp_call<P, NK, 2, kHess, kGrad>;
+        case 4: return &launch_fp_call<P, NK, 4, kHess, kGrad>;
+        case 8: return &launch_fp_call<P, NK, 8, kHess, kGrad>;
+        case 16: return &launch_fp_call<P, NK, 16, kHess, kGrad>;
+        default: return nullptr;
+    }
+}
+
+template <class P, bool kHess, bool kGrad>
+FpMfmaLaunch fp_call_by_steps(int C, int nk) {
+    switch (nk) {
+        case 1: return fp_call_entry_c<P, 1, kHess, kGrad>(C);
+        case 2: return fp_call_entry_c<P, 2, kHess, kGrad>(C);
+        case 4: return fp_call_entry_c<P, 4, kHess, kGrad>(C);
+        case 8: return fp_call_entry_c<P, 8, kHess, kGrad>(C);
+        default: return nullptr;
+    }
+}
+
+// The per-call Fletcher-Powell kernel (n <= 16) for a chunk, K-step count and
+// output kind: float64 H.v / Hessian, float64 H.v with the gradient and f, and
+// mixed precision (one translation unit each).
+FpMfmaLaunch fp_call_entry(int C, int nk, bool hess);
+FpMfmaLaunch fp_call_entry_grad(int C, int nk);
+FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 

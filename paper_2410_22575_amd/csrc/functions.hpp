@@ -6,7 +6,8 @@
 //   tables(x, t0, t1)    those values for one coordinate, in float64
 //   isl_tasks / isl_size per-point float64 "island" work: how many tasks and
 //                        how many values per point
-//   island(task, ...)    one task of it, in float64
+//   island(task, ...)    one task of it, in float64 (stored in float64; the
+//                        hDual arithmetic rounds an island where it uses it)
 //   eval<P, C>(pv, prm)  f evaluated on the CHUNK-INIT seeds of one
 //                        (point, row i, chunk cs) work item
 // Values that every call of a point shares - the transcendentals of single
@@ -32,12 +33,13 @@ struct PointView {
     const T* xs;          // coordinates (hDual precision)
     const double* t0;     // tables (float64)
     const double* t1;
-    const T* isl;         // per-point island values (hDual precision)
+    const double* isl;    // per-point island values (float64)
     int n, i, cs;
     CF_DEV T x(int k) const { return xs[k]; }
     CF_DEV T tab0(int k) const { return (T)t0[k]; }
     CF_DEV T tab1(int k) const { return (T)t1[k]; }
-    CF_DEV T island(int q) const { return isl[q]; }
+    CF_DEV T island(int q) const { return (T)isl[q]; }
+    CF_DEV double island64(int q) const { return isl[q]; }
     template <int C>
     CF_DEV HD1<T, C> y(int k) const { return seed<T, C>(x(k), k, i, cs); }
     // y_k restricted to the W chunk components m0 .. m0 + W - 1 (slots of that
@@ -76,8 +78,7 @@ struct Rosenbrock {
     static CF_DEV void tables(double, double&, double&) {}
     __host__ __device__ static int isl_tasks(int) { return 0; }
     __host__ __device__ static int isl_size(int) { return 0; }
-    template <typename T>
-    static CF_DEV void island(int, int, const double*, const double*, const double*, int, const FpParams&, T*) {}
+    static CF_DEV void island(int, int, const double*, const double*, const double*, int, const FpParams&, double*) {}
 
     template <typename T, int C>
     static CF_DEV HD<T, C> term(const HD1<T, C>& yk, const HD1<T, C>& yk1) {
@@ -129,9 +130,8 @@ struct Ackley {
     //   G(c) = -exp(c / n)                at c = sum cos(2 pi x)
     // With r = sqrt(s / n) and E = exp(-0.2 r): F' = 2E / (n r) and
     // F'' = -E (0.2 + 1 / r) / (n r)^2; G' = G / n, G'' = G / n^2.
-    template <typename T>
     static CF_DEV void island(int, int n, const double* xg, const double* t0, const double*, int stride,
-                              const FpParams&, T* isl) {
+                              const FpParams&, double* isl) {
         double ss = xg[0] * xg[0], cs = t0[0];
         for (int k = 1; k < n; ++k) {
             ss += xg[k] * xg[k];
@@ -141,13 +141,13 @@ struct Ackley {
         const double rt = sqrt(inv_n * ss);
         const double e1 = exp(-0.2 * rt);
         const double nr = n * rt;
-        isl[0] = (T)(-20.0 * e1);
-        isl[1 * stride] = (T)(2.0 * e1 / nr);
-        isl[2 * stride] = (T)(-e1 * (0.2 + 1.0 / rt) / (nr * nr));
+        isl[0] = -20.0 * e1;
+        isl[1 * stride] = 2.0 * e1 / nr;
+        isl[2 * stride] = -e1 * (0.2 + 1.0 / rt) / (nr * nr);
         const double g = -exp(inv_n * cs);
-        isl[3 * stride] = (T)g;
-        isl[4 * stride] = (T)(g * inv_n);
-        isl[5 * stride] = (T)(g * inv_n * inv_n);
+        isl[3 * stride] = g;
+        isl[4 * stride] = g * inv_n;
+        isl[5 * stride] = g * inv_n * inv_n;
     }
 
     template <typename T, int C>
@@ -177,9 +177,12 @@ struct Ackley {
             ssd += sq(y).d;
             csd += cos_term<T, 0>(pv, k).d;
         }
-        // chain(a, g, g', g''): r.d = g' a.d, r.g = g' a.g, r.h = g' a.h + (g'' a.d) a.g
-        const T f1 = pv.island(1), f2d = pv.island(2) * ssd;
-        const T g1 = pv.island(4), g2d = pv.island(5) * csd;
+        // chain(a, g, g', g''): r.d = g' a.d, r.g = g' a.g, r.h = g' a.h + (g'' a.d) a.g;
+        // F'' grows like 1 / |x|^3 near x = 0, so its product with the row
+        // derivative (like 1 / |x|^2) is formed in float64 before it takes
+        // the hDual precision
+        const T f1 = pv.island(1), f2d = (T)(pv.island64(2) * (double)ssd);
+        const T g1 = pv.island(4), g2d = (T)(pv.island64(5) * (double)csd);
         HD<T, C> r;
         r.v = (pv.island(0) + pv.island(3)) + T(20.0 + kE);
         r.d = f1 * ssd + g1 * csd;
@@ -210,9 +213,8 @@ struct FletcherPowell {
     __host__ __device__ static int isl_size(int n) { return n; }
 
     // float64 residual value r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j
-    template <typename T>
     static CF_DEV void island(int m, int n, const double*, const double* t0, const double* t1, int stride,
-                              const FpParams& prm, T* isl) {
+                              const FpParams& prm, double* isl) {
         const double* Am = prm.A + (size_t)m * n;
         const double* Bm = prm.B + (size_t)m * n;
         double acc = Am[0] * t0[0];
@@ -221,7 +223,7 @@ struct FletcherPowell {
             acc = acc + Am[j] * t0[j * stride];
             acc = acc + Bm[j] * t1[j * stride];
         }
-        isl[m * stride] = (T)(prm.E[m] - acc);
+        isl[m * stride] = prm.E[m] - acc;
     }
 
     // the derivative components of inner_m = sum_j A_mj sin y_j + B_mj cos y_j;

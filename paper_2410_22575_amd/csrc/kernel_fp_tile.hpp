@@ -1,9 +1,11 @@
 // Fletcher-Powell, n <= 16: all second-order components of a point as one
-// 16 x 16 MFMA tile.
+// 16 x 16 MFMA tile - the closed form 2 (J^T J + diag(D^T r)), kept as a
+// comparison for the chunked method (CHESSFAD_OPT_FP_MFMA = 3); it makes no
+// per-call evaluation.
 //
-// The hDual evaluation of one call (point p, row i, chunk cs) has two layers
-// (Sec. VII): the residuals r_m = E_m - sum_j A_mj sin(y_j) + B_mj cos(y_j)
-// and f = sum_m r_m * r_m.  On the CHUNK-INIT seeds every seeded sin/cos has
+// The hDual evaluation of one call (point p, row i, chunk cs) has two layers:
+// the residuals r_m = E_m - sum_j A_mj sin(y_j) + B_mj cos(y_j) and
+// f = sum_m r_m * r_m.  On the CHUNK-INIT seeds every seeded sin/cos has
 // its first-order parts on one coordinate only, so the residual layer gives,
 // with J_mj = B_mj sin x_j - A_mj cos x_j,
 //   r_m.v    = E_m - sum_j A_mj sin x_j + B_mj cos x_j   (the same in every call)

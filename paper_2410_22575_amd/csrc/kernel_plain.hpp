@@ -45,14 +45,14 @@ struct PlainArgs {
 constexpr int kMaxBlock = 512;
 
 // LDS bytes for one workgroup (host and device agree on this layout):
-// doubles: red[block], t0, t1 [pstride][ks]; T: xs, vs [pstride][ks],
-// isl [pstride][ki], with ks = aos_stride(n) and ki = aos_stride(isl_size(n))
+// doubles: red[block], t0, t1 [pstride][ks], isl [pstride][ki]; T: xs, vs
+// [pstride][ks], with ks = aos_stride(n) and ki = aos_stride(isl_size(n))
 template <class P, class F>
 __host__ __device__ inline size_t plain_lds_bytes(int n, int pstride, int block, bool hess) {
     using T = typename P::T;
     const size_t ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
-    const size_t dbl = (size_t)block + (F::kTables ? 2 * ks * pstride : 0);
-    const size_t tt = ks * pstride * (hess ? 1 : 2) + ki * pstride;
+    const size_t dbl = (size_t)block + (F::kTables ? 2 * ks * pstride : 0) + ki * pstride;
+    const size_t tt = ks * pstride * (hess ? 1 : 2);
     return dbl * sizeof(double) + tt * sizeof(T);
 }
 
@@ -62,9 +62,9 @@ struct PlainStage {
     double* red;
     double* t0;
     double* t1;
+    double* isl;
     T* xs;
     T* vs;
-    T* isl;
     int ks, ki;   // row lengths: coordinate arrays, islands
 };
 
@@ -83,9 +83,9 @@ __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs
     st.red = lds;
     st.t0 = st.red + nthr;
     st.t1 = st.t0 + (F::kTables ? ks * ps : 0);
-    st.xs = reinterpret_cast<T*>(st.t1 + (F::kTables ? ks * ps : 0));
+    st.isl = st.t1 + (F::kTables ? ks * ps : 0);
+    st.xs = reinterpret_cast<T*>(st.isl + ki * ps);
     st.vs = st.xs + ks * ps;
-    st.isl = st.vs + (kHess ? 0 : ks * ps);
 
     const double* xg = a.x + p0 * n;
     const double* vg = a.v + p0 * n;

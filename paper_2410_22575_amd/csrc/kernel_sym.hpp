@@ -1,6 +1,6 @@
 // Symmetric chunked Hessian / Hessian-vector kernel (vector ALU), gfx950.
 //
-// SCHUNK-HESS (Sec. IV) and SC-HESS-VEC (Sec. VI) evaluate f only for the
+// SCHUNK-HESS (Sec. III.B) and SC-HESS-VEC (Sec. VI) evaluate f only for the
 // chunks of a row that start at the row's own chunk b = i / C or after it:
 // n (n / C + 1) / 2 calls per point when C divides n (Sec. V) instead of
 // n ceil(n / C).  An entry H(i, s) of a later chunk stands in for its mirror
@@ -68,16 +68,16 @@ __host__ __device__ inline int sym_mir_off(int s) {
 }
 
 // LDS bytes (host and device agree on this layout):
-// doubles: partial sums [ppb][C nc^2] (H.v), t0, t1 [pstride][ks];
-// T: xs, vs [pstride][ks], isl [pstride][ki] (per-point rows, aos_stride)
+// doubles: partial sums [ppb][C nc^2] (H.v), t0, t1 [pstride][ks],
+// isl [pstride][ki]; T: xs, vs [pstride][ks] (per-point rows, aos_stride)
 template <class P, class F>
 __host__ __device__ inline size_t sym_lds_bytes(int n, int C, int ppb, int pstride, bool hess) {
     using T = typename P::T;
     const int nc = (n + C - 1) / C;
     const size_t red = hess ? 0 : (size_t)ppb * C * nc * nc;
     const size_t ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
-    const size_t dbl = red + (F::kTables ? 2 * ks * pstride : 0);
-    const size_t tt = ks * pstride * (hess ? 1 : 2) + ki * pstride;
+    const size_t dbl = red + (F::kTables ? 2 * ks * pstride : 0) + ki * pstride;
+    const size_t tt = ks * pstride * (hess ? 1 : 2);
     return dbl * sizeof(double) + tt * sizeof(T);
 }
 
@@ -113,9 +113,9 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
     double* t0 = red + (kHess ? 0 : (size_t)ppb * slots);
     const int ks = aos_stride(n), ki = aos_stride(F::isl_size(n));
     double* t1 = t0 + (F::kTables ? ks * ps : 0);
-    T* xs = reinterpret_cast<T*>(t1 + (F::kTables ? ks * ps : 0));
+    double* isl = t1 + (F::kTables ? ks * ps : 0);
+    T* xs = reinterpret_cast<T*>(isl + ki * ps);
     T* vs = xs + ks * ps;
-    T* isl = vs + (kHess ? 0 : ks * ps);
 
     // 1. stage coordinates (and vectors) in per-point rows, with the
     //    per-coordinate tables

@@ -158,7 +158,7 @@ def test_user_function_registration_host_only(lib):
 
 def test_options(lib):
     assert lib.chessfad_set_option(99, 0) == E_ARG
-    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 3) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 4) == E_ARG
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 2) == 1   # the default is 1
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_MFMA, 1) == 2
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 3) == E_ARG
@@ -233,3 +233,4 @@ def test_autotune_argument_checks(lib):
     assert lib.chessfad_autotune(R, 1, 0, 100, None, None, None) == E_N
     assert lib.chessfad_autotune(A, 16, 3, 100, None, None, None) == E_ARG
     assert lib.chessfad_autotune(A, 16, 0, 0, None, None, None) == E_ARG
+

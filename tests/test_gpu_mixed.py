@@ -117,3 +117,59 @@ def test_mixed_argument_checks(gpu_lib):
     assert ei.value.code == -3
     empty = torch.zeros(0, 8, dtype=torch.float64, device="cuda")
     assert gpu_lib.chessfad_hvp_mixed(A, empty, empty).shape == (0, 8)
+
+
+@pytest.mark.parametrize("n", [65, 130, 256, 512])
+def test_mixed_fletcher_powell_large_n(gpu_lib, n):
+    """Fletcher-Powell above 16 variables in mixed precision: the row-block
+    kernel with float32 contraction tiles, blocked compensated sums and
+    several variable passes from n = 129 on (n = 512 is the large-n
+    workload's shape), H.v and Hessians element by element on a few points."""
+    npts = 8 if n <= 256 else 4
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(7400 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref = cf.hessian(FP, w.x, w.A, w.B, E)
+    hmax = np.abs(H_ref).max(axis=(1, 2))
+    r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
+    for c in (4, 16):
+        print(f"[case] mixed fp n={n} chunk={c} npts={npts}", flush=True)
+        r = gpu_lib.chessfad_hvp_mixed(FP, x, v, chunk=c).cpu().numpy()
+        e_r = (np.abs(r - r_ref).max(axis=1) / (hmax * np.abs(w.v).max(axis=1))).max()
+        H = gpu_lib.chessfad_hessian_mixed(FP, x, chunk=c).cpu().numpy()
+        e_H = (np.abs(H - H_ref).max(axis=(1, 2)) / hmax).max()
+        print(f"  max rel err: hvp {e_r:.3e}  hessian {e_H:.3e}", flush=True)
+        assert e_r <= TOL32 and e_H <= TOL32
+        assert e_r > 0.0
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-3, 1e-6, 1e-9])
+@pytest.mark.parametrize("n", [5, 16, 64])
+def test_mixed_ackley_near_zero(gpu_lib, n, scale):
+    """Ackley where sqrt(sum x^2 / n) -> 0: F' grows like 1 / |x| and F'' like
+    1 / |x|^3, the reason its outer functions are float64 islands.  Points
+    x ~ U[-1e-3, 1e-3] * scale; the float64 path to 1e-12 and the mixed path to
+    TOL32 normwise, and entry by entry on the entries of at least 1e-3 of the
+    largest (the diagnostic of the oracle's error metric)."""
+    npts = 64
+    rng = inputs.rng_for(7500 + n)
+    x = rng.uniform(-1e-3, 1e-3, size=(npts, n)) * scale
+    vv = rng.standard_normal(size=(npts, n))
+    H_ref = cf.hessian(A, x)
+    hmax = np.abs(H_ref).max(axis=(1, 2))
+    r_ref = cf.hvp(A, x, vv)
+    xd, vd = _dev(x), _dev(vv)
+    big = np.abs(H_ref) >= 1e-3 * hmax[:, None, None]
+    for name, fn, fh, tol in (("f64", gpu_lib.chessfad_hvp, gpu_lib.chessfad_hessian, 1e-12),
+                              ("mixed", gpu_lib.chessfad_hvp_mixed, gpu_lib.chessfad_hessian_mixed, TOL32)):
+        for c in (1, min(16, n)):
+            print(f"[case] ackley near zero n={n} scale={scale} {name} chunk={c}", flush=True)
+            r = fn(A, xd, vd, chunk=c).cpu().numpy()
+            H = fh(A, xd, chunk=c).cpu().numpy()
+            assert np.all(np.isfinite(r)) and np.all(np.isfinite(H))
+            e_r = (np.abs(r - r_ref).max(axis=1) / (hmax * np.abs(vv).max(axis=1))).max()
+            e_H = (np.abs(H - H_ref).max(axis=(1, 2)) / hmax).max()
+            e_el = (np.abs(H - H_ref)[big] / np.abs(H_ref)[big]).max()
+            print(f"  max rel err: hvp {e_r:.3e}  hessian {e_H:.3e}  entrywise {e_el:.3e}", flush=True)
+            assert e_r <= tol and e_H <= tol
+            assert e_el <= (1e-10 if name == "f64" else 1e-3)

@@ -20,12 +20,13 @@ TOL64 = 1e-12
 CHUNKS = (1, 2, 4, 8, 16)
 
 
-FUNC_PATHS = [(R, None), (A, None), (FP, 1), (FP, 2), (FP, 0)]  # (function, Fletcher-Powell MFMA option)
+FUNC_PATHS = [(R, None), (A, None), (FP, 1), (FP, 2), (FP, 3), (FP, 0)]  # (function, Fletcher-Powell engine)
 
 
 class fp_path:
-    """Select the Fletcher-Powell path (1 = MFMA point tile in float64, 2 = MFMA
-    contraction per call, 0 = vector ALUs)."""
+    """Select the Fletcher-Powell path at n <= 16 (1 = the per-call kernel with
+    DPP lane broadcasts, 2 = MFMA contraction per call, 3 = the closed-form
+    point tile, 0 = vector ALUs)."""
 
     def __init__(self, lib, mfma):
         self.lib, self.mfma = lib, mfma
@@ -200,15 +201,17 @@ def test_edge_cases(gpu_lib):
     assert ei.value.code == -5
 
 
-def test_fp_mfma_matches_vector_path(gpu_lib):
-    """Both Fletcher-Powell paths form the derivative components with the
-    same single products; only the order of the sum over residuals differs."""
+@pytest.mark.parametrize("engine", [1, 2, 3])
+def test_fp_mfma_matches_vector_path(gpu_lib, engine):
+    """Every Fletcher-Powell engine forms the derivative components with the
+    same single products as the vector path; only the order of the sum over
+    residuals differs."""
     n, npts = 16, 700
     w = inputs.make_workload(FP, n, npts, inputs.rng_for(6000))
     _setup(gpu_lib, w)
     x = _dev(w.x)
     for c in (1, 2, 4, 8, 16):
-        with fp_path(gpu_lib, 1):
+        with fp_path(gpu_lib, engine):
             H1 = gpu_lib.chessfad_hessian(FP, x, chunk=c)
         with fp_path(gpu_lib, 0):
             H0 = gpu_lib.chessfad_hessian(FP, x, chunk=c)

@@ -89,3 +89,18 @@ def test_user_edge_cases(gpu_lib, user_ids):
     with pytest.raises(gpu_lib.ChessfadError) as ei:
         gpu_lib.chessfad_hvp_mixed(fid, _dev(w.x), _dev(w.v))
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("n", [3, 16])
+def test_user_fletcher_powell_against_closed_form(gpu_lib, n):
+    """Fletcher-Powell written once over the generic hDual, its parameter set
+    as constants in the source (the package's user_sources), every chunk."""
+    from paper_2410_22575_amd import user_sources
+
+    w = inputs.make_workload(2, n, 33, inputs.rng_for(9650 + n))
+    E = cf.fp_offsets(w.A, w.B, w.alpha)
+    fid = gpu_lib.chessfad_register_function(user_sources.fletcher_powell_hip(w.A, w.B, E))
+    try:
+        _check(gpu_lib, fid, w.x, w.v, cf.hessian(2, w.x, w.A, w.B, E), (1, 2, 4, 8, 16))
+    finally:
+        gpu_lib.chessfad_release_function(fid)

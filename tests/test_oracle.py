@@ -243,7 +243,7 @@ def test_chunked_c_threads_agree():
                                   chunked.hvp(R, w.x, w.v, 4, nthreads=4))
 
 
-# ------------------------------- symmetric variants (Sec. IV, Sec. V, Sec. VI)
+# ----------------------------- symmetric variants (Sec. III.B, Sec. V, Sec. VI)
 @pytest.mark.parametrize("func", [R, A, FP])
 @pytest.mark.parametrize("n,c", [(2, 1), (2, 2), (5, 2), (5, 3), (8, 4), (16, 4), (16, 16), (13, 4), (7, 16),
                                  (12, 1)])

@@ -1,24 +1,9 @@
-"""User functions written twice: HIP source for chessfad_register_function
-(over chessfad_device.h's hDual) and Python over the oracle's number types
-(oracle.hyperdual), so the oracle computes their Hessians independently."""
-ROSENBROCK_HIP = """
-template <class V, class Y> __device__ V chessfad_user_f(const Y& y, int n) {
-    V s = 0.0;
-    for (int k = 0; k + 1 < n; ++k) s += 100.0 * sq(y[k + 1] - y[k] * y[k]) + sq(1.0 - y[k]);
-    return s;
-}
-"""
-
-ACKLEY_HIP = """
-template <class V, class Y> __device__ V chessfad_user_f(const Y& y, int n) {
-    V ss = 0.0, cs = 0.0;
-    for (int k = 0; k < n; ++k) {
-        ss += y[k] * y[k];
-        cs += cos(6.283185307179586 * y[k]);
-    }
-    return -20.0 * exp(-0.2 * sqrt(ss / (double)n)) - exp(cs / (double)n) + 20.0 + 2.718281828459045;
-}
-"""
+"""User functions for the GPU tests: the package's Rosenbrock and Ackley
+sources, and a function over every operator written twice - HIP source for
+chessfad_register_function (over chessfad_device.h's hDual) and Python over
+the oracle's number types (oracle.hyperdual), so the oracle computes its
+Hessian independently."""
+from paper_2410_22575_amd.user_sources import ACKLEY_HIP, ROSENBROCK_HIP  # noqa: F401
 
 # every operator of chessfad_device.h, and a branch on a value (n >= 6)
 MIXED_OPS_HIP = """
