@@ -10,6 +10,10 @@
 //                        hDual arithmetic rounds an island where it uses it)
 //   eval<P, C>(pv, prm)  f evaluated on the CHUNK-INIT seeds of one
 //                        (point, row i, chunk cs) work item
+//   hvp<P, C>(pv, prm, vrow)  the same call's chunk dot
+//                        sum_l h[l] v[cs + l] (CHESS-VEC), with f evaluated
+//                        only on the terms whose seeds give them a
+//                        second-order part (see below)
 // Values that every call of a point shares - the transcendentals of single
 // coordinates, Ackley's sqrt and exponentials of its two sums, the
 // Fletcher-Powell residual values - are computed once per point in float64
@@ -72,6 +76,29 @@ CF_DEV float fp_b<float>(const FpParams& p, size_t idx) { return p.B32[idx]; }
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kE = 2.718281828459045235360287471352;
 
+// The chunk dot of a full evaluation: sum_l h[l] v[cs + l] over columns < n.
+template <class P, class F, int C>
+CF_DEV double eval_dot(const PointView<typename P::T>& pv, const FpParams& prm, const typename P::T* vrow) {
+    const HD<typename P::T, C> res = F::template eval<P, C>(pv, prm);
+    typename P::Dot acc;
+#pragma unroll
+    for (int l = 0; l < C; ++l)
+        if (pv.cs + l < pv.n) acc.add(res.h[l], vrow[pv.cs + l]);
+    return acc.get();
+}
+
+// Second-order parts in a call (i, cs).  The row seed [k = i] is nonzero
+// only on x_i, and every second-order component of an hDual operation is a
+// sum of products that each hold a row-derivative factor (u_d w_g, w_d u_g,
+// g'' u_d u_g) or an operand's second-order part.  So a term of f in which
+// x_i does not occur has an exactly zero second-order part whatever its chunk
+// seeds: it contributes value and chunk-gradient components only.  H.v reads
+// the second-order part alone; `hvp` evaluates the terms that reach it -
+// Rosenbrock's terms in x_i, and for Ackley the term in x_i together with the
+// chunk's terms, whose gradient components pass through the outer functions'
+// second derivatives - each on its CHUNK-INIT seeds, and dots their
+// second-order components with v as it goes.
+
 // sum_{k<n-1} 100 (y_{k+1} - y_k^2)^2 + (1 - y_k)^2
 struct Rosenbrock {
     static constexpr int kTables = 0;
@@ -113,6 +140,53 @@ struct Rosenbrock {
         });
         for (int k = k1; k < nt; ++k) P::add_light(s, term<T, 0>(pv.template y<0>(k), pv.template y<0>(k + 1)));
         return P::value(s);
+    }
+
+    // H.v chunk dot of call (i, cs): the terms in x_i are k = i - 1 (on
+    // x_{i-1}, x_i) and k = i (on x_i, x_{i+1}).  Each runs on the window of
+    // its two variables: y_i carries the row seed, and each variable carries
+    // its chunk seed when it lies in [cs, cs + C) (otherwise a zero seed, and
+    // that window slot comes out zero).  A term outside 0 <= k < n - 1 gets a
+    // zero row seed, so its second-order part is zero; its index is clamped.
+    template <class P, int C>
+    static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams&, const typename P::T* vrow) {
+        using T = typename P::T;
+        const int i = pv.i, n = pv.n, cs = pv.cs;
+        auto chunk_seed = [&](int k) { return (k >= cs && k < cs + C) ? T(1) : T(0); };
+        const int km = i > 0 ? i - 1 : 0, kp = i + 1 < n ? i + 1 : i;
+        const T xm = pv.x(km), xi = pv.x(i), xp = pv.x(kp);
+        typename P::Dot acc;
+        {
+            // term k = i - 1: window (x_{i-1}, x_i)
+            HD1<T, 2> a, b;
+            a.v = xm;
+            a.d = T(0);
+            a.g[0] = chunk_seed(i - 1);
+            a.g[1] = T(0);
+            b.v = xi;
+            b.d = i > 0 ? T(1) : T(0);
+            b.g[0] = T(0);
+            b.g[1] = chunk_seed(i);
+            const HD<T, 2> t = term<T, 2>(a, b);
+            acc.add(t.h[0], vrow[km]);
+            acc.add(t.h[1], vrow[i]);
+        }
+        {
+            // term k = i: window (x_i, x_{i+1})
+            HD1<T, 2> a, b;
+            a.v = xi;
+            a.d = i + 1 < n ? T(1) : T(0);
+            a.g[0] = chunk_seed(i);
+            a.g[1] = T(0);
+            b.v = xp;
+            b.d = T(0);
+            b.g[0] = T(0);
+            b.g[1] = chunk_seed(i + 1);
+            const HD<T, 2> t = term<T, 2>(a, b);
+            acc.add(t.h[0], vrow[i]);
+            acc.add(t.h[1], vrow[kp]);
+        }
+        return acc.get();
     }
 };
 
@@ -202,6 +276,49 @@ struct Ackley {
         });
         return r;
     }
+
+    // H.v chunk dot of call (i, cs).  The sums' row-derivative components
+    // come from the one term in x_i, evaluated on the seed <x_i, 1, [i in
+    // chunk], 0>; its second-order parts (the row seed times its own chunk
+    // seed) are the sums' only ones, at slot i - cs.  The chunk's terms run on
+    // seeds without the row part (<x_k, 0, 1, 0> at their slot, whose
+    // second-order parts are exact zeros) and give the sums' gradient
+    // components.  F's and G's chain rule then gives, per slot m,
+    //   h[m] = F' S.h[m] + (F'' S.d) S.g[m] + G' C.h[m] + (G'' C.d) C.g[m]
+    // with S.h, C.h nonzero only at slot i - cs: the gradient products are
+    // dotted with v slot by slot, and the own slot's second-order products
+    // with v_i (zero when x_i lies outside the chunk).
+    template <class P, int C>
+    static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams&, const typename P::T* vrow) {
+        using T = typename P::T;
+        const int i = pv.i, cs = pv.cs;
+        HD1<T, 1> yi;
+        yi.v = pv.x(i);
+        yi.d = T(1);
+        yi.g[0] = (i >= cs && i < cs + C) ? T(1) : T(0);
+        const HD<T, 1> si = sq(yi), ci = cos_of(pv, yi, i);
+        const T f1 = pv.island(1), f2d = (T)(pv.island64(2) * (double)si.d);
+        const T g1 = pv.island(4), g2d = (T)(pv.island64(5) * (double)ci.d);
+        typename P::Dot acc;
+        auto slot = [&](int k) {
+            HD1<T, 1> y;
+            y.v = pv.x(k);
+            y.d = T(0);
+            y.g[0] = T(1);
+            const HD<T, 1> st = sq(y), ct = cos_of(pv, y, k);
+            acc.add((f1 * st.h[0] + f2d * st.g[0]) + (g1 * ct.h[0] + g2d * ct.g[0]), vrow[k]);
+        };
+        if (cs + C <= pv.n) {
+            static_for<C>([&](auto mc) { slot(cs + decltype(mc)::value); });
+        } else {
+            static_for<C>([&](auto mc) {
+                const int k = cs + decltype(mc)::value;
+                if (k < pv.n) slot(k);
+            });
+        }
+        acc.add(f1 * si.h[0] + g1 * ci.h[0], vrow[i]);
+        return acc.get();
+    }
 };
 
 // sum_m (E_m - sum_j A_mj sin y_j + B_mj cos y_j)^2
@@ -257,6 +374,12 @@ struct FletcherPowell {
             P::add(f, r * r);
         }
         return P::value(f);
+    }
+
+    // every residual depends on every variable: the full evaluation
+    template <class P, int C>
+    static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams& prm, const typename P::T* vrow) {
+        return eval_dot<P, FletcherPowell, C>(pv, prm, vrow);
     }
 };
 

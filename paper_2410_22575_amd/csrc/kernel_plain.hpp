@@ -139,7 +139,12 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     const int cs = j * C;
 
     double dot = 0.0;
-    if (active) {
+    if (active && !kHess && !kGrad) {
+        PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
+        // 3-4b. f on the call's seeds, its second-order part dotted with
+        // v[p][cs .. cs + C)
+        dot = F::template hvp<P, C>(pv, a.fp, st.vs + pl * st.ks);
+    } else if (active) {
         PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
         // 3. one f evaluation on hDual<C> seeds
         const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
@@ -217,13 +222,8 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
         for (int j = 0; j < nc; ++j) {
             const int cs = j * C;
             PointView<T> pv{st.xs + pl * st.ks, st.t0 + pl * st.ks, st.t1 + pl * st.ks, st.isl + pl * st.ki, n, i, cs};
-            // the lanes of a wave are at the same chunk: terms outside it run light
-            const HD<T, C> h = F::template eval<P, C>(pv, a.fp);
-            typename P::Dot acc;
-#pragma unroll
-            for (int l = 0; l < C; ++l)
-                if (cs + l < n) acc.add(h.h[l], st.vs[pl * st.ks + cs + l]);
-            res += acc.get();
+            // f on the call's seeds, its second-order part dotted with v
+            res += F::template hvp<P, C>(pv, a.fp, st.vs + pl * st.ks);
         }
         a.out[q] = res;
     }
