@@ -39,6 +39,7 @@
 #ifndef CHESSFAD_H
 #define CHESSFAD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -310,6 +311,32 @@ int chessfad_batch_run(chessfad_batch* plan, void* stream);
 int chessfad_batch_destroy(chessfad_batch* plan);
 /* Work items, persistent workgroups launched, and paper-model flops of one run. */
 int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgroups, double* model_flops);
+
+/*
+ * Allocation-free batched H.v, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Validates and plans the instances exactly as
+ * chessfad_batch_create does (same work items, same kernels, so the same
+ * results as a plan of the same instances), but places the plan - its
+ * descriptors, work lists, counters and Fletcher-Powell offsets and float32
+ * copies - in a fixed library-owned device array of
+ * CHESSFAD_NOALLOC_SCRATCH_BYTES bytes instead of allocating, launches the
+ * persistent kernels directly on `stream` (no graph), and waits for
+ * `stream` before returning.  No device memory is allocated or freed (the
+ * planning itself uses host memory).
+ * Each GPU the library runs on holds one such array from its first use
+ * until the process ends; every call on that GPU uses it, so calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.
+ * Errors: as chessfad_batch_create (on a failed check *bad_index names the
+ * instance; nothing is enqueued); CHESSFAD_E_ARG when the plan needs more
+ * than CHESSFAD_NOALLOC_SCRATCH_BYTES bytes (8 bytes per work item and
+ * about 100 per instance, plus per Fletcher-Powell instance 8n bytes of
+ * offsets and, in mixed precision, 8n^2 bytes of float32 copies, each
+ * rounded up to 256 bytes); CHESSFAD_E_HIP for a HIP error.
+ */
+#define CHESSFAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int chessfad_batch_run_noalloc(const chessfad_instance* inst, int ninst, void* stream, int* bad_index);
 
 /*
  * Autotuner: times chessfad_hvp (precision 0) or chessfad_hvp_mixed (1) for

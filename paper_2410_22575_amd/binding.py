@@ -46,6 +46,7 @@ SIGNATURES = {
     "chessfad_batch_run": (_i, [_p, _p]),
     "chessfad_batch_destroy": (_i, [_p]),
     "chessfad_batch_info": (_i, [_p, _pi64, _pi, _pd]),
+    "chessfad_batch_run_noalloc": (_i, [_p, _i, _p, _pi]),
     "chessfad_autotune": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
     "chessfad_hvp_sym": (_i, [_i, _i, _i64, _p, _p, _p, _i, _i, _p]),
     "chessfad_hvp_grad": (_i, [_i, _i, _i64, _p, _p, _p, _p, _p, _i, _p]),
@@ -292,6 +293,21 @@ def chessfad_batch_create(instances, stream=None) -> BatchPlan:
         err.bad_index = bad.value
         raise err
     return BatchPlan(h, keep)
+
+
+def chessfad_batch_run_noalloc(instances, stream=None) -> None:
+    """Plan and run the instances (as chessfad_batch_create) in the library's
+    fixed device array, without allocating device memory; returns when the
+    stream has finished the work."""
+    arr, keep = _instances(instances)
+    bad = ctypes.c_int(-1)
+    rc = load().chessfad_batch_run_noalloc(ctypes.cast(arr, ctypes.c_void_p), len(instances), _stream(stream),
+                                           ctypes.byref(bad))
+    if rc != 0:
+        err = ChessfadError(rc, f"chessfad_batch_run_noalloc (instance {bad.value})")
+        err.bad_index = bad.value
+        raise err
+    del keep
 
 
 def chessfad_autotune(func_id: int, n: int, precision: int = 0, npts: int = 1 << 16, stream=None):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "batch.hpp"
@@ -159,7 +160,8 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
             e.d.pstride = 0;
             e.blocks = c.npts * e.d.row_blocks;
             L.ws_off[k] = ws_bytes;
-            ws_bytes += align_up(sizeof(double) * c.n, 256) + 2 * align_up(sizeof(float) * (size_t)c.n * c.n, 256);
+            ws_bytes += align_up(sizeof(double) * c.n, 256);
+            if (c.precision == 1) ws_bytes += 2 * align_up(sizeof(float) * (size_t)c.n * c.n, 256);
         } else {
             e.d.kind = 0;
             e.d.rows = kBatchThreads / nc;
@@ -261,13 +263,13 @@ hipError_t materialize(PlanLayout& L, const chessfad_instance* inst, char* base,
                                                   align_up(sizeof(float) * (size_t)c.n * c.n, 256));
             hipLaunchKernelGGL(fp_offsets_kernel, dim3((c.n + 63) / 64), dim3(64), 0, s, c.n, c.A, c.B, c.alpha, E);
             err = hipGetLastError();
-            if (err == hipSuccess) {
+            if (c.precision == 1 && err == hipSuccess) {
                 const int count = c.n * c.n;
                 hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, c.A, c.B,
                                    A32, B32);
                 err = hipGetLastError();
             }
-            e.d.fp = FpParams{c.A, c.B, E, A32, B32};
+            e.d.fp = c.precision == 1 ? FpParams{c.A, c.B, E, A32, B32} : FpParams{c.A, c.B, E, nullptr, nullptr};
         }
         L.descs[2 * e.prec + e.d.kind].push_back(e.d);
     }
@@ -296,6 +298,31 @@ hipError_t launch_lists(const BatchArgs args[4], const int grid[4], const size_t
 }
 
 hipError_t launch_all(chessfad_batch* b, hipStream_t s) { return launch_lists(b->args, b->grid, b->lds, b->counters, s); }
+
+// ------------------------------------------------ allocation-free batches
+// The device memory of chessfad_batch_run_noalloc: one fixed array per GPU
+// (each device holds its own copy of this module's globals), kept until the
+// process ends.  Host code never passes `scratch` itself to the device: its
+// address on a device comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+constexpr size_t kScratchBytes = CHESSFAD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[64] = {};
+
+hipError_t scratch_base(int device, char** base) {
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<char*>(ptr);
+    }
+    *base = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -342,6 +369,30 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
     }
     *plan = b;
     return CHESSFAD_OK;
+}
+
+int chessfad_batch_run_noalloc(const chessfad_instance* inst, int ninst, void* stream, int* bad_index) {
+    if (bad_index) *bad_index = -1;
+    PlanLayout L;
+    const int rc = plan_instances(inst, ninst, bad_index, L);
+    if (rc) return rc;
+    if (L.total > kScratchBytes) return CHESSFAD_E_ARG;
+    if (L.items == 0) return CHESSFAD_OK;
+    int device = 0;
+    hipError_t err = hipGetDevice(&device);
+    char* base = nullptr;
+    if (err == hipSuccess) err = scratch_base(device, &base);
+    if (err == hipSuccess) err = size_grids(L, device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchArgs args[4];
+    unsigned* counters = nullptr;
+    if (err == hipSuccess) err = materialize(L, inst, base, s, args, counters);
+    if (err == hipSuccess) err = launch_lists(args, L.grid, L.lds, counters, s);
+    // the uploads read L's host arrays, and the next call on this GPU reuses
+    // the array: wait for this call's work
+    const hipError_t serr = hipStreamSynchronize(s);
+    if (err == hipSuccess) err = serr;
+    return err == hipSuccess ? CHESSFAD_OK : hip_fail(err);
 }
 
 int chessfad_batch_run(chessfad_batch* plan, void* stream) {

@@ -234,3 +234,21 @@ def test_autotune_argument_checks(lib):
     assert lib.chessfad_autotune(A, 16, 3, 100, None, None, None) == E_ARG
     assert lib.chessfad_autotune(A, 16, 0, 0, None, None, None) == E_ARG
 
+
+def test_batch_noalloc_checks_before_any_device_work(lib):
+    def run(insts):
+        arr = (binding.Instance * len(insts))(*insts)
+        bad = ctypes.c_int(-7)
+        rc = lib.chessfad_batch_run_noalloc(ctypes.cast(arr, ctypes.c_void_p), len(insts), None, ctypes.byref(bad))
+        return rc, bad.value
+
+    ok = _inst()
+    assert run([ok, _inst(chunk=16)]) == (E_CHUNK, 1)
+    assert run([_inst(func=9), ok]) == (E_FUNC, 0)
+    assert run([_inst(func=FP)]) == (E_PARAMS, 0)
+    assert run([_inst(out=FAKE)]) == (E_OVERLAP, 0)
+    assert lib.chessfad_batch_run_noalloc(None, 2, None, None) == E_ARG
+    # 40 mixed Fletcher-Powell instances at n = 512 keep 80 MiB of float32
+    # copies of A and B: more than the fixed array holds
+    big = _inst(func=FP, n=512, chunk=16, precision=1, A=FAKE * 8, B=FAKE * 16, alpha=FAKE * 32)
+    assert run([big] * 40) == (E_ARG, -1)
