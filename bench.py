@@ -45,47 +45,103 @@ NAMES = {0: "rosenbrock", 1: "ackley", 2: "fletcher_powell"}
 N = 16
 NPTS = 1 << 20
 PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (FMA = 2), vector and MFMA
+PEAK_HBM_TBPS = 8.0      # HBM3E
 VALU_ISSUE_PER_S = 256 * 2.4e9   # vector wave-instructions per second (one per CU-clock)
 METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at stated error"
 
 # ---------------------------------------------------------------- counters
-# Per-launch figures from rocprofv3 --pmc runs of `bench.py --only step`
-# (profiles/hvp_n16_step_counters.md), keyed by kernel.  They hold for the
-# kernel source they were taken on: COUNTER_SOURCE_SHA is source_sha() at that
-# time, and a run whose source differs reports them with "stale": true.
+# Per-launch figures from rocprofv3 --pmc runs of `bench.py --only kernels`
+# (profiles/hvp_n16_step_kernels_counters.md), keyed by kernel.  Each entry
+# holds for the sources it was taken on: "sha" is kernel_sha() of its kernel
+# family then, and a run whose sources differ reports the roofline with
+# "stale": true.
 #   traffic     HBM bytes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, copy-kernel
 #               calibration; each x 1024)
 #   valu_flops  SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes (FMA = 2)
 #   valu_insts  SQ_INSTS_VALU wave-instructions (MFMA included)
 #   mfma_flops  SQ_INSTS_VALU_MFMA_MOPS_F64 x 512
-COUNTER_SOURCE_SHA = None
-COUNTERS = {}
+#   classes     wave-instructions per class: SQ_INSTS_VALU_{ADD,MUL,FMA}_F64,
+#               _INT32, _INT64, _CVT, _TRANS_F64, SQ_INSTS_LDS, SQ_INSTS_SALU
+COUNTERS = {
+    'coarse_kernel<F64, Ackley, 1, 1>': {'traffic': 402801024, 'valu_flops': 6861881344, 'valu_insts': 142606336, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20250624, 'valu_mul_f64': 41025536, 'valu_fma_f64': 22806528, 'valu_int32': 22478848, 'valu_int64': 2818048, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 27983872, 'salu': 55836672}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Ackley, 16, 1>': {'traffic': 402806784, 'valu_flops': 3841982464, 'valu_insts': 86769664, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8454144, 'valu_mul_f64': 13500416, 'valu_fma_f64': 18874368, 'valu_int32': 16711680, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 10682368, 'salu': 47972352}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Ackley, 2, 1>': {'traffic': 402781184, 'valu_flops': 4781506560, 'valu_insts': 106692608, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12124160, 'valu_mul_f64': 20840448, 'valu_fma_f64': 20709376, 'valu_int32': 21954560, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 9895936, 'salu': 61603840}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Ackley, 4, 1>': {'traffic': 402780160, 'valu_flops': 4244635648, 'valu_insts': 99352576, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10027008, 'valu_mul_f64': 16646144, 'valu_fma_f64': 19660800, 'valu_int32': 23003136, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 13041664, 'salu': 58195968}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Ackley, 8, 1>': {'traffic': 402784256, 'valu_flops': 3976200192, 'valu_insts': 90963968, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8978432, 'valu_mul_f64': 14548992, 'valu_fma_f64': 19136512, 'valu_int32': 18808832, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 11468800, 'salu': 51380224}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Rosenbrock, 1, 1>': {'traffic': 402728320, 'valu_flops': 5502926848, 'valu_insts': 131072000, 'mfma_flops': 0, 'classes': {'valu_add_f64': 5242880, 'valu_mul_f64': 38273024, 'valu_fma_f64': 21233664, 'valu_int32': 30146560, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 36700160}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Rosenbrock, 16, 1>': {'traffic': 402723840, 'valu_flops': 486539264, 'valu_insts': 37486592, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1310720, 'valu_mul_f64': 3145728, 'valu_fma_f64': 1572864, 'valu_int32': 15204352, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 29622272}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Rosenbrock, 2, 1>': {'traffic': 402708480, 'valu_flops': 3070230528, 'valu_insts': 90701824, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 26214400, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 40632320}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Rosenbrock, 4, 1>': {'traffic': 402720768, 'valu_flops': 1593835520, 'valu_insts': 60293120, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 19922944, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 34340864}, 'sha': '43d5b9b647d4ce2c'},
+    'coarse_kernel<F64, Rosenbrock, 8, 1>': {'traffic': 402723840, 'valu_flops': 855638016, 'valu_insts': 45088768, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 16777216, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 31195136}, 'sha': '43d5b9b647d4ce2c'},
+    'fp_call_kernel<F64, 8, 1, false, false>': {'traffic': 403010496, 'valu_flops': 12549357568, 'valu_insts': 154337280, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 6815744, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12648448, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 25624576}, 'sha': 'de43c40b8b613429'},
+    'fp_call_kernel<F64, 8, 16, false, false>': {'traffic': 402976384, 'valu_flops': 12297699328, 'valu_insts': 145293312, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12058624, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 19726336}, 'sha': 'de43c40b8b613429'},
+    'fp_call_kernel<F64, 8, 2, false, false>': {'traffic': 402958976, 'valu_flops': 12415139840, 'valu_insts': 149880832, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 4718592, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12517376, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 22478848}, 'sha': 'de43c40b8b613429'},
+    'fp_call_kernel<F64, 8, 4, false, false>': {'traffic': 403012992, 'valu_flops': 12348030976, 'valu_insts': 147259392, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 3670016, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12255232, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20905984}, 'sha': 'de43c40b8b613429'},
+    'fp_call_kernel<F64, 8, 8, false, false>': {'traffic': 402997952, 'valu_flops': 12314476544, 'valu_insts': 145948672, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12124160, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20119552}, 'sha': 'de43c40b8b613429'},
+    'plain_kernel<F64, Ackley, 1, false, false>': {'traffic': 402777088, 'valu_flops': 22347251712, 'valu_insts': 803209216, 'mfma_flops': 0, 'classes': {'valu_add_f64': 55574528, 'valu_mul_f64': 68157440, 'valu_fma_f64': 110100480, 'valu_int32': 266338304, 'valu_int64': 35651584, 'valu_cvt': 39845888, 'valu_trans_f64': 5242880, 'lds': 78643200, 'salu': 653262848}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Ackley, 2, false, false>': {'traffic': 402783232, 'valu_flops': 11844714496, 'valu_insts': 407371776, 'mfma_flops': 0, 'classes': {'valu_add_f64': 25690112, 'valu_mul_f64': 38273024, 'valu_fma_f64': 59244544, 'valu_int32': 128450560, 'valu_int64': 19922944, 'valu_cvt': 19922944, 'valu_trans_f64': 2621440, 'lds': 35127296, 'salu': 330825728}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Ackley, 4, false, false>': {'traffic': 402783232, 'valu_flops': 6794772480, 'valu_insts': 217317376, 'mfma_flops': 0, 'classes': {'valu_add_f64': 13893632, 'valu_mul_f64': 23330816, 'valu_fma_f64': 33816576, 'valu_int32': 66322432, 'valu_int64': 9961472, 'valu_cvt': 9961472, 'valu_trans_f64': 1310720, 'lds': 22806528, 'salu': 169607168}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Ackley, 8, false, false>': {'traffic': 402794496, 'valu_flops': 4815060992, 'valu_insts': 135004160, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10092544, 'valu_mul_f64': 16777216, 'valu_fma_f64': 23855104, 'valu_int32': 36569088, 'valu_int64': 5373952, 'valu_cvt': 5373952, 'valu_trans_f64': 655360, 'lds': 15073280, 'salu': 93061120}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Rosenbrock, 1, false, false>': {'traffic': 402733056, 'valu_flops': 8254390272, 'valu_insts': 589299712, 'mfma_flops': 0, 'classes': {'valu_add_f64': 32505856, 'valu_mul_f64': 46137344, 'valu_fma_f64': 25165824, 'valu_int32': 238026752, 'valu_int64': 19922944, 'valu_cvt': 35651584, 'valu_trans_f64': 0, 'lds': 48234496, 'salu': 466616320}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Rosenbrock, 2, false, false>': {'traffic': 402733056, 'valu_flops': 3992977408, 'valu_insts': 298319872, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12058624, 'valu_mul_f64': 25165824, 'valu_fma_f64': 12582912, 'valu_int32': 124780544, 'valu_int64': 9961472, 'valu_cvt': 17825792, 'valu_trans_f64': 0, 'lds': 19922944, 'salu': 233308160}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Rosenbrock, 4, false, false>': {'traffic': 402733056, 'valu_flops': 1929379840, 'valu_insts': 147062784, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 12582912, 'valu_fma_f64': 6291456, 'valu_int32': 61341696, 'valu_int64': 4980736, 'valu_cvt': 8912896, 'valu_trans_f64': 0, 'lds': 8912896, 'salu': 114556928}, 'sha': '43d5b9b647d4ce2c'},
+    'plain_kernel<F64, Rosenbrock, 8, false, false>': {'traffic': 402732032, 'valu_flops': 956301312, 'valu_insts': 78381056, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2359296, 'valu_mul_f64': 6291456, 'valu_fma_f64': 3145728, 'valu_int32': 33554432, 'valu_int64': 2883584, 'valu_cvt': 4718592, 'valu_trans_f64': 0, 'lds': 4718592, 'salu': 62128128}, 'sha': '43d5b9b647d4ce2c'},
+}
+
+# The sources each kernel family is compiled from (with the build flags and,
+# for the Fletcher-Powell DPP kernels, the generator of their inline-asm blocks).
+KERNEL_SOURCES = {
+    "coarse_kernel": ("hd.hpp", "functions.hpp", "kernel_plain.hpp"),
+    "plain_kernel": ("hd.hpp", "functions.hpp", "kernel_plain.hpp"),
+    "fp_call_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
+    "fp_dpp_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp"),
+    "fp_rows_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_rows.hpp"),
+}
 
 
-def source_sha() -> str:
-    """sha256 over the library's sources and build flags (the kernels the
-    counters describe)."""
+def kernel_sha(key, read=None) -> str:
+    """sha256 (16 hex digits) over the sources and build flags of the kernel
+    family of `key`; `read(relpath)` returns a file's bytes (default: the
+    working tree)."""
+    import inspect
+
+    sys.path.insert(0, ROOT)
+    from paper_2410_22575_amd import build
+
+    read = read or (lambda rel: open(os.path.join(ROOT, rel), "rb").read())
+    family = key.split("<")[0]
     h = hashlib.sha256()
-    paths = [os.path.join(ROOT, "paper_2410_22575_amd", "build.py")]
-    for d in (os.path.join(ROOT, "paper_2410_22575_amd", "csrc"), os.path.join(ROOT, "include")):
-        paths += [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith((".hip", ".hpp", ".h"))]
-    for p in paths:
-        h.update(os.path.relpath(p, ROOT).encode())
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+    h.update(" ".join(build.FLAGS[:-6]).encode())   # the flags, without the include paths
+    if family.startswith("fp_call") or family.startswith("fp_dpp"):
+        h.update(inspect.getsource(build.write_dpp_blocks_inc).encode())
+    for f in KERNEL_SOURCES.get(family, ()):
+        rel = os.path.join("paper_2410_22575_amd", "csrc", f)
+        h.update(rel.encode())
+        h.update(read(rel))
     return h.hexdigest()[:16]
 
 
-def kernel_key(f, c, n=N, mapping=2):
-    """The kernel chessfad_hvp runs for (function, chunk, mapping) at n, as
-    keyed in COUNTERS."""
+def kernel_key(f, c, n=N, mapping=2, mixed=False):
+    """The kernel chessfad_hvp (or _mixed) runs for (function, chunk,
+    mapping) at n, named as the profiler's demangled kernel name with the
+    namespace and argument list removed (the keys of COUNTERS)."""
+    prec = "F32C" if mixed else "F64"
     if f == 2 and n <= 16:
-        return f"fp_call_kernel<NK={min(8, max(1, (2 * n + 3) // 4))}, C={c}, H.v>"
+        return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false>"
     if f == 2:
-        return f"fp_rows_kernel<C={c}, H.v>"
+        return f"fp_rows_kernel<{prec}, {c}, false>"
+    func = {0: "Rosenbrock", 1: "Ackley"}[f]
     if c >= n or mapping == 1:
-        return f"coarse_kernel<{NAMES[f]}, C={c}, L1, H.v>"
-    return f"plain_kernel<{NAMES[f]}, C={c}, H.v>"
+        return f"coarse_kernel<{prec}, {func}, {c}, 1>"
+    return f"plain_kernel<{prec}, {func}, {c}, false, false>"
+
+
+def profiler_key(name):
+    """A rocprofv3 kernel name reduced to the form of kernel_key."""
+    name = name.replace("chessfad::", "").strip()
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0].strip()
 
 
 def fp_value_column_mfma_flops(n, npts):
@@ -108,7 +164,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance workload")
     ap.add_argument("--batch-instances", type=int, default=8192)
     ap.add_argument("--no-large", action="store_true", help="skip the n = 64 and n = 512 workloads")
-    ap.add_argument("--only", choices=("step", "large", "batch", "fp"), default=None,
+    ap.add_argument("--only", choices=("step", "large", "batch", "fp", "kernels"), default=None,
                     help="only run one part and print its JSON (for profiling; not the benchmark line)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
@@ -264,9 +320,18 @@ def large_n(ctx):
         mf = ctx.flops.flops_per_hvp(f, n, c)
         name = f"{NAMES[f]}_n{n}_{'mixed' if prec else 'f64'}"
         res[name] = {"npts": npts, "chunk": c,
-                     "mapping": "MFMA rows" if f == 2 else f"L{b.chessfad_default_mapping(f, n, prec)}",
+                     "mapping": "per-call, DPP lane broadcasts" if f == 2 else f"L{b.chessfad_default_mapping(f, n, prec)}",
                      "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                      "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
+        if f == 2:
+            # the row-block kernel with MFMA contraction tiles, for comparison
+            prev = b.chessfad_set_option(b.CHESSFAD_OPT_FP_MFMA, 2)
+            try:
+                ms2 = ctx.time_ms(lambda: fn(f, x, v, out, chunk=c), reps=3)
+            finally:
+                b.chessfad_set_option(b.CHESSFAD_OPT_FP_MFMA, prev)
+            res[name]["rows_mfma_kernel_ms"] = round(ms2, 4)
+            res[name]["speedup_vs_rows_mfma"] = ms2 / ms
         print(f"  large: {name} C={c} {ms:.3f} ms err {err:.2e}", file=sys.stderr, flush=True)
     for f in FUNCS:
         a, m = res[f"{NAMES[f]}_n64_f64"], res[f"{NAMES[f]}_n64_mixed"]
@@ -502,6 +567,22 @@ def main():
     if args.only == "fp":
         print(json.dumps({"fp_engines": fp_engines(ctx, ws[2], Es[2], xs[2], vs[2])}), flush=True)
         return
+    if args.only == "kernels":
+        # every kernel the step can run at n = 16 (each function, chunk and
+        # vector mapping), one warm-up and one launch each: the rocprofv3
+        # counter runs of COUNTERS use this
+        for f in FUNCS:
+            for c in (1, 2, 4, 8, 16):
+                for level in ((1, 2) if f != 2 else (2,)):
+                    prev = b.chessfad_set_option(b.CHESSFAD_OPT_MAPPING, level)
+                    try:
+                        for _ in range(2):
+                            b.chessfad_hvp(f, xs[f], vs[f], outs[f], chunk=c)
+                    finally:
+                        b.chessfad_set_option(b.CHESSFAD_OPT_MAPPING, prev)
+                torch.cuda.synchronize()
+                print(f"  kernels: {NAMES[f]} C={c} {kernel_key(f, c, mapping=1)}", file=sys.stderr, flush=True)
+        return
 
     # chunk per function: explicit, autotuned (outside the timed region), or default
     chunks, mchunks, schunks, tuned = {}, {}, {}, {}
@@ -550,8 +631,6 @@ def main():
         return
 
     # ---- roofline of the dominant kernel, on the executed-flop basis
-    sha = source_sha()
-    stale = COUNTER_SOURCE_SHA != sha
     per_func = {}
     for f in FUNCS:
         mf = flops.flops_per_hvp(f, N, chunks[f])
@@ -574,22 +653,33 @@ def main():
     t_dom = kernel_ms[dom] * 1e-3
     model_launch = flops.flops_per_hvp(dom, N, chunks[dom]) * npts
     cnt = COUNTERS.get(kname)
+    algo_bytes = 24 * N * npts   # x and v read, H.v written, float64
     if cnt:
-        work = cnt.get("valu_flops", 0.0) + cnt.get("mfma_flops", 0.0)
-        basis = "executed float64 flops (rocprofv3 counters: VALU FLOPS_FP64 x 64" + (
-            " + MFMA MOPS_F64 x 512)" if cnt.get("mfma_flops") else ")")
-        bound = "alu"
+        # executed flops (the lower of the executed and the paper-model count)
+        work = min(cnt.get("valu_flops", 0.0) + cnt.get("mfma_flops", 0.0), model_launch)
+        flop_frac = work / t_dom / 1e12 / PEAK_F64_TFLOPS
+        byte_frac = algo_bytes / t_dom / 1e12 / PEAK_HBM_TBPS
+        stale = cnt.get("sha") != kernel_sha(kname)
+        if byte_frac > flop_frac:
+            roofline = {"bound": "hbm", "achieved": algo_bytes / t_dom / 1e9, "peak": PEAK_HBM_TBPS * 1e3,
+                        "unit": "GB/s", "frac": byte_frac}
+        else:
+            roofline = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": PEAK_F64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flop_frac}
+        roofline.update({
+            "traffic": cnt.get("traffic"), "kernel": kname, "flops_per_launch": work,
+            "flop_basis": "executed float64 flops (rocprofv3: VALU FLOPS_FP64 x 64" + (
+                " + MFMA MOPS_F64 x 512)" if cnt.get("mfma_flops") else ")"),
+            "flop_frac": flop_frac, "bytes_per_launch": algo_bytes, "byte_frac": byte_frac,
+            "valu_issue_frac": per_func[NAMES[dom]]["valu_issue_frac"],
+            "instruction_classes": cnt.get("classes"),
+            "model_flops_per_launch": model_launch, "model_tflops": model_launch / t_dom / 1e12,
+            "counters_sha": cnt.get("sha"), "source_sha": kernel_sha(kname), "stale": stale})
     else:
-        work, basis, bound = model_launch, "paper-model flops (no counters for this kernel)", "alu"
-    if work > model_launch:
-        work, basis = model_launch, "paper-model flops (below the executed count)"
-    achieved = work / t_dom / 1e12
-    roofline = {"bound": bound, "kernel": kname, "achieved": achieved, "peak": PEAK_F64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS,
-                "traffic": (cnt or {}).get("traffic"), "flops_per_launch": work, "basis": basis,
-                "model_flops_per_launch": model_launch, "model_tflops": model_launch / t_dom / 1e12,
-                "valu_issue_frac": per_func[NAMES[dom]]["valu_issue_frac"],
-                "counters_source_sha": COUNTER_SOURCE_SHA, "source_sha": sha, "stale": stale}
+        roofline = {"bound": "alu", "achieved": None, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                    "traffic": None, "kernel": kname, "note": "no counters recorded for this kernel",
+                    "model_flops_per_launch": model_launch, "model_tflops": model_launch / t_dom / 1e12,
+                    "source_sha": kernel_sha(kname), "stale": True}
 
     # ---- comparisons outside the timed region
     fp_eng = fp_engines(ctx, ws[2], Es[2], xs[2], vs[2])

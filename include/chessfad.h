@@ -235,8 +235,19 @@ const char* chessfad_strerror(int code);
  *                         0: every step of f on the vector ALUs.
  *                         All give the same derivative components; only the
  *                         order of the final sum over residuals differs.
- *                         Fletcher-Powell with n > 16 runs its row-block
- *                         kernel for every value but 0.
+ *                         Fletcher-Powell with n > 16: 1 runs the per-call
+ *                         kernel for n > 16 (each lane row of 16 lanes holds
+ *                         16 rows of one point; per call and residual the
+ *                         lanes form their J entries elementwise and the
+ *                         chunk's products read the chunk columns from the
+ *                         other lanes by DPP broadcasts); 2 and 3 run the
+ *                         row-block kernel that contracts the hDual columns
+ *                         as 16 x 16 MFMA tiles; 0 the vector ALUs.
+ *   CHESSFAD_OPT_FP_POINTS  points per workgroup of the per-call kernel for
+ *                         Fletcher-Powell with n > 16: 16, 4 or 1 (16 / value
+ *                         lane rows per point; fewer where a point's four LDS
+ *                         rows of 16 ceil(n / 16) float64 would not fit);
+ *                         0 (default): the most that fit.
  *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
  *                         plan's captured hipGraph; 0: it launches the same
  *                         kernels directly on the stream.
@@ -256,7 +267,12 @@ const char* chessfad_strerror(int code);
  *                         in the last bits).  Other entry points always use
  *                         their own mapping.
  */
-enum chessfad_option { CHESSFAD_OPT_FP_MFMA = 1, CHESSFAD_OPT_BATCH_GRAPH = 2, CHESSFAD_OPT_MAPPING = 3 };
+enum chessfad_option {
+    CHESSFAD_OPT_FP_MFMA = 1,
+    CHESSFAD_OPT_BATCH_GRAPH = 2,
+    CHESSFAD_OPT_MAPPING = 3,
+    CHESSFAD_OPT_FP_POINTS = 4
+};
 int chessfad_set_option(int option, int value);
 
 /*

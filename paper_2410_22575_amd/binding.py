@@ -57,6 +57,7 @@ SIGNATURES = {
 CHESSFAD_OPT_FP_MFMA = 1
 CHESSFAD_OPT_BATCH_GRAPH = 2
 CHESSFAD_OPT_MAPPING = 3
+CHESSFAD_OPT_FP_POINTS = 4
 
 _lib = None
 

@@ -6,6 +6,7 @@
 // Host side only: every argument check happens before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -24,6 +25,7 @@ int g_tuned_map[2][3][CHESSFAD_MAX_N + 1];  // autotuned mapping of H.v per prec
 int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
+int g_opt_fp_points = 0;                 // CHESSFAD_OPT_FP_POINTS
 }  // namespace
 
 namespace chessfad {
@@ -112,6 +114,7 @@ int option_value(int option) {
     if (option == CHESSFAD_OPT_FP_MFMA) return g_opt_fp_mfma;
     if (option == CHESSFAD_OPT_BATCH_GRAPH) return g_opt_batch_graph;
     if (option == CHESSFAD_OPT_MAPPING) return g_opt_mapping;
+    if (option == CHESSFAD_OPT_FP_POINTS) return g_opt_fp_points;
     return CHESSFAD_E_ARG;
 }
 
@@ -286,6 +289,25 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 
 }  // namespace
 
+FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points) {
+    FpDppGeometry g;
+    g.nb = (n + 15) / 16;
+    const int n16 = 16 * g.nb;
+    // points per workgroup: as many as the LDS rows allow, or the option's
+    g.ppw = points ? points : (16 * n16 <= kFpDppMaxStage ? 16 : 4 * n16 <= kFpDppMaxStage ? 4 : 1);
+    while (g.ppw > 1 && g.ppw * n16 > kFpDppMaxStage) g.ppw /= 4;
+    const int rbw = 16 / g.ppw;
+    const int iters = (g.nb + rbw - 1) / rbw;   // row blocks per lane row without a split
+    const int64_t groups = (npts + g.ppw - 1) / g.ppw;
+    // split a point group's row blocks over workgroups until about 2048
+    // workgroups fill the GPU
+    int64_t want = (2048 + groups - 1) / groups;
+    g.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>(iters, want));
+    g.grid = groups * g.rsplit;
+    g.lds = fp_dpp_lds_bytes(g.nb, g.ppw);
+    return g;
+}
+
 int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, const double* v, double* out, int chunk,
                          void* stream, bool hess, bool mixed, bool sym, double* grad, double* fval, int mapping) {
     if (func_id >= CHESSFAD_USER_BASE) {
@@ -371,6 +393,17 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         if (!launch) return CHESSFAD_E_CHUNK;
         SymArgs a{x, v, out, fp, npts, n, g.nc, g.ppb, g.pstride};
         hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kSymThreads), g.lds, s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
+    if (func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma == 1) {
+        // the per-call kernel (DPP lane broadcasts)
+        FpDppLaunch launch = mixed ? fp_dpp_entry_mixed(chunk, hess)
+                                   : (grad || fval) ? fp_dpp_entry_grad(chunk) : fp_dpp_entry(chunk, hess);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        const FpDppGeometry g = fp_dpp_geometry(n, npts, g_opt_fp_points);
+        if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, g.rsplit, grad, fval};
+        hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kFpDppThreads), g.lds, s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
     if (func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma) {
@@ -514,9 +547,15 @@ const char* chessfad_strerror(int code) {
 int chessfad_set_option(int option, int value) {
     int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
               : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
-              : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping : nullptr;
-    const int maxv = option == CHESSFAD_OPT_FP_MFMA ? 3 : option == CHESSFAD_OPT_MAPPING ? 2 : 1;
-    if (!slot || value < 0 || value > maxv) return CHESSFAD_E_ARG;
+              : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping
+              : option == CHESSFAD_OPT_FP_POINTS ? &g_opt_fp_points : nullptr;
+    if (!slot) return CHESSFAD_E_ARG;
+    if (option == CHESSFAD_OPT_FP_POINTS) {
+        if (value != 0 && value != 1 && value != 4 && value != 16) return CHESSFAD_E_ARG;
+    } else {
+        const int maxv = option == CHESSFAD_OPT_FP_MFMA ? 3 : option == CHESSFAD_OPT_MAPPING ? 2 : 1;
+        if (value < 0 || value > maxv) return CHESSFAD_E_ARG;
+    }
     const int prev = *slot;
     *slot = value;
     return prev;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernel_fp_call.hpp"
+#include "kernel_fp_dpp.hpp"
 #include "kernel_fp_mfma.hpp"
 #include "kernel_fp_tile.hpp"
 #include "kernel_fp_rows.hpp"
@@ -155,6 +156,33 @@ FpMfmaLaunch fp_call_by_steps(int C, int nk) {
 FpMfmaLaunch fp_call_entry(int C, int nk, bool hess);
 FpMfmaLaunch fp_call_entry_grad(int C, int nk);
 FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess);
+
+using FpDppLaunch = hipError_t (*)(const FpDppArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
+
+template <class P, int C, bool kHess, bool kGrad>
+hipError_t launch_fp_dpp(const FpDppArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((fp_dpp_kernel<P, C, kHess, kGrad>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <class P, bool kHess, bool kGrad>
+FpDppLaunch fp_dpp_entry_c(int C) {
+    switch (C) {
+        case 1: return &launch_fp_dpp<P, 1, kHess, kGrad>;
+        case 2: return &launch_fp_dpp<P, 2, kHess, kGrad>;
+        case 4: return &launch_fp_dpp<P, 4, kHess, kGrad>;
+        case 8: return &launch_fp_dpp<P, 8, kHess, kGrad>;
+        case 16: return &launch_fp_dpp<P, 16, kHess, kGrad>;
+        default: return nullptr;
+    }
+}
+
+// The per-call Fletcher-Powell kernel for n > 16 (DPP lane broadcasts):
+// float64 H.v / Hessian, float64 H.v with the gradient and f, mixed
+// precision (one translation unit each).
+FpDppLaunch fp_dpp_entry(int C, bool hess);
+FpDppLaunch fp_dpp_entry_grad(int C);
+FpDppLaunch fp_dpp_entry_mixed(int C, bool hess);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 

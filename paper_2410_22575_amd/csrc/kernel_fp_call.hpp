@@ -52,6 +52,10 @@ struct DppChunkProducts;
 // dot += v (lane cs + l) * h[l], l = 0 .. C - 1 in order
 template <int C, int CS>
 struct DppChunkDot;
+// acc[l] += g[u] (lane cs + l of this lane's 16-lane row) * d[u] (own lane),
+// u = 0 .. 3 in order, l = 0 .. C - 1
+template <typename T, int C, int CS>
+struct DppRowProducts;
 
 #include "dpp_blocks.inc"
 

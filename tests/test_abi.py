@@ -166,6 +166,10 @@ def test_options(lib):
     prev = lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, 0)
     assert prev == 2
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_MAPPING, prev) == 0
+    for bad in (-1, 2, 3, 5, 17):
+        assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, bad) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 4) == 0   # the default is 0 (automatic)
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 0) == 4
 
 
 def test_default_chunk(lib):
@@ -233,6 +237,7 @@ def test_autotune_argument_checks(lib):
     assert lib.chessfad_autotune(R, 1, 0, 100, None, None, None) == E_N
     assert lib.chessfad_autotune(A, 16, 3, 100, None, None, None) == E_ARG
     assert lib.chessfad_autotune(A, 16, 0, 0, None, None, None) == E_ARG
+
 
 
 def test_batch_noalloc_checks_before_any_device_work(lib):

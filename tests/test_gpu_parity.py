@@ -220,11 +220,13 @@ def test_fp_mfma_matches_vector_path(gpu_lib, engine):
         assert e.max().item() <= 1e-14
 
 
+@pytest.mark.parametrize("engine", [1, 2])
 @pytest.mark.parametrize("n", [17, 24, 40, 64, 130, 200])
-def test_fp_general_n_mfma(gpu_lib, n):
-    """n > 16: the Fletcher-Powell MFMA kernel (row blocks of a point, shared
-    g columns per m tile, several variable blocks once n > 128), against the
-    oracle and the vector path, every chunk size, H.v and Hessian."""
+def test_fp_general_n(gpu_lib, engine, n):
+    """n > 16: the per-call kernel with DPP lane broadcasts (engine 1) and the
+    row-block MFMA kernel (engine 2: shared g columns per m tile, several
+    variable blocks once n > 128), against the oracle and the vector path,
+    every chunk size, H.v and Hessian."""
     npts = 9 if n <= 64 else 3
     w = inputs.make_workload(FP, n, npts, inputs.rng_for(8000 + n))
     E = _setup(gpu_lib, w)
@@ -232,8 +234,8 @@ def test_fp_general_n_mfma(gpu_lib, n):
     H_ref, hmax = _hmax(FP, w, E)
     r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
     for c in CHUNKS:
-        print(f"[case] fp rows n={n} chunk={c}", flush=True)
-        with fp_path(gpu_lib, 1):
+        print(f"[case] fp n={n} engine={engine} chunk={c}", flush=True)
+        with fp_path(gpu_lib, engine):
             r = gpu_lib.chessfad_hvp(FP, x, v, chunk=c).cpu().numpy()
             H = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
         assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
@@ -300,3 +302,35 @@ def test_hvp_with_gradient_and_value(gpu_lib, func, mfma, n):
             _, g2, f2 = gpu_lib.chessfad_hvp_grad(func, x, v, chunk=c, want_f=False)
             assert f2 is None
             np.testing.assert_array_equal(g2.cpu().numpy(), g)
+
+
+@pytest.mark.parametrize("points", [16, 4, 1])
+@pytest.mark.parametrize("n,npts", [(17, 37), (33, 5), (100, 18), (257, 2)])
+def test_fp_per_call_points_per_workgroup(gpu_lib, points, n, npts):
+    """The per-call Fletcher-Powell kernel for n > 16 at each points-per-
+    workgroup setting (16, 4 or 1 points, each on 16 / points lane rows; the
+    kernel takes fewer where the LDS rows do not fit), with ragged variable
+    blocks, point groups and row-block splits: H.v, Hessian and the gradient
+    against the oracle."""
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(8600 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref, hmax = _hmax(FP, w, E)
+    r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
+    g_ref = cf.grad(FP, w.x, w.A, w.B, E)
+    f_ref = cf.f(FP, w.x, w.A, w.B, E)
+    prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_POINTS, points)
+    try:
+        for c in (4, 16):
+            print(f"[case] fp per-call n={n} npts={npts} points={points} chunk={c}", flush=True)
+            r = gpu_lib.chessfad_hvp(FP, x, v, chunk=c).cpu().numpy()
+            H = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
+            assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
+            assert np.max(np.abs(H - H_ref).max(axis=(1, 2)) / hmax) <= TOL64
+            r2, g, f = gpu_lib.chessfad_hvp_grad(FP, x, v, chunk=c)
+            assert np.max(_hvp_err(r2.cpu().numpy(), r_ref, hmax, w.v)) <= TOL64
+            gs = np.abs(g_ref).max(axis=1, keepdims=True) + 1e-300
+            assert np.max(np.abs(g.cpu().numpy() - g_ref) / gs) <= TOL64
+            assert np.max(np.abs(f.cpu().numpy() - f_ref) / (np.abs(f_ref) + 1e-300)) <= 1e-11
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_POINTS, prev)
