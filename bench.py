@@ -370,11 +370,14 @@ def symmetric_large_n(ctx):
 def batched(ctx, ninst):
     """Mixed-function batch: `ninst` single-point instances, function uniform
     over the three, n log-uniform in [8, 256], each Fletcher-Powell instance
-    with its own parameters.  One replay of the plan's hipGraph, mixed and
-    float64; the float64 baseline as plain launches grouped per (function,
-    n) - Rosenbrock and Ackley instances of one n as one launch over their
-    points, each Fletcher-Powell instance (its own parameters) as its own
-    launch - kernel time only, summed."""
+    with its own parameters.  Plans are tuned at creation (chunk and mapping,
+    or points per workgroup, per function, octave of n and precision, timed
+    on the instances themselves); one replay of the plan's hipGraph is
+    timed for float64 and mixed hDuals, each with float64 and with float32
+    I/O.  The float64 baseline: plain launches grouped per (function, n) -
+    Rosenbrock and Ackley instances of one n as one launch over their points,
+    each Fletcher-Powell instance (its own parameters) as its own launch -
+    kernel time only, summed."""
     b, torch = ctx.binding, ctx.torch
     ws = ctx.inputs.mixed_instances(ninst, ctx.inputs.rng_for(4), 8, 256, npts=1)
     insts = []
@@ -386,20 +389,30 @@ def batched(ctx, ninst):
         insts.append(d)
     torch.cuda.synchronize()
     res = {"workload": f"{ninst} single-point instances, function uniform over Rosenbrock/Ackley/Fletcher-Powell, "
-                       "n log-uniform in [8, 256], own Fletcher-Powell parameters each; chunk per (function, n) "
-                       "from the autotuned table or the default"}
+                       "n log-uniform in [8, 256], own Fletcher-Powell parameters each; body configuration tuned "
+                       "per (function, octave of n, precision) at plan time"}
     outs = {}
-    for prec, name in ((1, "mixed_f32"), (0, "f64")):
-        for d in insts:
-            d["precision"] = prec
-        plan = b.chessfad_batch_create(insts)
-        ms = ctx.time_ms(plan.run)
-        info = plan.info()
-        res[name] = {"graph_ms": round(ms, 4), "hvps_per_s": ninst / (ms * 1e-3),
-                     "model_tflops": info["model_flops"] / (ms * 1e-3) / 1e12,
-                     "items": info["items"], "workgroups": info["workgroups"]}
-        outs[name] = [d["out"].clone() for d in insts]
-        plan.destroy()
+    for io32 in (0, 1):
+        for prec, pname in ((1, "mixed_f32"), (0, "f64")):
+            run = []
+            for d in insts:
+                e = dict(d, precision=prec)
+                if io32:
+                    e["x"], e["v"] = d["x"].float(), d["v"].float()
+                    e["out"] = torch.empty(d["out"].shape, dtype=torch.float32, device=ctx.dev)
+                run.append(e)
+            t0 = time.perf_counter()
+            plan = b.chessfad_batch_create(run)
+            plan_s = time.perf_counter() - t0
+            ms = ctx.time_ms(plan.run)
+            info = plan.info()
+            name = pname + ("_io32" if io32 else "")
+            res[name] = {"graph_ms": round(ms, 4), "hvps_per_s": ninst / (ms * 1e-3),
+                         "model_tflops": info["model_flops"] / (ms * 1e-3) / 1e12,
+                         "items": info["items"], "workgroups": info["workgroups"], "plan_seconds": round(plan_s, 3),
+                         "tuned": plan.choices()}
+            outs[name] = [e["out"].double().clone() for e in run]
+            plan.destroy()
     # the grouped float64 baseline
     groups = {}
     for k, w in enumerate(ws):
@@ -422,15 +435,19 @@ def batched(ctx, ninst):
         launches += 1
     res["grouped_f64_launches"] = launches
     res["grouped_f64_kernel_ms_sum"] = round(total, 3)
-    res["speedup_mixed_batched_vs_grouped_f64"] = total / res["mixed_f32"]["graph_ms"]
-    res["speedup_f64_batched_vs_grouped_f64"] = total / res["f64"]["graph_ms"]
+    for name in ("mixed_f32", "f64", "mixed_f32_io32", "f64_io32"):
+        res[name]["speedup_vs_grouped_f64"] = total / res[name]["graph_ms"]
     res["speedup_mixed_batched_vs_f64_batched"] = res["f64"]["graph_ms"] / res["mixed_f32"]["graph_ms"]
     idx = np.random.default_rng(11).choice(ninst, min(64, ninst), replace=False)
-    for name in ("mixed_f32", "f64"):
+    for name in outs:
         worst = 0.0
         for k in idx:
             w = ws[k]
             E = ctx.cf.fp_offsets(w.A, w.B, w.alpha) if w.func == 2 else None
+            if name.endswith("_io32"):
+                # the oracle at the float32 inputs
+                w = ctx.inputs.Workload(**{**w.__dict__, "x": w.x.astype(np.float32).astype(np.float64),
+                                           "v": w.v.astype(np.float32).astype(np.float64)})
             worst = max(worst, ctx.hvp_err(w, E, outs[name][k], np.arange(w.npts)))
         res[name]["max_rel_err_sampled"] = worst
     return res

@@ -244,10 +244,15 @@ const char* chessfad_strerror(int code);
  *                         row-block kernel that contracts the hDual columns
  *                         as 16 x 16 MFMA tiles; 0 the vector ALUs.
  *   CHESSFAD_OPT_FP_POINTS  points per workgroup of the per-call kernel for
- *                         Fletcher-Powell with n > 16: 16, 4 or 1 (16 / value
- *                         lane rows per point; fewer where a point's four LDS
- *                         rows of 16 ceil(n / 16) float64 would not fit);
- *                         0 (default): the most that fit.
+ *                         Fletcher-Powell with n > 16: 16, 4 or 1, at most
+ *                         16 / ceil(n / 16) (each point's rows then take
+ *                         fewer row blocks per round); 0 (default): as many
+ *                         as fill the workgroup's 16 lane rows with whole
+ *                         rounds of row and column blocks.
+ *   CHESSFAD_OPT_BATCH_TUNE  1 (default): chessfad_batch_create tunes the
+ *                         body configuration of the instances with chunk 0
+ *                         on the instances themselves (see below); 0: they
+ *                         take the defaults.
  *   CHESSFAD_OPT_BATCH_GRAPH  1 (default): chessfad_batch_run replays the
  *                         plan's captured hipGraph; 0: it launches the same
  *                         kernels directly on the stream.
@@ -271,7 +276,8 @@ enum chessfad_option {
     CHESSFAD_OPT_FP_MFMA = 1,
     CHESSFAD_OPT_BATCH_GRAPH = 2,
     CHESSFAD_OPT_MAPPING = 3,
-    CHESSFAD_OPT_FP_POINTS = 4
+    CHESSFAD_OPT_FP_POINTS = 4,
+    CHESSFAD_OPT_BATCH_TUNE = 5
 };
 int chessfad_set_option(int option, int value);
 
@@ -280,44 +286,69 @@ int chessfad_set_option(int option, int value);
  * persistent launch.
  *
  * An instance is one function with its own n, points, vectors, output,
- * chunk, precision and (Fletcher-Powell) parameters.  chessfad_batch_create
- * validates every instance (on failure *bad_index names it), prepares the
- * Fletcher-Powell offsets and float32 copies, and splits every instance
- * into work items of the single-instance kernels' workgroup bodies
- * (Rosenbrock and Ackley: row blocks of the vector-ALU hDual evaluation;
- * Fletcher-Powell: row blocks of the MFMA kernel that shares each S
- * column's contraction across the calls of its rows).  The items are sorted by their operation-count cost, largest
- * first, and a persistent kernel per (precision, body kind) - sized to fill
- * the GPU - takes them from an atomic counter until none is left.  The plan captures
+ * chunk, precision, input/output type and (Fletcher-Powell) parameters.
+ * chessfad_batch_create validates every instance (on failure *bad_index
+ * names it), prepares the Fletcher-Powell offsets and float32 copies, and
+ * splits every instance into work items of the single-instance kernels'
+ * workgroup bodies (Rosenbrock and Ackley: the vector-ALU hDual evaluation
+ * in the L1 mapping, one lane per (point, row), or the L2 mapping, one lane
+ * per (point, row, chunk); Fletcher-Powell: the per-call kernel with DPP
+ * lane broadcasts, one item per point group and share of its row blocks).
+ * The items are sorted by their operation-count cost, largest first, and a
+ * persistent kernel per (precision, body kind) - sized to fill the GPU -
+ * takes them from an atomic counter until none is left.  The plan captures
  * a counter reset kernel and the persistent kernels in one hipGraph;
  * chessfad_batch_run replays it on `stream` (asynchronous; replays on one
  * stream are ordered, replays of one plan on different streams race on its
  * counters).
  *
- * chunk == 0 takes the autotuned chunk for (func_id, n, precision) if
- * chessfad_autotune has recorded one, else the default; batched plans are
- * compiled for chunks 1, 2, 4 and 8 (Fletcher-Powell also 16, its default
- * above 16 variables).  Rosenbrock and Ackley need
- * ceil(n / chunk) <= 256.  All arrays are device pointers that must stay
- * valid while the plan is used; outputs must not overlap their inputs.
+ * chunk == 0 leaves the body configuration to the library.  With
+ * CHESSFAD_OPT_BATCH_TUNE set (the default), chessfad_batch_create groups
+ * those instances by (function, octave of n, precision) and times every
+ * candidate configuration on each group's own instances - Rosenbrock and
+ * Ackley: each compiled chunk up to the group's smallest n in the L1
+ * mapping, and up to 8 in the L2 mapping; Fletcher-Powell: 16, 4 or 1
+ * points per workgroup - keeping the fastest (the tuning runs write the
+ * instances' outputs; chessfad_batch_choices lists the choices).  Otherwise
+ * they take the autotuned chunk for (func_id, n, precision) if
+ * chessfad_autotune has recorded one, else the default.  A given chunk must
+ * be compiled (1, 2, 4, 8, 16) and at most n; Rosenbrock and Ackley run
+ * chunks above 8, and rows of a single chunk, in the L1 mapping.
+ * All arrays are device pointers that must stay valid while the plan is
+ * used; outputs must not overlap their inputs.  With io_fp32 = 1, x, v and
+ * out are float32 (the parameters A, B, alpha stay float64): the inputs are
+ * widened on load and the float64 results rounded on store.
  * The plan owns its device memory (descriptors, work list, counters,
  * Fletcher-Powell offsets and float32 copies); chessfad_batch_destroy frees it.
  * Results are the same as chessfad_hvp / chessfad_hvp_mixed on each instance
- * up to the order of the sum over residuals (Fletcher-Powell, n <= 16).
+ * in the same body configuration, up to the order of the sum over residuals
+ * (Fletcher-Powell) and multiply-add contraction.
  */
 typedef struct chessfad_instance {
     int func_id;          /* chessfad_func */
     int n;                /* variables, 1..CHESSFAD_MAX_N */
-    int chunk;            /* 0, 1, 2, 4 or 8; Fletcher-Powell also 16 */
+    int chunk;            /* 0 or a compiled chunk <= n */
     int precision;        /* 0: float64 hDuals; 1: mixed, as chessfad_hvp_mixed */
+    int io_fp32;          /* 0: x, v, out are float64; 1: float32 */
     int64_t npts;         /* points of this instance, >= 0 */
-    const double* x;      /* [npts][n] */
-    const double* v;      /* [npts][n] */
-    double* out;          /* [npts][n] */
+    const void* x;        /* [npts][n] */
+    const void* v;        /* [npts][n] */
+    void* out;            /* [npts][n] */
     const double* A;      /* Fletcher-Powell only: [n][n] */
     const double* B;      /* Fletcher-Powell only: [n][n] */
     const double* alpha;  /* Fletcher-Powell only: [n] */
 } chessfad_instance;
+
+/* One plan-time tuning decision: the instances of func_id with n in
+ * [n_lo, n_hi] (one octave) at `precision` run `chunk` with `mapping`
+ * (Rosenbrock, Ackley: 1 = L1, 2 = L2) or `points` per workgroup
+ * (Fletcher-Powell; 0 = the default); ms is its time on those instances,
+ * `candidates` the number of configurations timed. */
+typedef struct chessfad_batch_choice {
+    int func_id, n_lo, n_hi, precision, instances;
+    int chunk, mapping, points, candidates;
+    float ms;
+} chessfad_batch_choice;
 
 typedef struct chessfad_batch chessfad_batch;
 
@@ -327,13 +358,16 @@ int chessfad_batch_run(chessfad_batch* plan, void* stream);
 int chessfad_batch_destroy(chessfad_batch* plan);
 /* Work items, persistent workgroups launched, and paper-model flops of one run. */
 int chessfad_batch_info(const chessfad_batch* plan, int64_t* items, int* workgroups, double* model_flops);
+/* The plan-time tuner's choices: up to `cap` into out[], their number in *count. */
+int chessfad_batch_choices(const chessfad_batch* plan, chessfad_batch_choice* out, int cap, int* count);
 
 /*
  * Allocation-free batched H.v, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Validates and plans the instances exactly as
- * chessfad_batch_create does (same work items, same kernels, so the same
- * results as a plan of the same instances), but places the plan - its
+ * chessfad_batch_create does with CHESSFAD_OPT_BATCH_TUNE = 0 (same work
+ * items, same kernels, so the same results as such a plan of the same
+ * instances; it does not tune), but places the plan - its
  * descriptors, work lists, counters and Fletcher-Powell offsets and float32
  * copies - in a fixed library-owned device array of
  * CHESSFAD_NOALLOC_SCRATCH_BYTES bytes instead of allocating, launches the

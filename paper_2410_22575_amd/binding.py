@@ -25,9 +25,17 @@ _pi, _pi64, _pd, _pf, _pp = (ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes
 class Instance(ctypes.Structure):
     """struct chessfad_instance"""
     _fields_ = [("func_id", ctypes.c_int), ("n", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("precision", ctypes.c_int), ("npts", ctypes.c_int64), ("x", ctypes.c_void_p),
-                ("v", ctypes.c_void_p), ("out", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("precision", ctypes.c_int), ("io_fp32", ctypes.c_int), ("npts", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("out", ctypes.c_void_p), ("A", ctypes.c_void_p),
                 ("B", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
+
+class BatchChoice(ctypes.Structure):
+    """struct chessfad_batch_choice"""
+    _fields_ = [("func_id", ctypes.c_int), ("n_lo", ctypes.c_int), ("n_hi", ctypes.c_int),
+                ("precision", ctypes.c_int), ("instances", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("mapping", ctypes.c_int), ("points", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("ms", ctypes.c_float)]
 
 SIGNATURES = {
     "chessfad_hvp": (_i, [_i, _i, _i64, _p, _p, _p, _i, _p]),
@@ -47,6 +55,7 @@ SIGNATURES = {
     "chessfad_batch_destroy": (_i, [_p]),
     "chessfad_batch_info": (_i, [_p, _pi64, _pi, _pd]),
     "chessfad_batch_run_noalloc": (_i, [_p, _i, _p, _pi]),
+    "chessfad_batch_choices": (_i, [_p, _p, _i, _pi]),
     "chessfad_autotune": (_i, [_i, _i, _i, _i64, _p, _pi, _pf]),
     "chessfad_hvp_sym": (_i, [_i, _i, _i64, _p, _p, _p, _i, _i, _p]),
     "chessfad_hvp_grad": (_i, [_i, _i, _i64, _p, _p, _p, _p, _p, _i, _p]),
@@ -58,6 +67,7 @@ CHESSFAD_OPT_FP_MFMA = 1
 CHESSFAD_OPT_BATCH_GRAPH = 2
 CHESSFAD_OPT_MAPPING = 3
 CHESSFAD_OPT_FP_POINTS = 4
+CHESSFAD_OPT_BATCH_TUNE = 5
 
 _lib = None
 
@@ -248,6 +258,16 @@ class BatchPlan:
                "chessfad_batch_info")
         return {"items": items.value, "workgroups": wg.value, "model_flops": fl.value}
 
+    def choices(self):
+        """The plan-time tuner's choices, one dict per (function, octave of n,
+        precision) group."""
+        count = ctypes.c_int()
+        _raise(load().chessfad_batch_choices(self._h, None, 0, ctypes.byref(count)), "chessfad_batch_choices")
+        arr = (BatchChoice * max(1, count.value))()
+        _raise(load().chessfad_batch_choices(self._h, ctypes.cast(arr, ctypes.c_void_p), count.value,
+                                             ctypes.byref(count)), "chessfad_batch_choices")
+        return [{f: getattr(arr[k], f) for f, _ in BatchChoice._fields_} for k in range(count.value)]
+
     def destroy(self):
         if self._h:
             load().chessfad_batch_destroy(self._h)
@@ -266,23 +286,29 @@ def _instances(instances):
     keep = []
     for k, d in enumerate(instances):
         x, v, out = d["x"], d["v"], d["out"]
-        _check_pts("x", x)
+        # x, v, out: all float64, or all float32 (the instance's io_fp32)
+        io32 = x.dtype == torch.float32
+        dt = torch.float32 if io32 else torch.float64
+        for name, t in (("x", x), ("v", v), ("out", out)):
+            if not (t.is_cuda and t.dtype == dt and t.dim() == 2 and t.is_contiguous()):
+                raise ValueError(f"instance {k}: {name} must be a contiguous [npts, n] {dt} CUDA tensor")
         npts, n = x.shape
-        _check_pts("v", v, n)
-        _check_pts("out", out, n)
+        if v.shape != x.shape or out.shape != x.shape:
+            raise ValueError(f"instance {k}: x, v and out must have the same shape")
         A, B, alpha = d.get("A"), d.get("B"), d.get("alpha")
         for name, t in (("A", A), ("B", B), ("alpha", alpha)):
             if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
                 raise ValueError(f"instance {k}: {name} must be a contiguous float64 CUDA tensor")
-        arr[k] = Instance(d["func_id"], n, d.get("chunk", 0), d.get("precision", 0), npts, _ptr(x), _ptr(v),
-                          _ptr(out), _ptr(A), _ptr(B), _ptr(alpha))
+        arr[k] = Instance(d["func_id"], n, d.get("chunk", 0), d.get("precision", 0), int(io32), npts, _ptr(x),
+                          _ptr(v), _ptr(out), _ptr(A), _ptr(B), _ptr(alpha))
         keep += [t for t in (x, v, out, A, B, alpha) if t is not None]
     return arr, keep
 
 
 def chessfad_batch_create(instances, stream=None) -> BatchPlan:
-    """instances: list of dicts with func_id, x, v, out (float64 CUDA tensors
-    [npts, n]), optional chunk (0), precision (0 or 1) and, for
+    """instances: list of dicts with func_id, x, v, out (CUDA tensors
+    [npts, n], all float64 or all float32), optional chunk (0), precision
+    (0 or 1) and, for
     Fletcher-Powell, A, B, alpha (float64 CUDA tensors)."""
     arr, keep = _instances(instances)
     h = ctypes.c_void_p()

@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "batch.hpp"
@@ -26,19 +28,19 @@ struct chessfad_batch {
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<chessfad_batch_choice> choices;   // the plan-time tuner's choices
 };
 
 namespace {
 
-constexpr int kBatchChunks[] = {1, 2, 4, 8};
-
-bool batch_chunk(int c) {
-    for (int k : kBatchChunks)
-        if (k == c) return true;
-    return false;
-}
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// An instance's body configuration: chunk, mapping of the vector bodies (1 =
+// L1, 2 = L2) and points per workgroup of the Fletcher-Powell body; 0 =
+// the default.
+struct InstCfg {
+    int C = 0, mapping = 0, points = 0;
+};
 
 struct PlanEntry {
     BatchDesc d;
@@ -46,13 +48,13 @@ struct PlanEntry {
     int prec;
     int64_t blocks;
     double cost_per_block;  // paper-model flops of a full block
-    int64_t calls_per_point;
+    size_t lds;             // LDS bytes of its body
 };
 
 template <class P>
-size_t plain_lds_for(const BatchDesc& d) {
-    return d.func == CHESSFAD_ROSENBROCK ? plain_lds_bytes<P, Rosenbrock>(d.n, d.pstride, d.rows * d.nc, false)
-                                         : plain_lds_bytes<P, Ackley>(d.n, d.pstride, d.rows * d.nc, false);
+size_t vector_lds(int func, int n, int pstride, int block) {
+    return func == CHESSFAD_ROSENBROCK ? plain_lds_bytes<P, Rosenbrock>(n, pstride, block, false)
+                                       : plain_lds_bytes<P, Ackley>(n, pstride, block, false);
 }
 
 using BatchKernel = void (*)(BatchArgs);
@@ -110,8 +112,11 @@ struct PlanLayout {
 };
 
 // Validates the instances and builds the work lists (host only; nothing is
-// enqueued).  On failure *bad_index names the instance.
-int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, PlanLayout& L) {
+// enqueued).  cfg (optional, one per instance) overrides the chunk, mapping
+// and points per workgroup of instances.  On failure *bad_index names the
+// instance.
+int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, PlanLayout& L,
+                   const InstCfg* cfg = nullptr) {
     if (bad_index) *bad_index = -1;
     if ((ninst > 0 && !inst) || ninst < 0) return CHESSFAD_E_ARG;
     L.entries.reserve(ninst);
@@ -126,18 +131,25 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
         int rc = check_func_n(c.func_id, c.n);
         if (rc) return bad(rc);
         if (c.precision != 0 && c.precision != 1) return bad(CHESSFAD_E_ARG);
+        if (c.io_fp32 != 0 && c.io_fp32 != 1) return bad(CHESSFAD_E_ARG);
         if (c.npts < 0) return bad(CHESSFAD_E_ARG);
-        // Fletcher-Powell bodies take every compiled chunk, the vector bodies
-        // up to 8 (their persistent kernel's registers are the maximum over them)
         const bool fp = c.func_id == CHESSFAD_FLETCHER_POWELL;
-        int C = c.chunk ? c.chunk : resolve_chunk(c.func_id, c.n, c.precision, fp ? 16 : 8);
-        if (!(fp ? chunk_compiled(C) : batch_chunk(C)) || C > c.n) return bad(CHESSFAD_E_CHUNK);
+        const InstCfg o = cfg ? cfg[k] : InstCfg{};
+        const int C = o.C ? o.C : c.chunk ? c.chunk : resolve_chunk(c.func_id, c.n, c.precision, 16);
+        if (C < 0 || !chunk_compiled(C) || C > c.n) return bad(CHESSFAD_E_CHUNK);
         const int nc = (c.n + C - 1) / C;
-        if (!fp && nc > kBatchThreads) return bad(CHESSFAD_E_CHUNK);
+        // vector bodies: L1 for one chunk per row or C = 16 (L2 is compiled
+        // for chunks up to 8), else the given or tuned mapping
+        int mapping = 0;
+        if (!fp) {
+            mapping = o.mapping ? o.mapping : (nc == 1 || C > 8) ? 1 : tuned_mapping(c.func_id, c.n, c.precision);
+            if (mapping != 1 && mapping != 2) return bad(CHESSFAD_E_ARG);
+            if (mapping == 2 && (C > 8 || nc > kBatchThreads)) return bad(CHESSFAD_E_CHUNK);
+        }
         if (c.npts == 0) continue;
         if (!c.x || !c.v || !c.out) return bad(CHESSFAD_E_NULL);
         if (fp && (!c.A || !c.B || !c.alpha)) return bad(CHESSFAD_E_PARAMS);
-        const size_t bytes = sizeof(double) * (size_t)c.npts * c.n;
+        const size_t bytes = (c.io_fp32 ? sizeof(float) : sizeof(double)) * (size_t)c.npts * c.n;
         if (overlaps(c.out, bytes, c.x, bytes) || overlaps(c.out, bytes, c.v, bytes)) return bad(CHESSFAD_E_OVERLAP);
 
         PlanEntry e{};
@@ -147,30 +159,39 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
         e.d.C = C;
         e.d.n = c.n;
         e.d.nc = nc;
+        e.d.io32 = c.io_fp32;
         e.d.npts = c.npts;
-        e.d.x = c.x;
-        e.d.v = c.v;
-        e.d.out = c.out;
+        e.d.x = static_cast<const double*>(c.x);
+        e.d.v = static_cast<const double*>(c.v);
+        e.d.out = static_cast<double*>(c.out);
         e.d.fp = FpParams{c.A, c.B, nullptr, nullptr, nullptr};
-        e.calls_per_point = (int64_t)c.n * nc;
+        const double per_call = model_flops_per_call(c.func_id, c.n, C);
         if (fp) {
+            const FpDppGeometry g = fp_dpp_geometry(c.n, c.npts, o.points, c.precision == 1);
             e.d.kind = 1;
-            e.d.rows = fp_rows_per_block(c.n, C);
-            e.d.row_blocks = (c.n + e.d.rows - 1) / e.d.rows;
-            e.d.pstride = 0;
-            e.blocks = c.npts * e.d.row_blocks;
+            e.d.nb = g.nb;
+            e.d.ppw = g.ppw;
+            e.d.rb = g.rb;
+            e.d.kbg = g.kbg;
+            e.d.rsplit = g.rsplit;
+            e.blocks = g.grid;
+            e.lds = g.lds;
+            e.cost_per_block = per_call * (double)c.n * nc * g.ppw / g.rsplit;
             L.ws_off[k] = ws_bytes;
             ws_bytes += align_up(sizeof(double) * c.n, 256);
             if (c.precision == 1) ws_bytes += 2 * align_up(sizeof(float) * (size_t)c.n * c.n, 256);
         } else {
             e.d.kind = 0;
-            e.d.rows = kBatchThreads / nc;
+            e.d.mapping = mapping;
+            e.d.rows = mapping == 1 ? kBatchThreads : kBatchThreads / nc;
             e.d.pstride = (e.d.rows - 1) / c.n + 2;
-            e.d.row_blocks = 0;
             e.blocks = (c.npts * c.n + e.d.rows - 1) / e.d.rows;
+            const int block = mapping == 1 ? 0 : e.d.rows * nc;
+            e.lds = c.precision ? vector_lds<F32C>(c.func_id, c.n, e.d.pstride, block)
+                                : vector_lds<F64>(c.func_id, c.n, e.d.pstride, block);
+            e.cost_per_block = per_call * e.d.rows * nc;
         }
         if (e.blocks > 0x7fffffffLL) return bad(CHESSFAD_E_ARG);
-        e.cost_per_block = model_flops_per_call(c.func_id, c.n, C) * e.d.rows * nc;
         L.entries.push_back(e);
     }
 
@@ -204,9 +225,6 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
             if (e.d.kind == 0) {
                 const int64_t q0 = blk * e.d.rows, rows = std::min<int64_t>(e.d.rows, e.d.npts * e.d.n - q0);
                 cost = cost * (double)rows / e.d.rows;
-            } else {
-                const int r0 = (int)(blk % e.d.row_blocks) * e.d.rows;
-                cost = cost * (double)std::min(e.d.rows, e.d.n - r0) / e.d.rows;
             }
             items[list].push_back({cost, BatchItem{di, (int)blk}});
             L.flops += cost;
@@ -218,13 +236,8 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
         L.flat[l].reserve(items[l].size());
         for (const auto& it : items[l]) L.flat[l].push_back(it.second);
         L.items += (int64_t)L.flat[l].size();
-        const int pr = l / 2;
-        for (const PlanEntry& e : L.entries) {
-            if (2 * e.prec + e.d.kind != l) continue;
-            const size_t need = e.d.kind == 1 ? (pr ? sizeof(FpRowsShared<float>) : sizeof(FpRowsShared<double>))
-                                              : (pr ? plain_lds_for<F32C>(e.d) : plain_lds_for<F64>(e.d));
-            L.lds[l] = std::max(L.lds[l], need);
-        }
+        for (const PlanEntry& e : L.entries)
+            if (2 * e.prec + e.d.kind == l) L.lds[l] = std::max(L.lds[l], e.lds);
     }
     return CHESSFAD_OK;
 }
@@ -299,6 +312,113 @@ hipError_t launch_lists(const BatchArgs args[4], const int grid[4], const size_t
 
 hipError_t launch_all(chessfad_batch* b, hipStream_t s) { return launch_lists(b->args, b->grid, b->lds, b->counters, s); }
 
+// ------------------------------------------------------ plan-time tuning
+// For the instances that leave the chunk to the library, grouped by
+// (function, octave of n, precision): each candidate body configuration is
+// timed on the group's own instances (a plan of just those, one warm-up and
+// two timed runs of its persistent kernels; the runs write the instances'
+// outputs) and the fastest is kept; a larger chunk within 2% of the fastest
+// wins (fewer f calls).  Candidates: Rosenbrock and Ackley, every compiled
+// chunk up to the group's smallest n in the L1 mapping and, up to 8 with
+// several chunks per row, in the L2 mapping; Fletcher-Powell, the largest
+// chunk up to 16 at 16, 4 and 1 points per workgroup (and the default).
+int tune_plan(const chessfad_instance* inst, int ninst, hipStream_t s, std::vector<InstCfg>& cfg,
+              std::vector<chessfad_batch_choice>& choices) {
+    struct Group {
+        int func, prec, nmin = 1 << 30, nmax = 0;
+        std::vector<int> members;
+    };
+    std::map<std::tuple<int, int, int>, Group> groups;
+    for (int k = 0; k < ninst; ++k) {
+        const chessfad_instance& c = inst[k];
+        if (c.chunk != 0 || c.npts <= 0 || check_func_n(c.func_id, c.n) != CHESSFAD_OK) continue;
+        int oct = 0;
+        while ((2 << oct) <= c.n) ++oct;
+        Group& g = groups[std::make_tuple(c.func_id, oct, c.precision)];
+        g.func = c.func_id;
+        g.prec = c.precision;
+        g.nmin = std::min(g.nmin, c.n);
+        g.nmax = std::max(g.nmax, c.n);
+        g.members.push_back(k);
+    }
+    if (groups.empty()) return CHESSFAD_OK;
+    int device = 0;
+    hipError_t err = hipGetDevice(&device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    for (auto& kv : groups) {
+        if (err != hipSuccess) break;
+        Group& g = kv.second;
+        std::vector<InstCfg> cands;
+        if (g.func == CHESSFAD_FLETCHER_POWELL) {
+            int C = 1;
+            for (int k = 0; k < kNumChunks; ++k)
+                if (kChunks[k] <= std::min(16, g.nmin)) C = kChunks[k];
+            for (int pts : {0, 16, 4, 1}) cands.push_back(InstCfg{C, 0, pts});
+        } else {
+            for (int k = 0; k < kNumChunks; ++k) {
+                const int C = kChunks[k];
+                if (C > g.nmin) break;
+                cands.push_back(InstCfg{C, 1, 0});
+                if (C <= 8 && C < g.nmax) cands.push_back(InstCfg{C, 2, 0});
+            }
+        }
+        std::vector<chessfad_instance> sub;
+        for (int k : g.members) sub.push_back(inst[k]);
+        const int m = (int)sub.size();
+        float best_ms = -1.0f, fastest = -1.0f;
+        std::vector<float> times(cands.size(), -1.0f);
+        for (size_t ci = 0; ci < cands.size() && err == hipSuccess; ++ci) {
+            std::vector<InstCfg> cc(m, cands[ci]);
+            PlanLayout L;
+            if (plan_instances(sub.data(), m, nullptr, L, cc.data()) != CHESSFAD_OK) continue;
+            char* mem = nullptr;
+            err = hipMalloc(&mem, std::max<size_t>(L.total, 256));
+            if (err == hipSuccess) err = size_grids(L, device);
+            BatchArgs args[4];
+            unsigned* counters = nullptr;
+            if (err == hipSuccess) err = materialize(L, sub.data(), mem, s, args, counters);
+            if (err == hipSuccess) err = launch_lists(args, L.grid, L.lds, counters, s);
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch_lists(args, L.grid, L.lds, counters, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (mem) (void)hipFree(mem);
+            if (err != hipSuccess) break;
+            times[ci] = ms / 2.0f;
+            if (fastest < 0.0f || times[ci] < fastest) fastest = times[ci];
+        }
+        if (err != hipSuccess || fastest < 0.0f) continue;
+        int pick = -1;
+        for (size_t ci = 0; ci < cands.size(); ++ci)
+            if (times[ci] >= 0.0f && times[ci] <= 1.02f * fastest &&
+                (pick < 0 || cands[ci].C > cands[pick].C || (cands[ci].C == cands[pick].C && times[ci] < best_ms))) {
+                pick = (int)ci;
+                best_ms = times[ci];
+            }
+        for (int k : g.members) cfg[k] = cands[pick];
+        chessfad_batch_choice ch{};
+        ch.func_id = g.func;
+        ch.n_lo = g.nmin;
+        ch.n_hi = g.nmax;
+        ch.precision = g.prec;
+        ch.instances = m;
+        ch.chunk = cands[pick].C;
+        ch.mapping = cands[pick].mapping;
+        ch.points = cands[pick].points;
+        ch.ms = best_ms;
+        ch.candidates = (int)cands.size();
+        choices.push_back(ch);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return err == hipSuccess ? CHESSFAD_OK : hip_fail(err);
+}
+
+
 // ------------------------------------------------ allocation-free batches
 // The device memory of chessfad_batch_run_noalloc: one fixed array per GPU
 // (each device holds its own copy of this module's globals), kept until the
@@ -334,10 +454,21 @@ int chessfad_batch_create(const chessfad_instance* inst, int ninst, void* stream
     if (!plan) return CHESSFAD_E_ARG;
     *plan = nullptr;
     PlanLayout L;
-    const int rc = plan_instances(inst, ninst, bad_index, L);
+    int rc = plan_instances(inst, ninst, bad_index, L);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<chessfad_batch_choice> choices;
+    if (option_value(CHESSFAD_OPT_BATCH_TUNE)) {
+        // the instances were valid as given; re-plan them with the tuned bodies
+        std::vector<InstCfg> cfg(ninst);
+        rc = tune_plan(inst, ninst, s, cfg, choices);
+        if (rc) return rc;
+        L = PlanLayout{};
+        rc = plan_instances(inst, ninst, bad_index, L, cfg.data());
+        if (rc) return rc;
+    }
     chessfad_batch* b = new chessfad_batch;
+    b->choices = std::move(choices);
     hipError_t err = hipGetDevice(&b->device);
     if (err == hipSuccess) err = hipMalloc(&b->dmem, std::max<size_t>(L.total, 256));
     if (err == hipSuccess) err = size_grids(L, b->device);
@@ -405,6 +536,14 @@ int chessfad_batch_run(chessfad_batch* plan, void* stream) {
 int chessfad_batch_destroy(chessfad_batch* plan) {
     if (!plan) return CHESSFAD_E_ARG;
     destroy(plan);
+    return CHESSFAD_OK;
+}
+
+int chessfad_batch_choices(const chessfad_batch* plan, chessfad_batch_choice* out, int cap, int* count) {
+    if (!plan || cap < 0 || (cap > 0 && !out)) return CHESSFAD_E_ARG;
+    const int total = (int)plan->choices.size();
+    for (int k = 0; k < total && k < cap; ++k) out[k] = plan->choices[k];
+    if (count) *count = total;
     return CHESSFAD_OK;
 }
 

@@ -26,6 +26,7 @@ int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
 int g_opt_fp_points = 0;                 // CHESSFAD_OPT_FP_POINTS
+int g_opt_batch_tune = 1;                // CHESSFAD_OPT_BATCH_TUNE
 }  // namespace
 
 namespace chessfad {
@@ -115,6 +116,7 @@ int option_value(int option) {
     if (option == CHESSFAD_OPT_BATCH_GRAPH) return g_opt_batch_graph;
     if (option == CHESSFAD_OPT_MAPPING) return g_opt_mapping;
     if (option == CHESSFAD_OPT_FP_POINTS) return g_opt_fp_points;
+    if (option == CHESSFAD_OPT_BATCH_TUNE) return g_opt_batch_tune;
     return CHESSFAD_E_ARG;
 }
 
@@ -289,22 +291,32 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 
 }  // namespace
 
-FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points) {
+FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, bool mixed) {
     FpDppGeometry g;
     g.nb = (n + 15) / 16;
-    const int n16 = 16 * g.nb;
-    // points per workgroup: as many as the LDS rows allow, or the option's
-    g.ppw = points ? points : (16 * n16 <= kFpDppMaxStage ? 16 : 4 * n16 <= kFpDppMaxStage ? 4 : 1);
-    while (g.ppw > 1 && g.ppw * n16 > kFpDppMaxStage) g.ppw /= 4;
-    const int rbw = 16 / g.ppw;
-    const int iters = (g.nb + rbw - 1) / rbw;   // row blocks per lane row without a split
+    g.kbg = std::min(g.nb, 16);
+    // points per workgroup (the option's, or as many as fill the 16 lane
+    // rows with whole rounds), then row blocks per round
+    int ppw = points ? std::max(1, std::min(points, 16 / g.kbg)) : 0;
+    auto fit = [&](int pp) { return std::max(1, std::min(g.nb, 16 / (pp * g.kbg))); };
+    if (!ppw) ppw = std::max(1, 16 / (fit(1) * g.kbg));
+    g.rb = fit(ppw);
+    auto bytes = [&](int pp, int rb) {
+        return mixed ? fp_dpp_lds_bytes<float>(g.nb, pp, rb, g.kbg) : fp_dpp_lds_bytes<double>(g.nb, pp, rb, g.kbg);
+    };
+    while (ppw > 1 && bytes(ppw, g.rb) > 64 * 1024) {
+        ppw /= 2;
+        g.rb = fit(ppw);
+    }
+    g.ppw = ppw;
+    const int ibr_n = (g.nb + g.rb - 1) / g.rb;   // row-block rounds per point group
     const int64_t groups = (npts + g.ppw - 1) / g.ppw;
-    // split a point group's row blocks over workgroups until about 2048
+    // split a point group's rounds over workgroups until about 2048
     // workgroups fill the GPU
-    int64_t want = (2048 + groups - 1) / groups;
-    g.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>(iters, want));
+    const int64_t want = (2048 + groups - 1) / groups;
+    g.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ibr_n, want));
     g.grid = groups * g.rsplit;
-    g.lds = fp_dpp_lds_bytes(g.nb, g.ppw);
+    g.lds = bytes(g.ppw, g.rb);
     return g;
 }
 
@@ -400,9 +412,9 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpDppLaunch launch = mixed ? fp_dpp_entry_mixed(chunk, hess)
                                    : (grad || fval) ? fp_dpp_entry_grad(chunk) : fp_dpp_entry(chunk, hess);
         if (!launch) return CHESSFAD_E_CHUNK;
-        const FpDppGeometry g = fp_dpp_geometry(n, npts, g_opt_fp_points);
+        const FpDppGeometry g = fp_dpp_geometry(n, npts, g_opt_fp_points, mixed);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, g.rsplit, grad, fval};
+        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, g.rb, g.kbg, g.rsplit, grad, fval};
         hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kFpDppThreads), g.lds, s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
@@ -548,7 +560,8 @@ int chessfad_set_option(int option, int value) {
     int* slot = option == CHESSFAD_OPT_FP_MFMA ? &g_opt_fp_mfma
               : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
               : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping
-              : option == CHESSFAD_OPT_FP_POINTS ? &g_opt_fp_points : nullptr;
+              : option == CHESSFAD_OPT_FP_POINTS ? &g_opt_fp_points
+              : option == CHESSFAD_OPT_BATCH_TUNE ? &g_opt_batch_tune : nullptr;
     if (!slot) return CHESSFAD_E_ARG;
     if (option == CHESSFAD_OPT_FP_POINTS) {
         if (value != 0 && value != 1 && value != 4 && value != 16) return CHESSFAD_E_ARG;

@@ -30,6 +30,14 @@ namespace chessfad {
 // points start in different banks; offsets within a row are then immediates.
 __host__ __device__ inline int aos_stride(int m) { return m | 1; }
 
+// Element idx of a float64 (or, with io32, float32) output array.
+CF_DEV void st_io(double* p, int64_t idx, double val, int io32) {
+    if (io32)
+        reinterpret_cast<float*>(p)[idx] = (float)val;
+    else
+        p[idx] = val;
+}
+
 // One work item's view of its point, staged in LDS: entry k of the point
 // lives at base[k].
 template <typename T>
@@ -105,7 +113,8 @@ struct Rosenbrock {
     static CF_DEV void tables(double, double&, double&) {}
     __host__ __device__ static int isl_tasks(int) { return 0; }
     __host__ __device__ static int isl_size(int) { return 0; }
-    static CF_DEV void island(int, int, const double*, const double*, const double*, int, const FpParams&, double*) {}
+    template <typename XT>
+    static CF_DEV void island(int, int, const XT*, const double*, const double*, int, const FpParams&, double*) {}
 
     template <typename T, int C>
     static CF_DEV HD<T, C> term(const HD1<T, C>& yk, const HD1<T, C>& yk1) {
@@ -204,11 +213,12 @@ struct Ackley {
     //   G(c) = -exp(c / n)                at c = sum cos(2 pi x)
     // With r = sqrt(s / n) and E = exp(-0.2 r): F' = 2E / (n r) and
     // F'' = -E (0.2 + 1 / r) / (n r)^2; G' = G / n, G'' = G / n^2.
-    static CF_DEV void island(int, int n, const double* xg, const double* t0, const double*, int stride,
+    template <typename XT>
+    static CF_DEV void island(int, int n, const XT* xg, const double* t0, const double*, int stride,
                               const FpParams&, double* isl) {
-        double ss = xg[0] * xg[0], cs = t0[0];
+        double ss = (double)xg[0] * (double)xg[0], cs = t0[0];
         for (int k = 1; k < n; ++k) {
-            ss += xg[k] * xg[k];
+            ss += (double)xg[k] * (double)xg[k];
             cs += t0[k * stride];
         }
         const double inv_n = 1.0 / n;
@@ -330,7 +340,8 @@ struct FletcherPowell {
     __host__ __device__ static int isl_size(int n) { return n; }
 
     // float64 residual value r_m = E_m - sum_j A_mj sin x_j + B_mj cos x_j
-    static CF_DEV void island(int m, int n, const double*, const double* t0, const double* t1, int stride,
+    template <typename XT>
+    static CF_DEV void island(int m, int n, const XT*, const double* t0, const double* t1, int stride,
                               const FpParams& prm, double* isl) {
         const double* Am = prm.A + (size_t)m * n;
         const double* Bm = prm.B + (size_t)m * n;

@@ -12,25 +12,30 @@
 //   f.h[l] = sum_m 2 r_m.d r_m.g[l] + [cs + l = i] sum_m 2 r_m.v r_m.h[l].
 //
 // Mapping: the variables are taken in blocks of 16 and a workgroup's 256
-// lanes form 16 rows of 16 lanes.  A lane row is one (point, row block ib):
-// lane t holds row i = 16 ib + t and walks its calls in order - the column
-// blocks kb and within each the chunks cs = 16 kb + jC (the paper's L1
-// mapping, one lane per (point, row)).  In column block kb lane t also holds
-// the residual-layer column of variable 16 kb + t, so the call's g components
-// J_m,cs+l are the values of lanes jC + l of the same lane row, which
-// v_fmac_*_dpp (row_newbcast) reads inside the multiply-add: the product rule
-// costs one instruction per product.  Per call and residual the lane forms
-// its own r_m.d = J_mi and its column's J_m,16kb+t from A, B (global memory,
-// cached: they are shared by every point) and the point's sin x, cos x (LDS),
-// then the C products.  The row's own second-order part,
-// sum_m r_m.v D_mi, is formed once per row and added in the call that holds
-// column i.  H.v: each call's chunk dot with v (v of lane jC + l), the row's
-// sum over its calls in order; Hessian: H[p][i][cs + l] is stored.
+// lanes form 16 lane rows of 16 lanes.  A lane row is one (point, row block
+// ib, column block kb) pair: lane t holds row i = 16 ib + t and the calls of
+// that row whose chunks lie in kb, cs = 16 kb + jC, in order (the paper's L1
+// mapping, one lane per (point, row), with the row's column blocks spread
+// over lane rows).  In the pair the lane also holds the residual-layer
+// column of variable 16 kb + t, so the call's g components J_m,cs+l are the
+// values of lanes jC + l of the same lane row, which v_fmac_*_dpp
+// (row_newbcast) reads inside the multiply-add: the product rule costs one
+// instruction per product.  A round gives the lane rows kbg column blocks of
+// rb row blocks of ppw points (ppw rb kbg <= 16); the residuals are taken in
+// tiles of 16, and per tile the workgroup forms the J entries of the round's
+// row and column blocks in LDS once, each from A, B and the point's
+// sin x, cos x, so that every call reads its r_m.d = J_mi and r_m.g = J_m,k
+// there.  The row's own second-order part, sum_m r_m.v D_mi, is formed once
+// per row by the lane row of its diagonal pair and added in the call that
+// holds column i (D_mi is formed in LDS beside the J tile in the round of the
+// diagonal pair).  H.v: each call's chunk dot with v (v of lane jC + l); the
+// row's partials of its column blocks are summed in block order through
+// LDS.  Hessian: H[p][i][cs + l] is stored per call.
 //
-// The value column r_m.v is computed once per point per workgroup (float64)
-// and staged in LDS with sin x, cos x and v.  A workgroup holds ppw points
-// (16, 4 or 1), each on 16 / ppw lane rows, and the row blocks of its points
-// are split over `rsplit` workgroups: few large points still fill the GPU.
+// The value column r_m.v is computed once per point per workgroup (float64,
+// a lane row per residual) and staged in LDS with sin x, cos x and v.  The row-block rounds of a point
+// group are split over `rsplit` workgroups: few large points still fill the
+// GPU.
 //
 // Precision policies: F64 runs everything in float64.  F32C forms J from the
 // float32 copies of A and B (exact: small integers) and float32 sin, cos,
@@ -52,19 +57,33 @@ struct FpDppArgs {
     double* out;        // [npts][n] for H.v, [npts][n][n] for the Hessian
     FpParams fp;
     int64_t npts;
-    int n;              // 17 .. 512 (any n <= 512 works)
+    int n;              // any n <= 512 (the library runs it for n > 16)
     int nb;             // blocks of 16 variables, ceil(n / 16)
-    int ppw;            // points per workgroup: 16, 4 or 1
-    int rsplit;         // workgroups per point group (each takes every rsplit-th row block slot)
+    int ppw;            // points per workgroup
+    int rb;             // row blocks per round
+    int kbg;            // column blocks per round
+    int rsplit;         // workgroups per point group (each takes a range of row-block rounds)
     double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
     double* fval = nullptr;  // H.v only, optional: [npts] f
+    int io32 = 0;            // H.v: x, v and out are float32 (batched instances)
 };
 
 constexpr int kFpDppThreads = 256;
-constexpr int kFpDppMaxStage = 2048;  // ppw * 16 nb: LDS of 4 float64 rows per point = 64 KiB
+constexpr int kFpDppTile = 16;   // residuals per J tile (MT x 16 lanes = the workgroup's 256 threads)
 
-// LDS bytes of one workgroup: sin x, cos x, r.v and v, ppw rows of 16 nb each
-__host__ __device__ inline size_t fp_dpp_lds_bytes(int nb, int ppw) { return (size_t)4 * ppw * 16 * nb * sizeof(double); }
+// LDS of one workgroup, in doubles (host and device agree): per point sin x,
+// cos x, r.v, v (16 nb each); the row partials of a round (16 x 16), the
+// rows' running sums and own parts (ppw x rb x 16 each); the D tile of the
+// round's row blocks, [point][row-block slot][residual][lane] (float64);
+// then the J tile, [point][block slot][residual][lane] of T.
+__host__ __device__ inline size_t fp_dpp_lds_doubles(int nb, int ppw, int rb) {
+    return (size_t)4 * ppw * 16 * nb + 256 + 2 * (size_t)ppw * rb * 16 + (size_t)ppw * rb * kFpDppTile * 16;
+}
+template <typename T>
+__host__ __device__ inline size_t fp_dpp_lds_bytes(int nb, int ppw, int rb, int kbg) {
+    return fp_dpp_lds_doubles(nb, ppw, rb) * sizeof(double) +
+           (size_t)ppw * (kbg + rb) * kFpDppTile * 16 * sizeof(T);
+}
 
 // A and B (float64, or the float32 copies) at element offset `idx`: a
 // uniform base and a 32-bit offset, the addressing of a scalar-base load
@@ -86,13 +105,14 @@ CF_DEV T ld_at(const T* base, uint32_t idx) {
 }
 
 // Per-call accumulation of the C products over the residuals: float64
-// directly; float32 in 16-residual blocks added into a two-sum running sum.
+// directly; float32 in 16-residual blocks (one J tile) added into a two-sum
+// running sum.
 template <class Prec, int C>
 struct DppCallSum;
 template <int C>
 struct DppCallSum<F64, C> {
     double acc[C];
-    CF_DEV DppCallSum() {
+    CF_DEV void reset() {
 #pragma unroll
         for (int l = 0; l < C; ++l) acc[l] = 0.0;
     }
@@ -103,7 +123,7 @@ struct DppCallSum<F64, C> {
 template <int C>
 struct DppCallSum<F32C, C> {
     float blk[C], hi[C], lo[C];
-    CF_DEV DppCallSum() {
+    CF_DEV void reset() {
 #pragma unroll
         for (int l = 0; l < C; ++l) blk[l] = hi[l] = lo[l] = 0.0f;
     }
@@ -121,54 +141,83 @@ struct DppCallSum<F32C, C> {
     CF_DEV double value(int l) const { return (double)hi[l] + (double)lo[l]; }
 };
 
-template <class Prec, int C, bool kHess, bool kGrad>
-__global__ __launch_bounds__(kFpDppThreads) void fp_dpp_kernel(FpDppArgs a) {
-    using T = typename Prec::T;
-    extern __shared__ double lds[];
-    const int n = a.n, nb = a.nb, ppw = a.ppw, n16 = 16 * nb;
-    double* sins = lds;
-    double* coss = sins + ppw * n16;
-    double* rvs = coss + ppw * n16;
-    double* vs = rvs + ppw * n16;
-    const int64_t pg = blockIdx.x / a.rsplit;
-    const int rpart = (int)(blockIdx.x - pg * a.rsplit);
-    const int64_t p0 = pg * ppw;
-
-    // 1. sin x, cos x and v of the workgroup's points (zeros past n and npts)
-    for (int idx = threadIdx.x; idx < ppw * n16; idx += kFpDppThreads) {
+// sin x, cos x and v of the points p0 .. p0 + ppw - 1 (zeros past n and
+// npts), from x and v stored as XT.
+template <bool kHess, typename XT>
+__device__ __forceinline__ void fp_dpp_stage(const FpDppArgs& a, const XT* x, const XT* v, int64_t p0, double* sins,
+                                             double* coss, double* vs) {
+    const int n = a.n, n16 = 16 * a.nb;
+    for (int idx = threadIdx.x; idx < a.ppw * n16; idx += kFpDppThreads) {
         const int ps = idx / n16, k = idx - ps * n16;
         const int64_t p = p0 + ps;
         const bool live = p < a.npts && k < n;
         double s = 0.0, c = 0.0;
-        if (live) sincos(a.x[p * n + k], &s, &c);
+        if (live) sincos((double)x[p * n + k], &s, &c);
         sins[idx] = s;
         coss[idx] = c;
-        if (!kHess) vs[idx] = live ? a.v[p * n + k] : 0.0;
+        if (!kHess) vs[idx] = live ? (double)v[p * n + k] : 0.0;
     }
+}
+
+// One workgroup: point group pg, row-block rounds [ibr0, ibr1).
+//
+// A lane row (16 lanes) d is (point slot ps, row-block slot ibs, column-
+// block slot kbs); in round (ibr, kgr) it holds the calls of rows
+// i = 16 ib + t, ib = ibr rb + ibs, whose chunks lie in column block
+// kb = kgr kbg + kbs.  Per tile of 16 residuals the workgroup forms the J
+// entries the round needs - columns of its kbg column blocks and rb row
+// blocks - in LDS once, each from A, B and the point's sin, cos; every lane
+// then reads its own r.d = J_mi and its column's J_m,16kb+t, and the calls'
+// C products r.d r.g[l] take the chunk columns from the lanes that hold them
+// (DPP).  After the last tile: the Hessian chunk of each call is stored, or
+// each call's chunk dot with v is added to the row's partial; the partials
+// of a row's column blocks are summed in block order through LDS.
+template <class Prec, int C, bool kHess, bool kGrad>
+__device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int ibr0, int ibr1, double* lds) {
+    using T = typename Prec::T;
+    constexpr int MT = kFpDppTile;
+    const int n = a.n, nb = a.nb, ppw = a.ppw, rb = a.rb, kbg = a.kbg, n16 = 16 * nb;
+    const int nslots = kbg + rb;
+    double* sins = lds;
+    double* coss = sins + ppw * n16;
+    double* rvs = coss + ppw * n16;
+    double* vs = rvs + ppw * n16;
+    double* part = vs + ppw * n16;            // [16 lane rows][16]
+    double* rowsum = part + 256;              // [ppw][rb][16]
+    double* owns = rowsum + ppw * rb * 16;    // [ppw][rb][16]
+    double* dt = owns + ppw * rb * 16;        // [ppw][rb][MT][16]
+    T* jt = reinterpret_cast<T*>(dt + ppw * rb * MT * 16);   // [ppw][nslots][MT][16]
+    const int64_t p0 = pg * ppw;
+
+    // 1. sin x, cos x and v of the workgroup's points (zeros past n and npts);
+    // the input type is uniform: one loop per type
+    if (a.io32)
+        fp_dpp_stage<kHess>(a, reinterpret_cast<const float*>(a.x), reinterpret_cast<const float*>(a.v), p0, sins,
+                            coss, vs);
+    else
+        fp_dpp_stage<kHess>(a, a.x, a.v, p0, sins, coss, vs);
     __syncthreads();
-    // 2. the value column r_m.v (float64), points fastest so that neighbouring
-    // lanes read the same row of A and B
-    for (int idx = threadIdx.x; idx < ppw * n16; idx += kFpDppThreads) {
-        const int m = idx / ppw, ps = idx - m * ppw;
+    // 2. the value column r_m.v (float64): a lane row per (point, residual),
+    // lane t summing the terms j = t, t + 16, ... in order, then the 16
+    // partial sums in a fixed tree
+    for (int task = threadIdx.x >> 4; task < ppw * n16; task += kFpDppThreads / 16) {
+        const int ps = task / n16, m = task - ps * n16, t = threadIdx.x & 15;
         const int64_t p = p0 + ps;
-        double r = 0.0;
-        if (m < n && p < a.npts) {
+        const bool on = m < n && p < a.npts;
+        const double* sp = sins + ps * n16;
+        const double* cp = coss + ps * n16;
+        double acc = 0.0;
+        if (on) {
             const double* Am = a.fp.A + (size_t)m * n;
             const double* Bm = a.fp.B + (size_t)m * n;
-            const double* sp = sins + ps * n16;
-            const double* cp = coss + ps * n16;
-            double acc = Am[0] * sp[0];
-            acc = acc + Bm[0] * cp[0];
-            for (int j = 1; j < n; ++j) {
-                acc = acc + Am[j] * sp[j];
-                acc = acc + Bm[j] * cp[j];
-            }
-            r = a.fp.E[m] - acc;
+            for (int j = t; j < n; j += 16) acc += Am[j] * sp[j] + Bm[j] * cp[j];
         }
-        rvs[ps * n16 + m] = r;
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 16);
+        if (t == 0) rvs[ps * n16 + m] = on ? a.fp.E[m] - acc : 0.0;
     }
     __syncthreads();
-    if (kGrad && a.fval && rpart == 0 && (int)threadIdx.x < ppw) {
+    if (kGrad && a.fval && ibr0 == 0 && (int)threadIdx.x < ppw) {
         const int64_t p = p0 + threadIdx.x;
         if (p < a.npts) {
             const double* rp = rvs + threadIdx.x * n16;
@@ -178,106 +227,190 @@ __global__ __launch_bounds__(kFpDppThreads) void fp_dpp_kernel(FpDppArgs a) {
         }
     }
 
-    // 3. the calls: lane row d = (point slot, row-block slot), lane t
+    // 3. the rounds
     const int d = threadIdx.x >> 4, t = threadIdx.x & 15;
-    const int rbw = 16 / ppw;
-    const int ps = d / rbw, rs = d - ps * rbw;
+    const int per_pt = rb * kbg;
+    const bool lr_on = d < ppw * per_pt;
+    const int ps = lr_on ? d / per_pt : 0;
+    const int ibs = lr_on ? (d - ps * per_pt) / kbg : 0;
+    const int kbs = lr_on ? d - ps * per_pt - ibs * kbg : 0;
     const int64_t p = p0 + ps;
-    const bool pt_live = p < a.npts;
-    const double* sp = sins + ps * n16;
-    const double* cp = coss + ps * n16;
     const double* rp = rvs + ps * n16;
     const double* vp = vs + (kHess ? 0 : ps * n16);
-    for (int ib = rpart * rbw + rs; ib < nb; ib += a.rsplit * rbw) {
+    const T* Ab = fp_a_base<T>(a.fp);
+    const T* Bb = fp_b_base<T>(a.fp);
+    const T* jk = jt + ((size_t)(ps * nslots + kbs) * MT) * 16 + t;          // this lane's column's entries
+    const T* ji = jt + ((size_t)(ps * nslots + kbg + ibs) * MT) * 16 + t;    // this lane's row's entries
+    const int kgr_n = (nb + kbg - 1) / kbg;
+    const int tiles = (n + MT - 1) / MT;
+    DppCallSum<Prec, C> sums[16 / C];
+
+    for (int ibr = ibr0; ibr < ibr1; ++ibr) {
+        const int ib = ibr * rb + ibs;
         const int i = 16 * ib + t;
-        const bool row_live = pt_live && i < n;
-        const int ia = i < n ? i : 0;   // an in-range column for the loads of padded lanes
-        const double si64 = sp[i], ci64 = cp[i];
-        const T si = (T)si64, ci = (T)ci64;
-        // the row's own second-order part sum_m r_m.v D_mi (and, for the
-        // gradient, its first-order part sum_m r_m.v J_mi), float64
-        // (sin and cos are staged as zeros past n, which masks padded rows)
-        double own = 0.0, gd = 0.0;
-        for (int m = 0; m < n; ++m) {
-            const double am = ld_at(a.fp.A, (uint32_t)(m * n + ia)), bm = ld_at(a.fp.B, (uint32_t)(m * n + ia));
-            const double rv = rp[m];
-            own += rv * (am * si64 + bm * ci64);
-            if (kGrad) gd += rv * (bm * si64 - am * ci64);
-        }
-        if (kGrad && row_live) a.grad[p * n + i] = gd + gd;
-        const double vi = kHess ? 0.0 : vp[i];
-        double row = 0.0;
-        for (int kb = 0; kb < nb; ++kb) {
-            const int k = 16 * kb + t;
-            const int ka = k < n ? k : 0;
-            const T sk = (T)sp[k], ck = (T)cp[k];
-            const double vk = kHess ? 0.0 : vp[k];
-            static_for<16 / C>([&](auto jcc) {
-                constexpr int jc = decltype(jcc)::value;
-                constexpr int cl = jc * C;   // the chunk's first lane in the row
-                const int cs = 16 * kb + cl;
-                if (cs >= n) return;
-                // the call (i, cs): products r_m.d r_m.g[l] over the residuals
-                DppCallSum<Prec, C> sum;
-                const T* Ab = fp_a_base<T>(a.fp);
-                const T* Bb = fp_b_base<T>(a.fp);
-                // J_mi and J_m,k of four residuals; padded lanes have zero
-                // sin and cos, so their J entries are zero; residuals past n
-                // (the last group) are zero
-                auto group = [&](int m0, bool tail) {
-                    T g[4], dd[4];
+        const bool row_live = lr_on && p < a.npts && ib < nb && i < n;
+        for (int kgr = 0; kgr < kgr_n; ++kgr) {
+            const int kb = kgr * kbg + kbs;
+            const bool pair_on = lr_on && ib < nb && kb < nb;
+            // the lane row of the row's diagonal pair also forms the row's own
+            // part sum_m r_m.v D_mi (and the gradient's sum_m r_m.v J_mi),
+            // float64, from the tiles
+            const bool diag = pair_on && kb == ib;
+            double own = 0.0, gd = 0.0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int m = tail && m0 + u >= n ? n - 1 : m0 + u;
-                        const uint32_t mo = (uint32_t)(m * n);
-                        const T ai = ld_at(Ab, mo + ia), bi = ld_at(Bb, mo + ia);
-                        const T ak = ld_at(Ab, mo + ka), bk = ld_at(Bb, mo + ka);
-                        dd[u] = bi * si - ai * ci;
-                        g[u] = bk * sk - ak * ck;
-                        if (tail && m0 + u >= n) dd[u] = g[u] = T(0);
+            for (int jc = 0; jc < 16 / C; ++jc) sums[jc].reset();
+            for (int mt = 0; mt < tiles; ++mt) {
+                __syncthreads();   // the previous tile has been read
+                // the round's J entries of this tile, J_mk = B_mk sin x_k -
+                // A_mk cos x_k: entry [q][u][tt] of q = (point, block slot) is
+                // thread 16 u + tt's in step q (MT x 16 = 256 threads)
+                {
+                    const int u = threadIdx.x >> 4, tt = threadIdx.x & 15;
+                    const int m = mt * MT + u;
+                    const bool m_on = m < n;
+                    const uint32_t mrow = (uint32_t)((m_on ? m : 0) * n);
+                    // four entries at a time, their loads from clamped, in-range
+                    // offsets all in flight together; sin and cos are zero past
+                    // n, and blocks past nb and residuals past n are masked
+                    const int nq = ppw * nslots;
+                    for (int q0 = 0; q0 < nq; q0 += 4) {
+                        T bv[4], av[4];
+                        int sc[4];
+                        bool on[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = q0 + r < nq ? q0 + r : nq - 1;
+                            const int qs = q / nslots, bs = q - qs * nslots;
+                            const int blk = bs < kbg ? kgr * kbg + bs : ibr * rb + (bs - kbg);
+                            on[r] = m_on && blk < nb;
+                            const int col = on[r] ? 16 * blk + tt : 0;
+                            sc[r] = qs * n16 + col;
+                            const uint32_t o = mrow + (uint32_t)(col < n ? col : n - 1);
+                            bv[r] = ld_at(Bb, o);
+                            av[r] = ld_at(Ab, o);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const T jv = bv[r] * (T)sins[sc[r]] - av[r] * (T)coss[sc[r]];
+                            if (q0 + r < nq) jt[(q0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
+                        }
                     }
-                    DppRowProducts<T, C, cl>::run(sum.block(), g, dd);
-                };
-                int m0 = 0, groups = 0;
-                for (; m0 + 4 <= n; m0 += 4) {
-                    group(m0, false);
-                    // float32: a block of 16 residuals enters the running sum
-                    if (++groups == 4) {
-                        sum.close_block();
-                        groups = 0;
+                    // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row
+                    // blocks whose diagonal pair is in this round
+                    for (int q = 0; q < ppw * rb; ++q) {
+                        const int qs = q / rb, blk = ibr * rb + (q - qs * rb);
+                        if (blk >= nb || blk < kgr * kbg || blk >= kgr * kbg + kbg) continue;
+                        const int col = 16 * blk + tt;
+                        const uint32_t o = mrow + (uint32_t)(col < n ? col : n - 1);
+                        const double dv = ld_at(a.fp.A, o) * sins[qs * n16 + col] + ld_at(a.fp.B, o) * coss[qs * n16 + col];
+                        dt[q * (MT * 16) + threadIdx.x] = m_on ? dv : 0.0;
                     }
                 }
-                if (m0 < n) group(m0, true);
-                sum.close_block();
-                double h[C];
-#pragma unroll
-                for (int l = 0; l < C; ++l) h[l] = sum.value(l);
-                if constexpr (kHess) {
-                    // CHUNK-HESS: H[p][i][cs + l] = 2 (products + [cs + l = i] own)
-#pragma unroll
-                    for (int l = 0; l < C; ++l) {
-                        if (cs + l == i) h[l] += own;
-                        h[l] += h[l];
+                __syncthreads();
+                if (diag) {
+                    const double* dp = dt + (size_t)((ps * rb + ibs) * MT) * 16 + t;
+#pragma unroll 4
+                    for (int u = 0; u < MT; ++u) {
+                        const double rv = rp[mt * MT + u];   // zero past n
+                        own += rv * dp[u * 16];
+                        if (kGrad) gd += rv * (double)ji[u * 16];
                     }
-                    if (row_live) {
-                        double* dst = a.out + ((size_t)p * n + i) * n + cs;
-#pragma unroll
-                        for (int l = 0; l < C; ++l)
-                            if (cs + l < n) dst[l] = h[l];
-                    }
-                } else {
-                    // the chunk dot with v (v of lane cl + l), the row sum in call order
-                    double dot = 0.0;
-                    DppChunkDot<C, cl>::run(dot, vk, h);
-                    row += dot;
                 }
-            });
+                if (pair_on) {
+#pragma unroll
+                    for (int ug = 0; ug < MT / 4; ++ug) {
+                        T g[4], dd[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            g[u] = jk[(4 * ug + u) * 16];
+                            dd[u] = ji[(4 * ug + u) * 16];
+                        }
+                        static_for<16 / C>([&](auto jcc) {
+                            constexpr int jc = decltype(jcc)::value;
+                            DppRowProducts<T, C, jc * C>::run(sums[jc].block(), g, dd);
+                        });
+                    }
+#pragma unroll
+                    for (int jc = 0; jc < 16 / C; ++jc) sums[jc].close_block();
+                }
+            }
+            if (diag) {
+                owns[(ps * rb + ibs) * 16 + t] = own;
+                if (kGrad && row_live) a.grad[p * n + i] = gd + gd;
+            }
+            // the calls of the pair
+            double prt = 0.0;
+            if (pair_on) {
+                const double vk = kHess ? 0.0 : vp[16 * kb + t];
+                static_for<16 / C>([&](auto jcc) {
+                    constexpr int jc = decltype(jcc)::value;
+                    constexpr int cl = jc * C;   // the chunk's first lane in the row
+                    const int cs = 16 * kb + cl;
+                    if (cs >= n) return;
+                    double h[C];
+#pragma unroll
+                    for (int l = 0; l < C; ++l) h[l] = sums[jc].value(l);
+                    if constexpr (kHess) {
+                        // CHUNK-HESS: H[p][i][cs + l] = 2 (products + [cs + l = i] own)
+                        if (kb == ib) {
+                            const double own = owns[(ps * rb + ibs) * 16 + t];
+#pragma unroll
+                            for (int l = 0; l < C; ++l)
+                                if (cs + l == i) h[l] += own;
+                        }
+                        if (row_live) {
+                            double* dst = a.out + ((size_t)p * n + i) * n + cs;
+#pragma unroll
+                            for (int l = 0; l < C; ++l)
+                                if (cs + l < n) dst[l] = h[l] + h[l];
+                        }
+                    } else {
+                        // the chunk dot with v (v of lane cl + l), in call order
+                        double dot = 0.0;
+                        DppChunkDot<C, cl>::run(dot, vk, h);
+                        prt += dot;
+                    }
+                });
+            }
+            if constexpr (!kHess) {
+                // the row's partials over the round's column blocks, in block order
+                part[d * 16 + t] = prt;
+                __syncthreads();
+                if (lr_on && kbs == 0) {
+                    double* rs = rowsum + (ps * rb + ibs) * 16 + t;
+                    double acc = kgr == 0 ? 0.0 : *rs;
+                    for (int b = 0; b < kbg; ++b) acc += part[(d + b) * 16 + t];
+                    *rs = acc;
+                }
+            }
         }
         if constexpr (!kHess) {
-            row += own * vi;
-            if (row_live) a.out[p * n + i] = row + row;
+            __syncthreads();
+            if (row_live && kbs == 0) {
+                const double own = owns[(ps * rb + ibs) * 16 + t];
+                const double row = rowsum[(ps * rb + ibs) * 16 + t] + own * vp[i];
+                st_io(a.out, p * n + i, row + row, a.io32);
+            }
         }
     }
+}
+
+// The row-block rounds [ibr0, ibr1) of workgroup rpart of a point group (a
+// point group's rounds split over rsplit workgroups).
+__host__ __device__ inline void fp_dpp_rounds(int nb, int rb, int rsplit, int rpart, int& ibr0, int& ibr1) {
+    const int ibr_n = (nb + rb - 1) / rb;
+    const int per = (ibr_n + rsplit - 1) / rsplit;
+    ibr0 = rpart * per;
+    ibr1 = ibr0 + per < ibr_n ? ibr0 + per : ibr_n;
+}
+
+template <class Prec, int C, bool kHess, bool kGrad>
+__global__ __launch_bounds__(kFpDppThreads) void fp_dpp_kernel(FpDppArgs a) {
+    extern __shared__ double lds[];
+    const int64_t pg = blockIdx.x / a.rsplit;
+    int ibr0, ibr1;
+    fp_dpp_rounds(a.nb, a.rb, a.rsplit, (int)(blockIdx.x - pg * a.rsplit), ibr0, ibr1);
+    fp_dpp_block<Prec, C, kHess, kGrad>(a, pg, ibr0, ibr1, lds);
 }
 
 }  // namespace chessfad

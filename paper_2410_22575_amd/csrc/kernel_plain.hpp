@@ -40,6 +40,7 @@ struct PlainArgs {
     int pstride;        // LDS rows per staged array (>= points per workgroup)
     double* grad = nullptr;  // kGrad kernels: [npts][n] gradient (row i's d component)
     double* fval = nullptr;  // kGrad kernels, optional: [npts] f (the value component)
+    int io32 = 0;            // H.v: x, v and out are float32 (batched instances)
 };
 
 constexpr int kMaxBlock = 512;
@@ -68,6 +69,33 @@ struct PlainStage {
     int ks, ki;   // row lengths: coordinate arrays, islands
 };
 
+// Coordinates (and vectors) of the points p0 .. p0 + npb - 1, stored as XT
+// in global memory, into the staging rows; then the islands.
+template <class P, class F, bool kHess, typename XT>
+__device__ __forceinline__ void plain_stage_points(const PlainArgs& a, const PlainStage<typename P::T>& st,
+                                                   const XT* x, const XT* v, int64_t p0, int npb) {
+    using T = typename P::T;
+    const int n = a.n, ks = st.ks, ki = st.ki;
+    const XT* xg = x + p0 * n;
+    const XT* vg = v + p0 * n;
+    for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
+        const int pl = idx / n, k = idx - pl * n;
+        const double xv = (double)xg[idx];
+        st.xs[pl * ks + k] = (T)xv;
+        if (!kHess) st.vs[pl * ks + k] = (T)vg[idx];
+        if (F::kTables) F::tables(xv, st.t0[pl * ks + k], st.t1[pl * ks + k]);
+    }
+    __syncthreads();
+    const int tasks = F::isl_tasks(n);
+    if (tasks) {
+        for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
+            const int pl = idx / tasks, task = idx - pl * tasks;
+            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
+        }
+        __syncthreads();
+    }
+}
+
 // Steps 1 and 2 for the points p0 .. p0 + npb - 1: coordinates (and vectors)
 // in per-point rows with the per-coordinate tables, then the per-point
 // float64 islands.  `nthr` doubles of reduction space come first.
@@ -87,24 +115,12 @@ __device__ __forceinline__ PlainStage<typename P::T> plain_stage(const PlainArgs
     st.xs = reinterpret_cast<T*>(st.isl + ki * ps);
     st.vs = st.xs + ks * ps;
 
-    const double* xg = a.x + p0 * n;
-    const double* vg = a.v + p0 * n;
-    for (int idx = threadIdx.x; idx < npb * n; idx += blockDim.x) {
-        const int pl = idx / n, k = idx - pl * n;
-        const double xv = xg[idx];
-        st.xs[pl * ks + k] = (T)xv;
-        if (!kHess) st.vs[pl * ks + k] = (T)vg[idx];
-        if (F::kTables) F::tables(xv, st.t0[pl * ks + k], st.t1[pl * ks + k]);
-    }
-    __syncthreads();
-    const int tasks = F::isl_tasks(n);
-    if (tasks) {
-        for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
-            const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
-        }
-        __syncthreads();
-    }
+    // the input type is uniform: one staging loop per type
+    if (a.io32)
+        plain_stage_points<P, F, kHess>(a, st, reinterpret_cast<const float*>(a.x), reinterpret_cast<const float*>(a.v),
+                                        p0, npb);
+    else
+        plain_stage_points<P, F, kHess>(a, st, a.x, a.v, p0, npb);
     return st;
 }
 
@@ -179,7 +195,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
     if (!kHess) {
         if (nc == 1) {
             // one chunk per row: the lane holds the row's whole sum
-            if (active) a.out[q] = dot;
+            if (active) st_io(a.out, q, dot, a.io32);
         } else {
             // row sum over the nc chunk lanes, in chunk order
             if (threadIdx.x < nthr) st.red[threadIdx.x] = dot;
@@ -187,7 +203,7 @@ __device__ __forceinline__ void plain_block(const PlainArgs& a, int64_t blk, dou
             if (active && j == 0) {
                 double s = st.red[threadIdx.x];
                 for (int k = 1; k < nc; ++k) s += st.red[threadIdx.x + k * a.rows];
-                a.out[q] = s;
+                st_io(a.out, q, s, a.io32);
             }
         }
     }
@@ -225,7 +241,7 @@ __device__ __forceinline__ void coarse_block(const PlainArgs& a, int64_t blk, do
             // f on the call's seeds, its second-order part dotted with v
             res += F::template hvp<P, C>(pv, a.fp, st.vs + pl * st.ks);
         }
-        a.out[q] = res;
+        st_io(a.out, q, res, a.io32);
     }
 }
 

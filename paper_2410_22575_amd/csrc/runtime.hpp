@@ -51,15 +51,16 @@ double model_flops_per_call(int func_id, int n, int C);
 
 bool chunk_compiled(int c);
 
-// Launch shape of the per-call Fletcher-Powell kernel for n > 16: points per
-// workgroup (`points`, or chosen from the LDS rows when 0), the split of each
-// point group's row blocks over workgroups, grid and LDS bytes.
+// Launch shape of the per-call Fletcher-Powell kernel for n > 16: blocks of
+// 16 variables, points per workgroup (`points`, or chosen to fill the 16
+// lane rows when 0), row blocks and column blocks per round, the split of a
+// point group's rounds over workgroups, grid and LDS bytes.
 struct FpDppGeometry {
-    int nb = 0, ppw = 0, rsplit = 1;
+    int nb = 0, ppw = 0, rb = 1, kbg = 1, rsplit = 1;
     int64_t grid = 0;
     size_t lds = 0;
 };
-FpDppGeometry fp_dpp_geometry(int n, int64_t npts, int points);
+FpDppGeometry fp_dpp_geometry(int n, int64_t npts, int points, bool mixed);
 
 // Current value of a chessfad_option.
 int option_value(int option);

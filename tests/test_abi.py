@@ -200,8 +200,10 @@ def test_binding_rejects_bad_tensors():
         binding.chessfad_hessian(R, x)
 
 
-def _inst(func=R, n=16, chunk=4, precision=0, npts=3, x=FAKE, v=FAKE * 2, out=FAKE * 4, A=None, B=None, alpha=None):
-    return binding.Instance(func, n, chunk, precision, npts, x, v, out, A, B, alpha)
+def _inst(func=R, n=16, chunk=4, precision=0, npts=3, x=FAKE, v=FAKE * 2, out=FAKE * 4, A=None, B=None, alpha=None,
+          io_fp32=0):
+    return binding.Instance(func_id=func, n=n, chunk=chunk, precision=precision, io_fp32=io_fp32, npts=npts, x=x, v=v,
+                            out=out, A=A, B=B, alpha=alpha)
 
 
 def _create(lib, insts):
@@ -214,7 +216,11 @@ def _create(lib, insts):
 
 def test_batch_validation_before_any_device_work(lib):
     ok = _inst()
-    assert _create(lib, [ok, _inst(chunk=16)]) == (E_CHUNK, 1)          # vector bodies: 1, 2, 4, 8
+    assert _create(lib, [ok, _inst(chunk=32)]) == (E_CHUNK, 1)          # compiled chunks: 1, 2, 4, 8, 16
+    assert _create(lib, [ok, _inst(n=8, chunk=16)]) == (E_CHUNK, 1)     # chunk above n
+    assert _create(lib, [_inst(io_fp32=2)]) == (E_ARG, 0)
+    # float32 I/O: an output overlapping its input by the float32 extent only
+    assert _create(lib, [_inst(npts=4, n=16, x=FAKE, v=FAKE * 8, out=FAKE + 4 * 64 - 8, io_fp32=1)]) == (E_OVERLAP, 0)
     assert _create(lib, [_inst(func=FP, chunk=16)]) == (E_PARAMS, 0)   # Fletcher-Powell takes 16
     assert _create(lib, [_inst(func=9), ok]) == (E_FUNC, 0)
     assert _create(lib, [ok, ok, _inst(n=600)]) == (E_N, 2)
@@ -229,6 +235,7 @@ def test_batch_validation_before_any_device_work(lib):
     assert lib.chessfad_batch_run(None, None) == E_ARG
     assert lib.chessfad_batch_destroy(None) == E_ARG
     assert lib.chessfad_batch_info(None, None, None, None) == E_ARG
+    assert lib.chessfad_batch_choices(None, None, 0, None) == E_ARG
 
 
 def test_autotune_argument_checks(lib):
@@ -248,7 +255,7 @@ def test_batch_noalloc_checks_before_any_device_work(lib):
         return rc, bad.value
 
     ok = _inst()
-    assert run([ok, _inst(chunk=16)]) == (E_CHUNK, 1)
+    assert run([ok, _inst(chunk=32)]) == (E_CHUNK, 1)
     assert run([_inst(func=9), ok]) == (E_FUNC, 0)
     assert run([_inst(func=FP)]) == (E_PARAMS, 0)
     assert run([_inst(out=FAKE)]) == (E_OVERLAP, 0)

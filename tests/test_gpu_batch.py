@@ -182,7 +182,78 @@ def test_autotune_records_default(gpu_lib):
 def test_batch_errors_name_the_instance(gpu_lib):
     ws = _workloads(9500, 3, 8, 16)
     insts = _make(ws)
-    insts[1]["chunk"] = 16
+    insts[1]["chunk"] = 32   # not a compiled chunk
     with pytest.raises(gpu_lib.ChessfadError) as ei:
         gpu_lib.chessfad_batch_create(insts)
     assert ei.value.code == -3 and ei.value.bad_index == 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_float32_io(gpu_lib, precision):
+    """io_fp32: x, v and out as float32.  Against the oracle evaluated at the
+    float32 inputs (widened exactly): the float64 path to 1e-6 (the float32
+    rounding of the output, about 6e-8 of each entry, dominates), the mixed
+    path to the mixed gate; and against the same instances with float64 I/O
+    to the same bars."""
+    ws = _workloads(9600 + precision, 36, 8, 96, npts_choices=(1, 3))
+    for w in ws:
+        w.x = w.x.astype(np.float32).astype(np.float64)
+        w.v = w.v.astype(np.float32).astype(np.float64)
+    i64 = _make(ws, precision=precision)
+    i32 = []
+    for d in i64:
+        e = dict(d)
+        e["x"], e["v"] = d["x"].float(), d["v"].float()
+        e["out"] = torch.full(d["out"].shape, np.nan, dtype=torch.float32, device="cuda")
+        i32.append(e)
+    print(f"[case] batch float32 io precision={precision}: {len(ws)} instances", flush=True)
+    for insts in (i64, i32):
+        plan = gpu_lib.chessfad_batch_create(insts)
+        plan.run()
+        torch.cuda.synchronize()
+        plan.destroy()
+    bar = 1e-6 if precision == 0 else 1e-5
+    worst = 0.0
+    for w, a, b in zip(ws, i64, i32):
+        got = b["out"].double().cpu().numpy()
+        assert np.all(np.isfinite(got)), (w.func, w.n)
+        e = _oracle_err(w, got)
+        worst = max(worst, e)
+        assert e <= bar, (w.func, w.n)
+        ref = a["out"].cpu().numpy()
+        scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-300
+        assert np.max(np.abs(got - ref) / scale) <= bar, (w.func, w.n)
+    print(f"  float32 io max rel err {worst:.3e}", flush=True)
+
+
+def test_batch_plan_time_tuning(gpu_lib):
+    """chunk = 0 instances are tuned per (function, octave of n, precision) on
+    the plan's own instances: one choice per group, each a configuration the
+    bodies are compiled for, and the results still match the oracle."""
+    ws = _workloads(9700, 60, 8, 200, npts_choices=(1, 2))
+    insts = _make(ws, precision=0)
+    prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_BATCH_TUNE, 1)
+    try:
+        plan = gpu_lib.chessfad_batch_create(insts)
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_BATCH_TUNE, prev)
+    choices = plan.choices()
+    groups = {(w.func, int(np.floor(np.log2(w.n)))) for w in ws}
+    assert len(choices) == len(groups)
+    for ch in choices:
+        print(f"  choice {ch}", flush=True)
+        assert ch["chunk"] in (1, 2, 4, 8, 16) and ch["chunk"] <= ch["n_lo"]
+        assert ch["candidates"] >= 1 and ch["ms"] > 0 and ch["instances"] >= 1
+        if ch["func_id"] == FP:
+            assert ch["points"] in (0, 1, 4, 16)
+        else:
+            assert ch["mapping"] in (1, 2)
+            assert ch["mapping"] == 1 or ch["chunk"] <= 8
+    assert sum(ch["instances"] for ch in choices) == len(ws)
+    for d in insts:
+        d["out"].fill_(np.nan)
+    plan.run()
+    torch.cuda.synchronize()
+    for w, d in zip(ws, insts):
+        assert _oracle_err(w, d["out"].cpu().numpy()) <= 1e-12, (w.func, w.n)
+    plan.destroy()

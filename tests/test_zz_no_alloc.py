@@ -1,6 +1,6 @@
 """The allocation-free batched entry point (chessfad_batch_run_noalloc)
-against a plan of the same instances (chessfad_batch_create + run), through
-the C ABI.
+against a plan of the same instances (chessfad_batch_create + run, without
+plan-time tuning), through the C ABI.
 
 Both place the same work items on the same kernels, so the bar is ③'s
 float64 bar met exactly: the outputs must agree bit for bit (and, as a
@@ -61,7 +61,12 @@ def test_noalloc_matches_planned_batch_twice(gpu_lib, precision):
         ws = _workloads(31000 + 10 * precision + call, count, 8, nmax)
         print(f"[case] noalloc precision={precision} call={call}: {count} instances, n <= {nmax}", flush=True)
         ref = _instances(ws, precision)
-        plan = gpu_lib.chessfad_batch_create(ref)
+        # a plan of the same instances without plan-time tuning: the same work items
+        prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_BATCH_TUNE, 0)
+        try:
+            plan = gpu_lib.chessfad_batch_create(ref)
+        finally:
+            gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_BATCH_TUNE, prev)
         plan.run()
         torch.cuda.synchronize()
         plan.destroy()
