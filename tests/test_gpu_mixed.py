@@ -3,22 +3,22 @@ against the float64 oracle, through the C ABI.
 
 Bar: the same normwise relative errors as the float64 tests,
     e_hvp = max|r - r*| / (max|H*| max|v|),  e_H = max|H - H*| / max|H*|,
-must stay below TOL32 = 1e-5 (about 170 float32 units of rounding: the
-inputs are rounded to float32 and each Hessian entry goes through a few
-dozen float32 operations before the compensated sums).  The measured
-maxima are printed; they are a few 1e-7.
+must stay below the per-function gates of tests/gates.py (four times the
+measured maxima, which are 1.7e-7 - 2.6e-7: the inputs are rounded to
+float32 and each Hessian entry goes through a few dozen float32 operations
+before the compensated sums).  The measured maxima are printed.
 """
 import numpy as np
 import pytest
 import torch
 
 from oracle import closed_form as cf
+from gates import TOL32
 from paper_2410_22575_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
 R, A, FP = 0, 1, 2
-TOL32 = 1e-5
 
 
 def _dev(a):
@@ -49,7 +49,7 @@ def test_mixed_against_oracle(gpu_lib, func, n, chunks):
         H = gpu_lib.chessfad_hessian_mixed(func, x, chunk=c).cpu().numpy()
         e_H = (np.abs(H - H_ref).max(axis=(1, 2)) / hmax).max()
         print(f"  max rel err: hvp {e_r:.3e}  hessian {e_H:.3e}", flush=True)
-        assert e_r <= TOL32 and e_H <= TOL32
+        assert e_r <= TOL32[func] and e_H <= TOL32[func]
         assert e_r > 0.0  # it really is a float32 computation
 
 
@@ -57,7 +57,7 @@ def test_mixed_against_oracle(gpu_lib, func, n, chunks):
 def test_mixed_mappings(gpu_lib, func):
     """The L0 / L1 mappings of chessfad_hvp_mixed compute the sums L2 does, in
     the same order (float32 rounding may differ where the compiler contracts
-    multiply-adds differently); each stays within TOL32 of the oracle."""
+    multiply-adds differently); each stays within the mixed gate of the oracle."""
     prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 2)
     try:
         for n, npts in ((5, 70), (16, 300), (33, 9)):
@@ -77,7 +77,7 @@ def test_mixed_mappings(gpu_lib, func):
                     gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, level)
                     r = gpu_lib.chessfad_hvp_mixed(func, x, v, chunk=c).cpu().numpy()
                     assert (np.abs(r - r2).max(axis=1) / scale).max() <= 1e-6
-                    assert (np.abs(r - r_ref).max(axis=1) / scale).max() <= TOL32
+                    assert (np.abs(r - r_ref).max(axis=1) / scale).max() <= TOL32[func]
     finally:
         gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev)
 
@@ -94,7 +94,7 @@ def test_mixed_full_size_sampled(gpu_lib, func):
     ref = np.einsum("pij,pj->pi", H, w.v[idx])
     e = np.abs(r[idx] - ref).max(axis=1) / (np.abs(H).max(axis=(1, 2)) * np.abs(w.v[idx]).max(axis=1))
     print(f"  full size func={func}: max rel err {e.max():.3e}", flush=True)
-    assert e.max() <= TOL32
+    assert e.max() <= TOL32[func]
 
 
 def test_mixed_rosenbrock_structure(gpu_lib):
@@ -139,7 +139,7 @@ def test_mixed_fletcher_powell_large_n(gpu_lib, n):
         H = gpu_lib.chessfad_hessian_mixed(FP, x, chunk=c).cpu().numpy()
         e_H = (np.abs(H - H_ref).max(axis=(1, 2)) / hmax).max()
         print(f"  max rel err: hvp {e_r:.3e}  hessian {e_H:.3e}", flush=True)
-        assert e_r <= TOL32 and e_H <= TOL32
+        assert e_r <= TOL32[FP] and e_H <= TOL32[FP]
         assert e_r > 0.0
 
 
@@ -149,7 +149,7 @@ def test_mixed_ackley_near_zero(gpu_lib, n, scale):
     """Ackley where sqrt(sum x^2 / n) -> 0: F' grows like 1 / |x| and F'' like
     1 / |x|^3, the reason its outer functions are float64 islands.  Points
     x ~ U[-1e-3, 1e-3] * scale; the float64 path to 1e-12 and the mixed path to
-    TOL32 normwise, and entry by entry on the entries of at least 1e-3 of the
+    the mixed gate normwise, and entry by entry on the entries of at least 1e-3 of the
     largest (the diagnostic of the oracle's error metric)."""
     npts = 64
     rng = inputs.rng_for(7500 + n)
@@ -161,7 +161,7 @@ def test_mixed_ackley_near_zero(gpu_lib, n, scale):
     xd, vd = _dev(x), _dev(vv)
     big = np.abs(H_ref) >= 1e-3 * hmax[:, None, None]
     for name, fn, fh, tol in (("f64", gpu_lib.chessfad_hvp, gpu_lib.chessfad_hessian, 1e-12),
-                              ("mixed", gpu_lib.chessfad_hvp_mixed, gpu_lib.chessfad_hessian_mixed, TOL32)):
+                              ("mixed", gpu_lib.chessfad_hvp_mixed, gpu_lib.chessfad_hessian_mixed, TOL32[A])):
         for c in (1, max(c for c in (1, 2, 4, 8, 16) if c <= n)):
             print(f"[case] ackley near zero n={n} scale={scale} {name} chunk={c}", flush=True)
             r = fn(A, xd, vd, chunk=c).cpu().numpy()
