@@ -48,6 +48,7 @@ PEAK_F64_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 float64 flops per CU-clock (F
 PEAK_HBM_TBPS = 8.0      # HBM3E
 VALU_ISSUE_PER_S = 256 * 2.4e9   # vector wave-instructions per second (one per CU-clock)
 METRIC = "HVPs/sec at n=16..512; FP32/batched vs FP64 plain on same GPU at stated error"
+LARGE_FP_NPTS = {64: 1 << 18, 512: 1024}   # points of the Fletcher-Powell large-n workloads
 
 # ---------------------------------------------------------------- counters
 # Per-launch figures from rocprofv3 --pmc runs of `bench.py --only kernels`
@@ -96,6 +97,9 @@ KERNEL_SOURCES = {
     "fp_call_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
     "fp_dpp_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp"),
     "fp_rows_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_rows.hpp"),
+    "fp_sym_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp",
+                      "kernel_fp_sym.hpp"),
+    "sym_kernel": ("hd.hpp", "functions.hpp", "kernel_sym.hpp"),
 }
 
 
@@ -112,7 +116,7 @@ def kernel_sha(key, read=None) -> str:
     family = key.split("<")[0]
     h = hashlib.sha256()
     h.update(" ".join(build.FLAGS[:-6]).encode())   # the flags, without the include paths
-    if family.startswith("fp_call") or family.startswith("fp_dpp"):
+    if family.startswith(("fp_call", "fp_dpp", "fp_sym")):
         h.update(inspect.getsource(build.write_dpp_blocks_inc).encode())
     for f in KERNEL_SOURCES.get(family, ()):
         rel = os.path.join("paper_2410_22575_amd", "csrc", f)
@@ -121,19 +125,25 @@ def kernel_sha(key, read=None) -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_key(f, c, n=N, mapping=2, mixed=False):
-    """The kernel chessfad_hvp (or _mixed) runs for (function, chunk,
-    mapping) at n, named as the profiler's demangled kernel name with the
-    namespace and argument list removed (the keys of COUNTERS)."""
+def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
+    """The kernel chessfad_hvp (or _mixed, or _sym) runs for (function,
+    chunk, mapping) at n, named as the profiler's demangled kernel name with
+    the namespace and argument list removed; COUNTERS keys add " n=<n>" for
+    n != 16."""
     prec = "F32C" if mixed else "F64"
+    at = "" if n == N else f" n={n}"
     if f == 2 and n <= 16:
-        return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false>"
+        if sym:
+            return f"fp_mfma_kernel<{prec}, {c}, {min(8, max(1, (2 * n + 3) // 4))}, false, true>" + at
+        return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false>" + at
     if f == 2:
-        return f"fp_rows_kernel<{prec}, {c}, false>"
+        return (f"fp_sym_kernel<{prec}, {c}, false>" if sym else f"fp_dpp_kernel<{prec}, {c}, false, false>") + at
     func = {0: "Rosenbrock", 1: "Ackley"}[f]
+    if sym:
+        return f"sym_kernel<{prec}, {func}, {c}, false>" + at
     if c >= n or mapping == 1:
-        return f"coarse_kernel<{prec}, {func}, {c}, 1>"
-    return f"plain_kernel<{prec}, {func}, {c}, false, false>"
+        return f"coarse_kernel<{prec}, {func}, {c}, 1>" + at
+    return f"plain_kernel<{prec}, {func}, {c}, false, false>" + at
 
 
 def profiler_key(name):
@@ -164,8 +174,11 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance workload")
     ap.add_argument("--batch-instances", type=int, default=8192)
     ap.add_argument("--no-large", action="store_true", help="skip the n = 64 and n = 512 workloads")
-    ap.add_argument("--only", choices=("step", "large", "batch", "fp", "kernels"), default=None,
+    ap.add_argument("--only", choices=("step", "large", "sym", "batch", "fp", "kernels"), default=None,
                     help="only run one part and print its JSON (for profiling; not the benchmark line)")
+    ap.add_argument("--kernels-n", type=int, default=N, choices=(N, 64, 512),
+                    help="--only kernels: the n = 16 step kernels, or the Fletcher-Powell n = 64 / 512 launches "
+                         "of the large-n workloads (full and symmetric H.v)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -323,6 +336,19 @@ def large_n(ctx):
                      "mapping": "per-call, DPP lane broadcasts" if f == 2 else f"L{b.chessfad_default_mapping(f, n, prec)}",
                      "kernel_ms": round(ms, 4), "hvps_per_s": npts / (ms * 1e-3),
                      "model_tflops": mf * npts / (ms * 1e-3) / 1e12, "max_rel_err_sampled": err}
+        key = kernel_key(f, c, n=n, mixed=bool(prec))
+        cnt = COUNTERS.get(key)
+        if cnt:
+            # counters of this launch (rocprofv3 runs of bench.py --only kernels --kernels-n n)
+            algo = 24 * n * npts + (16 * n * n + 8 * n if f == 2 else 0)   # x, v, out; A, B, E once
+            work = cnt["valu_flops"] + cnt["mfma_flops"]
+            res[name]["counters"] = {
+                "kernel": key, "hbm_bytes": cnt["traffic"], "algorithmic_bytes": algo,
+                "hbm_over_algorithmic": cnt["traffic"] / algo,
+                "executed_f64_tflops": work / (ms * 1e-3) / 1e12,
+                "flop_frac": work / (ms * 1e-3) / 1e12 / PEAK_F64_TFLOPS,
+                "valu_issue_frac": cnt["valu_insts"] / VALU_ISSUE_PER_S / (ms * 1e-3),
+                "stale": cnt.get("sha") != kernel_sha(key)}
         if f == 2:
             # the row-block kernel with MFMA contraction tiles, for comparison
             prev = b.chessfad_set_option(b.CHESSFAD_OPT_FP_MFMA, 2)
@@ -344,15 +370,17 @@ def large_n(ctx):
 def symmetric_large_n(ctx):
     """SC-HESS-VEC against CHESS-VEC (float64) where symmetry has calls to
     save (C < n): Rosenbrock and Ackley at n = 64 and 128 over 2^16 points,
-    Fletcher-Powell at n = 64 over 2^12 points, C = 4, 8, 16."""
+    Fletcher-Powell at n = 64 over 2^14 points (C = 4, 8, 16) and at n = 512
+    over 1024 points (C = 16)."""
     b, torch = ctx.binding, ctx.torch
     res = {}
-    for f, n, npts in ((0, 64, 1 << 16), (0, 128, 1 << 16), (1, 64, 1 << 16), (1, 128, 1 << 16), (2, 64, 1 << 12)):
+    for f, n, npts in ((0, 64, 1 << 16), (0, 128, 1 << 16), (1, 64, 1 << 16), (1, 128, 1 << 16), (2, 64, 1 << 14),
+                       (2, 512, 1024)):
         w = ctx.inputs.make_workload(f, n, npts, ctx.inputs.rng_for(700 + n))
         x, v = ctx.dev_array(w.x), ctx.dev_array(w.v)
         E = ctx.set_fp(w) if f == 2 else None
         out = torch.empty_like(x)
-        for c in (4, 8, 16):
+        for c in ((16,) if n == 512 else (4, 8, 16)):
             full = ctx.time_ms(lambda: b.chessfad_hvp(f, x, v, out, chunk=c))
             try:
                 sym = ctx.time_ms(lambda: b.chessfad_hvp_sym(f, x, v, out, chunk=c))
@@ -569,6 +597,24 @@ def main():
         return
     if args.only == "batch":
         print(json.dumps({"batched": batched(ctx, args.batch_instances)}), flush=True)
+        return
+    if args.only == "sym":
+        print(json.dumps({"symmetric_large_n": symmetric_large_n(ctx)}), flush=True)
+        return
+    if args.only == "kernels" and args.kernels_n != N:
+        # the large-n Fletcher-Powell launches (float64 H.v, C = 16, full and
+        # symmetric form), one warm-up and one launch each
+        n = args.kernels_n
+        npts = LARGE_FP_NPTS[n]
+        w = inputs.make_workload(2, n, npts, inputs.rng_for(100 + n))
+        x, v = ctx.dev_array(w.x), ctx.dev_array(w.v)
+        ctx.set_fp(w)
+        out = torch.empty_like(x)
+        for fn, sym in ((b.chessfad_hvp, False), (b.chessfad_hvp_sym, True)):
+            for _ in range(2):
+                fn(2, x, v, out, chunk=16)
+            torch.cuda.synchronize()
+            print(f"  kernels: {kernel_key(2, 16, n=n, sym=sym)}", file=sys.stderr, flush=True)
         return
     npts = args.npts
 

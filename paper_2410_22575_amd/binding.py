@@ -37,6 +37,12 @@ class BatchChoice(ctypes.Structure):
                 ("mapping", ctypes.c_int), ("points", ctypes.c_int), ("candidates", ctypes.c_int),
                 ("ms", ctypes.c_float)]
 
+class FpShape(ctypes.Structure):
+    """struct chessfad_fp_shape"""
+    _fields_ = [("points", ctypes.c_int), ("row_blocks", ctypes.c_int), ("column_blocks", ctypes.c_int),
+                ("pairs_per_pass", ctypes.c_int), ("split", ctypes.c_int), ("grid", ctypes.c_int64),
+                ("lds_bytes", ctypes.c_size_t)]
+
 SIGNATURES = {
     "chessfad_hvp": (_i, [_i, _i, _i64, _p, _p, _p, _i, _p]),
     "chessfad_hessian": (_i, [_i, _i, _i64, _p, _p, _i, _p]),
@@ -47,6 +53,7 @@ SIGNATURES = {
     "chessfad_strerror": (_s, [_i]),
     "chessfad_default_chunk": (_i, [_i, _i]),
     "chessfad_default_mapping": (_i, [_i, _i, _i]),
+    "chessfad_fp_launch_shape": (_i, [_i, _i64, _i, _i, _p]),
     "chessfad_register_function": (_i, [_s, _pi]),
     "chessfad_release_function": (_i, [_i]),
     "chessfad_set_option": (_i, [_i, _i]),
@@ -68,6 +75,7 @@ CHESSFAD_OPT_BATCH_GRAPH = 2
 CHESSFAD_OPT_MAPPING = 3
 CHESSFAD_OPT_FP_POINTS = 4
 CHESSFAD_OPT_BATCH_TUNE = 5
+CHESSFAD_OPT_FP_BLOCKS = 6
 
 _lib = None
 
@@ -220,6 +228,14 @@ def chessfad_release_function(func_id: int) -> None:
 
 def chessfad_default_mapping(func_id: int, n: int, precision: int = 0) -> int:
     return load().chessfad_default_mapping(func_id, n, precision)
+
+
+def chessfad_fp_launch_shape(n: int, npts: int, precision: int = 0, sym: bool = False) -> dict:
+    """The launch shape of the per-call Fletcher-Powell kernel for n > 16 (host only)."""
+    out = FpShape()
+    _raise(load().chessfad_fp_launch_shape(n, npts, precision, int(sym), ctypes.byref(out)),
+           "chessfad_fp_launch_shape")
+    return {f: getattr(out, f) for f, _ in FpShape._fields_}
 
 
 def chessfad_default_chunk(func_id: int, n: int) -> int:

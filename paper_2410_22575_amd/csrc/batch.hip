@@ -167,7 +167,7 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
         e.d.fp = FpParams{c.A, c.B, nullptr, nullptr, nullptr};
         const double per_call = model_flops_per_call(c.func_id, c.n, C);
         if (fp) {
-            const FpDppGeometry g = fp_dpp_geometry(c.n, c.npts, o.points, c.precision == 1);
+            const FpDppGeometry g = fp_dpp_geometry(c.n, c.npts, o.points, 0, c.precision == 1);
             e.d.kind = 1;
             e.d.nb = g.nb;
             e.d.ppw = g.ppw;

@@ -26,6 +26,7 @@ int g_opt_fp_mfma = 1;                   // CHESSFAD_OPT_FP_MFMA
 int g_opt_batch_graph = 1;               // CHESSFAD_OPT_BATCH_GRAPH
 int g_opt_mapping = 2;                   // CHESSFAD_OPT_MAPPING
 int g_opt_fp_points = 0;                 // CHESSFAD_OPT_FP_POINTS
+int g_opt_fp_blocks = 0;                 // CHESSFAD_OPT_FP_BLOCKS
 int g_opt_batch_tune = 1;                // CHESSFAD_OPT_BATCH_TUNE
 }  // namespace
 
@@ -116,6 +117,7 @@ int option_value(int option) {
     if (option == CHESSFAD_OPT_BATCH_GRAPH) return g_opt_batch_graph;
     if (option == CHESSFAD_OPT_MAPPING) return g_opt_mapping;
     if (option == CHESSFAD_OPT_FP_POINTS) return g_opt_fp_points;
+    if (option == CHESSFAD_OPT_FP_BLOCKS) return g_opt_fp_blocks;
     if (option == CHESSFAD_OPT_BATCH_TUNE) return g_opt_batch_tune;
     return CHESSFAD_E_ARG;
 }
@@ -291,24 +293,42 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 
 }  // namespace
 
-FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, bool mixed) {
+FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, int blocks, bool mixed) {
     FpDppGeometry g;
     g.nb = (n + 15) / 16;
-    g.kbg = std::min(g.nb, 16);
-    // points per workgroup (the option's, or as many as fill the 16 lane
-    // rows with whole rounds), then row blocks per round
-    int ppw = points ? std::max(1, std::min(points, 16 / g.kbg)) : 0;
-    auto fit = [&](int pp) { return std::max(1, std::min(g.nb, 16 / (pp * g.kbg))); };
-    if (!ppw) ppw = std::max(1, 16 / (fit(1) * g.kbg));
-    g.rb = fit(ppw);
-    auto bytes = [&](int pp, int rb) {
-        return mixed ? fp_dpp_lds_bytes<float>(g.nb, pp, rb, g.kbg) : fp_dpp_lds_bytes<double>(g.nb, pp, rb, g.kbg);
+    auto bytes = [&](int pp, int rb, int kbg) {
+        return mixed ? fp_dpp_lds_bytes<float>(g.nb, pp, rb, kbg) : fp_dpp_lds_bytes<double>(g.nb, pp, rb, kbg);
     };
-    while (ppw > 1 && bytes(ppw, g.rb) > 64 * 1024) {
-        ppw /= 2;
-        g.rb = fit(ppw);
+    // column blocks per round (the option's, or every count up to 16), points
+    // per workgroup (the option's, or any that leaves a column block per
+    // lane row), and then as many row blocks as fill the 16 lane rows; the
+    // cost of a point is its rounds times a round's work per lane: 256
+    // products per tile, and about 16 instructions per J entry the lane forms
+    // (ppw (kbg + rb) entries per tile)
+    auto fit = [&](int pp, int kbg) { return std::max(1, std::min(g.nb, 16 / (pp * kbg))); };
+    double best = -1.0;
+    for (int kbg = 1; kbg <= std::min(g.nb, 16); ++kbg) {
+        if (blocks && kbg != std::min(blocks, g.nb)) continue;
+        const int pp_hi = std::max(1, 16 / kbg);
+        const int pp_lo = points ? std::max(1, std::min(points, pp_hi)) : 1;
+        for (int pp0 = pp_lo; pp0 <= (points ? pp_lo : pp_hi); ++pp0) {
+            // fewer points where their LDS rows do not fit
+            int pp = pp0, rb = fit(pp, kbg);
+            while (pp > 1 && bytes(pp, rb, kbg) > 64 * 1024) {
+                pp /= 2;
+                rb = fit(pp, kbg);
+            }
+            const int rounds = ((g.nb + rb - 1) / rb) * ((g.nb + kbg - 1) / kbg);
+            const double cost = rounds * (256.0 + 16.0 * pp * (kbg + rb)) / pp;
+            if (best < 0.0 || cost < best) {
+                best = cost;
+                g.ppw = pp;
+                g.rb = rb;
+                g.kbg = kbg;
+            }
+        }
     }
-    g.ppw = ppw;
+    while (g.rb > 1 && bytes(g.ppw, g.rb, g.kbg) > 64 * 1024) --g.rb;
     const int ibr_n = (g.nb + g.rb - 1) / g.rb;   // row-block rounds per point group
     const int64_t groups = (npts + g.ppw - 1) / g.ppw;
     // split a point group's rounds over workgroups until about 2048
@@ -316,7 +336,33 @@ FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, bool mi
     const int64_t want = (2048 + groups - 1) / groups;
     g.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ibr_n, want));
     g.grid = groups * g.rsplit;
-    g.lds = bytes(g.ppw, g.rb);
+    g.lds = bytes(g.ppw, g.rb, g.kbg);
+    return g;
+}
+
+FpDppGeometry chessfad::fp_sym_geometry(int n, int64_t npts, bool mixed) {
+    FpDppGeometry g;
+    g.nb = (n + 15) / 16;
+    const int npairs = fp_sym_pairs(g.nb);
+    double best = 0.0;
+    for (int pp = 1; pp <= 16; ++pp) {
+        // more points per workgroup only while about 1024 workgroups remain
+        if (pp > 1 && (npts + pp - 1) / pp < 1024) break;
+        const int q = std::min(16 / pp, npairs);
+        const size_t lds = mixed ? fp_sym_lds_bytes<float>(g.nb, pp, q) : fp_sym_lds_bytes<double>(g.nb, pp, q);
+        if (lds > 64 * 1024) continue;
+        // a pass: 256 products per lane and tile, and (q + 1) pp J entries
+        // per thread and tile at about 8 instructions each
+        const int passes = (npairs + q - 1) / q;
+        const double cost = passes * (256.0 + 8.0 * pp * (q + 1)) / pp;
+        if (!g.ppw || cost < best) {
+            best = cost;
+            g.ppw = pp;
+            g.q = q;
+            g.lds = lds;
+        }
+    }
+    g.grid = (npts + g.ppw - 1) / g.ppw;
     return g;
 }
 
@@ -389,6 +435,17 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         hipError_t e = launch(a, dim3((unsigned)grid), dim3(64 * kFpWaves), s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
+    if (sym && func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma == 1) {
+        // the symmetric form of the per-call kernel (DPP lane broadcasts)
+        FpDppLaunch launch = mixed ? fp_sym_entry_mixed(chunk, hess) : fp_sym_entry(chunk, hess);
+        if (!launch) return CHESSFAD_E_CHUNK;
+        const FpDppGeometry g = fp_sym_geometry(n, npts, mixed);
+        if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, 1, 1, 1};
+        a.q = g.q;
+        hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kFpDppThreads), g.lds, s);
+        return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+    }
     if (sym) {
         // symmetric vector kernel (all three functions; Fletcher-Powell with
         // n > 16 runs its contraction on the vector unit here)
@@ -412,7 +469,7 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpDppLaunch launch = mixed ? fp_dpp_entry_mixed(chunk, hess)
                                    : (grad || fval) ? fp_dpp_entry_grad(chunk) : fp_dpp_entry(chunk, hess);
         if (!launch) return CHESSFAD_E_CHUNK;
-        const FpDppGeometry g = fp_dpp_geometry(n, npts, g_opt_fp_points, mixed);
+        const FpDppGeometry g = fp_dpp_geometry(n, npts, g_opt_fp_points, g_opt_fp_blocks, mixed);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
         FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, g.rb, g.kbg, g.rsplit, grad, fval};
         hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kFpDppThreads), g.lds, s);
@@ -561,10 +618,13 @@ int chessfad_set_option(int option, int value) {
               : option == CHESSFAD_OPT_BATCH_GRAPH ? &g_opt_batch_graph
               : option == CHESSFAD_OPT_MAPPING ? &g_opt_mapping
               : option == CHESSFAD_OPT_FP_POINTS ? &g_opt_fp_points
+              : option == CHESSFAD_OPT_FP_BLOCKS ? &g_opt_fp_blocks
               : option == CHESSFAD_OPT_BATCH_TUNE ? &g_opt_batch_tune : nullptr;
     if (!slot) return CHESSFAD_E_ARG;
     if (option == CHESSFAD_OPT_FP_POINTS) {
         if (value != 0 && value != 1 && value != 4 && value != 16) return CHESSFAD_E_ARG;
+    } else if (option == CHESSFAD_OPT_FP_BLOCKS) {
+        if (value < 0 || value > 16) return CHESSFAD_E_ARG;
     } else {
         const int maxv = option == CHESSFAD_OPT_FP_MFMA ? 3 : option == CHESSFAD_OPT_MAPPING ? 2 : 1;
         if (value < 0 || value > maxv) return CHESSFAD_E_ARG;
@@ -577,6 +637,22 @@ int chessfad_set_option(int option, int value) {
 int chessfad_default_chunk(int func_id, int n) {
     int rc = check_func_n(func_id, n);
     return rc ? rc : resolve_chunk(func_id, n, 0, 16);
+}
+
+int chessfad_fp_launch_shape(int n, int64_t npts, int precision, int sym, chessfad_fp_shape* out) {
+    if (n <= kFpMaxN || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
+    if (npts < 1 || (precision != 0 && precision != 1)) return CHESSFAD_E_ARG;
+    if (!out) return CHESSFAD_E_NULL;
+    const FpDppGeometry g = sym ? fp_sym_geometry(n, npts, precision == 1)
+                                : fp_dpp_geometry(n, npts, g_opt_fp_points, g_opt_fp_blocks, precision == 1);
+    out->points = g.ppw;
+    out->row_blocks = sym ? 1 : g.rb;
+    out->column_blocks = sym ? 1 : g.kbg;
+    out->pairs_per_pass = sym ? g.q : g.rb * g.kbg;
+    out->split = g.rsplit;
+    out->grid = g.grid;
+    out->lds_bytes = g.lds;
+    return CHESSFAD_OK;
 }
 
 int chessfad_default_mapping(int func_id, int n, int precision) {

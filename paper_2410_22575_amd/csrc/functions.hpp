@@ -157,14 +157,13 @@ struct Rosenbrock {
     // its chunk seed when it lies in [cs, cs + C) (otherwise a zero seed, and
     // that window slot comes out zero).  A term outside 0 <= k < n - 1 gets a
     // zero row seed, so its second-order part is zero; its index is clamped.
-    template <class P, int C>
-    static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams&, const typename P::T* vrow) {
-        using T = typename P::T;
+    template <typename T, int C>
+    static CF_DEV void row_terms(const PointView<T>& pv, HD<T, 2>& tm, HD<T, 2>& tp, int& km, int& kp) {
         const int i = pv.i, n = pv.n, cs = pv.cs;
         auto chunk_seed = [&](int k) { return (k >= cs && k < cs + C) ? T(1) : T(0); };
-        const int km = i > 0 ? i - 1 : 0, kp = i + 1 < n ? i + 1 : i;
+        km = i > 0 ? i - 1 : 0;
+        kp = i + 1 < n ? i + 1 : i;
         const T xm = pv.x(km), xi = pv.x(i), xp = pv.x(kp);
-        typename P::Dot acc;
         {
             // term k = i - 1: window (x_{i-1}, x_i)
             HD1<T, 2> a, b;
@@ -176,9 +175,7 @@ struct Rosenbrock {
             b.d = i > 0 ? T(1) : T(0);
             b.g[0] = T(0);
             b.g[1] = chunk_seed(i);
-            const HD<T, 2> t = term<T, 2>(a, b);
-            acc.add(t.h[0], vrow[km]);
-            acc.add(t.h[1], vrow[i]);
+            tm = term<T, 2>(a, b);
         }
         {
             // term k = i: window (x_i, x_{i+1})
@@ -191,11 +188,41 @@ struct Rosenbrock {
             b.d = T(0);
             b.g[0] = T(0);
             b.g[1] = chunk_seed(i + 1);
-            const HD<T, 2> t = term<T, 2>(a, b);
-            acc.add(t.h[0], vrow[i]);
-            acc.add(t.h[1], vrow[kp]);
+            tp = term<T, 2>(a, b);
         }
+    }
+
+    template <class P, int C>
+    static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams&, const typename P::T* vrow) {
+        using T = typename P::T;
+        HD<T, 2> tm, tp;
+        int km, kp;
+        row_terms<T, C>(pv, tm, tp, km, kp);
+        typename P::Dot acc;
+        acc.add(tm.h[0], vrow[km]);
+        acc.add(tm.h[1], vrow[pv.i]);
+        acc.add(tp.h[0], vrow[pv.i]);
+        acc.add(tp.h[1], vrow[kp]);
         return acc.get();
+    }
+
+    // The call's second-order components h[l] from the same two terms (for
+    // the symmetric H.v, which also needs them one by one): column i - 1
+    // from term i - 1, column i from both in order of k, column i + 1 from
+    // term i; every other column of the chunk is an exact zero.
+    static constexpr bool kRowTerms = true;
+    template <class P, int C>
+    static CF_DEV void hrow(const PointView<typename P::T>& pv, const FpParams&, typename P::T (&h)[C]) {
+        using T = typename P::T;
+        HD<T, 2> tm, tp;
+        int km, kp;
+        row_terms<T, C>(pv, tm, tp, km, kp);
+        const int i = pv.i, cs = pv.cs;
+#pragma unroll
+        for (int l = 0; l < C; ++l) {
+            const int k = cs + l;
+            h[l] = k == i - 1 ? tm.h[0] : k == i ? tm.h[1] + tp.h[0] : k == i + 1 ? tp.h[1] : T(0);
+        }
     }
 };
 
@@ -329,6 +356,39 @@ struct Ackley {
         acc.add(f1 * si.h[0] + g1 * ci.h[0], vrow[i]);
         return acc.get();
     }
+
+    // The call's second-order components h[m] from the same terms (for the
+    // symmetric H.v): each slot's gradient products, and at slot i - cs the
+    // own term's second-order products added to them.
+    static constexpr bool kRowTerms = true;
+    template <class P, int C>
+    static CF_DEV void hrow(const PointView<typename P::T>& pv, const FpParams&, typename P::T (&h)[C]) {
+        using T = typename P::T;
+        const int i = pv.i, cs = pv.cs;
+        HD1<T, 1> yi;
+        yi.v = pv.x(i);
+        yi.d = T(1);
+        yi.g[0] = (i >= cs && i < cs + C) ? T(1) : T(0);
+        const HD<T, 1> si = sq(yi), ci = cos_of(pv, yi, i);
+        const T f1 = pv.island(1), f2d = (T)(pv.island64(2) * (double)si.d);
+        const T g1 = pv.island(4), g2d = (T)(pv.island64(5) * (double)ci.d);
+        const T own = f1 * si.h[0] + g1 * ci.h[0];
+        static_for<C>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int k = cs + m;
+            T hm = T(0);
+            if (k < pv.n) {
+                HD1<T, 1> y;
+                y.v = pv.x(k);
+                y.d = T(0);
+                y.g[0] = T(1);
+                const HD<T, 1> st = sq(y), ct = cos_of(pv, y, k);
+                hm = f2d * st.g[0] + g2d * ct.g[0];
+                if (k == i) hm += own;
+            }
+            h[m] = hm;
+        });
+    }
 };
 
 // sum_m (E_m - sum_j A_mj sin y_j + B_mj cos y_j)^2
@@ -388,6 +448,7 @@ struct FletcherPowell {
     }
 
     // every residual depends on every variable: the full evaluation
+    static constexpr bool kRowTerms = false;
     template <class P, int C>
     static CF_DEV double hvp(const PointView<typename P::T>& pv, const FpParams& prm, const typename P::T* vrow) {
         return eval_dot<P, FletcherPowell, C>(pv, prm, vrow);

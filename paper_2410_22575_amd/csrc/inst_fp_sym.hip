@@ -1,0 +1,11 @@
+// Symmetric forms of the per-call Fletcher-Powell kernel for n > 16, float64:
+// every compiled chunk size, H.v and Hessian.
+#include "dispatch.hpp"
+
+namespace chessfad {
+
+FpDppLaunch fp_sym_entry(int C, bool hess) {
+    return hess ? fp_sym_entry_c<F64, true>(C) : fp_sym_entry_c<F64, false>(C);
+}
+
+}  // namespace chessfad

@@ -1,0 +1,11 @@
+// Symmetric forms of the per-call Fletcher-Powell kernel for n > 16, mixed
+// precision: every compiled chunk size, H.v and Hessian.
+#include "dispatch.hpp"
+
+namespace chessfad {
+
+FpDppLaunch fp_sym_entry_mixed(int C, bool hess) {
+    return hess ? fp_sym_entry_c<F32C, true>(C) : fp_sym_entry_c<F32C, false>(C);
+}
+
+}  // namespace chessfad

@@ -66,6 +66,7 @@ struct FpDppArgs {
     double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
     double* fval = nullptr;  // H.v only, optional: [npts] f
     int io32 = 0;            // H.v: x, v and out are float32 (batched instances)
+    int q = 0;               // symmetric form: pairs of blocks per point per pass
 };
 
 constexpr int kFpDppThreads = 256;
@@ -159,6 +160,32 @@ __device__ __forceinline__ void fp_dpp_stage(const FpDppArgs& a, const XT* x, co
     }
 }
 
+// The value column r_m.v = E_m - sum_j A_mj sin x_j + B_mj cos x_j (float64)
+// of the points p0 .. p0 + ppw - 1 from their staged sin x and cos x: a lane
+// row per (point, residual), lane t summing the terms j = t, t + 16, ... in
+// order, then the 16 partial sums in a fixed tree; zeros past n and npts.
+__device__ __forceinline__ void fp_dpp_value_column(const FpDppArgs& a, int64_t p0, const double* sins,
+                                                    const double* coss, double* rvs) {
+    const int n = a.n, n16 = 16 * a.nb;
+    for (int task = threadIdx.x >> 4; task < a.ppw * n16; task += kFpDppThreads / 16) {
+        const int ps = task / n16, m = task - ps * n16, t = threadIdx.x & 15;
+        const int64_t p = p0 + ps;
+        const bool on = m < n && p < a.npts;
+        const double* sp = sins + ps * n16;
+        const double* cp = coss + ps * n16;
+        double acc = 0.0;
+        if (on) {
+            const double* Am = a.fp.A + (size_t)m * n;
+            const double* Bm = a.fp.B + (size_t)m * n;
+#pragma unroll 4
+            for (int j = t; j < n; j += 16) acc += Am[j] * sp[j] + Bm[j] * cp[j];
+        }
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 16);
+        if (t == 0) rvs[ps * n16 + m] = on ? a.fp.E[m] - acc : 0.0;
+    }
+}
+
 // One workgroup: point group pg, row-block rounds [ibr0, ibr1).
 //
 // A lane row (16 lanes) d is (point slot ps, row-block slot ibs, column-
@@ -197,25 +224,8 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     else
         fp_dpp_stage<kHess>(a, a.x, a.v, p0, sins, coss, vs);
     __syncthreads();
-    // 2. the value column r_m.v (float64): a lane row per (point, residual),
-    // lane t summing the terms j = t, t + 16, ... in order, then the 16
-    // partial sums in a fixed tree
-    for (int task = threadIdx.x >> 4; task < ppw * n16; task += kFpDppThreads / 16) {
-        const int ps = task / n16, m = task - ps * n16, t = threadIdx.x & 15;
-        const int64_t p = p0 + ps;
-        const bool on = m < n && p < a.npts;
-        const double* sp = sins + ps * n16;
-        const double* cp = coss + ps * n16;
-        double acc = 0.0;
-        if (on) {
-            const double* Am = a.fp.A + (size_t)m * n;
-            const double* Bm = a.fp.B + (size_t)m * n;
-            for (int j = t; j < n; j += 16) acc += Am[j] * sp[j] + Bm[j] * cp[j];
-        }
-#pragma unroll
-        for (int w = 8; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 16);
-        if (t == 0) rvs[ps * n16 + m] = on ? a.fp.E[m] - acc : 0.0;
-    }
+    // 2. the value column r_m.v (float64)
+    fp_dpp_value_column(a, p0, sins, coss, rvs);
     __syncthreads();
     if (kGrad && a.fval && ibr0 == 0 && (int)threadIdx.x < ppw) {
         const int64_t p = p0 + threadIdx.x;
@@ -269,30 +279,31 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     const int m = mt * MT + u;
                     const bool m_on = m < n;
                     const uint32_t mrow = (uint32_t)((m_on ? m : 0) * n);
-                    // four entries at a time, their loads from clamped, in-range
-                    // offsets all in flight together; sin and cos are zero past
-                    // n, and blocks past nb and residuals past n are masked
-                    const int nq = ppw * nslots;
-                    for (int q0 = 0; q0 < nq; q0 += 4) {
-                        T bv[4], av[4];
-                        int sc[4];
-                        bool on[4];
+                    // eight block slots at a time, their A and B loads (from
+                    // clamped, in-range offsets) all in flight together and
+                    // shared by the points; sin and cos are zero past n, and
+                    // blocks past nb and residuals past n are masked
+                    for (int b0 = 0; b0 < nslots; b0 += 8) {
+                        T bv[8], av[8];
+                        int col[8];
+                        bool on[8];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int q = q0 + r < nq ? q0 + r : nq - 1;
-                            const int qs = q / nslots, bs = q - qs * nslots;
+                        for (int r = 0; r < 8; ++r) {
+                            const int bs = b0 + r < nslots ? b0 + r : nslots - 1;
                             const int blk = bs < kbg ? kgr * kbg + bs : ibr * rb + (bs - kbg);
                             on[r] = m_on && blk < nb;
-                            const int col = on[r] ? 16 * blk + tt : 0;
-                            sc[r] = qs * n16 + col;
-                            const uint32_t o = mrow + (uint32_t)(col < n ? col : n - 1);
+                            col[r] = on[r] ? 16 * blk + tt : 0;
+                            const uint32_t o = mrow + (uint32_t)(col[r] < n ? col[r] : n - 1);
                             bv[r] = ld_at(Bb, o);
                             av[r] = ld_at(Ab, o);
                         }
+                        for (int qs = 0; qs < ppw; ++qs) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const T jv = bv[r] * (T)sins[sc[r]] - av[r] * (T)coss[sc[r]];
-                            if (q0 + r < nq) jt[(q0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
+                            for (int r = 0; r < 8; ++r) {
+                                const int sc = qs * n16 + col[r];
+                                const T jv = bv[r] * (T)sins[sc] - av[r] * (T)coss[sc];
+                                if (b0 + r < nslots) jt[(qs * nslots + b0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
+                            }
                         }
                     }
                     // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row

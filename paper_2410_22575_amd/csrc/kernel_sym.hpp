@@ -168,7 +168,23 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
         double m[C];
 #pragma unroll
         for (int l = 0; l < C; ++l) m[l] = 0.0;
-        if (active) {
+        if (active && !kHess && F::kRowTerms) {
+            // H.v of a function whose calls reach their second-order part
+            // through a few terms: those terms alone, component by component
+            PointView<T> pv{xs + pl * ks, t0 + pl * ks, t1 + pl * ks, isl + pl * ki, n, i, cs};
+            T h[C];
+            if constexpr (F::kRowTerms) F::template hrow<P, C>(pv, a.fp, h);
+            typename P::Dot acc;
+#pragma unroll
+            for (int l = 0; l < C; ++l)
+                if (cs + l < n) acc.add(h[l], vs[pl * ks + cs + l]);
+            red[(size_t)pl * slots + local] = acc.get();
+            if (mirrored) {
+                const double vi = (double)vs[pl * ks + i];
+#pragma unroll
+                for (int l = 0; l < C; ++l) m[l] = cs + l < n ? (double)h[l] * vi : 0.0;
+            }
+        } else if (active) {
             PointView<T> pv{xs + pl * ks, t0 + pl * ks, t1 + pl * ks, isl + pl * ki, n, i, cs};
             const HD<T, C> res = F::template eval<P, C>(pv, a.fp);
             if (kHess) {

@@ -52,15 +52,21 @@ double model_flops_per_call(int func_id, int n, int C);
 bool chunk_compiled(int c);
 
 // Launch shape of the per-call Fletcher-Powell kernel for n > 16: blocks of
-// 16 variables, points per workgroup (`points`, or chosen to fill the 16
-// lane rows when 0), row blocks and column blocks per round, the split of a
-// point group's rounds over workgroups, grid and LDS bytes.
+// 16 variables, points per workgroup and column blocks per round (`points`
+// and `blocks`, or chosen by a cost model where 0), row blocks per round
+// (as many as fill the 16 lane rows), the split of a point group's rounds
+// over workgroups, grid and LDS bytes.
 struct FpDppGeometry {
     int nb = 0, ppw = 0, rb = 1, kbg = 1, rsplit = 1;
+    int q = 0;   // symmetric form: block pairs per point per pass
     int64_t grid = 0;
     size_t lds = 0;
 };
-FpDppGeometry fp_dpp_geometry(int n, int64_t npts, int points, bool mixed);
+FpDppGeometry fp_dpp_geometry(int n, int64_t npts, int points, int blocks, bool mixed);
+// Launch shape of its symmetric form: points per workgroup and block pairs
+// per pass, from a cost model of a pass (products per lane plus J entries
+// formed per thread), within 64 KiB of LDS.
+FpDppGeometry fp_sym_geometry(int n, int64_t npts, bool mixed);
 
 // Current value of a chessfad_option.
 int option_value(int option);

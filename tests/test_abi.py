@@ -170,6 +170,10 @@ def test_options(lib):
         assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, bad) == E_ARG
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 4) == 0   # the default is 0 (automatic)
     assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 0) == 4
+    for bad in (-1, 17):
+        assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, bad) == E_ARG
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, 3) == 0   # the default is 0 (cost model)
+    assert lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, 0) == 3
 
 
 def test_default_chunk(lib):
@@ -264,3 +268,39 @@ def test_batch_noalloc_checks_before_any_device_work(lib):
     # copies of A and B: more than the fixed array holds
     big = _inst(func=FP, n=512, chunk=16, precision=1, A=FAKE * 8, B=FAKE * 16, alpha=FAKE * 32)
     assert run([big] * 40) == (E_ARG, -1)
+
+
+def test_fp_launch_shape_invariants(lib):
+    """The per-call Fletcher-Powell kernel's launch shapes (n > 16), full and
+    symmetric form, both precisions, every points / column-blocks option:
+    at most 16 lane rows per workgroup, no more blocks than the variables
+    have, LDS within 64 KiB, a nonempty grid that covers the points."""
+    import itertools
+    for n in list(range(17, 80)) + [100, 128, 200, 255, 256, 257, 300, 400, 511, 512]:
+        nb = (n + 15) // 16
+        for npts, prec in itertools.product((1, 5, 37, 1024, 1 << 18), (0, 1)):
+            for points, blocks in itertools.product((0, 1, 4, 16), (0, 1, 3, 16)):
+                lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, points)
+                lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, blocks)
+                s = binding.chessfad_fp_launch_shape(n, npts, prec)
+                assert s["points"] >= 1 and 1 <= s["row_blocks"] <= nb and 1 <= s["column_blocks"] <= nb, (n, s)
+                assert s["points"] * s["row_blocks"] * s["column_blocks"] <= 16, (n, s)
+                if blocks:
+                    assert s["column_blocks"] == min(blocks, nb), (n, blocks, s)
+                assert 0 < s["lds_bytes"] <= 64 * 1024, (n, s)
+                rounds = -(-nb // s["row_blocks"])
+                assert 1 <= s["split"] <= rounds, (n, s)
+                assert s["grid"] == -(-npts // s["points"]) * s["split"], (n, npts, s)
+            lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 0)
+            lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, 0)
+            s = binding.chessfad_fp_launch_shape(n, npts, prec, sym=True)
+            assert s["points"] >= 1 and 1 <= s["pairs_per_pass"] <= nb * (nb + 1) // 2, (n, s)
+            assert s["points"] * s["pairs_per_pass"] <= 16 and 0 < s["lds_bytes"] <= 64 * 1024, (n, s)
+            assert s["grid"] == -(-npts // s["points"]), (n, npts, s)
+    for bad_n in (16, 513):
+        with pytest.raises(binding.ChessfadError):
+            binding.chessfad_fp_launch_shape(bad_n, 10)
+    with pytest.raises(binding.ChessfadError):
+        binding.chessfad_fp_launch_shape(64, 0)
+    with pytest.raises(binding.ChessfadError):
+        binding.chessfad_fp_launch_shape(64, 10, precision=2)

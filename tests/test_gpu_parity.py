@@ -334,3 +334,32 @@ def test_fp_per_call_points_per_workgroup(gpu_lib, points, n, npts):
             assert np.max(np.abs(f.cpu().numpy() - f_ref) / (np.abs(f_ref) + 1e-300)) <= 1e-11
     finally:
         gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_POINTS, prev)
+
+
+@pytest.mark.parametrize("blocks", [1, 3, 4, 16])
+@pytest.mark.parametrize("n,npts", [(64, 21), (100, 9), (257, 2)])
+def test_fp_per_call_column_blocks(gpu_lib, blocks, n, npts):
+    """The per-call Fletcher-Powell kernel for n > 16 with 1, 3, 4 or 16
+    column blocks per round (row blocks then fill the lane rows; the last
+    round of each kind ragged): H.v and Hessian against the closed form, and
+    H.v bit for bit against the cost model's choice where only the round
+    shape differs (same products, same order within each call; the row's
+    partials are summed over its column blocks in block order either way)."""
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(8800 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref, hmax = _hmax(FP, w, E)
+    r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
+    r0 = gpu_lib.chessfad_hvp(FP, x, v, chunk=8).cpu().numpy()
+    prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_BLOCKS, blocks)
+    try:
+        for c in (2, 8):
+            print(f"[case] fp per-call n={n} npts={npts} blocks={blocks} chunk={c}", flush=True)
+            r = gpu_lib.chessfad_hvp(FP, x, v, chunk=c).cpu().numpy()
+            H = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
+            assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64
+            assert np.max(np.abs(H - H_ref).max(axis=(1, 2)) / hmax) <= TOL64
+            if c == 8:
+                np.testing.assert_array_equal(r, r0)
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_BLOCKS, prev)

@@ -95,6 +95,60 @@ def test_symmetric_agrees_with_full_form(gpu_lib, func, mfma):
             assert np.abs(ry - rf).max() <= 1e-13 * scale * np.abs(w.v).max()
 
 
+@pytest.mark.parametrize("n,npts", [(17, 11), (33, 9), (64, 7), (100, 5)])
+def test_fp_symmetric_per_call_kernel(gpu_lib, n, npts):
+    """Fletcher-Powell n > 16: the per-call kernel's symmetric form (block
+    pairs kb >= ib in passes, mirrors summed per column) against the oracle's
+    SC-HESS-VEC and SCHUNK-HESS at every point, every chunk size; mirrored
+    entries are exact copies; the own-chunk entries and the counted calls
+    equal the full form's (same products in the same order; the own part
+    is summed in another place)."""
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(6600 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    for c in CHUNKS:
+        print(f"[case] fp sym per-call n={n} npts={npts} C={c}", flush=True)
+        r = gpu_lib.chessfad_hvp_sym(FP, x, v, chunk=c).cpu().numpy()
+        H = gpu_lib.chessfad_hessian_sym(FP, x, chunk=c).cpu().numpy()
+        ro = chunked.hvp(FP, w.x, w.v, c, w.A, w.B, E, sym=True, nthreads=4)
+        Ho = chunked.hessian(FP, w.x, c, w.A, w.B, E, sym=True, nthreads=4)
+        scale = np.abs(Ho).max(axis=(1, 2))
+        er = (np.abs(r - ro).max(axis=1) / (scale * np.abs(w.v).max(axis=1))).max()
+        eh = (np.abs(H - Ho).max(axis=(1, 2)) / scale).max()
+        assert er <= 1e-12 and eh <= 1e-12, (c, er, eh)
+        for i in range(n):
+            own = (i // c) * c
+            np.testing.assert_array_equal(H[:, i, :own], H[:, :own, i])
+        Hf = gpu_lib.chessfad_hessian(FP, x, chunk=c).cpu().numpy()
+        for i in range(n):
+            own = (i // c) * c
+            assert np.abs(H[:, i, own:] - Hf[:, i, own:]).max() <= 1e-14 * scale.max()
+
+
+@pytest.mark.parametrize("n", [40, 200])
+def test_fp_symmetric_mixed_and_many_points(gpu_lib, n):
+    """Several points per workgroup (2^12 points) and the mixed policy of the
+    symmetric per-call kernel, against the closed form on sampled points."""
+    npts = 1 << 12 if n == 40 else 1100
+    w = inputs.make_workload(FP, n, npts, inputs.rng_for(6700 + n))
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    idx = np.random.default_rng(n).choice(npts, 6, replace=False)
+    idx[0] = npts - 1   # the last, ragged workgroup
+    Hs = cf.hessian(FP, w.x[idx], w.A, w.B, E)
+    hmax = np.abs(Hs).max(axis=(1, 2))
+    rs = np.einsum("pij,pj->pi", Hs, w.v[idx])
+    for c in (2, 8, 16):
+        for prec, tol in ((0, 1e-12), (1, TOL32[FP])):
+            fn = gpu_lib.chessfad_hvp_sym
+            r = fn(FP, x, v, chunk=c, precision=prec).cpu().numpy()[idx]
+            er = (np.abs(r - rs).max(axis=1) / (hmax * np.abs(w.v[idx]).max(axis=1))).max()
+            print(f"[case] fp sym n={n} C={c} precision={prec}: err {er:.2e}", flush=True)
+            assert er <= tol, (c, prec, er)
+            if prec == 1:
+                assert er > 1e-12   # float32 arithmetic really ran
+
+
 @pytest.mark.parametrize("func", [R, A, FP])
 @pytest.mark.parametrize("n", [16, 40])
 def test_symmetric_mixed_precision(gpu_lib, func, n):
@@ -115,9 +169,9 @@ def test_symmetric_mixed_precision(gpu_lib, func, n):
 
 @pytest.mark.parametrize("func", [R, A, FP])
 def test_symmetric_larger_n_and_default_chunk(gpu_lib, func):
-    for n, npts in ((64, 40), (128, 6), (256, 2)):
-        if func == FP and n > 64:
-            continue  # the vector contraction at n >= 128 is slow to check; n = 64 covers the path
+    for n, npts in ((64, 40), (128, 6), (256, 2), (512, 2)):
+        if func != FP and n > 256:
+            continue
         w = inputs.make_workload(func, n, npts, inputs.rng_for(6300 + 10 * func + n))
         E = _setup(gpu_lib, w)
         r = gpu_lib.chessfad_hvp_sym(func, _dev(w.x), _dev(w.v)).cpu().numpy()   # chunk = 0
