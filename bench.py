@@ -97,8 +97,6 @@ KERNEL_SOURCES = {
     "fp_call_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
     "fp_dpp_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp"),
     "fp_rows_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_rows.hpp"),
-    "fp_sym_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp",
-                      "kernel_fp_sym.hpp"),
     "sym_kernel": ("hd.hpp", "functions.hpp", "kernel_sym.hpp"),
 }
 
@@ -116,7 +114,7 @@ def kernel_sha(key, read=None) -> str:
     family = key.split("<")[0]
     h = hashlib.sha256()
     h.update(" ".join(build.FLAGS[:-6]).encode())   # the flags, without the include paths
-    if family.startswith(("fp_call", "fp_dpp", "fp_sym")):
+    if family.startswith(("fp_call", "fp_dpp")):
         h.update(inspect.getsource(build.write_dpp_blocks_inc).encode())
     for f in KERNEL_SOURCES.get(family, ()):
         rel = os.path.join("paper_2410_22575_amd", "csrc", f)
@@ -137,7 +135,7 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
             return f"fp_mfma_kernel<{prec}, {c}, {min(8, max(1, (2 * n + 3) // 4))}, false, true>" + at
         return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false>" + at
     if f == 2:
-        return (f"fp_sym_kernel<{prec}, {c}, false>" if sym else f"fp_dpp_kernel<{prec}, {c}, false, false>") + at
+        return f"fp_dpp_kernel<{prec}, {c}, false, false, {'true' if sym else 'false'}>" + at
     func = {0: "Rosenbrock", 1: "Ackley"}[f]
     if sym:
         return f"sym_kernel<{prec}, {func}, {c}, false>" + at

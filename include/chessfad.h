@@ -250,10 +250,11 @@ const char* chessfad_strerror(int code);
  *                         as fill the workgroup's 16 lane rows with whole
  *                         rounds of row and column blocks.
  *   CHESSFAD_OPT_FP_BLOCKS  column blocks of 16 variables per round of the
- *                         same kernel: 1 .. 16 (at most ceil(n / 16)); 0
- *                         (default): with the points per workgroup, the
- *                         count that a cost model of a round (products per
- *                         lane, J entries formed per lane) finds cheapest.
+ *                         same kernel (full and symmetric form): 1 .. 16 (at
+ *                         most ceil(n / 16)); 0 (default): with the points
+ *                         per workgroup, the count that a cost model of a
+ *                         round (products per lane, J entries formed per
+ *                         lane) finds cheapest.
  *   CHESSFAD_OPT_BATCH_TUNE  1 (default): chessfad_batch_create tunes the
  *                         body configuration of the instances with chunk 0
  *                         on the instances themselves (see below); 0: they
@@ -399,16 +400,16 @@ int chessfad_batch_run_noalloc(const chessfad_instance* inst, int ninst, void* s
  * (host only, no device work): what chessfad_hvp / _mixed (sym = 0) or
  * chessfad_hvp_sym (sym = 1) would launch for npts points at precision 0
  * or 1 under the current CHESSFAD_OPT_FP_POINTS / CHESSFAD_OPT_FP_BLOCKS.
- * Full form: each of `points` points per workgroup takes, per round,
- * row_blocks x column_blocks (block of 16 rows, block of 16 columns) pairs
- * on that many 16-lane rows, a point group's rounds split over `split`
- * workgroups.  Symmetric form: per pass, pairs_per_pass of the pairs
- * kb >= ib per point.  CHESSFAD_E_N for n outside 17 .. 512,
+ * Each of `points` points per workgroup takes, per round, row_blocks x
+ * column_blocks (block of 16 rows, block of 16 columns) pairs on that many
+ * 16-lane rows, a point group's rounds split over `split` workgroups; the
+ * symmetric form takes only the pairs with column block >= row block, one
+ * workgroup per point group (split = 1).  CHESSFAD_E_N for n outside 17 .. 512,
  * CHESSFAD_E_ARG for npts < 1 or another precision, CHESSFAD_E_NULL for
  * out == NULL.
  */
 typedef struct {
-    int points, row_blocks, column_blocks, pairs_per_pass, split;
+    int points, row_blocks, column_blocks, split;
     int64_t grid;        /* workgroups */
     size_t lds_bytes;    /* per workgroup */
 } chessfad_fp_shape;

@@ -40,7 +40,7 @@ class BatchChoice(ctypes.Structure):
 class FpShape(ctypes.Structure):
     """struct chessfad_fp_shape"""
     _fields_ = [("points", ctypes.c_int), ("row_blocks", ctypes.c_int), ("column_blocks", ctypes.c_int),
-                ("pairs_per_pass", ctypes.c_int), ("split", ctypes.c_int), ("grid", ctypes.c_int64),
+                ("split", ctypes.c_int), ("grid", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_size_t)]
 
 SIGNATURES = {

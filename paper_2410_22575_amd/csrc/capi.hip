@@ -340,29 +340,49 @@ FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, int blo
     return g;
 }
 
-FpDppGeometry chessfad::fp_sym_geometry(int n, int64_t npts, bool mixed) {
+FpDppGeometry chessfad::fp_sym_geometry(int n, int64_t npts, int blocks, bool mixed) {
     FpDppGeometry g;
     g.nb = (n + 15) / 16;
-    const int npairs = fp_sym_pairs(g.nb);
-    double best = 0.0;
-    for (int pp = 1; pp <= 16; ++pp) {
-        // more points per workgroup only while about 1024 workgroups remain
-        if (pp > 1 && (npts + pp - 1) / pp < 1024) break;
-        const int q = std::min(16 / pp, npairs);
-        const size_t lds = mixed ? fp_sym_lds_bytes<float>(g.nb, pp, q) : fp_sym_lds_bytes<double>(g.nb, pp, q);
-        if (lds > 64 * 1024) continue;
-        // a pass: 256 products per lane and tile, and (q + 1) pp J entries
-        // per thread and tile at about 8 instructions each
-        const int passes = (npairs + q - 1) / q;
-        const double cost = passes * (256.0 + 8.0 * pp * (q + 1)) / pp;
-        if (!g.ppw || cost < best) {
-            best = cost;
-            g.ppw = pp;
-            g.q = q;
-            g.lds = lds;
+    auto bytes = [&](int pp, int rb, int kbg) {
+        return mixed ? fp_dpp_lds_bytes<float>(g.nb, pp, rb, kbg, true)
+                     : fp_dpp_lds_bytes<double>(g.nb, pp, rb, kbg, true);
+    };
+    // the rounds of the pairs kb >= ib: row-block group r starts at the
+    // column group that holds its first row block
+    auto rounds = [&](int rb, int kbg) {
+        const int kgr_n = (g.nb + kbg - 1) / kbg;
+        int r = 0;
+        for (int ibr = 0; ibr * rb < g.nb; ++ibr) r += kgr_n - (ibr * rb) / kbg;
+        return r;
+    };
+    // the full form's cost model over these rounds; a point group is one
+    // workgroup, so more points per workgroup only while about 1024
+    // workgroups remain
+    // (equal costs: the fewer LDS bytes per point, for occupancy)
+    double best = -1.0, best_lds = 0.0;
+    for (int kbg = 1; kbg <= std::min(g.nb, 16); ++kbg)
+        for (int pp = 1; pp * kbg <= 16; ++pp) {
+            if (blocks && kbg != std::min(blocks, g.nb)) break;
+            if (pp > 1 && (npts + pp - 1) / pp < 1024) break;
+            const int rb = std::max(1, std::min(g.nb, 16 / (pp * kbg)));
+            const size_t lds = bytes(pp, rb, kbg);
+            if (lds > 64 * 1024) continue;
+            const double cost = rounds(rb, kbg) * (256.0 + 16.0 * pp * (kbg + rb)) / pp;
+            const double lds_pt = (double)lds / pp;
+            if (best < 0.0 || cost < best * (1.0 - 1e-9) || (cost <= best * (1.0 + 1e-9) && lds_pt < best_lds)) {
+                best = cost;
+                best_lds = lds_pt;
+                g.ppw = pp;
+                g.rb = rb;
+                g.kbg = kbg;
+            }
         }
+    if (best < 0.0) {   // not reached for n <= 512 (one point, one block pair fits)
+        g.ppw = g.rb = g.kbg = 1;
     }
+    g.rsplit = 1;
     g.grid = (npts + g.ppw - 1) / g.ppw;
+    g.lds = bytes(g.ppw, g.rb, g.kbg);
     return g;
 }
 
@@ -437,12 +457,11 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     }
     if (sym && func_id == CHESSFAD_FLETCHER_POWELL && n > kFpMaxN && g_opt_fp_mfma == 1) {
         // the symmetric form of the per-call kernel (DPP lane broadcasts)
-        FpDppLaunch launch = mixed ? fp_sym_entry_mixed(chunk, hess) : fp_sym_entry(chunk, hess);
+        FpDppLaunch launch = mixed ? fp_dpp_sym_entry_mixed(chunk, hess) : fp_dpp_sym_entry(chunk, hess);
         if (!launch) return CHESSFAD_E_CHUNK;
-        const FpDppGeometry g = fp_sym_geometry(n, npts, mixed);
+        const FpDppGeometry g = fp_sym_geometry(n, npts, g_opt_fp_blocks, mixed);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
-        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, 1, 1, 1};
-        a.q = g.q;
+        FpDppArgs a{x, v, out, fp, npts, n, g.nb, g.ppw, g.rb, g.kbg, 1};
         hipError_t e = launch(a, dim3((unsigned)g.grid), dim3(kFpDppThreads), g.lds, s);
         return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
     }
@@ -643,12 +662,11 @@ int chessfad_fp_launch_shape(int n, int64_t npts, int precision, int sym, chessf
     if (n <= kFpMaxN || n > CHESSFAD_MAX_N) return CHESSFAD_E_N;
     if (npts < 1 || (precision != 0 && precision != 1)) return CHESSFAD_E_ARG;
     if (!out) return CHESSFAD_E_NULL;
-    const FpDppGeometry g = sym ? fp_sym_geometry(n, npts, precision == 1)
+    const FpDppGeometry g = sym ? fp_sym_geometry(n, npts, g_opt_fp_blocks, precision == 1)
                                 : fp_dpp_geometry(n, npts, g_opt_fp_points, g_opt_fp_blocks, precision == 1);
     out->points = g.ppw;
-    out->row_blocks = sym ? 1 : g.rb;
-    out->column_blocks = sym ? 1 : g.kbg;
-    out->pairs_per_pass = sym ? g.q : g.rb * g.kbg;
+    out->row_blocks = g.rb;
+    out->column_blocks = g.kbg;
     out->split = g.rsplit;
     out->grid = g.grid;
     out->lds_bytes = g.lds;

@@ -5,7 +5,6 @@
 
 #include "kernel_fp_call.hpp"
 #include "kernel_fp_dpp.hpp"
-#include "kernel_fp_sym.hpp"
 #include "kernel_fp_mfma.hpp"
 #include "kernel_fp_tile.hpp"
 #include "kernel_fp_rows.hpp"
@@ -160,20 +159,20 @@ FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess);
 
 using FpDppLaunch = hipError_t (*)(const FpDppArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
 
-template <class P, int C, bool kHess, bool kGrad>
+template <class P, int C, bool kHess, bool kGrad, bool kSym>
 hipError_t launch_fp_dpp(const FpDppArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((fp_dpp_kernel<P, C, kHess, kGrad>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((fp_dpp_kernel<P, C, kHess, kGrad, kSym>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
-template <class P, bool kHess, bool kGrad>
+template <class P, bool kHess, bool kGrad, bool kSym = false>
 FpDppLaunch fp_dpp_entry_c(int C) {
     switch (C) {
-        case 1: return &launch_fp_dpp<P, 1, kHess, kGrad>;
-        case 2: return &launch_fp_dpp<P, 2, kHess, kGrad>;
-        case 4: return &launch_fp_dpp<P, 4, kHess, kGrad>;
-        case 8: return &launch_fp_dpp<P, 8, kHess, kGrad>;
-        case 16: return &launch_fp_dpp<P, 16, kHess, kGrad>;
+        case 1: return &launch_fp_dpp<P, 1, kHess, kGrad, kSym>;
+        case 2: return &launch_fp_dpp<P, 2, kHess, kGrad, kSym>;
+        case 4: return &launch_fp_dpp<P, 4, kHess, kGrad, kSym>;
+        case 8: return &launch_fp_dpp<P, 8, kHess, kGrad, kSym>;
+        case 16: return &launch_fp_dpp<P, 16, kHess, kGrad, kSym>;
         default: return nullptr;
     }
 }
@@ -185,28 +184,9 @@ FpDppLaunch fp_dpp_entry(int C, bool hess);
 FpDppLaunch fp_dpp_entry_grad(int C);
 FpDppLaunch fp_dpp_entry_mixed(int C, bool hess);
 
-template <class P, int C, bool kHess>
-hipError_t launch_fp_sym(const FpDppArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((fp_sym_kernel<P, C, kHess>), grid, block, lds, s, a);
-    return hipGetLastError();
-}
-
-template <class P, bool kHess>
-FpDppLaunch fp_sym_entry_c(int C) {
-    switch (C) {
-        case 1: return &launch_fp_sym<P, 1, kHess>;
-        case 2: return &launch_fp_sym<P, 2, kHess>;
-        case 4: return &launch_fp_sym<P, 4, kHess>;
-        case 8: return &launch_fp_sym<P, 8, kHess>;
-        case 16: return &launch_fp_sym<P, 16, kHess>;
-        default: return nullptr;
-    }
-}
-
-// The symmetric forms of the per-call Fletcher-Powell kernel for n > 16:
-// float64 and mixed precision (one translation unit each).
-FpDppLaunch fp_sym_entry(int C, bool hess);
-FpDppLaunch fp_sym_entry_mixed(int C, bool hess);
+// Its symmetric forms: float64 and mixed precision (one translation unit each).
+FpDppLaunch fp_dpp_sym_entry(int C, bool hess);
+FpDppLaunch fp_dpp_sym_entry_mixed(int C, bool hess);
 
 using FpRowsLaunch = hipError_t (*)(const FpRowsArgs&, dim3 grid, dim3 block, hipStream_t);
 

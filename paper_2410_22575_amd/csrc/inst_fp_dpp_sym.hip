@@ -4,8 +4,8 @@
 
 namespace chessfad {
 
-FpDppLaunch fp_sym_entry(int C, bool hess) {
-    return hess ? fp_sym_entry_c<F64, true>(C) : fp_sym_entry_c<F64, false>(C);
+FpDppLaunch fp_dpp_sym_entry(int C, bool hess) {
+    return hess ? fp_dpp_entry_c<F64, true, false, true>(C) : fp_dpp_entry_c<F64, false, false, true>(C);
 }
 
 }  // namespace chessfad

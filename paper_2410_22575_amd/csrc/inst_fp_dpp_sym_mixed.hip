@@ -4,8 +4,8 @@
 
 namespace chessfad {
 
-FpDppLaunch fp_sym_entry_mixed(int C, bool hess) {
-    return hess ? fp_sym_entry_c<F32C, true>(C) : fp_sym_entry_c<F32C, false>(C);
+FpDppLaunch fp_dpp_sym_entry_mixed(int C, bool hess) {
+    return hess ? fp_dpp_entry_c<F32C, true, false, true>(C) : fp_dpp_entry_c<F32C, false, false, true>(C);
 }
 
 }  // namespace chessfad

@@ -66,7 +66,6 @@ struct FpDppArgs {
     double* grad = nullptr;  // H.v only, optional: [npts][n] gradient
     double* fval = nullptr;  // H.v only, optional: [npts] f
     int io32 = 0;            // H.v: x, v and out are float32 (batched instances)
-    int q = 0;               // symmetric form: pairs of blocks per point per pass
 };
 
 constexpr int kFpDppThreads = 256;
@@ -76,13 +75,17 @@ constexpr int kFpDppTile = 16;   // residuals per J tile (MT x 16 lanes = the wo
 // cos x, r.v, v (16 nb each); the row partials of a round (16 x 16), the
 // rows' running sums and own parts (ppw x rb x 16 each); the D tile of the
 // round's row blocks, [point][row-block slot][residual][lane] (float64);
-// then the J tile, [point][block slot][residual][lane] of T.
-__host__ __device__ inline size_t fp_dpp_lds_doubles(int nb, int ppw, int rb) {
+// then the J tile, [point][block slot][residual][lane] of T.  The symmetric
+// form keeps sin x, cos x, v, r.v (whose space then holds the running
+// results), the row and the mirror partials of a round (16 x 16 each) and
+// the J tile.
+__host__ __device__ inline size_t fp_dpp_lds_doubles(int nb, int ppw, int rb, bool sym = false) {
+    if (sym) return (size_t)4 * ppw * 16 * nb + 512;
     return (size_t)4 * ppw * 16 * nb + 256 + 2 * (size_t)ppw * rb * 16 + (size_t)ppw * rb * kFpDppTile * 16;
 }
 template <typename T>
-__host__ __device__ inline size_t fp_dpp_lds_bytes(int nb, int ppw, int rb, int kbg) {
-    return fp_dpp_lds_doubles(nb, ppw, rb) * sizeof(double) +
+__host__ __device__ inline size_t fp_dpp_lds_bytes(int nb, int ppw, int rb, int kbg, bool sym = false) {
+    return fp_dpp_lds_doubles(nb, ppw, rb, sym) * sizeof(double) +
            (size_t)ppw * (kbg + rb) * kFpDppTile * 16 * sizeof(T);
 }
 
@@ -199,8 +202,23 @@ __device__ __forceinline__ void fp_dpp_value_column(const FpDppArgs& a, int64_t 
 // (DPP).  After the last tile: the Hessian chunk of each call is stored, or
 // each call's chunk dot with v is added to the row's partial; the partials
 // of a row's column blocks are summed in block order through LDS.
-template <class Prec, int C, bool kHess, bool kGrad>
+//
+// kSym: the symmetric forms SC-HESS-VEC and SCHUNK-HESS (Sec. III.B,
+// Sec. VI).  Only the calls whose chunk is the row's own chunk or lies right
+// of it are evaluated: the pairs kb >= ib (a row-block group's rounds start
+// at the column group that holds its first row block).  In the diagonal pair
+// lane t counts its calls jc >= t / C and mirrors jc > t / C; right of the
+// diagonal every call is counted and mirrored.  A mirrored entry H(i, s)
+// stands for H(s, i) too: the Hessian stores it twice; H.v adds H(i, s) v_i
+// to the result of column s, summed over the pair's 16 rows by recursive
+// halving across the lane row (lane c ends with column 16 kb + c).  After a
+// round the pairs' row partials and mirror partials are added, pair by pair
+// in lane-row order, to a running result per (point, variable) in LDS; a
+// point group is one workgroup (no split), and the result is written after
+// its last round.
+template <class Prec, int C, bool kHess, bool kGrad, bool kSym = false>
 __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int ibr0, int ibr1, double* lds) {
+    static_assert(!(kSym && kGrad), "the symmetric form has no gradient output");
     using T = typename Prec::T;
     constexpr int MT = kFpDppTile;
     const int n = a.n, nb = a.nb, ppw = a.ppw, rb = a.rb, kbg = a.kbg, n16 = 16 * nb;
@@ -210,10 +228,12 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     double* rvs = coss + ppw * n16;
     double* vs = rvs + ppw * n16;
     double* part = vs + ppw * n16;            // [16 lane rows][16]
-    double* rowsum = part + 256;              // [ppw][rb][16]
+    double* rowsum = part + 256;              // [ppw][rb][16]; kSym: the mirror partials [16 lane rows][16]
     double* owns = rowsum + ppw * rb * 16;    // [ppw][rb][16]
     double* dt = owns + ppw * rb * 16;        // [ppw][rb][MT][16]
-    T* jt = reinterpret_cast<T*>(dt + ppw * rb * MT * 16);   // [ppw][nslots][MT][16]
+    T* jt = reinterpret_cast<T*>(kSym ? rowsum + 256 : dt + ppw * rb * MT * 16);   // [ppw][nslots][MT][16]
+    double* mirp = rowsum;
+    double* sacc = rvs;   // kSym, after the prologue: H.v running results, or the rows' own parts
     const int64_t p0 = pg * ppw;
 
     // 1. sin x, cos x and v of the workgroup's points (zeros past n and npts);
@@ -227,6 +247,38 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     // 2. the value column r_m.v (float64)
     fp_dpp_value_column(a, p0, sins, coss, rvs);
     __syncthreads();
+    if constexpr (kSym) {
+        // the rows' own parts own_i = sum_m r_m.v D_mi, D_mi = A_mi sin x_i +
+        // B_mi cos x_i (float64, m in order), held in registers until every
+        // thread has read r.v; their space then starts the running results
+        // at own_i v_i (H.v) or keeps own_i (Hessian)
+        constexpr int kMaxTasks = 8;   // ppw 16 nb <= 2048 (the LDS limit)
+        double ownr[kMaxTasks];
+#pragma unroll
+        for (int k = 0; k < kMaxTasks; ++k) {
+            const int task = threadIdx.x + k * kFpDppThreads;
+            ownr[k] = 0.0;
+            if (task < ppw * n16) {
+                const int ps = task / n16, i = task - ps * n16;
+                if (i < n) {
+                    const double s = sins[task], c = coss[task];
+                    const double* rp = rvs + ps * n16;
+                    const double* Ai = a.fp.A + i;
+                    const double* Bi = a.fp.B + i;
+                    double own = 0.0;
+#pragma unroll 4
+                    for (int m = 0; m < n; ++m) own += rp[m] * (Ai[(size_t)m * n] * s + Bi[(size_t)m * n] * c);
+                    ownr[k] = kHess ? own : own * vs[task];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxTasks; ++k) {
+            const int task = threadIdx.x + k * kFpDppThreads;
+            if (task < ppw * n16) sacc[task] = ownr[k];
+        }
+    }
     if (kGrad && a.fval && ibr0 == 0 && (int)threadIdx.x < ppw) {
         const int64_t p = p0 + threadIdx.x;
         if (p < a.npts) {
@@ -259,9 +311,9 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
         const int ib = ibr * rb + ibs;
         const int i = 16 * ib + t;
         const bool row_live = lr_on && p < a.npts && ib < nb && i < n;
-        for (int kgr = 0; kgr < kgr_n; ++kgr) {
+        for (int kgr = kSym ? (ibr * rb) / kbg : 0; kgr < kgr_n; ++kgr) {
             const int kb = kgr * kbg + kbs;
-            const bool pair_on = lr_on && ib < nb && kb < nb;
+            const bool pair_on = lr_on && ib < nb && kb < nb && (!kSym || kb >= ib);
             // the lane row of the row's diagonal pair also forms the row's own
             // part sum_m r_m.v D_mi (and the gradient's sum_m r_m.v J_mi),
             // float64, from the tiles
@@ -308,7 +360,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     }
                     // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row
                     // blocks whose diagonal pair is in this round
-                    for (int q = 0; q < ppw * rb; ++q) {
+                    for (int q = 0; q < (kSym ? 0 : ppw * rb); ++q) {
                         const int qs = q / rb, blk = ibr * rb + (q - qs * rb);
                         if (blk >= nb || blk < kgr * kbg || blk >= kgr * kbg + kbg) continue;
                         const int col = 16 * blk + tt;
@@ -318,7 +370,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     }
                 }
                 __syncthreads();
-                if (diag) {
+                if (!kSym && diag) {
                     const double* dp = dt + (size_t)((ps * rb + ibs) * MT) * 16 + t;
 #pragma unroll 4
                     for (int u = 0; u < MT; ++u) {
@@ -345,14 +397,18 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     for (int jc = 0; jc < 16 / C; ++jc) sums[jc].close_block();
                 }
             }
-            if (diag) {
+            if (!kSym && diag) {
                 owns[(ps * rb + ibs) * 16 + t] = own;
                 if (kGrad && row_live) a.grad[p * n + i] = gd + gd;
             }
-            // the calls of the pair
+            // the calls of the pair (kSym: calls jc >= tc counted, jc > tc mirrored)
             double prt = 0.0;
             if (pair_on) {
+                const int tc = kSym && kb == ib ? t / C : -1;
                 const double vk = kHess ? 0.0 : vp[16 * kb + t];
+                double w[kSym && !kHess ? 16 : 1];   // kSym H.v: mirror terms h v_i per column 16 kb + c
+#pragma unroll
+                for (int c = 0; c < (kSym && !kHess ? 16 : 1); ++c) w[c] = 0.0;
                 static_for<16 / C>([&](auto jcc) {
                     constexpr int jc = decltype(jcc)::value;
                     constexpr int cl = jc * C;   // the chunk's first lane in the row
@@ -362,9 +418,16 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
 #pragma unroll
                     for (int l = 0; l < C; ++l) h[l] = sums[jc].value(l);
                     if constexpr (kHess) {
+                        if (jc < tc) return;
+                        if (kSym && jc > tc && row_live) {
+                            // SCHUNK-HESS: the mirror image H[p][cs + l][i]
+#pragma unroll
+                            for (int l = 0; l < C; ++l)
+                                if (cs + l < n) a.out[((size_t)p * n + cs + l) * n + i] = h[l] + h[l];
+                        }
                         // CHUNK-HESS: H[p][i][cs + l] = 2 (products + [cs + l = i] own)
                         if (kb == ib) {
-                            const double own = owns[(ps * rb + ibs) * 16 + t];
+                            const double own = kSym ? sacc[ps * n16 + i] : owns[(ps * rb + ibs) * 16 + t];
 #pragma unroll
                             for (int l = 0; l < C; ++l)
                                 if (cs + l == i) h[l] += own;
@@ -379,11 +442,48 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         // the chunk dot with v (v of lane cl + l), in call order
                         double dot = 0.0;
                         DppChunkDot<C, cl>::run(dot, vk, h);
-                        prt += dot;
+                        if (jc >= tc) prt += dot;
+                        if constexpr (kSym) {
+                            const double vi = vp[i];   // zero past n
+#pragma unroll
+                            for (int l = 0; l < C; ++l) w[cl + l] = jc > tc ? h[l] * vi : 0.0;
+                        }
                     }
                 });
+                if constexpr (kSym && !kHess) {
+                    // recursive halving over the lane row: at step s the lanes
+                    // with bit s set keep the upper half of their live entries
+                    // and receive it from lane t ^ s, so lane t ends with
+                    // column t's sum
+#pragma unroll
+                    for (int s = 8; s >= 1; s >>= 1) {
+                        const bool up = (t & s) != 0;
+#pragma unroll
+                        for (int j = 0; j < s; ++j) {
+                            const double send = up ? w[j] : w[j + s];
+                            const double keep = up ? w[j + s] : w[j];
+                            w[j] = keep + __shfl_xor(send, s, 16);
+                        }
+                    }
+                    mirp[d * 16 + t] = w[0];
+                }
             }
-            if constexpr (!kHess) {
+            if constexpr (kSym && !kHess) {
+                // the round's row and mirror partials into the running
+                // results, pair by pair in lane-row order
+                part[d * 16 + t] = prt;
+                __syncthreads();
+                if ((int)threadIdx.x < ppw * 16) {
+                    const int ms = threadIdx.x >> 4;
+                    double* ap = sacc + ms * n16 + t;
+                    for (int e = 0; e < per_pt; ++e) {
+                        const int ibe = ibr * rb + e / kbg, kbe = kgr * kbg + e % kbg;
+                        if (ibe >= nb || kbe >= nb || kbe < ibe) continue;
+                        ap[16 * ibe] += part[(ms * per_pt + e) * 16 + t];
+                        ap[16 * kbe] += mirp[(ms * per_pt + e) * 16 + t];
+                    }
+                }
+            } else if constexpr (!kHess) {
                 // the row's partials over the round's column blocks, in block order
                 part[d * 16 + t] = prt;
                 __syncthreads();
@@ -395,13 +495,20 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                 }
             }
         }
-        if constexpr (!kHess) {
+        if constexpr (!kHess && !kSym) {
             __syncthreads();
             if (row_live && kbs == 0) {
                 const double own = owns[(ps * rb + ibs) * 16 + t];
                 const double row = rowsum[(ps * rb + ibs) * 16 + t] + own * vp[i];
                 st_io(a.out, p * n + i, row + row, a.io32);
             }
+        }
+    }
+    if constexpr (kSym && !kHess) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < ppw * n16; idx += kFpDppThreads) {
+            const int pe = idx / n16, ie = idx - pe * n16;
+            if (ie < n && p0 + pe < a.npts) st_io(a.out, (p0 + pe) * n + ie, sacc[idx] + sacc[idx], a.io32);
         }
     }
 }
@@ -415,13 +522,14 @@ __host__ __device__ inline void fp_dpp_rounds(int nb, int rb, int rsplit, int rp
     ibr1 = ibr0 + per < ibr_n ? ibr0 + per : ibr_n;
 }
 
-template <class Prec, int C, bool kHess, bool kGrad>
+// kSym: a point group is one workgroup (rsplit = 1).
+template <class Prec, int C, bool kHess, bool kGrad, bool kSym>
 __global__ __launch_bounds__(kFpDppThreads) void fp_dpp_kernel(FpDppArgs a) {
     extern __shared__ double lds[];
     const int64_t pg = blockIdx.x / a.rsplit;
     int ibr0, ibr1;
     fp_dpp_rounds(a.nb, a.rb, a.rsplit, (int)(blockIdx.x - pg * a.rsplit), ibr0, ibr1);
-    fp_dpp_block<Prec, C, kHess, kGrad>(a, pg, ibr0, ibr1, lds);
+    fp_dpp_block<Prec, C, kHess, kGrad, kSym>(a, pg, ibr0, ibr1, lds);
 }
 
 }  // namespace chessfad

@@ -58,15 +58,14 @@ bool chunk_compiled(int c);
 // over workgroups, grid and LDS bytes.
 struct FpDppGeometry {
     int nb = 0, ppw = 0, rb = 1, kbg = 1, rsplit = 1;
-    int q = 0;   // symmetric form: block pairs per point per pass
     int64_t grid = 0;
     size_t lds = 0;
 };
 FpDppGeometry fp_dpp_geometry(int n, int64_t npts, int points, int blocks, bool mixed);
-// Launch shape of its symmetric form: points per workgroup and block pairs
-// per pass, from a cost model of a pass (products per lane plus J entries
-// formed per thread), within 64 KiB of LDS.
-FpDppGeometry fp_sym_geometry(int n, int64_t npts, bool mixed);
+// Launch shape of its symmetric form: the same cost model over the rounds
+// of the block pairs kb >= ib (column blocks per round: `blocks`, or the
+// model's where 0), one workgroup per point group.
+FpDppGeometry fp_sym_geometry(int n, int64_t npts, int blocks, bool mixed);
 
 // Current value of a chessfad_option.
 int option_value(int option);

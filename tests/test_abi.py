@@ -294,8 +294,9 @@ def test_fp_launch_shape_invariants(lib):
             lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_POINTS, 0)
             lib.chessfad_set_option(binding.CHESSFAD_OPT_FP_BLOCKS, 0)
             s = binding.chessfad_fp_launch_shape(n, npts, prec, sym=True)
-            assert s["points"] >= 1 and 1 <= s["pairs_per_pass"] <= nb * (nb + 1) // 2, (n, s)
-            assert s["points"] * s["pairs_per_pass"] <= 16 and 0 < s["lds_bytes"] <= 64 * 1024, (n, s)
+            assert s["points"] >= 1 and 1 <= s["row_blocks"] <= nb and 1 <= s["column_blocks"] <= nb, (n, s)
+            assert s["points"] * s["row_blocks"] * s["column_blocks"] <= 16, (n, s)
+            assert 0 < s["lds_bytes"] <= 64 * 1024 and s["split"] == 1, (n, s)
             assert s["grid"] == -(-npts // s["points"]), (n, npts, s)
     for bad_n in (16, 513):
         with pytest.raises(binding.ChessfadError):
