@@ -279,7 +279,7 @@ hipError_t materialize(PlanLayout& L, const chessfad_instance* inst, char* base,
             if (c.precision == 1 && err == hipSuccess) {
                 const int count = c.n * c.n;
                 hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, c.A, c.B,
-                                   A32, B32);
+                                   A32, B32, nullptr);
                 err = hipGetLastError();
             }
             e.d.fp = c.precision == 1 ? FpParams{c.A, c.B, E, A32, B32} : FpParams{c.A, c.B, E, nullptr, nullptr};

@@ -133,6 +133,8 @@ struct FpSet {
     double* E = nullptr;
     float* A32 = nullptr;
     float* B32 = nullptr;
+    int* flag = nullptr;   // device: 1 if a float32 copy is inexact
+    int ab32 = 0;          // the float32 copies are exact
     int device = -1;
 };
 
@@ -145,6 +147,7 @@ void fp_free(FpSet& s) {
     if (s.E) (void)hipFree(s.E);
     if (s.A32) (void)hipFree(s.A32);
     if (s.B32) (void)hipFree(s.B32);
+    if (s.flag) (void)hipFree(s.flag);
     s = FpSet{};
 }
 
@@ -156,7 +159,7 @@ int fp_lookup_locked(int n, FpParams& out) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return CHESSFAD_E_HIP;
     if (!s.A || s.device != dev) return CHESSFAD_E_PARAMS;
-    out = FpParams{s.A, s.B, s.E, s.A32, s.B32};
+    out = FpParams{s.A, s.B, s.E, s.A32, s.B32, s.ab32};
     return CHESSFAD_OK;
 }
 
@@ -585,6 +588,11 @@ int chessfad_fp_set_params(int n, const double* A, const double* B, const double
     if (e == hipSuccess) e = hipMalloc(&set.E, sizeof(double) * n);
     if (e == hipSuccess) e = hipMalloc(&set.A32, sizeof(float) * (size_t)n * n);
     if (e == hipSuccess) e = hipMalloc(&set.B32, sizeof(float) * (size_t)n * n);
+    if (e == hipSuccess) e = hipMalloc(&set.flag, sizeof(int));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(fp_clear_flag_kernel, dim3(1), dim3(1), 0, s, set.flag);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(set.A, A, mat, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(set.B, B, mat, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) {
@@ -594,11 +602,14 @@ int chessfad_fp_set_params(int n, const double* A, const double* B, const double
     if (e == hipSuccess) {
         const int count = n * n;
         hipLaunchKernelGGL(fp_to_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count, set.A, set.B,
-                           set.A32, set.B32);
+                           set.A32, set.B32, set.flag);
         e = hipGetLastError();
     }
     // the set is complete on the device before any stream can read it
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int inexact = 1;
+    if (e == hipSuccess) e = hipMemcpy(&inexact, set.flag, sizeof(int), hipMemcpyDeviceToHost);
+    set.ab32 = inexact == 0;
     if (e != hipSuccess) {
         fp_free(set);
         return hip_fail(e);

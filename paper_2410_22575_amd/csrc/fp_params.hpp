@@ -21,12 +21,19 @@ static __global__ void fp_offsets_kernel(int n, const double* A, const double* B
     E[m] = acc;
 }
 
-// float32 copies of A and B (their entries are integers of magnitude <= 100: exact)
-static __global__ void fp_to_f32_kernel(int count, const double* A, const double* B, float* A32, float* B32) {
+// float32 copies of A and B (exact for the integer entries of the test
+// problems); `inexact` (optional) is set to 1 if any entry rounds
+static __global__ void fp_to_f32_kernel(int count, const double* A, const double* B, float* A32, float* B32,
+                                        int* inexact) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
-    A32[k] = (float)A[k];
-    B32[k] = (float)B[k];
+    const float a = (float)A[k], b = (float)B[k];
+    A32[k] = a;
+    B32[k] = b;
+    if (inexact && ((double)a != A[k] || (double)b != B[k])) atomicOr(inexact, 1);
 }
+
+// *flag = 0 (a kernel, not a memset node)
+static __global__ void fp_clear_flag_kernel(int* flag) { *flag = 0; }
 
 }  // namespace chessfad

@@ -64,8 +64,9 @@ struct FpParams {
     const double* A;    // [n][n]
     const double* B;    // [n][n]
     const double* E;    // [n]
-    const float* A32;   // float32 copies (exact: the entries are small integers)
+    const float* A32;   // float32 copies (exact for the integer entries of the test problems)
     const float* B32;
+    int ab32 = 0;       // 1: the float32 copies are exact, and float64 kernels may read A and B there
 };
 
 template <typename T>

@@ -47,6 +47,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernel_fp_call.hpp"
 
 namespace chessfad {
@@ -106,6 +108,27 @@ CF_DEV const float* fp_b_base<float>(const FpParams& p) { return p.B32; }
 template <typename T>
 CF_DEV T ld_at(const T* base, uint32_t idx) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)(idx * (uint32_t)sizeof(T)));
+}
+
+// A and B at R offsets, all loads in flight together: T = float reads the
+// float32 copies; T = double reads them too when they are exact (the same
+// values in half the bytes), else the float64 arrays.
+template <typename T, int R>
+CF_DEV void fp_ab_loads(const FpParams& fp, const T* Ab, const T* Bb, const uint32_t (&o)[R], T (&av)[R],
+                        T (&bv)[R]) {
+    if (std::is_same<T, double>::value && fp.ab32) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bv[r] = (T)ld_at(fp.B32, o[r]);
+            av[r] = (T)ld_at(fp.A32, o[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bv[r] = ld_at(Bb, o[r]);
+            av[r] = ld_at(Ab, o[r]);
+        }
+    }
 }
 
 // Per-call accumulation of the C products over the residuals: float64
@@ -177,7 +200,13 @@ __device__ __forceinline__ void fp_dpp_value_column(const FpDppArgs& a, int64_t 
         const double* sp = sins + ps * n16;
         const double* cp = coss + ps * n16;
         double acc = 0.0;
-        if (on) {
+        if (on && a.fp.ab32) {
+            // the exact float32 copies: the same values, half the bytes
+            const float* Am = a.fp.A32 + (size_t)m * n;
+            const float* Bm = a.fp.B32 + (size_t)m * n;
+#pragma unroll 4
+            for (int j = t; j < n; j += 16) acc += (double)Am[j] * sp[j] + (double)Bm[j] * cp[j];
+        } else if (on) {
             const double* Am = a.fp.A + (size_t)m * n;
             const double* Bm = a.fp.B + (size_t)m * n;
 #pragma unroll 4
@@ -263,11 +292,19 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                 if (i < n) {
                     const double s = sins[task], c = coss[task];
                     const double* rp = rvs + ps * n16;
-                    const double* Ai = a.fp.A + i;
-                    const double* Bi = a.fp.B + i;
                     double own = 0.0;
+                    if (a.fp.ab32) {
+                        const float* Ai = a.fp.A32 + i;
+                        const float* Bi = a.fp.B32 + i;
 #pragma unroll 4
-                    for (int m = 0; m < n; ++m) own += rp[m] * (Ai[(size_t)m * n] * s + Bi[(size_t)m * n] * c);
+                        for (int m = 0; m < n; ++m)
+                            own += rp[m] * ((double)Ai[(size_t)m * n] * s + (double)Bi[(size_t)m * n] * c);
+                    } else {
+                        const double* Ai = a.fp.A + i;
+                        const double* Bi = a.fp.B + i;
+#pragma unroll 4
+                        for (int m = 0; m < n; ++m) own += rp[m] * (Ai[(size_t)m * n] * s + Bi[(size_t)m * n] * c);
+                    }
                     ownr[k] = kHess ? own : own * vs[task];
                 }
             }
@@ -339,16 +376,16 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         T bv[8], av[8];
                         int col[8];
                         bool on[8];
+                        uint32_t o[8];
 #pragma unroll
                         for (int r = 0; r < 8; ++r) {
                             const int bs = b0 + r < nslots ? b0 + r : nslots - 1;
                             const int blk = bs < kbg ? kgr * kbg + bs : ibr * rb + (bs - kbg);
                             on[r] = m_on && blk < nb;
                             col[r] = on[r] ? 16 * blk + tt : 0;
-                            const uint32_t o = mrow + (uint32_t)(col[r] < n ? col[r] : n - 1);
-                            bv[r] = ld_at(Bb, o);
-                            av[r] = ld_at(Ab, o);
+                            o[r] = mrow + (uint32_t)(col[r] < n ? col[r] : n - 1);
                         }
+                        fp_ab_loads<T, 8>(a.fp, Ab, Bb, o, av, bv);
                         for (int qs = 0; qs < ppw; ++qs) {
 #pragma unroll
                             for (int r = 0; r < 8; ++r) {
@@ -365,7 +402,9 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         if (blk >= nb || blk < kgr * kbg || blk >= kgr * kbg + kbg) continue;
                         const int col = 16 * blk + tt;
                         const uint32_t o = mrow + (uint32_t)(col < n ? col : n - 1);
-                        const double dv = ld_at(a.fp.A, o) * sins[qs * n16 + col] + ld_at(a.fp.B, o) * coss[qs * n16 + col];
+                        const double ad = a.fp.ab32 ? (double)ld_at(a.fp.A32, o) : ld_at(a.fp.A, o);
+                        const double bd = a.fp.ab32 ? (double)ld_at(a.fp.B32, o) : ld_at(a.fp.B, o);
+                        const double dv = ad * sins[qs * n16 + col] + bd * coss[qs * n16 + col];
                         dt[q * (MT * 16) + threadIdx.x] = m_on ? dv : 0.0;
                     }
                 }

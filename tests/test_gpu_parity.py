@@ -10,13 +10,14 @@ import numpy as np
 import pytest
 import torch
 
+from gates import TOL32, TOL64
+
 from oracle import closed_form as cf
 from paper_2410_22575_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
 R, A, FP = 0, 1, 2
-TOL64 = 1e-12
 CHUNKS = (1, 2, 4, 8, 16)
 
 
@@ -363,3 +364,31 @@ def test_fp_per_call_column_blocks(gpu_lib, blocks, n, npts):
                 np.testing.assert_array_equal(r, r0)
     finally:
         gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_FP_BLOCKS, prev)
+
+
+@pytest.mark.parametrize("n", [40, 100])
+def test_fp_per_call_non_integer_parameters(gpu_lib, n):
+    """Fletcher-Powell n > 16 with A and B that float32 does not hold
+    exactly (the float64 kernels then read A and B in float64; with the
+    integer parameters of every other test they read the exact float32
+    copies): full and symmetric H.v and Hessians against the closed form,
+    and the mixed path within its gate."""
+    import dataclasses
+    w = inputs.make_workload(FP, n, 23, inputs.rng_for(8900 + n))
+    rng = np.random.default_rng(n)
+    w = dataclasses.replace(w, A=w.A + rng.uniform(-0.5, 0.5, w.A.shape) / 3.0,
+                            B=w.B + rng.uniform(-0.5, 0.5, w.B.shape) / 7.0)
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    H_ref, hmax = _hmax(FP, w, E)
+    r_ref = cf.hvp(FP, w.x, w.v, w.A, w.B, E)
+    for c in (4, 16):
+        print(f"[case] fp non-integer parameters n={n} chunk={c}", flush=True)
+        for fn in (gpu_lib.chessfad_hvp, gpu_lib.chessfad_hvp_sym):
+            r = fn(FP, x, v, chunk=c).cpu().numpy()
+            assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64, fn
+        for fn in (gpu_lib.chessfad_hessian, gpu_lib.chessfad_hessian_sym):
+            H = fn(FP, x, chunk=c).cpu().numpy()
+            assert np.max(np.abs(H - H_ref).max(axis=(1, 2)) / hmax) <= TOL64, fn
+        r = gpu_lib.chessfad_hvp_mixed(FP, x, v, chunk=c).cpu().numpy()
+        assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL32[FP]
