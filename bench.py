@@ -66,33 +66,33 @@ LARGE_FP_NPTS = {64: 1 << 18, 512: 1024}   # points of the Fletcher-Powell large
 #   classes     wave-instructions per class: SQ_INSTS_VALU_{ADD,MUL,FMA}_F64,
 #               _INT32, _INT64, _CVT, _TRANS_F64, SQ_INSTS_LDS, SQ_INSTS_SALU
 COUNTERS = {
-    'coarse_kernel<F64, Ackley, 1, 1>': {'traffic': 402803968, 'valu_flops': 6861881344, 'valu_insts': 142082048, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20250624, 'valu_mul_f64': 41025536, 'valu_fma_f64': 22806528, 'valu_int32': 22478848, 'valu_int64': 2818048, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 27983872, 'salu': 56426496}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Ackley, 16, 1>': {'traffic': 402802176, 'valu_flops': 3841982464, 'valu_insts': 86245376, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8454144, 'valu_mul_f64': 13500416, 'valu_fma_f64': 18874368, 'valu_int32': 16711680, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 10682368, 'salu': 48562176}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Ackley, 2, 1>': {'traffic': 402798592, 'valu_flops': 4781506560, 'valu_insts': 106168320, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12124160, 'valu_mul_f64': 20840448, 'valu_fma_f64': 20709376, 'valu_int32': 21954560, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 9895936, 'salu': 62193664}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Ackley, 4, 1>': {'traffic': 402796544, 'valu_flops': 4244635648, 'valu_insts': 98828288, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10027008, 'valu_mul_f64': 16646144, 'valu_fma_f64': 19660800, 'valu_int32': 23003136, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 13041664, 'salu': 58785792}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Ackley, 8, 1>': {'traffic': 402807808, 'valu_flops': 3976200192, 'valu_insts': 90439680, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8978432, 'valu_mul_f64': 14548992, 'valu_fma_f64': 19136512, 'valu_int32': 18808832, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 11468800, 'salu': 51970048}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Rosenbrock, 1, 1>': {'traffic': 402738944, 'valu_flops': 5502926848, 'valu_insts': 130547712, 'mfma_flops': 0, 'classes': {'valu_add_f64': 5242880, 'valu_mul_f64': 38273024, 'valu_fma_f64': 21233664, 'valu_int32': 30146560, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 37748736}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Rosenbrock, 16, 1>': {'traffic': 402732032, 'valu_flops': 486539264, 'valu_insts': 36962304, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1310720, 'valu_mul_f64': 3145728, 'valu_fma_f64': 1572864, 'valu_int32': 15204352, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 30670848}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Rosenbrock, 2, 1>': {'traffic': 402731008, 'valu_flops': 3070230528, 'valu_insts': 90177536, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 26214400, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 41680896}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Rosenbrock, 4, 1>': {'traffic': 402732032, 'valu_flops': 1593835520, 'valu_insts': 59768832, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 19922944, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 35389440}, 'sha': 'e5099f050057ac7e'},
-    'coarse_kernel<F64, Rosenbrock, 8, 1>': {'traffic': 402733056, 'valu_flops': 855638016, 'valu_insts': 44564480, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 16777216, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 32243712}, 'sha': 'e5099f050057ac7e'},
-    'fp_call_kernel<F64, 8, 1, false, false>': {'traffic': 403008320, 'valu_flops': 12549357568, 'valu_insts': 154337280, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 6815744, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12648448, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 25624576}, 'sha': '0277028de0b4d6d3'},
-    'fp_call_kernel<F64, 8, 16, false, false>': {'traffic': 402974400, 'valu_flops': 12297699328, 'valu_insts': 145293312, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12058624, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 19726336}, 'sha': '0277028de0b4d6d3'},
-    'fp_call_kernel<F64, 8, 2, false, false>': {'traffic': 402961152, 'valu_flops': 12415139840, 'valu_insts': 149880832, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 4718592, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12517376, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 22478848}, 'sha': '0277028de0b4d6d3'},
-    'fp_call_kernel<F64, 8, 4, false, false>': {'traffic': 403005312, 'valu_flops': 12348030976, 'valu_insts': 147259392, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 3670016, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12255232, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20905984}, 'sha': '0277028de0b4d6d3'},
-    'fp_call_kernel<F64, 8, 8, false, false>': {'traffic': 402995072, 'valu_flops': 12314476544, 'valu_insts': 145948672, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12124160, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20119552}, 'sha': '0277028de0b4d6d3'},
-    'plain_kernel<F64, Ackley, 1, false, false>': {'traffic': 402802688, 'valu_flops': 22347251712, 'valu_insts': 796917760, 'mfma_flops': 0, 'classes': {'valu_add_f64': 55574528, 'valu_mul_f64': 68157440, 'valu_fma_f64': 110100480, 'valu_int32': 266338304, 'valu_int64': 35651584, 'valu_cvt': 39845888, 'valu_trans_f64': 5242880, 'lds': 78643200, 'salu': 642777088}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Ackley, 2, false, false>': {'traffic': 402792448, 'valu_flops': 11844714496, 'valu_insts': 404226048, 'mfma_flops': 0, 'classes': {'valu_add_f64': 25690112, 'valu_mul_f64': 38273024, 'valu_fma_f64': 59244544, 'valu_int32': 128450560, 'valu_int64': 19922944, 'valu_cvt': 19922944, 'valu_trans_f64': 2621440, 'lds': 35127296, 'salu': 325582848}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Ackley, 4, false, false>': {'traffic': 402802688, 'valu_flops': 6794772480, 'valu_insts': 215744512, 'mfma_flops': 0, 'classes': {'valu_add_f64': 13893632, 'valu_mul_f64': 23330816, 'valu_fma_f64': 33816576, 'valu_int32': 66322432, 'valu_int64': 9961472, 'valu_cvt': 9961472, 'valu_trans_f64': 1310720, 'lds': 22806528, 'salu': 166985728}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Ackley, 8, false, false>': {'traffic': 402810880, 'valu_flops': 4815060992, 'valu_insts': 133955584, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10092544, 'valu_mul_f64': 16777216, 'valu_fma_f64': 23855104, 'valu_int32': 36569088, 'valu_int64': 5373952, 'valu_cvt': 5373952, 'valu_trans_f64': 655360, 'lds': 15073280, 'salu': 91357184}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Rosenbrock, 1, false, false>': {'traffic': 402737152, 'valu_flops': 8254390272, 'valu_insts': 584056832, 'mfma_flops': 0, 'classes': {'valu_add_f64': 32505856, 'valu_mul_f64': 46137344, 'valu_fma_f64': 25165824, 'valu_int32': 239075328, 'valu_int64': 19922944, 'valu_cvt': 35651584, 'valu_trans_f64': 0, 'lds': 48234496, 'salu': 481296384}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Rosenbrock, 2, false, false>': {'traffic': 402741248, 'valu_flops': 3992977408, 'valu_insts': 295698432, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12058624, 'valu_mul_f64': 25165824, 'valu_fma_f64': 12582912, 'valu_int32': 125304832, 'valu_int64': 9961472, 'valu_cvt': 17825792, 'valu_trans_f64': 0, 'lds': 19922944, 'salu': 240648192}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Rosenbrock, 4, false, false>': {'traffic': 402733056, 'valu_flops': 1929379840, 'valu_insts': 145752064, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 12582912, 'valu_fma_f64': 6291456, 'valu_int32': 61603840, 'valu_int64': 4980736, 'valu_cvt': 8912896, 'valu_trans_f64': 0, 'lds': 8912896, 'salu': 118226944}, 'sha': 'e5099f050057ac7e'},
-    'plain_kernel<F64, Rosenbrock, 8, false, false>': {'traffic': 402734080, 'valu_flops': 956301312, 'valu_insts': 77594624, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2359296, 'valu_mul_f64': 6291456, 'valu_fma_f64': 3145728, 'valu_int32': 33816576, 'valu_int64': 2883584, 'valu_cvt': 4718592, 'valu_trans_f64': 0, 'lds': 4718592, 'salu': 63176704}, 'sha': 'e5099f050057ac7e'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403144832, 'valu_flops': 164903256064, 'valu_insts': 2734161920, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 68681728, 'valu_fma_f64': 1231290368, 'valu_int32': 702545920, 'valu_int64': 56098816, 'valu_cvt': 149684224, 'valu_trans_f64': 0, 'lds': 352059392, 'salu': 1316749312}, 'sha': '31769338ecf9f1c8'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403311296, 'valu_flops': 127993380864, 'valu_insts': 2353135616, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 98304000, 'valu_fma_f64': 924057600, 'valu_int32': 616038400, 'valu_int64': 116391936, 'valu_cvt': 122945536, 'valu_trans_f64': 0, 'lds': 297271296, 'salu': 620298240}, 'sha': '31769338ecf9f1c8'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 37998592, 'valu_flops': 293617008640, 'valu_insts': 3689775104, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 79790080, 'valu_fma_f64': 2248523776, 'valu_int32': 690774016, 'valu_int64': 10248192, 'valu_cvt': 159531008, 'valu_trans_f64': 0, 'lds': 378126336, 'salu': 1702895616}, 'sha': '31769338ecf9f1c8'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29785152, 'valu_flops': 165019123712, 'valu_insts': 2012053504, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 48553984, 'valu_fma_f64': 1260822528, 'valu_int32': 311377920, 'valu_int64': 21958656, 'valu_cvt': 92372992, 'valu_trans_f64': 0, 'lds': 204541952, 'salu': 486019072}, 'sha': '31769338ecf9f1c8'},
+    'coarse_kernel<F64, Ackley, 1, 1>': {'traffic': 402816832, 'valu_flops': 6073352192, 'valu_insts': 129761280, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20250624, 'valu_mul_f64': 28704768, 'valu_fma_f64': 22806528, 'valu_int32': 22478848, 'valu_int64': 2818048, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 27983872, 'salu': 56950784}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 16, 1>': {'traffic': 402813536, 'valu_flops': 3556769792, 'valu_insts': 81788928, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8454144, 'valu_mul_f64': 9043968, 'valu_fma_f64': 18874368, 'valu_int32': 16711680, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 10682368, 'salu': 48562176}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 2, 1>': {'traffic': 402784448, 'valu_flops': 4378853376, 'valu_insts': 99876864, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12124160, 'valu_mul_f64': 14548992, 'valu_fma_f64': 20709376, 'valu_int32': 21954560, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 9895936, 'salu': 62193664}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 4, 1>': {'traffic': 402796544, 'valu_flops': 3909091328, 'valu_insts': 93585408, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10027008, 'valu_mul_f64': 11403264, 'valu_fma_f64': 19660800, 'valu_int32': 23003136, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 13041664, 'salu': 58785792}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 8, 1>': {'traffic': 402777088, 'valu_flops': 3674210304, 'valu_insts': 85721088, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8978432, 'valu_mul_f64': 9830400, 'valu_fma_f64': 19136512, 'valu_int32': 18808832, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 11468800, 'salu': 51970048}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 1, 1>': {'traffic': 402738752, 'valu_flops': 5502926848, 'valu_insts': 130547712, 'mfma_flops': 0, 'classes': {'valu_add_f64': 5242880, 'valu_mul_f64': 38273024, 'valu_fma_f64': 21233664, 'valu_int32': 30146560, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 37748736}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 16, 1>': {'traffic': 402732032, 'valu_flops': 486539264, 'valu_insts': 36962304, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1310720, 'valu_mul_f64': 3145728, 'valu_fma_f64': 1572864, 'valu_int32': 15204352, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 30670848}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 2, 1>': {'traffic': 402731008, 'valu_flops': 3070230528, 'valu_insts': 90177536, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 26214400, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 41680896}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 4, 1>': {'traffic': 402732032, 'valu_flops': 1593835520, 'valu_insts': 59768832, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 19922944, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 35389440}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 8, 1>': {'traffic': 402733120, 'valu_flops': 855638016, 'valu_insts': 44564480, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 16777216, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 32243712}, 'sha': 'fb9ae3d8046326fb'},
+    'fp_call_kernel<F64, 8, 1, false, false>': {'traffic': 402976128, 'valu_flops': 12297699328, 'valu_insts': 146341888, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12582912, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 25624576}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 16, false, false>': {'traffic': 402992896, 'valu_flops': 12297699328, 'valu_insts': 145293312, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12058624, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 19726336}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 2, false, false>': {'traffic': 402980288, 'valu_flops': 12297699328, 'valu_insts': 146210816, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12517376, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 22478848}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 4, false, false>': {'traffic': 402984384, 'valu_flops': 12297699328, 'valu_insts': 145686528, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12255232, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20905984}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 8, false, false>': {'traffic': 403016128, 'valu_flops': 12297699328, 'valu_insts': 145424384, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12124160, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20119552}, 'sha': '021b6e2a439d0177'},
+    'plain_kernel<F64, Ackley, 1, false, false>': {'traffic': 402795520, 'valu_flops': 21609054208, 'valu_insts': 785383424, 'mfma_flops': 0, 'classes': {'valu_add_f64': 55574528, 'valu_mul_f64': 56623104, 'valu_fma_f64': 110100480, 'valu_int32': 266338304, 'valu_int64': 35651584, 'valu_cvt': 39845888, 'valu_trans_f64': 5242880, 'lds': 78643200, 'salu': 636485632}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Ackley, 2, false, false>': {'traffic': 402786304, 'valu_flops': 11341398016, 'valu_insts': 396361728, 'mfma_flops': 0, 'classes': {'valu_add_f64': 25690112, 'valu_mul_f64': 30408704, 'valu_fma_f64': 59244544, 'valu_int32': 128450560, 'valu_int64': 19922944, 'valu_cvt': 19922944, 'valu_trans_f64': 2621440, 'lds': 35127296, 'salu': 320339968}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Ackley, 4, false, false>': {'traffic': 402805760, 'valu_flops': 6408896512, 'valu_insts': 209715200, 'mfma_flops': 0, 'classes': {'valu_add_f64': 13893632, 'valu_mul_f64': 17301504, 'valu_fma_f64': 33816576, 'valu_int32': 66322432, 'valu_int64': 9961472, 'valu_cvt': 9961472, 'valu_trans_f64': 1310720, 'lds': 22806528, 'salu': 162267136}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Ackley, 8, false, false>': {'traffic': 402810880, 'valu_flops': 4496293888, 'valu_insts': 128974848, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10092544, 'valu_mul_f64': 11796480, 'valu_fma_f64': 23855104, 'valu_int32': 36569088, 'valu_int64': 5373952, 'valu_cvt': 5373952, 'valu_trans_f64': 655360, 'lds': 15073280, 'salu': 89260032}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Rosenbrock, 1, false, false>': {'traffic': 402737152, 'valu_flops': 8254390272, 'valu_insts': 584056832, 'mfma_flops': 0, 'classes': {'valu_add_f64': 32505856, 'valu_mul_f64': 46137344, 'valu_fma_f64': 25165824, 'valu_int32': 239075328, 'valu_int64': 19922944, 'valu_cvt': 35651584, 'valu_trans_f64': 0, 'lds': 48234496, 'salu': 481296384}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Rosenbrock, 2, false, false>': {'traffic': 402741248, 'valu_flops': 3992977408, 'valu_insts': 295698432, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12058624, 'valu_mul_f64': 25165824, 'valu_fma_f64': 12582912, 'valu_int32': 125304832, 'valu_int64': 9961472, 'valu_cvt': 17825792, 'valu_trans_f64': 0, 'lds': 19922944, 'salu': 240648192}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Rosenbrock, 4, false, false>': {'traffic': 402733056, 'valu_flops': 1929379840, 'valu_insts': 145752064, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 12582912, 'valu_fma_f64': 6291456, 'valu_int32': 61603840, 'valu_int64': 4980736, 'valu_cvt': 8912896, 'valu_trans_f64': 0, 'lds': 8912896, 'salu': 118226944}, 'sha': 'fb9ae3d8046326fb'},
+    'plain_kernel<F64, Rosenbrock, 8, false, false>': {'traffic': 402734080, 'valu_flops': 956301312, 'valu_insts': 77594624, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2359296, 'valu_mul_f64': 6291456, 'valu_fma_f64': 3145728, 'valu_int32': 33816576, 'valu_int64': 2883584, 'valu_cvt': 4718592, 'valu_trans_f64': 0, 'lds': 4718592, 'salu': 63176704}, 'sha': 'fb9ae3d8046326fb'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403140160, 'valu_flops': 161682030592, 'valu_insts': 2643984384, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 51904512, 'valu_fma_f64': 1214513152, 'valu_int32': 671088640, 'valu_int64': 56098816, 'valu_cvt': 149684224, 'valu_trans_f64': 0, 'lds': 301727744, 'salu': 1340866560}, 'sha': '7c32fd72afb0fae8'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403287040, 'valu_flops': 124772155392, 'valu_insts': 2256928768, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 81526784, 'valu_fma_f64': 907280384, 'valu_int32': 584318976, 'valu_int64': 116391936, 'valu_cvt': 122945536, 'valu_trans_f64': 0, 'lds': 246939648, 'salu': 628686848}, 'sha': '7c32fd72afb0fae8'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 37993472, 'valu_flops': 292811702272, 'valu_insts': 3665805312, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 75595776, 'valu_fma_f64': 2244329472, 'valu_int32': 682934272, 'valu_int64': 10248192, 'valu_cvt': 159531008, 'valu_trans_f64': 0, 'lds': 365543424, 'salu': 1738817536}, 'sha': '7c32fd72afb0fae8'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29770624, 'valu_flops': 164213817344, 'valu_insts': 1987522560, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 44359680, 'valu_fma_f64': 1256628224, 'valu_int32': 303312896, 'valu_int64': 21958656, 'valu_cvt': 92372992, 'valu_trans_f64': 0, 'lds': 191959040, 'salu': 487661568}, 'sha': '7c32fd72afb0fae8'},
 }
 
 # The sources each kernel family is compiled from (with the build flags and,
@@ -734,7 +734,9 @@ def main():
             roofline = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": PEAK_F64_TFLOPS,
                         "unit": "TFLOP/s", "frac": flop_frac}
         roofline.update({
-            "traffic": cnt.get("traffic"), "kernel": kname, "flops_per_launch": work,
+            # HBM bytes per launch from the counters; null once the kernel's
+            # sources differ from those the counters were taken on
+            "traffic": None if stale else cnt.get("traffic"), "kernel": kname, "flops_per_launch": work,
             "flop_basis": "executed float64 flops (rocprofv3: VALU FLOPS_FP64 x 64" + (
                 " + MFMA MOPS_F64 x 512)" if cnt.get("mfma_flops") else ")"),
             "flop_frac": flop_frac, "bytes_per_launch": algo_bytes, "byte_frac": byte_frac,

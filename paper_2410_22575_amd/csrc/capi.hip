@@ -296,6 +296,26 @@ Geometry plain_geometry(int n, int64_t npts, int C) {
 
 }  // namespace
 
+namespace {
+
+// Cost per point of a launch shape of the per-call FP kernel for n > 16: per
+// round, 256 products per lane and tile plus about 16 instructions for each
+// J entry a lane forms (pp (kbg + rb) per tile; no row slots in a round whose
+// row blocks lie in its column group); the symmetric form's rounds start at
+// the column group that holds the round's first row block.
+double fp_round_cost(int nb, int pp, int rb, int kbg, bool sym) {
+    const int kgr_n = (nb + kbg - 1) / kbg;
+    double c = 0.0;
+    for (int ibr = 0; ibr * rb < nb; ++ibr)
+        for (int kgr = sym ? (ibr * rb) / kbg : 0; kgr < kgr_n; ++kgr) {
+            const bool alias = ibr * rb >= kgr * kbg && ibr * rb + rb <= kgr * kbg + kbg;
+            c += 256.0 + 16.0 * pp * (kbg + (alias ? 0 : rb));
+        }
+    return c / pp;
+}
+
+}  // namespace
+
 FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, int blocks, bool mixed) {
     FpDppGeometry g;
     g.nb = (n + 15) / 16;
@@ -304,10 +324,8 @@ FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, int blo
     };
     // column blocks per round (the option's, or every count up to 16), points
     // per workgroup (the option's, or any that leaves a column block per
-    // lane row), and then as many row blocks as fill the 16 lane rows; the
-    // cost of a point is its rounds times a round's work per lane: 256
-    // products per tile, and about 16 instructions per J entry the lane forms
-    // (ppw (kbg + rb) entries per tile)
+    // lane row), and then as many row blocks as fill the 16 lane rows, at
+    // the lowest fp_round_cost
     auto fit = [&](int pp, int kbg) { return std::max(1, std::min(g.nb, 16 / (pp * kbg))); };
     double best = -1.0;
     for (int kbg = 1; kbg <= std::min(g.nb, 16); ++kbg) {
@@ -321,8 +339,7 @@ FpDppGeometry chessfad::fp_dpp_geometry(int n, int64_t npts, int points, int blo
                 pp /= 2;
                 rb = fit(pp, kbg);
             }
-            const int rounds = ((g.nb + rb - 1) / rb) * ((g.nb + kbg - 1) / kbg);
-            const double cost = rounds * (256.0 + 16.0 * pp * (kbg + rb)) / pp;
+            const double cost = fp_round_cost(g.nb, pp, rb, kbg, false);
             if (best < 0.0 || cost < best) {
                 best = cost;
                 g.ppw = pp;
@@ -350,15 +367,7 @@ FpDppGeometry chessfad::fp_sym_geometry(int n, int64_t npts, int blocks, bool mi
         return mixed ? fp_dpp_lds_bytes<float>(g.nb, pp, rb, kbg, true)
                      : fp_dpp_lds_bytes<double>(g.nb, pp, rb, kbg, true);
     };
-    // the rounds of the pairs kb >= ib: row-block group r starts at the
-    // column group that holds its first row block
-    auto rounds = [&](int rb, int kbg) {
-        const int kgr_n = (g.nb + kbg - 1) / kbg;
-        int r = 0;
-        for (int ibr = 0; ibr * rb < g.nb; ++ibr) r += kgr_n - (ibr * rb) / kbg;
-        return r;
-    };
-    // the full form's cost model over these rounds; a point group is one
+    // fp_round_cost over the symmetric form's rounds; a point group is one
     // workgroup, so more points per workgroup only while about 1024
     // workgroups remain
     // (equal costs: the fewer LDS bytes per point, for occupancy)
@@ -370,7 +379,7 @@ FpDppGeometry chessfad::fp_sym_geometry(int n, int64_t npts, int blocks, bool mi
             const int rb = std::max(1, std::min(g.nb, 16 / (pp * kbg)));
             const size_t lds = bytes(pp, rb, kbg);
             if (lds > 64 * 1024) continue;
-            const double cost = rounds(rb, kbg) * (256.0 + 16.0 * pp * (kbg + rb)) / pp;
+            const double cost = fp_round_cost(g.nb, pp, rb, kbg, true);
             const double lds_pt = (double)lds / pp;
             if (best < 0.0 || cost < best * (1.0 - 1e-9) || (cost <= best * (1.0 + 1e-9) && lds_pt < best_lds)) {
                 best = cost;

@@ -230,8 +230,13 @@ struct Rosenbrock {
 // -20 exp(-0.2 sqrt(sum y^2 / n)) - exp(sum cos(2 pi y) / n) + 20 + e
 struct Ackley {
     static constexpr int kTables = 2;
-    // t0 = cos(2 pi x), t1 = sin(2 pi x)
-    static CF_DEV void tables(double x, double& t0, double& t1) { sincos(kTwoPi * x, &t1, &t0); }
+    // t0 = cos(2 pi x), t1 = -2 pi sin(2 pi x): the value and the first
+    // derivative of y -> cos(2 pi y) at x
+    static CF_DEV void tables(double x, double& t0, double& t1) {
+        double s;
+        sincos(kTwoPi * x, &s, &t0);
+        t1 = -kTwoPi * s;
+    }
     __host__ __device__ static int isl_tasks(int) { return 1; }
     __host__ __device__ static int isl_size(int) { return 6; }
 
@@ -266,10 +271,12 @@ struct Ackley {
     static CF_DEV HD<T, C> cos_term(const PointView<T>& pv, int k) {
         return cos_of(pv, pv.template y<C>(k), k);
     }
+    // cos(2 pi y) by the chain rule of y -> cos(2 pi y): g = cos(2 pi x),
+    // g' = -2 pi sin(2 pi x) (both from the point's tables), g'' = -4 pi^2 g
     template <typename T, int W>
     static CF_DEV HD<T, W> cos_of(const PointView<T>& pv, const HD1<T, W>& y, int k) {
-        const T c = pv.tab0(k), s = pv.tab1(k);
-        return chain(T(kTwoPi) * y, c, -s, -c);
+        const T c = pv.tab0(k), c1 = pv.tab1(k);
+        return chain(y, c, c1, T(-kTwoPi * kTwoPi) * c);
     }
 
     // As for Rosenbrock, the terms of variables outside the chunk carry no

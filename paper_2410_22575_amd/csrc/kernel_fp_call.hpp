@@ -24,8 +24,8 @@
 // the product rule runs at one instruction per product with no LDS traffic.
 // Per call and residual m the lane forms the C products r_m.d r_m.g[l]; the
 // row's own entry adds sum_m r_m.v D_mi (r_m.v broadcast from lane m); then
-// the chunk dot with v (v broadcast from lane cs + l) and the row sum over
-// the chunks in order.  The doubling of the product rule is applied once to
+// the call's terms h[l] v[cs + l] (v broadcast from lane cs + l) are added to
+// the row sum column by column, chunk by chunk in order.  The doubling of the product rule is applied once to
 // the row's sum (doubling is exact, so this equals doubling every term).
 //
 // The value column r_m.v is the one dense contraction, [A B] . [sin x; cos x]
@@ -226,10 +226,9 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_call_kernel(FpMfmaArgs a) {
                         }
                     }
                 } else {
-                    // the chunk dot with v (v of lane cs + l), then the row sum in chunk order
-                    double dot = 0.0;
-                    DppChunkDot<C, cs>::run(dot, vi, h64);
-                    row += dot;
+                    // the call's terms h[l] v[cs + l] (v of lane cs + l) added
+                    // to the row sum column by column, in order
+                    DppChunkDot<C, cs>::run(row, vi, h64);
                 }
             }
         });

@@ -28,7 +28,8 @@
 // there.  The row's own second-order part, sum_m r_m.v D_mi, is formed once
 // per row by the lane row of its diagonal pair and added in the call that
 // holds column i (D_mi is formed in LDS beside the J tile in the round of the
-// diagonal pair).  H.v: each call's chunk dot with v (v of lane jC + l); the
+// diagonal pair).  H.v: each call's terms h[l] v[cs + l] (v of lane jC + l)
+// are added to the row's partial of the pair column by column in order; the
 // row's partials of its column blocks are summed in block order through
 // LDS.  Hessian: H[p][i][cs + l] is stored per call.
 //
@@ -229,8 +230,8 @@ __device__ __forceinline__ void fp_dpp_value_column(const FpDppArgs& a, int64_t 
 // then reads its own r.d = J_mi and its column's J_m,16kb+t, and the calls'
 // C products r.d r.g[l] take the chunk columns from the lanes that hold them
 // (DPP).  After the last tile: the Hessian chunk of each call is stored, or
-// each call's chunk dot with v is added to the row's partial; the partials
-// of a row's column blocks are summed in block order through LDS.
+// each call's terms h[l] v[cs + l] are added to the row's partial; the
+// partials of a row's column blocks are summed in block order through LDS.
 //
 // kSym: the symmetric forms SC-HESS-VEC and SCHUNK-HESS (Sec. III.B,
 // Sec. VI).  Only the calls whose chunk is the row's own chunk or lies right
@@ -355,6 +356,11 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
             // part sum_m r_m.v D_mi (and the gradient's sum_m r_m.v J_mi),
             // float64, from the tiles
             const bool diag = pair_on && kb == ib;
+            // a round whose row blocks all lie in its column group forms no
+            // row slots: a row's entries are its column slot's
+            const bool alias = ibr * rb >= kgr * kbg && ibr * rb + rb <= kgr * kbg + kbg;
+            const int nform = alias ? kbg : nslots;
+            const T* jr = alias ? jt + ((size_t)(ps * nslots + ibr * rb + ibs - kgr * kbg) * MT) * 16 + t : ji;
             double own = 0.0, gd = 0.0;
 #pragma unroll
             for (int jc = 0; jc < 16 / C; ++jc) sums[jc].reset();
@@ -372,14 +378,14 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     // clamped, in-range offsets) all in flight together and
                     // shared by the points; sin and cos are zero past n, and
                     // blocks past nb and residuals past n are masked
-                    for (int b0 = 0; b0 < nslots; b0 += 8) {
+                    for (int b0 = 0; b0 < nform; b0 += 8) {
                         T bv[8], av[8];
                         int col[8];
                         bool on[8];
                         uint32_t o[8];
 #pragma unroll
                         for (int r = 0; r < 8; ++r) {
-                            const int bs = b0 + r < nslots ? b0 + r : nslots - 1;
+                            const int bs = b0 + r < nform ? b0 + r : nform - 1;
                             const int blk = bs < kbg ? kgr * kbg + bs : ibr * rb + (bs - kbg);
                             on[r] = m_on && blk < nb;
                             col[r] = on[r] ? 16 * blk + tt : 0;
@@ -391,7 +397,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                             for (int r = 0; r < 8; ++r) {
                                 const int sc = qs * n16 + col[r];
                                 const T jv = bv[r] * (T)sins[sc] - av[r] * (T)coss[sc];
-                                if (b0 + r < nslots) jt[(qs * nslots + b0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
+                                if (b0 + r < nform) jt[(qs * nslots + b0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
                             }
                         }
                     }
@@ -415,7 +421,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     for (int u = 0; u < MT; ++u) {
                         const double rv = rp[mt * MT + u];   // zero past n
                         own += rv * dp[u * 16];
-                        if (kGrad) gd += rv * (double)ji[u * 16];
+                        if (kGrad) gd += rv * (double)jr[u * 16];
                     }
                 }
                 if (pair_on) {
@@ -425,7 +431,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             g[u] = jk[(4 * ug + u) * 16];
-                            dd[u] = ji[(4 * ug + u) * 16];
+                            dd[u] = jr[(4 * ug + u) * 16];
                         }
                         static_for<16 / C>([&](auto jcc) {
                             constexpr int jc = decltype(jcc)::value;
@@ -477,16 +483,18 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                             for (int l = 0; l < C; ++l)
                                 if (cs + l < n) dst[l] = h[l] + h[l];
                         }
+                    } else if constexpr (!kSym) {
+                        // the call's terms h[l] v[cs + l] (v of lane cl + l)
+                        // added to the row's partial column by column, in order
+                        DppChunkDot<C, cl>::run(prt, vk, h);
                     } else {
-                        // the chunk dot with v (v of lane cl + l), in call order
+                        // a counted call's chunk dot with v (v of lane cl + l)
                         double dot = 0.0;
                         DppChunkDot<C, cl>::run(dot, vk, h);
                         if (jc >= tc) prt += dot;
-                        if constexpr (kSym) {
-                            const double vi = vp[i];   // zero past n
+                        const double vi = vp[i];   // zero past n
 #pragma unroll
-                            for (int l = 0; l < C; ++l) w[cl + l] = jc > tc ? h[l] * vi : 0.0;
-                        }
+                        for (int l = 0; l < C; ++l) w[cl + l] = jc > tc ? h[l] * vi : 0.0;
                     }
                 });
                 if constexpr (kSym && !kHess) {
