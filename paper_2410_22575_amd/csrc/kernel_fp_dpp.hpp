@@ -374,36 +374,55 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     const int m = mt * MT + u;
                     const bool m_on = m < n;
                     const uint32_t mrow = (uint32_t)((m_on ? m : 0) * n);
-                    // eight block slots at a time, their A and B loads (from
-                    // clamped, in-range offsets) all in flight together and
-                    // shared by the points; sin and cos are zero past n, and
-                    // blocks past nb and residuals past n are masked
-                    for (int b0 = 0; b0 < nform; b0 += 8) {
-                        T bv[8], av[8];
-                        int col[8];
-                        bool on[8];
-                        uint32_t o[8];
+                    // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row
+                    // blocks whose diagonal pair is in this round: in float64
+                    // from the loads of their column slots; in the mixed
+                    // policy (float32 loads) from a loop of its own below
+                    constexpr bool fuse_d = !kSym && std::is_same<T, double>::value;
+                    // eight (or four) block slots at a time, their A and B
+                    // loads (from clamped, in-range offsets) all in flight
+                    // together and shared by the points; sin and cos are zero
+                    // past n, and blocks past nb and residuals past n are masked
+                    auto form = [&](int b0, auto rc) {
+                        constexpr int R = decltype(rc)::value;
+                        T bv[R], av[R];
+                        int col[R], dslot[R];
+                        bool on[R];
+                        uint32_t o[R];
 #pragma unroll
-                        for (int r = 0; r < 8; ++r) {
+                        for (int r = 0; r < R; ++r) {
                             const int bs = b0 + r < nform ? b0 + r : nform - 1;
                             const int blk = bs < kbg ? kgr * kbg + bs : ibr * rb + (bs - kbg);
                             on[r] = m_on && blk < nb;
                             col[r] = on[r] ? 16 * blk + tt : 0;
                             o[r] = mrow + (uint32_t)(col[r] < n ? col[r] : n - 1);
+                            const int ds = blk - ibr * rb;
+                            dslot[r] = bs < kbg && b0 + r < nform && blk < nb && ds >= 0 && ds < rb ? ds : -1;
                         }
-                        fp_ab_loads<T, 8>(a.fp, Ab, Bb, o, av, bv);
+                        fp_ab_loads<T, R>(a.fp, Ab, Bb, o, av, bv);
                         for (int qs = 0; qs < ppw; ++qs) {
 #pragma unroll
-                            for (int r = 0; r < 8; ++r) {
+                            for (int r = 0; r < R; ++r) {
                                 const int sc = qs * n16 + col[r];
                                 const T jv = bv[r] * (T)sins[sc] - av[r] * (T)coss[sc];
                                 if (b0 + r < nform) jt[(qs * nslots + b0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
+                                if (fuse_d && dslot[r] >= 0) {   // T = double: av, bv are float64-exact
+                                    const double dv = (double)av[r] * sins[sc] + (double)bv[r] * coss[sc];
+                                    dt[(qs * rb + dslot[r]) * (MT * 16) + threadIdx.x] = m_on ? dv : 0.0;
+                                }
                             }
                         }
+                    };
+                    for (int b0 = 0; b0 < nform;) {
+                        if (nform - b0 > 4) {
+                            form(b0, std::integral_constant<int, 8>{});
+                            b0 += 8;
+                        } else {
+                            form(b0, std::integral_constant<int, 4>{});
+                            b0 += 4;
+                        }
                     }
-                    // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row
-                    // blocks whose diagonal pair is in this round
-                    for (int q = 0; q < (kSym ? 0 : ppw * rb); ++q) {
+                    for (int q = 0; q < (kSym || fuse_d ? 0 : ppw * rb); ++q) {
                         const int qs = q / rb, blk = ibr * rb + (q - qs * rb);
                         if (blk >= nb || blk < kgr * kbg || blk >= kgr * kbg + kbg) continue;
                         const int col = 16 * blk + tt;
