@@ -66,21 +66,21 @@ LARGE_FP_NPTS = {64: 1 << 18, 512: 1024}   # points of the Fletcher-Powell large
 #   classes     wave-instructions per class: SQ_INSTS_VALU_{ADD,MUL,FMA}_F64,
 #               _INT32, _INT64, _CVT, _TRANS_F64, SQ_INSTS_LDS, SQ_INSTS_SALU
 COUNTERS = {
-    'coarse_kernel<F64, Ackley, 1, 1>': {'traffic': 402816512, 'valu_flops': 6073352192, 'valu_insts': 129761280, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20250624, 'valu_mul_f64': 28704768, 'valu_fma_f64': 22806528, 'valu_int32': 22478848, 'valu_int64': 2818048, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 27983872, 'salu': 56950784}, 'sha': 'fb9ae3d8046326fb'},
-    'coarse_kernel<F64, Ackley, 16, 1>': {'traffic': 402813472, 'valu_flops': 3556769792, 'valu_insts': 81788928, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8454144, 'valu_mul_f64': 9043968, 'valu_fma_f64': 18874368, 'valu_int32': 16711680, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 10682368, 'salu': 48562176}, 'sha': 'fb9ae3d8046326fb'},
-    'coarse_kernel<F64, Ackley, 2, 1>': {'traffic': 402784384, 'valu_flops': 4378853376, 'valu_insts': 99876864, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12124160, 'valu_mul_f64': 14548992, 'valu_fma_f64': 20709376, 'valu_int32': 21954560, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 9895936, 'salu': 62193664}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 1, 1>': {'traffic': 402816384, 'valu_flops': 6073352192, 'valu_insts': 129761280, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20250624, 'valu_mul_f64': 28704768, 'valu_fma_f64': 22806528, 'valu_int32': 22478848, 'valu_int64': 2818048, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 27983872, 'salu': 56950784}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 16, 1>': {'traffic': 402813504, 'valu_flops': 3556769792, 'valu_insts': 81788928, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8454144, 'valu_mul_f64': 9043968, 'valu_fma_f64': 18874368, 'valu_int32': 16711680, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 10682368, 'salu': 48562176}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Ackley, 2, 1>': {'traffic': 402784640, 'valu_flops': 4378853376, 'valu_insts': 99876864, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12124160, 'valu_mul_f64': 14548992, 'valu_fma_f64': 20709376, 'valu_int32': 21954560, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 9895936, 'salu': 62193664}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Ackley, 4, 1>': {'traffic': 402796544, 'valu_flops': 3909091328, 'valu_insts': 93585408, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10027008, 'valu_mul_f64': 11403264, 'valu_fma_f64': 19660800, 'valu_int32': 23003136, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 13041664, 'salu': 58785792}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Ackley, 8, 1>': {'traffic': 402777088, 'valu_flops': 3674210304, 'valu_insts': 85721088, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8978432, 'valu_mul_f64': 9830400, 'valu_fma_f64': 19136512, 'valu_int32': 18808832, 'valu_int64': 3080192, 'valu_cvt': 2555904, 'valu_trans_f64': 327680, 'lds': 11468800, 'salu': 51970048}, 'sha': 'fb9ae3d8046326fb'},
-    'coarse_kernel<F64, Rosenbrock, 1, 1>': {'traffic': 402738816, 'valu_flops': 5502926848, 'valu_insts': 130547712, 'mfma_flops': 0, 'classes': {'valu_add_f64': 5242880, 'valu_mul_f64': 38273024, 'valu_fma_f64': 21233664, 'valu_int32': 30146560, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 37748736}, 'sha': 'fb9ae3d8046326fb'},
+    'coarse_kernel<F64, Rosenbrock, 1, 1>': {'traffic': 402738368, 'valu_flops': 5502926848, 'valu_insts': 130547712, 'mfma_flops': 0, 'classes': {'valu_add_f64': 5242880, 'valu_mul_f64': 38273024, 'valu_fma_f64': 21233664, 'valu_int32': 30146560, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 37748736}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Rosenbrock, 16, 1>': {'traffic': 402732032, 'valu_flops': 486539264, 'valu_insts': 36962304, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1310720, 'valu_mul_f64': 3145728, 'valu_fma_f64': 1572864, 'valu_int32': 15204352, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 30670848}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Rosenbrock, 2, 1>': {'traffic': 402731008, 'valu_flops': 3070230528, 'valu_insts': 90177536, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 26214400, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 41680896}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Rosenbrock, 4, 1>': {'traffic': 402732032, 'valu_flops': 1593835520, 'valu_insts': 59768832, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 19922944, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 35389440}, 'sha': 'fb9ae3d8046326fb'},
     'coarse_kernel<F64, Rosenbrock, 8, 1>': {'traffic': 402733056, 'valu_flops': 855638016, 'valu_insts': 44564480, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 16777216, 'valu_int64': 1835008, 'valu_cvt': 2097152, 'valu_trans_f64': 0, 'lds': 2097152, 'salu': 32243712}, 'sha': 'fb9ae3d8046326fb'},
-    'fp_call_kernel<F64, 8, 1, false, false>': {'traffic': 402971968, 'valu_flops': 12297699328, 'valu_insts': 146341888, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12582912, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 25624576}, 'sha': '021b6e2a439d0177'},
-    'fp_call_kernel<F64, 8, 16, false, false>': {'traffic': 402993344, 'valu_flops': 12297699328, 'valu_insts': 145293312, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12058624, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 19726336}, 'sha': '021b6e2a439d0177'},
-    'fp_call_kernel<F64, 8, 2, false, false>': {'traffic': 402975808, 'valu_flops': 12297699328, 'valu_insts': 146210816, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12517376, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 22478848}, 'sha': '021b6e2a439d0177'},
-    'fp_call_kernel<F64, 8, 4, false, false>': {'traffic': 402982912, 'valu_flops': 12297699328, 'valu_insts': 145686528, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12255232, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20905984}, 'sha': '021b6e2a439d0177'},
-    'fp_call_kernel<F64, 8, 8, false, false>': {'traffic': 403018048, 'valu_flops': 12297699328, 'valu_insts': 145424384, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12124160, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20119552}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 1, false, false>': {'traffic': 402976704, 'valu_flops': 12297699328, 'valu_insts': 146341888, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12582912, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 25624576}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 16, false, false>': {'traffic': 402993600, 'valu_flops': 12297699328, 'valu_insts': 145293312, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12058624, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 19726336}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 2, false, false>': {'traffic': 402978944, 'valu_flops': 12297699328, 'valu_insts': 146210816, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12517376, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 22478848}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 4, false, false>': {'traffic': 402982272, 'valu_flops': 12297699328, 'valu_insts': 145686528, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12255232, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20905984}, 'sha': '021b6e2a439d0177'},
+    'fp_call_kernel<F64, 8, 8, false, false>': {'traffic': 403019904, 'valu_flops': 12297699328, 'valu_insts': 145424384, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 2883584, 'valu_mul_f64': 9961472, 'valu_fma_f64': 89653248, 'valu_int32': 12124160, 'valu_int64': 2686976, 'valu_cvt': 786432, 'valu_trans_f64': 0, 'lds': 2752512, 'salu': 20119552}, 'sha': '021b6e2a439d0177'},
     'plain_kernel<F64, Ackley, 1, false, false>': {'traffic': 402795520, 'valu_flops': 21609054208, 'valu_insts': 785383424, 'mfma_flops': 0, 'classes': {'valu_add_f64': 55574528, 'valu_mul_f64': 56623104, 'valu_fma_f64': 110100480, 'valu_int32': 266338304, 'valu_int64': 35651584, 'valu_cvt': 39845888, 'valu_trans_f64': 5242880, 'lds': 78643200, 'salu': 636485632}, 'sha': 'fb9ae3d8046326fb'},
     'plain_kernel<F64, Ackley, 2, false, false>': {'traffic': 402786304, 'valu_flops': 11341398016, 'valu_insts': 396361728, 'mfma_flops': 0, 'classes': {'valu_add_f64': 25690112, 'valu_mul_f64': 30408704, 'valu_fma_f64': 59244544, 'valu_int32': 128450560, 'valu_int64': 19922944, 'valu_cvt': 19922944, 'valu_trans_f64': 2621440, 'lds': 35127296, 'salu': 320339968}, 'sha': 'fb9ae3d8046326fb'},
     'plain_kernel<F64, Ackley, 4, false, false>': {'traffic': 402805760, 'valu_flops': 6408896512, 'valu_insts': 209715200, 'mfma_flops': 0, 'classes': {'valu_add_f64': 13893632, 'valu_mul_f64': 17301504, 'valu_fma_f64': 33816576, 'valu_int32': 66322432, 'valu_int64': 9961472, 'valu_cvt': 9961472, 'valu_trans_f64': 1310720, 'lds': 22806528, 'salu': 162267136}, 'sha': 'fb9ae3d8046326fb'},
@@ -89,10 +89,10 @@ COUNTERS = {
     'plain_kernel<F64, Rosenbrock, 2, false, false>': {'traffic': 402741248, 'valu_flops': 3992977408, 'valu_insts': 295698432, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12058624, 'valu_mul_f64': 25165824, 'valu_fma_f64': 12582912, 'valu_int32': 125304832, 'valu_int64': 9961472, 'valu_cvt': 17825792, 'valu_trans_f64': 0, 'lds': 19922944, 'salu': 240648192}, 'sha': 'fb9ae3d8046326fb'},
     'plain_kernel<F64, Rosenbrock, 4, false, false>': {'traffic': 402733056, 'valu_flops': 1929379840, 'valu_insts': 145752064, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 12582912, 'valu_fma_f64': 6291456, 'valu_int32': 61603840, 'valu_int64': 4980736, 'valu_cvt': 8912896, 'valu_trans_f64': 0, 'lds': 8912896, 'salu': 118226944}, 'sha': 'fb9ae3d8046326fb'},
     'plain_kernel<F64, Rosenbrock, 8, false, false>': {'traffic': 402734080, 'valu_flops': 956301312, 'valu_insts': 77594624, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2359296, 'valu_mul_f64': 6291456, 'valu_fma_f64': 3145728, 'valu_int32': 33816576, 'valu_int64': 2883584, 'valu_cvt': 4718592, 'valu_trans_f64': 0, 'lds': 4718592, 'salu': 63176704}, 'sha': 'fb9ae3d8046326fb'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403154560, 'valu_flops': 161682030592, 'valu_insts': 2341994496, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 51904512, 'valu_fma_f64': 1214513152, 'valu_int32': 483393536, 'valu_int64': 56098816, 'valu_cvt': 82575360, 'valu_trans_f64': 0, 'lds': 301727744, 'salu': 966524928}, 'sha': 'd8796d7c2e52ef1d'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403292224, 'valu_flops': 124772155392, 'valu_insts': 2045640704, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 81526784, 'valu_fma_f64': 907280384, 'valu_int32': 446169088, 'valu_int64': 116391936, 'valu_cvt': 97779712, 'valu_trans_f64': 0, 'lds': 246939648, 'salu': 490274816}, 'sha': 'd8796d7c2e52ef1d'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 38038272, 'valu_flops': 292811702272, 'valu_insts': 3630505984, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 75595776, 'valu_fma_f64': 2244329472, 'valu_int32': 666083328, 'valu_int64': 10248192, 'valu_cvt': 142753792, 'valu_trans_f64': 0, 'lds': 365543424, 'salu': 1962655744}, 'sha': 'd8796d7c2e52ef1d'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29805568, 'valu_flops': 164213817344, 'valu_insts': 1957105664, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 44359680, 'valu_fma_f64': 1256628224, 'valu_int32': 282345472, 'valu_int64': 21958656, 'valu_cvt': 83984384, 'valu_trans_f64': 0, 'lds': 191959040, 'salu': 523837440}, 'sha': 'd8796d7c2e52ef1d'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403153984, 'valu_flops': 161682030592, 'valu_insts': 2341994496, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 51904512, 'valu_fma_f64': 1214513152, 'valu_int32': 483393536, 'valu_int64': 56098816, 'valu_cvt': 82575360, 'valu_trans_f64': 0, 'lds': 301727744, 'salu': 966524928}, 'sha': '87c0d46d37539a84'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403292288, 'valu_flops': 124772155392, 'valu_insts': 2045640704, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 81526784, 'valu_fma_f64': 907280384, 'valu_int32': 446169088, 'valu_int64': 116391936, 'valu_cvt': 97779712, 'valu_trans_f64': 0, 'lds': 246939648, 'salu': 490274816}, 'sha': '87c0d46d37539a84'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 38038272, 'valu_flops': 292811702272, 'valu_insts': 3630505984, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 75595776, 'valu_fma_f64': 2244329472, 'valu_int32': 666083328, 'valu_int64': 10248192, 'valu_cvt': 142753792, 'valu_trans_f64': 0, 'lds': 365543424, 'salu': 1962655744}, 'sha': '87c0d46d37539a84'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29805440, 'valu_flops': 164213817344, 'valu_insts': 1957105664, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 44359680, 'valu_fma_f64': 1256628224, 'valu_int32': 282345472, 'valu_int64': 21958656, 'valu_cvt': 83984384, 'valu_trans_f64': 0, 'lds': 191959040, 'salu': 523837440}, 'sha': '87c0d46d37539a84'},
 }
 
 # The sources each kernel family is compiled from (with the build flags and,

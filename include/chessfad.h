@@ -348,12 +348,13 @@ typedef struct chessfad_instance {
 
 /* One plan-time tuning decision: the instances of func_id with n in
  * [n_lo, n_hi] (one octave) at `precision` run `chunk` with `mapping`
- * (Rosenbrock, Ackley: 1 = L1, 2 = L2) or `points` per workgroup
- * (Fletcher-Powell; 0 = the default); ms is its time on those instances,
+ * (Rosenbrock, Ackley: 1 = L1, 2 = L2) or `points` per workgroup and
+ * `blocks` column blocks per round (Fletcher-Powell; 0 = the default, as
+ * CHESSFAD_OPT_FP_POINTS / _FP_BLOCKS); ms is its time on those instances,
  * `candidates` the number of configurations timed. */
 typedef struct chessfad_batch_choice {
     int func_id, n_lo, n_hi, precision, instances;
-    int chunk, mapping, points, candidates;
+    int chunk, mapping, points, blocks, candidates;
     float ms;
 } chessfad_batch_choice;
 

@@ -34,7 +34,8 @@ class BatchChoice(ctypes.Structure):
     """struct chessfad_batch_choice"""
     _fields_ = [("func_id", ctypes.c_int), ("n_lo", ctypes.c_int), ("n_hi", ctypes.c_int),
                 ("precision", ctypes.c_int), ("instances", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("mapping", ctypes.c_int), ("points", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("mapping", ctypes.c_int), ("points", ctypes.c_int), ("blocks", ctypes.c_int),
+                ("candidates", ctypes.c_int),
                 ("ms", ctypes.c_float)]
 
 class FpShape(ctypes.Structure):

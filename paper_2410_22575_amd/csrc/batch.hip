@@ -36,10 +36,10 @@ namespace {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // An instance's body configuration: chunk, mapping of the vector bodies (1 =
-// L1, 2 = L2) and points per workgroup of the Fletcher-Powell body; 0 =
-// the default.
+// L1, 2 = L2), points per workgroup and column blocks per round of the
+// Fletcher-Powell body; 0 = the default.
 struct InstCfg {
-    int C = 0, mapping = 0, points = 0;
+    int C = 0, mapping = 0, points = 0, blocks = 0;
 };
 
 struct PlanEntry {
@@ -167,7 +167,7 @@ int plan_instances(const chessfad_instance* inst, int ninst, int* bad_index, Pla
         e.d.fp = FpParams{c.A, c.B, nullptr, nullptr, nullptr};
         const double per_call = model_flops_per_call(c.func_id, c.n, C);
         if (fp) {
-            const FpDppGeometry g = fp_dpp_geometry(c.n, c.npts, o.points, 0, c.precision == 1);
+            const FpDppGeometry g = fp_dpp_geometry(c.n, c.npts, o.points, o.blocks, c.precision == 1);
             e.d.kind = 1;
             e.d.nb = g.nb;
             e.d.ppw = g.ppw;
@@ -321,7 +321,9 @@ hipError_t launch_all(chessfad_batch* b, hipStream_t s) { return launch_lists(b-
 // wins (fewer f calls).  Candidates: Rosenbrock and Ackley, every compiled
 // chunk up to the group's smallest n in the L1 mapping and, up to 8 with
 // several chunks per row, in the L2 mapping; Fletcher-Powell, the largest
-// chunk up to 16 at 16, 4 and 1 points per workgroup (and the default).
+// chunk up to 16 at 16, 4 and 1 points per workgroup and the default, each
+// with the default column blocks per round and with as many as the
+// variables have (up to 16).
 int tune_plan(const chessfad_instance* inst, int ninst, hipStream_t s, std::vector<InstCfg>& cfg,
               std::vector<chessfad_batch_choice>& choices) {
     struct Group {
@@ -355,7 +357,8 @@ int tune_plan(const chessfad_instance* inst, int ninst, hipStream_t s, std::vect
             int C = 1;
             for (int k = 0; k < kNumChunks; ++k)
                 if (kChunks[k] <= std::min(16, g.nmin)) C = kChunks[k];
-            for (int pts : {0, 16, 4, 1}) cands.push_back(InstCfg{C, 0, pts});
+            for (int blocks : {0, 16})
+                for (int pts : {0, 16, 4, 1}) cands.push_back(InstCfg{C, 0, pts, blocks});
         } else {
             for (int k = 0; k < kNumChunks; ++k) {
                 const int C = kChunks[k];
@@ -409,6 +412,7 @@ int tune_plan(const chessfad_instance* inst, int ninst, hipStream_t s, std::vect
         ch.chunk = cands[pick].C;
         ch.mapping = cands[pick].mapping;
         ch.points = cands[pick].points;
+        ch.blocks = cands[pick].blocks;
         ch.ms = best_ms;
         ch.candidates = (int)cands.size();
         choices.push_back(ch);

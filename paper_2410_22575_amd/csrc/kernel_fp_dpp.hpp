@@ -356,9 +356,12 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
             // part sum_m r_m.v D_mi (and the gradient's sum_m r_m.v J_mi),
             // float64, from the tiles
             const bool diag = pair_on && kb == ib;
-            // a round whose row blocks all lie in its column group forms no
-            // row slots: a row's entries are its column slot's
-            const bool alias = ibr * rb >= kgr * kbg && ibr * rb + rb <= kgr * kbg + kbg;
+            // a float64 round whose row blocks all lie in its column group
+            // forms no row slots: a row's entries are its column slot's (the
+            // float bodies keep their own row slots, which holds the batched
+            // kernel's mixed body to three waves per SIMD)
+            const bool alias = std::is_same<T, double>::value && ibr * rb >= kgr * kbg &&
+                               ibr * rb + rb <= kgr * kbg + kbg;
             const int nform = alias ? kbg : nslots;
             const T* jr = alias ? jt + ((size_t)(ps * nslots + ibr * rb + ibs - kgr * kbg) * MT) * 16 + t : ji;
             double own = 0.0, gd = 0.0;
@@ -414,7 +417,9 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         }
                     };
                     for (int b0 = 0; b0 < nform;) {
-                        if (nform - b0 > 4) {
+                        // (the mixed policy keeps one group size: a second
+                        // instantiation costs it registers in the batch kernel)
+                        if (!std::is_same<T, double>::value || nform - b0 > 4) {
                             form(b0, std::integral_constant<int, 8>{});
                             b0 += 8;
                         } else {
@@ -502,10 +507,16 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                             for (int l = 0; l < C; ++l)
                                 if (cs + l < n) dst[l] = h[l] + h[l];
                         }
-                    } else if constexpr (!kSym) {
+                    } else if constexpr (!kSym && std::is_same<T, double>::value) {
                         // the call's terms h[l] v[cs + l] (v of lane cl + l)
                         // added to the row's partial column by column, in order
                         DppChunkDot<C, cl>::run(prt, vk, h);
+                    } else if constexpr (!kSym) {
+                        // float calls: the chunk dot first, then one add (fewer
+                        // live registers than the float64 form)
+                        double dot = 0.0;
+                        DppChunkDot<C, cl>::run(dot, vk, h);
+                        prt += dot;
                     } else {
                         // a counted call's chunk dot with v (v of lane cl + l)
                         double dot = 0.0;

@@ -247,7 +247,7 @@ def test_batch_plan_time_tuning(gpu_lib):
         assert ch["chunk"] in (1, 2, 4, 8, 16) and ch["chunk"] <= ch["n_lo"]
         assert ch["candidates"] >= 1 and ch["ms"] > 0 and ch["instances"] >= 1
         if ch["func_id"] == FP:
-            assert ch["points"] in (0, 1, 4, 16)
+            assert ch["points"] in (0, 1, 4, 16) and ch["blocks"] in (0, 16)
         else:
             assert ch["mapping"] in (1, 2)
             assert ch["mapping"] == 1 or ch["chunk"] <= 8
