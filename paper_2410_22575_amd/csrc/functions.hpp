@@ -22,6 +22,7 @@
 #pragma once
 
 #include "hd.hpp"
+#include "trig.hpp"
 
 namespace chessfad {
 
@@ -234,7 +235,7 @@ struct Ackley {
     // derivative of y -> cos(2 pi y) at x
     static CF_DEV void tables(double x, double& t0, double& t1) {
         double s;
-        sincos(kTwoPi * x, &s, &t0);
+        cf_sincos(kTwoPi * x, &s, &t0);
         t1 = -kTwoPi * s;
     }
     __host__ __device__ static int isl_tasks(int) { return 1; }
@@ -257,10 +258,10 @@ struct Ackley {
         const double inv_n = 1.0 / n;
         const double rt = sqrt(inv_n * ss);
         const double e1 = exp(-0.2 * rt);
-        const double nr = n * rt;
+        const double inr = (1.0 / rt) * inv_n;   // 1 / (n r)
         isl[0] = -20.0 * e1;
-        isl[1 * stride] = 2.0 * e1 / nr;
-        isl[2 * stride] = -e1 * (0.2 + 1.0 / rt) / (nr * nr);
+        isl[1 * stride] = 2.0 * e1 * inr;
+        isl[2 * stride] = -e1 * (0.2 + n * inr) * (inr * inr);
         const double g = -exp(inv_n * cs);
         isl[3 * stride] = g;
         isl[4 * stride] = g * inv_n;
@@ -403,7 +404,7 @@ struct Ackley {
 struct FletcherPowell {
     static constexpr int kTables = 2;
     // t0 = sin(x), t1 = cos(x)
-    static CF_DEV void tables(double x, double& t0, double& t1) { sincos(x, &t0, &t1); }
+    static CF_DEV void tables(double x, double& t0, double& t1) { cf_sincos(x, &t0, &t1); }
     __host__ __device__ static int isl_tasks(int n) { return n; }
     __host__ __device__ static int isl_size(int n) { return n; }
 

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_call_kernel(FpMfmaArgs a) {
                 sj = ssv[s >= NK / 2 ? s - NK / 2 : 0];
                 cj = csv[s >= NK / 2 ? s - NK / 2 : 0];
             } else if (in && live) {
-                sincos(xv[s], &sj, &cj);
+                cf_sincos(xv[s], &sj, &cj);
             }
             ssv[s] = sj;
             csv[s] = cj;

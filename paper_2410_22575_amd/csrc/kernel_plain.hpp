@@ -90,7 +90,12 @@ __device__ __forceinline__ void plain_stage_points(const PlainArgs& a, const Pla
     if (tasks) {
         for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
             const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
+            // the coordinates in float64: the staged row when it holds them
+            // (an LDS read), else the input
+            if constexpr (std::is_same<T, double>::value)
+                F::island(task, n, st.xs + pl * ks, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
+            else
+                F::island(task, n, xg + (size_t)pl * n, st.t0 + pl * ks, st.t1 + pl * ks, 1, a.fp, st.isl + pl * ki);
         }
         __syncthreads();
     }

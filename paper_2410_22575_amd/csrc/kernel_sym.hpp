@@ -134,7 +134,10 @@ __global__ __launch_bounds__(kSymThreads) void sym_kernel(SymArgs a) {
     if (tasks) {
         for (int idx = threadIdx.x; idx < npb * tasks; idx += blockDim.x) {
             const int pl = idx / tasks, task = idx - pl * tasks;
-            F::island(task, n, xg + (size_t)pl * n, t0 + pl * ks, t1 + pl * ks, 1, a.fp, isl + pl * ki);
+            if constexpr (std::is_same<T, double>::value)
+                F::island(task, n, xs + pl * ks, t0 + pl * ks, t1 + pl * ks, 1, a.fp, isl + pl * ki);
+            else
+                F::island(task, n, xg + (size_t)pl * n, t0 + pl * ks, t1 + pl * ks, 1, a.fp, isl + pl * ki);
         }
         __syncthreads();
     }
