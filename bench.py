@@ -98,12 +98,14 @@ COUNTERS = {
 # The sources each kernel family is compiled from (with the build flags and,
 # for the Fletcher-Powell DPP kernels, the generator of their inline-asm blocks).
 KERNEL_SOURCES = {
-    "coarse_kernel": ("hd.hpp", "functions.hpp", "kernel_plain.hpp"),
-    "plain_kernel": ("hd.hpp", "functions.hpp", "kernel_plain.hpp"),
-    "fp_call_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
-    "fp_dpp_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp", "kernel_fp_dpp.hpp"),
-    "fp_rows_kernel": ("hd.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_rows.hpp"),
-    "sym_kernel": ("hd.hpp", "functions.hpp", "kernel_sym.hpp"),
+    "coarse_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_plain.hpp"),
+    "plain_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_plain.hpp"),
+    "row16_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_row16.hpp"),
+    "fp_call_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
+    "fp_dpp_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp",
+                      "kernel_fp_dpp.hpp"),
+    "fp_rows_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_rows.hpp"),
+    "sym_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_sym.hpp"),
 }
 
 
@@ -122,6 +124,8 @@ def kernel_sha(key, read=None) -> str:
     h.update(" ".join(build.FLAGS[:-6]).encode())   # the flags, without the include paths
     if family.startswith(("fp_call", "fp_dpp")):
         h.update(inspect.getsource(build.write_dpp_blocks_inc).encode())
+    if family.startswith("row16"):
+        h.update(inspect.getsource(build.write_dpp_ackley_row16_inc).encode())
     for f in KERNEL_SOURCES.get(family, ()):
         rel = os.path.join("paper_2410_22575_amd", "csrc", f)
         h.update(rel.encode())
@@ -145,6 +149,8 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
     func = {0: "Rosenbrock", 1: "Ackley"}[f]
     if sym:
         return f"sym_kernel<{prec}, {func}, {c}, false>" + at
+    if n == 16 and not mixed and (c >= n or mapping == 1):
+        return f"row16_kernel<{func}, {c}>"
     if c >= n or mapping == 1:
         return f"coarse_kernel<{prec}, {func}, {c}, 1>" + at
     return f"plain_kernel<{prec}, {func}, {c}, false, false>" + at

@@ -526,6 +526,15 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     const bool one_chunk = (n + chunk - 1) / chunk == 1;
     if (!hess && !grad && !fval && (want != 2 || one_chunk)) {
         const int level = want == 2 ? 1 : want;
+        if (level == 1 && n == 16 && !mixed && (func_id == CHESSFAD_ROSENBROCK || func_id == CHESSFAD_ACKLEY)) {
+            // a point's 16 rows on one 16-lane row, its values in registers
+            Row16Launch launch = func_id == CHESSFAD_ROSENBROCK ? row16_rosenbrock(chunk) : row16_ackley(chunk);
+            if (!launch) return CHESSFAD_E_CHUNK;
+            const int64_t grid = (npts * 16 + kRow16Threads - 1) / kRow16Threads;
+            if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+            hipError_t e = launch(Row16Args{x, v, out, npts}, dim3((unsigned)grid), s);
+            return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+        }
         size_t lds = 0;
         const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, mixed, lds);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;

@@ -9,6 +9,7 @@
 #include "kernel_fp_tile.hpp"
 #include "kernel_fp_rows.hpp"
 #include "kernel_plain.hpp"
+#include "kernel_row16.hpp"
 #include "kernel_sym.hpp"
 
 namespace chessfad {
@@ -57,6 +58,30 @@ CoarseLaunch coarse_entry(int C) {
         default: return nullptr;
     }
 }
+
+// float64 H.v at n = 16 on register-resident points (the L1 mapping with a
+// point's rows on one 16-lane row), Rosenbrock and Ackley.
+using Row16Launch = hipError_t (*)(const Row16Args&, dim3 grid, hipStream_t);
+
+template <class F, int C>
+hipError_t launch_row16(const Row16Args& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((row16_kernel<F, C>), grid, dim3(kRow16Threads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class F>
+Row16Launch row16_entry(int C) {
+    switch (C) {
+        case 1: return &launch_row16<F, 1>;
+        case 2: return &launch_row16<F, 2>;
+        case 4: return &launch_row16<F, 4>;
+        case 8: return &launch_row16<F, 8>;
+        case 16: return &launch_row16<F, 16>;
+        default: return nullptr;
+    }
+}
+Row16Launch row16_rosenbrock(int C);
+Row16Launch row16_ackley(int C);
 
 // float64 H.v that also stores the gradient and f, one per function.
 PlainLaunch grad_rosenbrock(int C);

@@ -161,11 +161,14 @@ struct Rosenbrock {
     // zero row seed, so its second-order part is zero; its index is clamped.
     template <typename T, int C>
     static CF_DEV void row_terms(const PointView<T>& pv, HD<T, 2>& tm, HD<T, 2>& tp, int& km, int& kp) {
-        const int i = pv.i, n = pv.n, cs = pv.cs;
+        km = pv.i > 0 ? pv.i - 1 : 0;
+        kp = pv.i + 1 < pv.n ? pv.i + 1 : pv.i;
+        row_terms_at<T, C>(pv.i, pv.n, pv.cs, pv.x(km), pv.x(pv.i), pv.x(kp), tm, tp);
+    }
+    // the same from the coordinates x_km, x_i, x_kp themselves
+    template <typename T, int C>
+    static CF_DEV void row_terms_at(int i, int n, int cs, T xm, T xi, T xp, HD<T, 2>& tm, HD<T, 2>& tp) {
         auto chunk_seed = [&](int k) { return (k >= cs && k < cs + C) ? T(1) : T(0); };
-        km = i > 0 ? i - 1 : 0;
-        kp = i + 1 < n ? i + 1 : i;
-        const T xm = pv.x(km), xi = pv.x(i), xp = pv.x(kp);
         {
             // term k = i - 1: window (x_{i-1}, x_i)
             HD1<T, 2> a, b;
@@ -255,6 +258,10 @@ struct Ackley {
             ss += (double)xg[k] * (double)xg[k];
             cs += t0[k * stride];
         }
+        outer(n, ss, cs, isl, stride);
+    }
+    // the island values from the sums ss = sum x^2 and cs = sum cos(2 pi x)
+    static CF_DEV void outer(int n, double ss, double cs, double* isl, int stride) {
         const double inv_n = 1.0 / n;
         const double rt = sqrt(inv_n * ss);
         const double e1 = exp(-0.2 * rt);

@@ -1,4 +1,5 @@
-// Ackley: float64, every compiled chunk size, H.v (also with the gradient) and Hessian; the L0 / L1 mappings of H.v.
+// Ackley: float64, every compiled chunk size, H.v (also with the gradient) and Hessian; the L0 / L1 mappings of H.v
+// (L1 at n = 16 on register-resident points).
 #include "dispatch.hpp"
 
 namespace chessfad {
@@ -12,5 +13,7 @@ PlainLaunch grad_ackley(int C) { return plain_entry<F64, Ackley, false, true>(C)
 CoarseLaunch coarse_ackley(int C, int level) {
     return level == 0 ? coarse_entry<F64, Ackley, 0>(C) : coarse_entry<F64, Ackley, 1>(C);
 }
+
+Row16Launch row16_ackley(int C) { return row16_entry<Ackley>(C); }
 
 }  // namespace chessfad

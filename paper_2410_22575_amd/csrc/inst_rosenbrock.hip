@@ -1,4 +1,5 @@
-// Rosenbrock: float64, every compiled chunk size, H.v (also with the gradient) and Hessian; the L0 / L1 mappings of H.v.
+// Rosenbrock: float64, every compiled chunk size, H.v (also with the gradient) and Hessian; the L0 / L1 mappings of H.v
+// (L1 at n = 16 on register-resident points).
 #include "dispatch.hpp"
 
 namespace chessfad {
@@ -12,5 +13,7 @@ PlainLaunch grad_rosenbrock(int C) { return plain_entry<F64, Rosenbrock, false, 
 CoarseLaunch coarse_rosenbrock(int C, int level) {
     return level == 0 ? coarse_entry<F64, Rosenbrock, 0>(C) : coarse_entry<F64, Rosenbrock, 1>(C);
 }
+
+Row16Launch row16_rosenbrock(int C) { return row16_entry<Rosenbrock>(C); }
 
 }  // namespace chessfad

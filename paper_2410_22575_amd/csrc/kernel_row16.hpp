@@ -1,0 +1,124 @@
+// H.v at n = 16 for Rosenbrock and Ackley in float64: the paper's L1 mapping
+// (Sec. VI: one lane per (point p, row i), the lane walks the row's chunks in
+// order and keeps the row sum), with a point's 16 rows on one 16-lane row of
+// the wave.  Lane 16 r + i of a workgroup holds coordinate i of its point:
+// x_i and v_i come from one coalesced load (the flattened index q = 16 p + i
+// is the lane's own), its table values from its own sin and cos.  A call
+// (i, cs) reads the other coordinates' values from their lanes:
+//   - Rosenbrock's terms in x_i need x and v of lanes i - 1 and i + 1 (DPP
+//     row shifts; at the row's ends the lane's own value, the clamped index
+//     of the LDS kernels, whose terms there carry a zero row seed);
+//   - Ackley's chunk slots need x_k, the table value -2 pi sin(2 pi x_k) and
+//     v_k of lanes k = cs .. cs + C - 1: DPP row broadcasts (row_newbcast:k)
+//     inside the FMAs, and the point's two sums over its coordinates are
+//     butterflies over the row (row rotations by 8, 4, 2, 1, whose adds give
+//     every lane the same value: each step adds a pair in both of its lanes).
+// Nothing is staged in LDS and no lane waits at a barrier.  The calls'
+// arithmetic is that of the functions' hvp (Rosenbrock: the same row_terms;
+// Ackley: the slots' second-order components h_k = F'' S.d S.g_k +
+// G'' C.d C.g_k with S.g_k = 2 x_k, C.g_k = -2 pi sin(2 pi x_k), then
+// h_k v_k, and the own term), in the same order; only the summation order
+// inside Ackley's two sums differs.
+#pragma once
+
+#include <stdint.h>
+
+#include "functions.hpp"
+
+namespace chessfad {
+
+// dot += v_k h_k over the chunk's slots k = cs + l, l = 0 .. C - 1 in order,
+// with h_k = x_k (2 F'' S.d) + t1_k (G'' C.d); x_k, t1_k and v_k are read from
+// lane k of this lane's 16-lane row
+template <int C, int CS>
+struct AckleyRow16Slots;
+
+#include "dpp_ackley_row16.inc"
+
+constexpr int kRow16Threads = 256;   // 16 points per workgroup
+
+struct Row16Args {
+    const double* x;    // [npts][16]
+    const double* v;    // [npts][16]
+    double* out;        // [npts][16]
+    int64_t npts;
+};
+
+// DPP on the two 32-bit halves of a double (ctrl: the DPP control code);
+// lanes whose source lies outside the row keep `own`
+template <int kCtrl>
+__device__ __forceinline__ double row16_dpp(double src, double own) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(own), __double2loint(src), kCtrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(own), __double2hiint(src), kCtrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowShl1 = 0x101;   // lane i reads lane i + 1
+constexpr int kDppRowShr1 = 0x111;   // lane i reads lane i - 1
+constexpr int kDppRowRor = 0x120;    // + r: lane i reads lane (i - r) mod 16
+
+// sum of a value over the lanes of the 16-lane row, the same in every lane
+__device__ __forceinline__ double row16_sum(double a) {
+    a += row16_dpp<kDppRowRor + 8>(a, a);
+    a += row16_dpp<kDppRowRor + 4>(a, a);
+    a += row16_dpp<kDppRowRor + 2>(a, a);
+    a += row16_dpp<kDppRowRor + 1>(a, a);
+    return a;
+}
+
+template <int C>
+__device__ __forceinline__ double row16_rosenbrock(double xi, double vi, int i) {
+    const double xm = row16_dpp<kDppRowShr1>(xi, xi), xp = row16_dpp<kDppRowShl1>(xi, xi);
+    const double vm = row16_dpp<kDppRowShr1>(vi, vi), vp = row16_dpp<kDppRowShl1>(vi, vi);
+    double res = 0.0;
+    static_for<16 / C>([&](auto jc) {
+        constexpr int cs = decltype(jc)::value * C;
+        HD<double, 2> tm, tp;
+        Rosenbrock::row_terms_at<double, C>(i, 16, cs, xm, xi, xp, tm, tp);
+        F64::Dot acc;
+        acc.add(tm.h[0], vm);
+        acc.add(tm.h[1], vi);
+        acc.add(tp.h[0], vi);
+        acc.add(tp.h[1], vp);
+        res += acc.get();
+    });
+    return res;
+}
+
+template <int C>
+__device__ __forceinline__ double row16_ackley(double xi, double vi, int i) {
+    double t0, t1;
+    Ackley::tables(xi, t0, t1);
+    double isl[6];
+    Ackley::outer(16, row16_sum(xi * xi), row16_sum(t0), isl, 1);
+    const double f1 = isl[1], g1 = isl[4];
+    // the row seed's first-order parts S.d = 2 x_i, C.d = t1_i through F'' and
+    // G''; the own term's second-order parts S.h = 2, C.h = -4 pi^2 t0_i
+    const double f2d = isl[2] * (2.0 * xi), g2d = isl[5] * t1;
+    const double own = f1 * 2.0 + g1 * (-kTwoPi * kTwoPi * t0);
+    double res = 0.0;
+    static_for<16 / C>([&](auto jc) {
+        constexpr int cs = decltype(jc)::value * C;
+        double dot = 0.0;
+        AckleyRow16Slots<C, cs>::run(dot, xi, t1, vi, f2d + f2d, g2d);
+        if (i >= cs && i < cs + C) dot += own * vi;
+        res += dot;
+    });
+    return res;
+}
+
+template <class F, int C>
+__global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
+    const int64_t q = (int64_t)blockIdx.x * kRow16Threads + threadIdx.x;
+    const int i = threadIdx.x & 15;
+    // whole points only: a lane past the end belongs to a point past the end
+    const bool live = q < a.npts * 16;
+    const double xi = live ? a.x[q] : 0.5, vi = live ? a.v[q] : 0.0;
+    double r;
+    if constexpr (std::is_same<F, Ackley>::value)
+        r = row16_ackley<C>(xi, vi, i);
+    else
+        r = row16_rosenbrock<C>(xi, vi, i);
+    if (live) a.out[q] = r;
+}
+
+}  // namespace chessfad

@@ -276,6 +276,34 @@ def test_coarse_mappings_match_l2(gpu_lib, func):
         gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev_map)
 
 
+@pytest.mark.parametrize("func", [R, A])
+@pytest.mark.parametrize("npts", [1, 15, 17, 300])
+def test_row16_register_path(gpu_lib, func, npts):
+    """n = 16 in the L1 mapping runs on register-resident points (a point's
+    16 rows on one 16-lane row of the wave, neighbours' values by DPP): every
+    chunk against the oracle, and against the LDS-staged L0 mapping (one
+    lane per point) to a few units of rounding; point counts that leave the
+    last workgroup partly empty (1, 15, 17 points)."""
+    n = 16
+    w = inputs.make_workload(func, n, npts, inputs.rng_for(8800 + 10 * func + npts))
+    x, v = _dev(w.x), _dev(w.v)
+    r_ref = cf.hvp(func, w.x, w.v)
+    _, hmax = _hmax(func, w, None)
+    prev = gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 1)
+    try:
+        for c in CHUNKS:
+            print(f"[case] row16 func={func} npts={npts} C={c}", flush=True)
+            gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 1)
+            out = torch.full_like(x, 7.0)
+            r = gpu_lib.chessfad_hvp(func, x, v, out, chunk=c).cpu().numpy()
+            assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64, (func, npts, c)
+            gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, 0)
+            r0 = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+            assert np.max(_hvp_err(r, r0, hmax, w.v)) <= 1e-14, (func, npts, c)
+    finally:
+        gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev)
+
+
 @pytest.mark.parametrize("func,mfma", FUNC_PATHS)
 @pytest.mark.parametrize("n", [2, 5, 16, 40])
 def test_hvp_with_gradient_and_value(gpu_lib, func, mfma, n):
