@@ -143,7 +143,7 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
     if f == 2 and n <= 16:
         if sym:
             return f"fp_mfma_kernel<{prec}, {c}, {min(8, max(1, (2 * n + 3) // 4))}, false, true>" + at
-        return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false>" + at
+        return f"fp_call_kernel<{prec}, {min(8, max(1, (2 * n + 3) // 4))}, {c}, false, false, {16 if n == 16 else 0}>" + at
     if f == 2:
         return f"fp_dpp_kernel<{prec}, {c}, false, false, {'true' if sym else 'false'}>" + at
     func = {0: "Rosenbrock", 1: "Ackley"}[f]

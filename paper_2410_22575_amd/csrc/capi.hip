@@ -447,8 +447,8 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
         FpMfmaLaunch launch = nullptr;
         if (g_opt_fp_mfma == 1 && !sym) {
             // the per-call kernel (DPP lane broadcasts)
-            launch = mixed ? fp_call_entry_mixed(chunk, nk, hess)
-                           : (grad || fval) ? fp_call_entry_grad(chunk, nk) : fp_call_entry(chunk, nk, hess);
+            launch = mixed ? fp_call_entry_mixed(chunk, nk, hess, n)
+                           : (grad || fval) ? fp_call_entry_grad(chunk, nk, n) : fp_call_entry(chunk, nk, hess, n);
         } else if (g_opt_fp_mfma == 3) {
             // the closed-form point tile: every call of a point is a block of
             // its J^T J tile (the chunk size and the symmetric form give the

@@ -146,26 +146,29 @@ FpMfmaLaunch fp_tile_by_steps(int nk) {
 FpMfmaLaunch fp_tile_entry(int nk, bool hess);
 FpMfmaLaunch fp_tile_entry_mixed(int nk, bool hess);
 
-template <class P, int NK, int C, bool kHess, bool kGrad>
+template <class P, int NK, int C, bool kHess, bool kGrad, int kN>
 hipError_t launch_fp_call(const FpMfmaArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-    hipLaunchKernelGGL((fp_call_kernel<P, NK, C, kHess, kGrad>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((fp_call_kernel<P, NK, C, kHess, kGrad, kN>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
-template <class P, int NK, bool kHess, bool kGrad>
+template <class P, int NK, bool kHess, bool kGrad, int kN = 0>
 FpMfmaLaunch fp_call_entry_c(int C) {
     switch (C) {
-        case 1: return &launch_fp_call<P, NK, 1, kHess, kGrad>;
-        case 2: return &launch_fp_call<P, NK, 2, kHess, kGrad>;
-        case 4: return &launch_fp_call<P, NK, 4, kHess, kGrad>;
-        case 8: return &launch_fp_call<P, NK, 8, kHess, kGrad>;
-        case 16: return &launch_fp_call<P, NK, 16, kHess, kGrad>;
+        case 1: return &launch_fp_call<P, NK, 1, kHess, kGrad, kN>;
+        case 2: return &launch_fp_call<P, NK, 2, kHess, kGrad, kN>;
+        case 4: return &launch_fp_call<P, NK, 4, kHess, kGrad, kN>;
+        case 8: return &launch_fp_call<P, NK, 8, kHess, kGrad, kN>;
+        case 16: return &launch_fp_call<P, NK, 16, kHess, kGrad, kN>;
         default: return nullptr;
     }
 }
 
+// H.v at n = 16 has an instance of its own (n a compile-time constant)
 template <class P, bool kHess, bool kGrad>
-FpMfmaLaunch fp_call_by_steps(int C, int nk) {
+FpMfmaLaunch fp_call_by_steps(int C, int nk, int n) {
+    if constexpr (!kHess && !kGrad)
+        if (n == 16) return fp_call_entry_c<P, 8, false, false, 16>(C);
     switch (nk) {
         case 1: return fp_call_entry_c<P, 1, kHess, kGrad>(C);
         case 2: return fp_call_entry_c<P, 2, kHess, kGrad>(C);
@@ -178,9 +181,9 @@ FpMfmaLaunch fp_call_by_steps(int C, int nk) {
 // The per-call Fletcher-Powell kernel (n <= 16) for a chunk, K-step count and
 // output kind: float64 H.v / Hessian, float64 H.v with the gradient and f, and
 // mixed precision (one translation unit each).
-FpMfmaLaunch fp_call_entry(int C, int nk, bool hess);
-FpMfmaLaunch fp_call_entry_grad(int C, int nk);
-FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess);
+FpMfmaLaunch fp_call_entry(int C, int nk, bool hess, int n);
+FpMfmaLaunch fp_call_entry_grad(int C, int nk, int n);
+FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess, int n);
 
 using FpDppLaunch = hipError_t (*)(const FpDppArgs&, dim3 grid, dim3 block, size_t lds, hipStream_t);
 

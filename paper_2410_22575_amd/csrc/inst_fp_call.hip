@@ -4,8 +4,8 @@
 
 namespace chessfad {
 
-FpMfmaLaunch fp_call_entry(int C, int nk, bool hess) {
-    return hess ? fp_call_by_steps<F64, true, false>(C, nk) : fp_call_by_steps<F64, false, false>(C, nk);
+FpMfmaLaunch fp_call_entry(int C, int nk, bool hess, int n) {
+    return hess ? fp_call_by_steps<F64, true, false>(C, nk, n) : fp_call_by_steps<F64, false, false>(C, nk, n);
 }
 
 }  // namespace chessfad

@@ -4,6 +4,6 @@
 
 namespace chessfad {
 
-FpMfmaLaunch fp_call_entry_grad(int C, int nk) { return fp_call_by_steps<F64, false, true>(C, nk); }
+FpMfmaLaunch fp_call_entry_grad(int C, int nk, int n) { return fp_call_by_steps<F64, false, true>(C, nk, n); }
 
 }  // namespace chessfad

@@ -4,8 +4,8 @@
 
 namespace chessfad {
 
-FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess) {
-    return hess ? fp_call_by_steps<F32C, true, false>(C, nk) : fp_call_by_steps<F32C, false, false>(C, nk);
+FpMfmaLaunch fp_call_entry_mixed(int C, int nk, bool hess, int n) {
+    return hess ? fp_call_by_steps<F32C, true, false>(C, nk, n) : fp_call_by_steps<F32C, false, false>(C, nk, n);
 }
 
 }  // namespace chessfad

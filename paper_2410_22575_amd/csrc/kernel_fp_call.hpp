@@ -61,8 +61,19 @@ struct DppRowProducts;
 
 constexpr int kFpCallRows = 4;  // points per wave in one pass (one per 16-lane row)
 
-template <class Prec, int NK, int C, bool kHess, bool kGrad>
-__global__ __launch_bounds__(64 * kFpWaves) void fp_call_kernel(FpMfmaArgs a) {
+// Waves per SIMD the register budget is cut for: four (128 VGPRs; the
+// value column's MFMA results stay in VGPRs), except float64 calls of 16
+// columns (and of 8 in the n = 16 instance), whose product sums and J values
+// need more (three waves).
+template <class Prec, int C, int kN>
+constexpr int fp_call_min_waves() {
+    return std::is_same<typename Prec::T, double>::value && (C == 16 || (kN && C == 8)) ? 3 : 4;
+}
+
+// kN = 16: the instance for n = 16 (n and the chunk count are constants, so
+// the bounds guards and index divisions fold); kN = 0: n from the arguments.
+template <class Prec, int NK, int C, bool kHess, bool kGrad, int kN>
+__global__ __launch_bounds__(64 * kFpWaves, (fp_call_min_waves<Prec, C, kN>())) void fp_call_kernel(FpMfmaArgs a) {
     using T = typename Prec::T;
     constexpr int P = kFpPointsPerWave, S = kFpVStride;
     // per wave: sin x, cos x, r.v and v of each (point, coordinate or
@@ -72,7 +83,7 @@ __global__ __launch_bounds__(64 * kFpWaves) void fp_call_kernel(FpMfmaArgs a) {
     // A and B as [m][k], zero outside n x n
     __shared__ double as[16 * S], bs[16 * S];
 
-    const int n = a.n, nc = a.nc;
+    const int n = kN ? kN : a.n, nc = kN ? (kN + C - 1) / C : a.nc;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
     const int64_t pbase = ((int64_t)blockIdx.x * kFpWaves + wave) * P;
