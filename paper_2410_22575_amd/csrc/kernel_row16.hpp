@@ -112,13 +112,15 @@ __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     const int i = threadIdx.x & 15;
     // whole points only: a lane past the end belongs to a point past the end
     const bool live = q < a.npts * 16;
-    const double xi = live ? a.x[q] : 0.5, vi = live ? a.v[q] : 0.0;
+    // every element is read and written once: streaming (non-temporal) accesses
+    const double xi = live ? __builtin_nontemporal_load(a.x + q) : 0.5;
+    const double vi = live ? __builtin_nontemporal_load(a.v + q) : 0.0;
     double r;
     if constexpr (std::is_same<F, Ackley>::value)
         r = row16_ackley<C>(xi, vi, i);
     else
         r = row16_rosenbrock<C>(xi, vi, i);
-    if (live) a.out[q] = r;
+    if (live) __builtin_nontemporal_store(r, a.out + q);
 }
 
 }  // namespace chessfad
