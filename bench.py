@@ -149,8 +149,8 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
     func = {0: "Rosenbrock", 1: "Ackley"}[f]
     if sym:
         return f"sym_kernel<{prec}, {func}, {c}, false>" + at
-    if n == 16 and not mixed and (c >= n or mapping == 1):
-        return f"row16_kernel<{func}, {c}>"
+    if n == 16 and (c >= n or mapping == 1):
+        return f"row16_kernel<{prec}, {func}, {c}>"
     if c >= n or mapping == 1:
         return f"coarse_kernel<{prec}, {func}, {c}, 1>" + at
     return f"plain_kernel<{prec}, {func}, {c}, false, false>" + at

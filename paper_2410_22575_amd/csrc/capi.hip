@@ -526,9 +526,11 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     const bool one_chunk = (n + chunk - 1) / chunk == 1;
     if (!hess && !grad && !fval && (want != 2 || one_chunk)) {
         const int level = want == 2 ? 1 : want;
-        if (level == 1 && n == 16 && !mixed && (func_id == CHESSFAD_ROSENBROCK || func_id == CHESSFAD_ACKLEY)) {
+        if (level == 1 && n == 16 && (func_id == CHESSFAD_ROSENBROCK || func_id == CHESSFAD_ACKLEY)) {
             // a point's 16 rows on one 16-lane row, its values in registers
-            Row16Launch launch = func_id == CHESSFAD_ROSENBROCK ? row16_rosenbrock(chunk) : row16_ackley(chunk);
+            Row16Launch launch = func_id == CHESSFAD_ROSENBROCK
+                                     ? (mixed ? row16_mixed_rosenbrock(chunk) : row16_rosenbrock(chunk))
+                                     : (mixed ? row16_mixed_ackley(chunk) : row16_ackley(chunk));
             if (!launch) return CHESSFAD_E_CHUNK;
             const int64_t grid = (npts * 16 + kRow16Threads - 1) / kRow16Threads;
             if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;

@@ -63,25 +63,27 @@ CoarseLaunch coarse_entry(int C) {
 // point's rows on one 16-lane row), Rosenbrock and Ackley.
 using Row16Launch = hipError_t (*)(const Row16Args&, dim3 grid, hipStream_t);
 
-template <class F, int C>
+template <class P, class F, int C>
 hipError_t launch_row16(const Row16Args& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((row16_kernel<F, C>), grid, dim3(kRow16Threads), 0, s, a);
+    hipLaunchKernelGGL((row16_kernel<P, F, C>), grid, dim3(kRow16Threads), 0, s, a);
     return hipGetLastError();
 }
 
-template <class F>
+template <class P, class F>
 Row16Launch row16_entry(int C) {
     switch (C) {
-        case 1: return &launch_row16<F, 1>;
-        case 2: return &launch_row16<F, 2>;
-        case 4: return &launch_row16<F, 4>;
-        case 8: return &launch_row16<F, 8>;
-        case 16: return &launch_row16<F, 16>;
+        case 1: return &launch_row16<P, F, 1>;
+        case 2: return &launch_row16<P, F, 2>;
+        case 4: return &launch_row16<P, F, 4>;
+        case 8: return &launch_row16<P, F, 8>;
+        case 16: return &launch_row16<P, F, 16>;
         default: return nullptr;
     }
 }
 Row16Launch row16_rosenbrock(int C);
 Row16Launch row16_ackley(int C);
+Row16Launch row16_mixed_rosenbrock(int C);
+Row16Launch row16_mixed_ackley(int C);
 
 // float64 H.v that also stores the gradient and f, one per function.
 PlainLaunch grad_rosenbrock(int C);

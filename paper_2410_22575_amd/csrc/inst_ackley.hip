@@ -14,6 +14,6 @@ CoarseLaunch coarse_ackley(int C, int level) {
     return level == 0 ? coarse_entry<F64, Ackley, 0>(C) : coarse_entry<F64, Ackley, 1>(C);
 }
 
-Row16Launch row16_ackley(int C) { return row16_entry<Ackley>(C); }
+Row16Launch row16_ackley(int C) { return row16_entry<F64, Ackley>(C); }
 
 }  // namespace chessfad

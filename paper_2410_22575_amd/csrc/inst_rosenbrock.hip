@@ -14,6 +14,6 @@ CoarseLaunch coarse_rosenbrock(int C, int level) {
     return level == 0 ? coarse_entry<F64, Rosenbrock, 0>(C) : coarse_entry<F64, Rosenbrock, 1>(C);
 }
 
-Row16Launch row16_rosenbrock(int C) { return row16_entry<Rosenbrock>(C); }
+Row16Launch row16_rosenbrock(int C) { return row16_entry<F64, Rosenbrock>(C); }
 
 }  // namespace chessfad

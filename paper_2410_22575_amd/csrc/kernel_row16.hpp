@@ -1,4 +1,4 @@
-// H.v at n = 16 for Rosenbrock and Ackley in float64: the paper's L1 mapping
+// H.v at n = 16 for Rosenbrock and Ackley: the paper's L1 mapping
 // (Sec. VI: one lane per (point p, row i), the lane walks the row's chunks in
 // order and keeps the row sum), with a point's 16 rows on one 16-lane row of
 // the wave.  Lane 16 r + i of a workgroup holds coordinate i of its point:
@@ -18,7 +18,10 @@
 // Ackley: the slots' second-order components h_k = F'' S.d S.g_k +
 // G'' C.d C.g_k with S.g_k = 2 x_k, C.g_k = -2 pi sin(2 pi x_k), then
 // h_k v_k, and the own term), in the same order; only the summation order
-// inside Ackley's two sums differs.
+// inside Ackley's two sums differs.  Precision policies as the LDS kernels:
+// F64 in float64 throughout; F32C with float32 hDual components (x, v and the
+// table values rounded where used), float64 islands and a float64 chunk dot
+// of the float32 values.
 #pragma once
 
 #include <stdint.h>
@@ -28,9 +31,9 @@
 namespace chessfad {
 
 // dot += v_k h_k over the chunk's slots k = cs + l, l = 0 .. C - 1 in order,
-// with h_k = x_k (2 F'' S.d) + t1_k (G'' C.d); x_k, t1_k and v_k are read from
-// lane k of this lane's 16-lane row
-template <int C, int CS>
+// with h_k = x_k (2 F'' S.d) + t1_k (G'' C.d) in T; x_k, t1_k and v_k are read
+// from lane k of this lane's 16-lane row (v_k as float64)
+template <typename T, int C, int CS>
 struct AckleyRow16Slots;
 
 #include "dpp_ackley_row16.inc"
@@ -44,13 +47,18 @@ struct Row16Args {
     int64_t npts;
 };
 
-// DPP on the two 32-bit halves of a double (ctrl: the DPP control code);
-// lanes whose source lies outside the row keep `own`
+// DPP on the two 32-bit halves of a double, or on a float (ctrl: the DPP
+// control code); lanes whose source lies outside the row keep `own`
 template <int kCtrl>
 __device__ __forceinline__ double row16_dpp(double src, double own) {
     const int lo = __builtin_amdgcn_update_dpp(__double2loint(own), __double2loint(src), kCtrl, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(__double2hiint(own), __double2hiint(src), kCtrl, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
+}
+template <int kCtrl>
+__device__ __forceinline__ float row16_dpp(float src, float own) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(own), __float_as_int(src), kCtrl, 0xf, 0xf, false));
 }
 constexpr int kDppRowShl1 = 0x101;   // lane i reads lane i + 1
 constexpr int kDppRowShr1 = 0x111;   // lane i reads lane i - 1
@@ -65,16 +73,18 @@ __device__ __forceinline__ double row16_sum(double a) {
     return a;
 }
 
-template <int C>
-__device__ __forceinline__ double row16_rosenbrock(double xi, double vi, int i) {
-    const double xm = row16_dpp<kDppRowShr1>(xi, xi), xp = row16_dpp<kDppRowShl1>(xi, xi);
-    const double vm = row16_dpp<kDppRowShr1>(vi, vi), vp = row16_dpp<kDppRowShl1>(vi, vi);
+template <class P, int C>
+__device__ __forceinline__ double row16_rosenbrock(double xd, double vd, int i) {
+    using T = typename P::T;
+    const T xi = (T)xd, vi = (T)vd;
+    const T xm = row16_dpp<kDppRowShr1>(xi, xi), xp = row16_dpp<kDppRowShl1>(xi, xi);
+    const T vm = row16_dpp<kDppRowShr1>(vi, vi), vp = row16_dpp<kDppRowShl1>(vi, vi);
     double res = 0.0;
     static_for<16 / C>([&](auto jc) {
         constexpr int cs = decltype(jc)::value * C;
-        HD<double, 2> tm, tp;
-        Rosenbrock::row_terms_at<double, C>(i, 16, cs, xm, xi, xp, tm, tp);
-        F64::Dot acc;
+        HD<T, 2> tm, tp;
+        Rosenbrock::row_terms_at<T, C>(i, 16, cs, xm, xi, xp, tm, tp);
+        typename P::Dot acc;
         acc.add(tm.h[0], vm);
         acc.add(tm.h[1], vi);
         acc.add(tp.h[0], vi);
@@ -84,29 +94,33 @@ __device__ __forceinline__ double row16_rosenbrock(double xi, double vi, int i) 
     return res;
 }
 
-template <int C>
-__device__ __forceinline__ double row16_ackley(double xi, double vi, int i) {
-    double t0, t1;
-    Ackley::tables(xi, t0, t1);
+template <class P, int C>
+__device__ __forceinline__ double row16_ackley(double xd, double vd, int i) {
+    using T = typename P::T;
+    double t0d, t1d;
+    Ackley::tables(xd, t0d, t1d);
+    // the islands in float64 from the float64 inputs
     double isl[6];
-    Ackley::outer(16, row16_sum(xi * xi), row16_sum(t0), isl, 1);
-    const double f1 = isl[1], g1 = isl[4];
+    Ackley::outer(16, row16_sum(xd * xd), row16_sum(t0d), isl, 1);
+    const T xi = (T)xd, t0 = (T)t0d, t1 = (T)t1d, vi = (T)vd;
+    const T f1 = (T)isl[1], g1 = (T)isl[4];
     // the row seed's first-order parts S.d = 2 x_i, C.d = t1_i through F'' and
-    // G''; the own term's second-order parts S.h = 2, C.h = -4 pi^2 t0_i
-    const double f2d = isl[2] * (2.0 * xi), g2d = isl[5] * t1;
-    const double own = f1 * 2.0 + g1 * (-kTwoPi * kTwoPi * t0);
+    // G'' (formed in float64, then rounded); the own term's second-order parts
+    // S.h = 2, C.h = -4 pi^2 t0_i
+    const T f2d = (T)(isl[2] * (double)(T(2) * xi)), g2d = (T)(isl[5] * (double)t1);
+    const T own = f1 * T(2) + g1 * (T(-kTwoPi * kTwoPi) * t0);
     double res = 0.0;
     static_for<16 / C>([&](auto jc) {
         constexpr int cs = decltype(jc)::value * C;
         double dot = 0.0;
-        AckleyRow16Slots<C, cs>::run(dot, xi, t1, vi, f2d + f2d, g2d);
-        if (i >= cs && i < cs + C) dot += own * vi;
+        AckleyRow16Slots<T, C, cs>::run(dot, xi, t1, (double)vi, f2d + f2d, g2d);
+        if (i >= cs && i < cs + C) dot += (double)own * (double)vi;
         res += dot;
     });
     return res;
 }
 
-template <class F, int C>
+template <class P, class F, int C>
 __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     const int64_t q = (int64_t)blockIdx.x * kRow16Threads + threadIdx.x;
     const int i = threadIdx.x & 15;
@@ -117,9 +131,9 @@ __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     const double vi = live ? __builtin_nontemporal_load(a.v + q) : 0.0;
     double r;
     if constexpr (std::is_same<F, Ackley>::value)
-        r = row16_ackley<C>(xi, vi, i);
+        r = row16_ackley<P, C>(xi, vi, i);
     else
-        r = row16_rosenbrock<C>(xi, vi, i);
+        r = row16_rosenbrock<P, C>(xi, vi, i);
     if (live) __builtin_nontemporal_store(r, a.out + q);
 }
 
