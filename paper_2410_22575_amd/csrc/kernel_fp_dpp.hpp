@@ -26,9 +26,9 @@
 // row and column blocks in LDS once, each from A, B and the point's
 // sin x, cos x, so that every call reads its r_m.d = J_mi and r_m.g = J_m,k
 // there.  The row's own second-order part, sum_m r_m.v D_mi, is formed once
-// per row by the lane row of its diagonal pair and added in the call that
-// holds column i (D_mi is formed in LDS beside the J tile in the round of the
-// diagonal pair).  H.v: each call's terms h[l] v[cs + l] (v of lane jC + l)
+// per row after the value column (float64, m in order, from the row's column
+// of A and B, loads coalesced across the rows) and added in the call that
+// holds column i.  H.v: each call's terms h[l] v[cs + l] (v of lane jC + l)
 // are added to the row's partial of the pair column by column in order; the
 // row's partials of its column blocks are summed in block order through
 // LDS.  Hessian: H[p][i][cs + l] is stored per call.
@@ -84,7 +84,7 @@ constexpr int kFpDppTile = 16;   // residuals per J tile (MT x 16 lanes = the wo
 // the J tile.
 __host__ __device__ inline size_t fp_dpp_lds_doubles(int nb, int ppw, int rb, bool sym = false) {
     if (sym) return (size_t)4 * ppw * 16 * nb + 512;
-    return (size_t)4 * ppw * 16 * nb + 256 + 2 * (size_t)ppw * rb * 16 + (size_t)ppw * rb * kFpDppTile * 16;
+    return (size_t)4 * ppw * 16 * nb + 256 + (size_t)ppw * rb * 16;
 }
 template <typename T>
 __host__ __device__ inline size_t fp_dpp_lds_bytes(int nb, int ppw, int rb, int kbg, bool sym = false) {
@@ -259,11 +259,11 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     double* vs = rvs + ppw * n16;
     double* part = vs + ppw * n16;            // [16 lane rows][16]
     double* rowsum = part + 256;              // [ppw][rb][16]; kSym: the mirror partials [16 lane rows][16]
-    double* owns = rowsum + ppw * rb * 16;    // [ppw][rb][16]
-    double* dt = owns + ppw * rb * 16;        // [ppw][rb][MT][16]
-    T* jt = reinterpret_cast<T*>(kSym ? rowsum + 256 : dt + ppw * rb * MT * 16);   // [ppw][nslots][MT][16]
+    T* jt = reinterpret_cast<T*>(kSym ? rowsum + 256 : rowsum + ppw * rb * 16);   // [ppw][nslots][MT][16]
     double* mirp = rowsum;
-    double* sacc = rvs;   // kSym, after the prologue: H.v running results, or the rows' own parts
+    // after the prologue: the rows' own parts (kSym H.v: the running results,
+    // started at own_i v_i)
+    double* sacc = rvs;
     const int64_t p0 = pg * ppw;
 
     // 1. sin x, cos x and v of the workgroup's points (zeros past n and npts);
@@ -277,46 +277,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     // 2. the value column r_m.v (float64)
     fp_dpp_value_column(a, p0, sins, coss, rvs);
     __syncthreads();
-    if constexpr (kSym) {
-        // the rows' own parts own_i = sum_m r_m.v D_mi, D_mi = A_mi sin x_i +
-        // B_mi cos x_i (float64, m in order), held in registers until every
-        // thread has read r.v; their space then starts the running results
-        // at own_i v_i (H.v) or keeps own_i (Hessian)
-        constexpr int kMaxTasks = 8;   // ppw 16 nb <= 2048 (the LDS limit)
-        double ownr[kMaxTasks];
-#pragma unroll
-        for (int k = 0; k < kMaxTasks; ++k) {
-            const int task = threadIdx.x + k * kFpDppThreads;
-            ownr[k] = 0.0;
-            if (task < ppw * n16) {
-                const int ps = task / n16, i = task - ps * n16;
-                if (i < n) {
-                    const double s = sins[task], c = coss[task];
-                    const double* rp = rvs + ps * n16;
-                    double own = 0.0;
-                    if (a.fp.ab32) {
-                        const float* Ai = a.fp.A32 + i;
-                        const float* Bi = a.fp.B32 + i;
-#pragma unroll 4
-                        for (int m = 0; m < n; ++m)
-                            own += rp[m] * ((double)Ai[(size_t)m * n] * s + (double)Bi[(size_t)m * n] * c);
-                    } else {
-                        const double* Ai = a.fp.A + i;
-                        const double* Bi = a.fp.B + i;
-#pragma unroll 4
-                        for (int m = 0; m < n; ++m) own += rp[m] * (Ai[(size_t)m * n] * s + Bi[(size_t)m * n] * c);
-                    }
-                    ownr[k] = kHess ? own : own * vs[task];
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kMaxTasks; ++k) {
-            const int task = threadIdx.x + k * kFpDppThreads;
-            if (task < ppw * n16) sacc[task] = ownr[k];
-        }
-    }
     if (kGrad && a.fval && ibr0 == 0 && (int)threadIdx.x < ppw) {
         const int64_t p = p0 + threadIdx.x;
         if (p < a.npts) {
@@ -324,6 +284,60 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
             double f = rp[0] * rp[0];
             for (int m = 1; m < n; ++m) f += rp[m] * rp[m];
             a.fval[p] = f;
+        }
+    }
+    {
+        // the own parts own_i = sum_m r_m.v D_mi, D_mi = A_mi sin x_i +
+        // B_mi cos x_i, of the rows of this workgroup's rounds (float64, m in
+        // order; kGrad: also the gradient 2 sum_m r_m.v J_mi, stored here),
+        // held in registers until every thread has read r.v; their space then
+        // keeps own_i (kSym H.v: starts the running results at own_i v_i)
+        constexpr int kMaxTasks = 8;   // ppw 16 nb <= 2048 (the LDS limit)
+        const int r0 = 16 * ibr0 * rb, r1 = 16 * ibr1 * rb < n16 ? 16 * ibr1 * rb : n16;
+        const int nr = r1 - r0;
+        double ownr[kMaxTasks];
+#pragma unroll
+        for (int k = 0; k < kMaxTasks; ++k) {
+            const int task = threadIdx.x + k * kFpDppThreads;
+            ownr[k] = 0.0;
+            if (task < ppw * nr) {
+                const int ps = task / nr, i = r0 + task - ps * nr;
+                if (i < n) {
+                    const double s = sins[ps * n16 + i], c = coss[ps * n16 + i];
+                    const double* rp = rvs + ps * n16;
+                    double own = 0.0, gr = 0.0;
+                    if (a.fp.ab32) {
+                        const float* Ai = a.fp.A32 + i;
+                        const float* Bi = a.fp.B32 + i;
+#pragma unroll 4
+                        for (int m = 0; m < n; ++m) {
+                            const double am = (double)Ai[(size_t)m * n], bm = (double)Bi[(size_t)m * n];
+                            own += rp[m] * (am * s + bm * c);
+                            if (kGrad) gr += rp[m] * (bm * s - am * c);
+                        }
+                    } else {
+                        const double* Ai = a.fp.A + i;
+                        const double* Bi = a.fp.B + i;
+#pragma unroll 4
+                        for (int m = 0; m < n; ++m) {
+                            const double am = Ai[(size_t)m * n], bm = Bi[(size_t)m * n];
+                            own += rp[m] * (am * s + bm * c);
+                            if (kGrad) gr += rp[m] * (bm * s - am * c);
+                        }
+                    }
+                    ownr[k] = kSym && !kHess ? own * vs[ps * n16 + i] : own;
+                    if (kGrad && p0 + ps < a.npts) a.grad[(p0 + ps) * n + i] = gr + gr;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxTasks; ++k) {
+            const int task = threadIdx.x + k * kFpDppThreads;
+            if (task < ppw * nr) {
+                const int ps = task / nr;
+                sacc[ps * n16 + r0 + task - ps * nr] = ownr[k];
+            }
         }
     }
 
@@ -335,7 +349,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
     const int ibs = lr_on ? (d - ps * per_pt) / kbg : 0;
     const int kbs = lr_on ? d - ps * per_pt - ibs * kbg : 0;
     const int64_t p = p0 + ps;
-    const double* rp = rvs + ps * n16;
     const double* vp = vs + (kHess ? 0 : ps * n16);
     const T* Ab = fp_a_base<T>(a.fp);
     const T* Bb = fp_b_base<T>(a.fp);
@@ -352,10 +365,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
         for (int kgr = kSym ? (ibr * rb) / kbg : 0; kgr < kgr_n; ++kgr) {
             const int kb = kgr * kbg + kbs;
             const bool pair_on = lr_on && ib < nb && kb < nb && (!kSym || kb >= ib);
-            // the lane row of the row's diagonal pair also forms the row's own
-            // part sum_m r_m.v D_mi (and the gradient's sum_m r_m.v J_mi),
-            // float64, from the tiles
-            const bool diag = pair_on && kb == ib;
             // a float64 round whose row blocks all lie in its column group
             // forms no row slots: a row's entries are its column slot's (the
             // float bodies keep their own row slots, which holds the batched
@@ -364,7 +373,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                                ibr * rb + rb <= kgr * kbg + kbg;
             const int nform = alias ? kbg : nslots;
             const T* jr = alias ? jt + ((size_t)(ps * nslots + ibr * rb + ibs - kgr * kbg) * MT) * 16 + t : ji;
-            double own = 0.0, gd = 0.0;
 #pragma unroll
             for (int jc = 0; jc < 16 / C; ++jc) sums[jc].reset();
             for (int mt = 0; mt < tiles; ++mt) {
@@ -377,11 +385,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     const int m = mt * MT + u;
                     const bool m_on = m < n;
                     const uint32_t mrow = (uint32_t)((m_on ? m : 0) * n);
-                    // D_mi = A_mi sin x_i + B_mi cos x_i (float64) of the row
-                    // blocks whose diagonal pair is in this round: in float64
-                    // from the loads of their column slots; in the mixed
-                    // policy (float32 loads) from a loop of its own below
-                    constexpr bool fuse_d = !kSym && std::is_same<T, double>::value;
                     // eight (or four) block slots at a time, their A and B
                     // loads (from clamped, in-range offsets) all in flight
                     // together and shared by the points; sin and cos are zero
@@ -389,7 +392,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                     auto form = [&](int b0, auto rc) {
                         constexpr int R = decltype(rc)::value;
                         T bv[R], av[R];
-                        int col[R], dslot[R];
+                        int col[R];
                         bool on[R];
                         uint32_t o[R];
 #pragma unroll
@@ -399,8 +402,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                             on[r] = m_on && blk < nb;
                             col[r] = on[r] ? 16 * blk + tt : 0;
                             o[r] = mrow + (uint32_t)(col[r] < n ? col[r] : n - 1);
-                            const int ds = blk - ibr * rb;
-                            dslot[r] = bs < kbg && b0 + r < nform && blk < nb && ds >= 0 && ds < rb ? ds : -1;
                         }
                         fp_ab_loads<T, R>(a.fp, Ab, Bb, o, av, bv);
                         for (int qs = 0; qs < ppw; ++qs) {
@@ -409,10 +410,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                                 const int sc = qs * n16 + col[r];
                                 const T jv = bv[r] * (T)sins[sc] - av[r] * (T)coss[sc];
                                 if (b0 + r < nform) jt[(qs * nslots + b0 + r) * (MT * 16) + threadIdx.x] = on[r] ? jv : T(0);
-                                if (fuse_d && dslot[r] >= 0) {   // T = double: av, bv are float64-exact
-                                    const double dv = (double)av[r] * sins[sc] + (double)bv[r] * coss[sc];
-                                    dt[(qs * rb + dslot[r]) * (MT * 16) + threadIdx.x] = m_on ? dv : 0.0;
-                                }
                             }
                         }
                     };
@@ -427,27 +424,8 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                             b0 += 4;
                         }
                     }
-                    for (int q = 0; q < (kSym || fuse_d ? 0 : ppw * rb); ++q) {
-                        const int qs = q / rb, blk = ibr * rb + (q - qs * rb);
-                        if (blk >= nb || blk < kgr * kbg || blk >= kgr * kbg + kbg) continue;
-                        const int col = 16 * blk + tt;
-                        const uint32_t o = mrow + (uint32_t)(col < n ? col : n - 1);
-                        const double ad = a.fp.ab32 ? (double)ld_at(a.fp.A32, o) : ld_at(a.fp.A, o);
-                        const double bd = a.fp.ab32 ? (double)ld_at(a.fp.B32, o) : ld_at(a.fp.B, o);
-                        const double dv = ad * sins[qs * n16 + col] + bd * coss[qs * n16 + col];
-                        dt[q * (MT * 16) + threadIdx.x] = m_on ? dv : 0.0;
-                    }
                 }
                 __syncthreads();
-                if (!kSym && diag) {
-                    const double* dp = dt + (size_t)((ps * rb + ibs) * MT) * 16 + t;
-#pragma unroll 4
-                    for (int u = 0; u < MT; ++u) {
-                        const double rv = rp[mt * MT + u];   // zero past n
-                        own += rv * dp[u * 16];
-                        if (kGrad) gd += rv * (double)jr[u * 16];
-                    }
-                }
                 if (pair_on) {
 #pragma unroll
                     for (int ug = 0; ug < MT / 4; ++ug) {
@@ -465,10 +443,6 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
 #pragma unroll
                     for (int jc = 0; jc < 16 / C; ++jc) sums[jc].close_block();
                 }
-            }
-            if (!kSym && diag) {
-                owns[(ps * rb + ibs) * 16 + t] = own;
-                if (kGrad && row_live) a.grad[p * n + i] = gd + gd;
             }
             // the calls of the pair (kSym: calls jc >= tc counted, jc > tc mirrored)
             double prt = 0.0;
@@ -496,7 +470,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         }
                         // CHUNK-HESS: H[p][i][cs + l] = 2 (products + [cs + l = i] own)
                         if (kb == ib) {
-                            const double own = kSym ? sacc[ps * n16 + i] : owns[(ps * rb + ibs) * 16 + t];
+                            const double own = sacc[ps * n16 + i];
 #pragma unroll
                             for (int l = 0; l < C; ++l)
                                 if (cs + l == i) h[l] += own;
@@ -575,7 +549,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
         if constexpr (!kHess && !kSym) {
             __syncthreads();
             if (row_live && kbs == 0) {
-                const double own = owns[(ps * rb + ibs) * 16 + t];
+                const double own = sacc[ps * n16 + i];
                 const double row = rowsum[(ps * rb + ibs) * 16 + t] + own * vp[i];
                 st_io(a.out, p * n + i, row + row, a.io32);
             }
