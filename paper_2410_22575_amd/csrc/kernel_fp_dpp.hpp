@@ -365,12 +365,9 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
         for (int kgr = kSym ? (ibr * rb) / kbg : 0; kgr < kgr_n; ++kgr) {
             const int kb = kgr * kbg + kbs;
             const bool pair_on = lr_on && ib < nb && kb < nb && (!kSym || kb >= ib);
-            // a float64 round whose row blocks all lie in its column group
-            // forms no row slots: a row's entries are its column slot's (the
-            // float bodies keep their own row slots, which holds the batched
-            // kernel's mixed body to three waves per SIMD)
-            const bool alias = std::is_same<T, double>::value && ibr * rb >= kgr * kbg &&
-                               ibr * rb + rb <= kgr * kbg + kbg;
+            // a round whose row blocks all lie in its column group forms no
+            // row slots: a row's entries are its column slot's
+            const bool alias = ibr * rb >= kgr * kbg && ibr * rb + rb <= kgr * kbg + kbg;
             const int nform = alias ? kbg : nslots;
             const T* jr = alias ? jt + ((size_t)(ps * nslots + ibr * rb + ibs - kgr * kbg) * MT) * 16 + t : ji;
 #pragma unroll
@@ -414,9 +411,7 @@ __device__ __forceinline__ void fp_dpp_block(const FpDppArgs& a, int64_t pg, int
                         }
                     };
                     for (int b0 = 0; b0 < nform;) {
-                        // (the mixed policy keeps one group size: a second
-                        // instantiation costs it registers in the batch kernel)
-                        if (!std::is_same<T, double>::value || nform - b0 > 4) {
+                        if (nform - b0 > 4) {
                             form(b0, std::integral_constant<int, 8>{});
                             b0 += 8;
                         } else {
