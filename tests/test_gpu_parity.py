@@ -276,6 +276,30 @@ def test_coarse_mappings_match_l2(gpu_lib, func):
         gpu_lib.chessfad_set_option(gpu_lib.CHESSFAD_OPT_MAPPING, prev_map)
 
 
+@pytest.mark.parametrize("func,n", [(A, 16), (A, 5), (FP, 16)])
+def test_large_arguments(gpu_lib, func, n):
+    """Arguments whose sin/cos leave the kernels' fast range (|2 pi x| or |x|
+    beyond 65536, where the library routine takes over): Ackley with
+    |x| in [2e4, 3e4] (the register-resident n = 16 path and the LDS path),
+    Fletcher-Powell with x shifted by 1e5 (alpha shifted with it)."""
+    npts = 64
+    rng = inputs.rng_for(9100 + 10 * func + n)
+    w = inputs.make_workload(func, n, npts, rng)
+    if func == A:
+        x = rng.uniform(2e4, 3e4, size=(npts, n)) * rng.choice([-1.0, 1.0], size=(npts, n))
+        w = inputs.Workload(func, n, np.ascontiguousarray(x), w.v)
+    else:
+        w = inputs.Workload(func, n, np.ascontiguousarray(w.x + 1e5), w.v, w.A, w.B, w.alpha + 1e5)
+    E = _setup(gpu_lib, w)
+    x, v = _dev(w.x), _dev(w.v)
+    r_ref = cf.hvp(func, w.x, w.v, w.A, w.B, E)
+    _, hmax = _hmax(func, w, E)
+    for c in (1, 16) if n == 16 else (1, 4):
+        print(f"[case] large arguments func={func} n={n} C={c}", flush=True)
+        r = gpu_lib.chessfad_hvp(func, x, v, chunk=c).cpu().numpy()
+        assert np.max(_hvp_err(r, r_ref, hmax, w.v)) <= TOL64, (func, n, c)
+
+
 @pytest.mark.parametrize("func", [R, A])
 @pytest.mark.parametrize("npts", [1, 15, 17, 300])
 def test_row16_register_path(gpu_lib, func, npts):
