@@ -151,6 +151,8 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
         return f"sym_kernel<{prec}, {func}, {c}, false>" + at
     if n == 16 and (c >= n or mapping == 1):
         return f"row16_kernel<{prec}, {func}, {c}>"
+    if f == 0 and (c >= n or mapping == 1):
+        return f"rosenbrock_rows_kernel<{prec}, {c}>" + at
     if c >= n or mapping == 1:
         return f"coarse_kernel<{prec}, {func}, {c}, 1>" + at
     return f"plain_kernel<{prec}, {func}, {c}, false, false>" + at

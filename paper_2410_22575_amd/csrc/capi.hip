@@ -537,6 +537,15 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
             hipError_t e = launch(Row16Args{x, v, out, npts}, dim3((unsigned)grid), s);
             return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
         }
+        if (level == 1 && func_id == CHESSFAD_ROSENBROCK) {
+            // Rosenbrock at other n: each lane loads its row's neighbours
+            RowsLaunch launch = mixed ? rosenbrock_rows_mixed(chunk) : rosenbrock_rows(chunk);
+            if (!launch) return CHESSFAD_E_CHUNK;
+            const int64_t grid = (npts * n + kRow16Threads - 1) / kRow16Threads;
+            if (grid > 0x7fffffffLL) return CHESSFAD_E_ARG;
+            hipError_t e = launch(Row16Args{x, v, out, npts}, n, dim3((unsigned)grid), s);
+            return e == hipSuccess ? CHESSFAD_OK : hip_fail(e);
+        }
         size_t lds = 0;
         const Geometry g = coarse_geometry(func_id, n, npts, chunk, level, mixed, lds);
         if (g.grid > 0x7fffffffLL) return CHESSFAD_E_ARG;

@@ -85,6 +85,27 @@ Row16Launch row16_ackley(int C);
 Row16Launch row16_mixed_rosenbrock(int C);
 Row16Launch row16_mixed_ackley(int C);
 
+// Rosenbrock H.v at any n on neighbour loads (L1 mapping)
+using RowsLaunch = hipError_t (*)(const Row16Args&, int n, dim3 grid, hipStream_t);
+template <class P, int C>
+hipError_t launch_rosenbrock_rows(const Row16Args& a, int n, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((rosenbrock_rows_kernel<P, C>), grid, dim3(kRow16Threads), 0, s, a, n);
+    return hipGetLastError();
+}
+template <class P>
+RowsLaunch rosenbrock_rows_entry(int C) {
+    switch (C) {
+        case 1: return &launch_rosenbrock_rows<P, 1>;
+        case 2: return &launch_rosenbrock_rows<P, 2>;
+        case 4: return &launch_rosenbrock_rows<P, 4>;
+        case 8: return &launch_rosenbrock_rows<P, 8>;
+        case 16: return &launch_rosenbrock_rows<P, 16>;
+        default: return nullptr;
+    }
+}
+RowsLaunch rosenbrock_rows(int C);
+RowsLaunch rosenbrock_rows_mixed(int C);
+
 // float64 H.v that also stores the gradient and f, one per function.
 PlainLaunch grad_rosenbrock(int C);
 PlainLaunch grad_ackley(int C);

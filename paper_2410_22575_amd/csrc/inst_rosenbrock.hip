@@ -16,4 +16,6 @@ CoarseLaunch coarse_rosenbrock(int C, int level) {
 
 Row16Launch row16_rosenbrock(int C) { return row16_entry<F64, Rosenbrock>(C); }
 
+RowsLaunch rosenbrock_rows(int C) { return rosenbrock_rows_entry<F64>(C); }
+
 }  // namespace chessfad

@@ -14,4 +14,6 @@ CoarseLaunch coarse_mixed_rosenbrock(int C, int level) {
 
 Row16Launch row16_mixed_rosenbrock(int C) { return row16_entry<F32C, Rosenbrock>(C); }
 
+RowsLaunch rosenbrock_rows_mixed(int C) { return rosenbrock_rows_entry<F32C>(C); }
+
 }  // namespace chessfad

@@ -120,6 +120,38 @@ __device__ __forceinline__ double row16_ackley(double xd, double vd, int i) {
     return res;
 }
 
+// Rosenbrock's H.v for any n in the same L1 mapping (one lane per (point,
+// row i), consecutive lanes consecutive rows): a call (i, cs) needs x and v of
+// rows i - 1, i, i + 1 only, so each lane loads those three itself (the
+// neighbours' loads hit the lines its neighbour lanes fetch; HBM bytes stay
+// those of x, v and the result) - no LDS staging, no barrier.  The index is
+// clamped at the point's ends as in the LDS kernels (those terms carry a zero
+// row seed).  Every chunk's call is evaluated, in order, by the same
+// row_terms code.
+template <class P, int C>
+__global__ __launch_bounds__(kRow16Threads) void rosenbrock_rows_kernel(Row16Args a, int n) {
+    using T = typename P::T;
+    const int64_t q = (int64_t)blockIdx.x * kRow16Threads + threadIdx.x;
+    if (q >= a.npts * n) return;
+    const int i = (int)(q % n);
+    const int64_t qm = i > 0 ? q - 1 : q, qp = i + 1 < n ? q + 1 : q;
+    const T xm = (T)a.x[qm], xi = (T)a.x[q], xp = (T)a.x[qp];
+    const T vm = (T)a.v[qm], vi = (T)a.v[q], vp = (T)a.v[qp];
+    const int nc = (n + C - 1) / C;
+    double res = 0.0;
+    for (int j = 0; j < nc; ++j) {
+        HD<T, 2> tm, tp;
+        Rosenbrock::row_terms_at<T, C>(i, n, j * C, xm, xi, xp, tm, tp);
+        typename P::Dot acc;
+        acc.add(tm.h[0], vm);
+        acc.add(tm.h[1], vi);
+        acc.add(tp.h[0], vi);
+        acc.add(tp.h[1], vp);
+        res += acc.get();
+    }
+    a.out[q] = res;
+}
+
 template <class P, class F, int C>
 __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     const int64_t q = (int64_t)blockIdx.x * kRow16Threads + threadIdx.x;
