@@ -29,19 +29,6 @@ constexpr double inv_fact(int k) {
     return 1.0 / f;
 }
 
-// The series coefficients: sin's inner coefficients 1/17! .. -1/3!
-// (alternating, Horner from the highest), then cos's 1/16! .. -1/2!.  The
-// kernels read them from constant memory with scalar loads into scalar
-// registers (an immediate float64 operand would take two vector moves at
-// every use).
-constexpr double kTrigCoefs[16] = {
-    inv_fact(17), -inv_fact(15), inv_fact(13), -inv_fact(11), inv_fact(9), -inv_fact(7), inv_fact(5), -inv_fact(3),
-    inv_fact(16), -inv_fact(14), inv_fact(12), -inv_fact(10), inv_fact(8), -inv_fact(6), inv_fact(4), -0.5};
-static __constant__ double kTrigCoefDev[16] = {
-    kTrigCoefs[0], kTrigCoefs[1], kTrigCoefs[2],  kTrigCoefs[3],  kTrigCoefs[4],  kTrigCoefs[5],
-    kTrigCoefs[6], kTrigCoefs[7], kTrigCoefs[8],  kTrigCoefs[9],  kTrigCoefs[10], kTrigCoefs[11],
-    kTrigCoefs[12], kTrigCoefs[13], kTrigCoefs[14], kTrigCoefs[15]};
-
 // the library's routine, out of line: its reduction for large arguments
 // needs registers that the fast path does not
 inline __host__ __device__ __attribute__((noinline)) double2 cf_sincos_large(double x) {
@@ -50,8 +37,7 @@ inline __host__ __device__ __attribute__((noinline)) double2 cf_sincos_large(dou
     return make_double2(s, c);
 }
 
-// cf: kTrigCoefs (or its constant-memory copy)
-__host__ __device__ __forceinline__ void cf_sincos_with(double x, double* s, double* c, const double* cf) {
+__host__ __device__ __forceinline__ void cf_sincos(double x, double* s, double* c) {
     if (!(fabs(x) <= kFastTrigMax)) {
         const double2 sc = cf_sincos_large(x);
         *s = sc.x;
@@ -63,12 +49,22 @@ __host__ __device__ __forceinline__ void cf_sincos_with(double x, double* s, dou
     r = fma(-k, kHalfPi2, r);
     const double z = r * r;
     // sin r = r + r z (-1/3! + z (1/5! - ...)), cos r = 1 + z (-1/2! + z (1/4! - ...))
-    double ps = cf[0], pc = cf[8];
-#pragma unroll
-    for (int j = 1; j < 8; ++j) {
-        ps = fma(ps, z, cf[j]);
-        pc = fma(pc, z, cf[8 + j]);
-    }
+    double ps = inv_fact(17);
+    ps = fma(ps, z, -inv_fact(15));
+    ps = fma(ps, z, inv_fact(13));
+    ps = fma(ps, z, -inv_fact(11));
+    ps = fma(ps, z, inv_fact(9));
+    ps = fma(ps, z, -inv_fact(7));
+    ps = fma(ps, z, inv_fact(5));
+    ps = fma(ps, z, -inv_fact(3));
+    double pc = inv_fact(16);
+    pc = fma(pc, z, -inv_fact(14));
+    pc = fma(pc, z, inv_fact(12));
+    pc = fma(pc, z, -inv_fact(10));
+    pc = fma(pc, z, inv_fact(8));
+    pc = fma(pc, z, -inv_fact(6));
+    pc = fma(pc, z, inv_fact(4));
+    pc = fma(pc, z, -0.5);
     const double sr = fma(r * z, ps, r);
     const double cr = fma(z, pc, 1.0);
     const int q = (int)k;
@@ -77,7 +73,5 @@ __host__ __device__ __forceinline__ void cf_sincos_with(double x, double* s, dou
     *s = (q & 2) ? -s1 : s1;
     *c = (q & 2) ? -c1 : c1;
 }
-
-__device__ __forceinline__ void cf_sincos(double x, double* s, double* c) { cf_sincos_with(x, s, c, kTrigCoefDev); }
 
 }  // namespace chessfad

@@ -1,5 +1,4 @@
-// Host build of the kernels' sin/cos routine (cf_sincos_with, with the
-// coefficient list the kernels copy to constant memory): reads float64
+// Host build of the kernels' sin/cos routine (cf_sincos): reads float64
 // arguments (one per line, as C99 hex floats) and prints sin x and cos x in
 // the same form.
 #include <cstdio>
@@ -12,7 +11,7 @@ int main() {
     while (std::fgets(buf, sizeof buf, stdin)) {
         const double x = std::strtod(buf, nullptr);
         double s, c;
-        chessfad::cf_sincos_with(x, &s, &c, chessfad::kTrigCoefs);
+        chessfad::cf_sincos(x, &s, &c);
         std::printf("%a %a\n", s, c);
     }
     return 0;
