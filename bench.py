@@ -595,8 +595,9 @@ def cfg1_cpu_seconds():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(points shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs one GPU "
+              f"per process (points would shard across GPUs with no communication during compute)",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
