@@ -105,6 +105,10 @@ int chessfad_hvp_grad(int func_id, int n, int64_t npts, const double* x, const d
  *   H [npts][n][n]  H[p][i][j] = d2f/dx_i dx_j at x[p]; every entry is
  *                   computed by its own row's call (no symmetry is used),
  *                   so the output is symmetric only up to rounding.
+ * chunk = 0: the largest compiled chunk <= n (at most 16), whatever the H.v
+ * autotuner recorded: Hessians are bound by their stores, and a wide call
+ * writes whole 16-byte pairs of its row (at n = 16 over 2^19 points: 0.41
+ * against 0.82 ms at chunk 1 for Fletcher-Powell).
  */
 int chessfad_hessian(int func_id, int n, int64_t npts, const double* x, double* H,
                      int chunk, void* stream);

@@ -418,7 +418,15 @@ int chessfad::run_single(int func_id, int n, int64_t npts, const double* x, cons
     int rc = check_func_n(func_id, n);
     if (rc) return rc;
     const bool auto_chunk = chunk == 0;
-    if (auto_chunk) chunk = resolve_chunk(func_id, n, mixed ? 1 : 0, 16, sym);
+    if (auto_chunk && hess && !sym) {
+        // full Hessians are store-bound: the widest call stores whole 16-byte
+        // pairs of its row (the H.v tuning does not apply)
+        chunk = 1;
+        for (int k = 0; k < kNumChunks; ++k)
+            if (kChunks[k] <= n) chunk = kChunks[k];
+    } else if (auto_chunk) {
+        chunk = resolve_chunk(func_id, n, mixed ? 1 : 0, 16, sym);
+    }
     if (chunk < 0 || !chunk_compiled(chunk) || chunk > n) return CHESSFAD_E_CHUNK;
     if (npts < 0) return CHESSFAD_E_ARG;
     if (npts == 0) return CHESSFAD_OK;
