@@ -101,6 +101,7 @@ KERNEL_SOURCES = {
     "coarse_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_plain.hpp"),
     "plain_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_plain.hpp"),
     "row16_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_row16.hpp"),
+    "row16_ackley_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_row16.hpp"),
     "fp_call_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp"),
     "fp_dpp_kernel": ("hd.hpp", "trig.hpp", "functions.hpp", "kernel_fp_mfma.hpp", "kernel_fp_call.hpp",
                       "kernel_fp_dpp.hpp"),
@@ -150,7 +151,7 @@ def kernel_key(f, c, n=N, mapping=2, mixed=False, sym=False):
     if sym:
         return f"sym_kernel<{prec}, {func}, {c}, false>" + at
     if n == 16 and (c >= n or mapping == 1):
-        return f"row16_kernel<{prec}, {func}, {c}>"
+        return f"row16_ackley_kernel<{prec}, {c}>" if f == 1 else f"row16_kernel<{prec}, {func}, {c}>"
     if f == 0 and (c >= n or mapping == 1):
         return f"rosenbrock_rows_kernel<{prec}, {c}>" + at
     if c >= n or mapping == 1:

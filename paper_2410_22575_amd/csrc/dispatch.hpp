@@ -65,7 +65,13 @@ using Row16Launch = hipError_t (*)(const Row16Args&, dim3 grid, hipStream_t);
 
 template <class P, class F, int C>
 hipError_t launch_row16(const Row16Args& a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((row16_kernel<P, F, C>), grid, dim3(kRow16Threads), 0, s, a);
+    if constexpr (std::is_same<F, Ackley>::value) {
+        // kAckleyRow16Points points per workgroup
+        const dim3 g((unsigned)((a.npts + kAckleyRow16Points - 1) / kAckleyRow16Points));
+        hipLaunchKernelGGL((row16_ackley_kernel<P, C>), g, dim3(kRow16Threads), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((row16_kernel<P, F, C>), grid, dim3(kRow16Threads), 0, s, a);
+    }
     return hipGetLastError();
 }
 

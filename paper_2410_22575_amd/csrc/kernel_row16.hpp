@@ -13,7 +13,10 @@
 //     inside the FMAs, and the point's two sums over its coordinates are
 //     butterflies over the row (row rotations by 8, 4, 2, 1, whose adds give
 //     every lane the same value: each step adds a pair in both of its lanes).
-// Nothing is staged in LDS and no lane waits at a barrier.  The calls'
+// Ackley's kernel runs a wave's 16 points in four such passes and forms each
+// point's island in four lanes instead of all sixteen of its row (see
+// row16_ackley_kernel).  Nothing is staged in LDS and no lane waits at a
+// barrier.  The calls'
 // arithmetic is that of the functions' hvp (Rosenbrock: the same row_terms;
 // Ackley: the slots' second-order components h_k = F'' S.d S.g_k +
 // G'' C.d C.g_k with S.g_k = 2 x_k, C.g_k = -2 pi sin(2 pi x_k), then
@@ -94,20 +97,19 @@ __device__ __forceinline__ double row16_rosenbrock(double xd, double vd, int i) 
     return res;
 }
 
+// the calls of row i of one point from its coordinate's x, v and table values
+// and the point's island (F', F'', G', G'' of its two sums: isl[1], isl[2],
+// isl[4], isl[5] of Ackley::outer)
 template <class P, int C>
-__device__ __forceinline__ double row16_ackley(double xd, double vd, int i) {
+__device__ __forceinline__ double row16_ackley_calls(double xd, double vd, double t0d, double t1d, double f1d,
+                                                     double f2, double g1d, double g2, int i) {
     using T = typename P::T;
-    double t0d, t1d;
-    Ackley::tables(xd, t0d, t1d);
-    // the islands in float64 from the float64 inputs
-    double isl[6];
-    Ackley::outer(16, row16_sum(xd * xd), row16_sum(t0d), isl, 1);
     const T xi = (T)xd, t0 = (T)t0d, t1 = (T)t1d, vi = (T)vd;
-    const T f1 = (T)isl[1], g1 = (T)isl[4];
+    const T f1 = (T)f1d, g1 = (T)g1d;
     // the row seed's first-order parts S.d = 2 x_i, C.d = t1_i through F'' and
     // G'' (formed in float64, then rounded); the own term's second-order parts
     // S.h = 2, C.h = -4 pi^2 t0_i
-    const T f2d = (T)(isl[2] * (double)(T(2) * xi)), g2d = (T)(isl[5] * (double)t1);
+    const T f2d = (T)(f2 * (double)(T(2) * xi)), g2d = (T)(g2 * (double)t1);
     const T own = f1 * T(2) + g1 * (T(-kTwoPi * kTwoPi) * t0);
     double res = 0.0;
     static_for<16 / C>([&](auto jc) {
@@ -118,6 +120,50 @@ __device__ __forceinline__ double row16_ackley(double xd, double vd, int i) {
         res += dot;
     });
     return res;
+}
+
+// Ackley: a wave takes 16 points in four passes of four (one point per 16-lane
+// row).  The first sweep loads each pass's x and v, forms the table values and
+// the point's two sums (row butterflies), and lane (lg, i) keeps the sums of
+// point 4 (i / 4) + lg of its row; after it every lane forms the island of one
+// point, four lanes per point rather than all sixteen of its row.  The second
+// sweep takes each pass's island from lane 4 s of the row and runs the calls.
+// The arithmetic is the same as with the island formed in every lane.
+constexpr int kAckleyRow16Passes = 4;
+constexpr int kAckleyRow16Points = (kRow16Threads / 64) * 4 * kAckleyRow16Passes;   // per workgroup
+
+template <class P, int C>
+__global__ __launch_bounds__(kRow16Threads) void row16_ackley_kernel(Row16Args a) {
+    constexpr int kPasses = kAckleyRow16Passes;
+    const int lane = threadIdx.x & 63, i = lane & 15, lg = lane >> 4;
+    const int64_t pw = ((int64_t)blockIdx.x * (kRow16Threads / 64) + (threadIdx.x >> 6)) * (4 * kPasses);
+    double xs[kPasses], vs[kPasses], t0s[kPasses], t1s[kPasses];
+    double ss = 0.0, cs = 0.0;
+#pragma unroll
+    for (int s = 0; s < kPasses; ++s) {
+        const int64_t q = (pw + 4 * s + lg) * 16 + i;
+        // whole points only: a lane past the end belongs to a point past the end
+        const bool live = q < a.npts * 16;
+        xs[s] = live ? __builtin_nontemporal_load(a.x + q) : 0.5;
+        vs[s] = live ? __builtin_nontemporal_load(a.v + q) : 0.0;
+        Ackley::tables(xs[s], t0s[s], t1s[s]);
+        const double sx = row16_sum(xs[s] * xs[s]), sc = row16_sum(t0s[s]);
+        if ((i >> 2) == s) {
+            ss = sx;
+            cs = sc;
+        }
+    }
+    // the islands in float64 from the float64 inputs
+    double isl[6];
+    Ackley::outer(16, ss, cs, isl, 1);
+#pragma unroll
+    for (int s = 0; s < kPasses; ++s) {
+        const double f1 = __shfl(isl[1], 4 * s, 16), f2 = __shfl(isl[2], 4 * s, 16);
+        const double g1 = __shfl(isl[4], 4 * s, 16), g2 = __shfl(isl[5], 4 * s, 16);
+        const double r = row16_ackley_calls<P, C>(xs[s], vs[s], t0s[s], t1s[s], f1, f2, g1, g2, i);
+        const int64_t q = (pw + 4 * s + lg) * 16 + i;
+        if (q < a.npts * 16) __builtin_nontemporal_store(r, a.out + q);
+    }
 }
 
 // Rosenbrock's H.v for any n in the same L1 mapping (one lane per (point,
@@ -152,6 +198,7 @@ __global__ __launch_bounds__(kRow16Threads) void rosenbrock_rows_kernel(Row16Arg
     a.out[q] = res;
 }
 
+// Rosenbrock (one point per 16-lane row)
 template <class P, class F, int C>
 __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     const int64_t q = (int64_t)blockIdx.x * kRow16Threads + threadIdx.x;
@@ -161,11 +208,7 @@ __global__ __launch_bounds__(kRow16Threads) void row16_kernel(Row16Args a) {
     // every element is read and written once: streaming (non-temporal) accesses
     const double xi = live ? __builtin_nontemporal_load(a.x + q) : 0.5;
     const double vi = live ? __builtin_nontemporal_load(a.v + q) : 0.0;
-    double r;
-    if constexpr (std::is_same<F, Ackley>::value)
-        r = row16_ackley<P, C>(xi, vi, i);
-    else
-        r = row16_rosenbrock<P, C>(xi, vi, i);
+    const double r = row16_rosenbrock<P, C>(xi, vi, i);
     if (live) __builtin_nontemporal_store(r, a.out + q);
 }
 
