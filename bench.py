@@ -71,6 +71,10 @@ COUNTERS = {
     'fp_call_kernel<F64, 8, 2, false, false, 16>': {'traffic': 402816064, 'valu_flops': 11995709440, 'valu_insts': 122552320, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 524288, 'valu_mul_f64': 9175040, 'valu_fma_f64': 88866816, 'valu_int32': 2686976, 'valu_int64': 1441792, 'valu_cvt': 262144, 'valu_trans_f64': 0, 'lds': 2555904, 'salu': 8781824}, 'sha': '45479999bf7d7b68'},
     'fp_call_kernel<F64, 8, 4, false, false, 16>': {'traffic': 402813696, 'valu_flops': 11995709440, 'valu_insts': 122552320, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 524288, 'valu_mul_f64': 9175040, 'valu_fma_f64': 88866816, 'valu_int32': 2686976, 'valu_int64': 1441792, 'valu_cvt': 262144, 'valu_trans_f64': 0, 'lds': 2555904, 'salu': 8781824}, 'sha': '45479999bf7d7b68'},
     'fp_call_kernel<F64, 8, 8, false, false, 16>': {'traffic': 402819136, 'valu_flops': 11995709440, 'valu_insts': 122552320, 'mfma_flops': 1073741824, 'classes': {'valu_add_f64': 524288, 'valu_mul_f64': 9175040, 'valu_fma_f64': 88866816, 'valu_int32': 2686976, 'valu_int64': 1441792, 'valu_cvt': 262144, 'valu_trans_f64': 0, 'lds': 2555904, 'salu': 8781824}, 'sha': '45479999bf7d7b68'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 38173888, 'valu_flops': 291201089536, 'valu_insts': 3469672448, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 75595776, 'valu_fma_f64': 2231746560, 'valu_int32': 520953856, 'valu_int64': 27066368, 'valu_cvt': 151175168, 'valu_trans_f64': 0, 'lds': 338042880, 'salu': 943480832}, 'sha': '2e3a289a8c793dc7'},
+    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403298432, 'valu_flops': 155239579648, 'valu_insts': 2216165376, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 51904512, 'valu_fma_f64': 1164181504, 'valu_int32': 412876800, 'valu_int64': 123731968, 'valu_cvt': 117178368, 'valu_trans_f64': 0, 'lds': 192413696, 'salu': 677642240}, 'sha': '2e3a289a8c793dc7'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29803520, 'valu_flops': 164213817344, 'valu_insts': 1957695488, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 44359680, 'valu_fma_f64': 1256628224, 'valu_int32': 282664960, 'valu_int64': 21958656, 'valu_cvt': 84000768, 'valu_trans_f64': 0, 'lds': 191954944, 'salu': 523919360}, 'sha': '2e3a289a8c793dc7'},
+    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403293184, 'valu_flops': 124772155392, 'valu_insts': 2056388608, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 81526784, 'valu_fma_f64': 907280384, 'valu_int32': 452460544, 'valu_int64': 116391936, 'valu_cvt': 98304000, 'valu_trans_f64': 0, 'lds': 246677504, 'salu': 493944832}, 'sha': '2e3a289a8c793dc7'},
     'plain_kernel<F64, Ackley, 1, false, false>': {'traffic': 402784256, 'valu_flops': 18723373056, 'valu_insts': 763363328, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45088768, 'valu_mul_f64': 53477376, 'valu_fma_f64': 95420416, 'valu_int32': 277872640, 'valu_int64': 20971520, 'valu_cvt': 39845888, 'valu_trans_f64': 3145728, 'lds': 91226112, 'salu': 618659840}, 'sha': 'c9b5758bb627f982'},
     'plain_kernel<F64, Ackley, 2, false, false>': {'traffic': 402777088, 'valu_flops': 9898557440, 'valu_insts': 385351680, 'mfma_flops': 0, 'classes': {'valu_add_f64': 20447232, 'valu_mul_f64': 28835840, 'valu_fma_f64': 51904512, 'valu_int32': 134217728, 'valu_int64': 12582912, 'valu_cvt': 19922944, 'valu_trans_f64': 1572864, 'lds': 41418752, 'salu': 311427072}, 'sha': 'c9b5758bb627f982'},
     'plain_kernel<F64, Ackley, 4, false, false>': {'traffic': 402775040, 'valu_flops': 5687476224, 'valu_insts': 204210176, 'mfma_flops': 0, 'classes': {'valu_add_f64': 11272192, 'valu_mul_f64': 16515072, 'valu_fma_f64': 30146560, 'valu_int32': 69206016, 'valu_int64': 6291456, 'valu_cvt': 9961472, 'valu_trans_f64': 786432, 'lds': 25952256, 'salu': 157810688}, 'sha': 'c9b5758bb627f982'},
@@ -79,20 +83,16 @@ COUNTERS = {
     'plain_kernel<F64, Rosenbrock, 2, false, false>': {'traffic': 402733056, 'valu_flops': 3992977408, 'valu_insts': 295698432, 'mfma_flops': 0, 'classes': {'valu_add_f64': 12058624, 'valu_mul_f64': 25165824, 'valu_fma_f64': 12582912, 'valu_int32': 125304832, 'valu_int64': 9961472, 'valu_cvt': 17825792, 'valu_trans_f64': 0, 'lds': 19922944, 'salu': 240648192}, 'sha': 'c9b5758bb627f982'},
     'plain_kernel<F64, Rosenbrock, 4, false, false>': {'traffic': 402734080, 'valu_flops': 1929379840, 'valu_insts': 145752064, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 12582912, 'valu_fma_f64': 6291456, 'valu_int32': 61603840, 'valu_int64': 4980736, 'valu_cvt': 8912896, 'valu_trans_f64': 0, 'lds': 8912896, 'salu': 118226944}, 'sha': 'c9b5758bb627f982'},
     'plain_kernel<F64, Rosenbrock, 8, false, false>': {'traffic': 402728960, 'valu_flops': 956301312, 'valu_insts': 77594624, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2359296, 'valu_mul_f64': 6291456, 'valu_fma_f64': 3145728, 'valu_int32': 33816576, 'valu_int64': 2883584, 'valu_cvt': 4718592, 'valu_trans_f64': 0, 'lds': 4718592, 'salu': 63176704}, 'sha': 'c9b5758bb627f982'},
-    'row16_kernel<F64, Ackley, 16>': {'traffic': 402708480, 'valu_flops': 4194304000, 'valu_insts': 72351744, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2621440, 'valu_mul_f64': 5242880, 'valu_fma_f64': 28573696, 'valu_int32': 524288, 'valu_int64': 1048576, 'valu_cvt': 786432, 'valu_trans_f64': 524288, 'lds': 0, 'salu': 16252928}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Ackley, 1>': {'traffic': 402722880, 'valu_flops': 4697620480, 'valu_insts': 97517568, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10747904, 'valu_mul_f64': 5505024, 'valu_fma_f64': 28311552, 'valu_int32': 4718592, 'valu_int64': 1048576, 'valu_cvt': 786432, 'valu_trans_f64': 524288, 'lds': 0, 'salu': 16252928}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Ackley, 2>': {'traffic': 402714624, 'valu_flops': 4429185024, 'valu_insts': 84934656, 'mfma_flops': 0, 'classes': {'valu_add_f64': 6553600, 'valu_mul_f64': 5505024, 'valu_fma_f64': 28311552, 'valu_int32': 2621440, 'valu_int64': 1048576, 'valu_cvt': 786432, 'valu_trans_f64': 524288, 'lds': 0, 'salu': 16252928}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Ackley, 4>': {'traffic': 402711552, 'valu_flops': 4294967296, 'valu_insts': 78643200, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4456448, 'valu_mul_f64': 5505024, 'valu_fma_f64': 28311552, 'valu_int32': 1572864, 'valu_int64': 1048576, 'valu_cvt': 786432, 'valu_trans_f64': 524288, 'lds': 0, 'salu': 16252928}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Ackley, 8>': {'traffic': 402707456, 'valu_flops': 4227858432, 'valu_insts': 75235328, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3407872, 'valu_mul_f64': 5505024, 'valu_fma_f64': 28311552, 'valu_int32': 786432, 'valu_int64': 1048576, 'valu_cvt': 786432, 'valu_trans_f64': 524288, 'lds': 0, 'salu': 16252928}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Rosenbrock, 16>': {'traffic': 402678784, 'valu_flops': 419430400, 'valu_insts': 15466496, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1048576, 'valu_mul_f64': 2359296, 'valu_fma_f64': 1572864, 'valu_int32': 524288, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Rosenbrock, 1>': {'traffic': 402728320, 'valu_flops': 5284823040, 'valu_insts': 100401152, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 37224448, 'valu_fma_f64': 20185088, 'valu_int32': 4194304, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Rosenbrock, 2>': {'traffic': 402702336, 'valu_flops': 3070230528, 'valu_insts': 70254592, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 5767168, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Rosenbrock, 4>': {'traffic': 402682880, 'valu_flops': 1593835520, 'valu_insts': 40894464, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 3407872, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': '26e8d7ea7df9ac29'},
-    'row16_kernel<F64, Rosenbrock, 8>': {'traffic': 402682880, 'valu_flops': 855638016, 'valu_insts': 25690112, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 1835008, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': '26e8d7ea7df9ac29'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=64': {'traffic': 403298432, 'valu_flops': 155239579648, 'valu_insts': 2216165376, 'mfma_flops': 0, 'classes': {'valu_add_f64': 45350912, 'valu_mul_f64': 51904512, 'valu_fma_f64': 1164181504, 'valu_int32': 412876800, 'valu_int64': 123731968, 'valu_cvt': 117178368, 'valu_trans_f64': 0, 'lds': 192413696, 'salu': 677642240}, 'sha': '2e3a289a8c793dc7'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=64': {'traffic': 403293184, 'valu_flops': 124772155392, 'valu_insts': 2056388608, 'mfma_flops': 0, 'classes': {'valu_add_f64': 53477376, 'valu_mul_f64': 81526784, 'valu_fma_f64': 907280384, 'valu_int32': 452460544, 'valu_int64': 116391936, 'valu_cvt': 98304000, 'valu_trans_f64': 0, 'lds': 246677504, 'salu': 493944832}, 'sha': '2e3a289a8c793dc7'},
-    'fp_dpp_kernel<F64, 16, false, false, false> n=512': {'traffic': 38173888, 'valu_flops': 291201089536, 'valu_insts': 3469672448, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10928128, 'valu_mul_f64': 75595776, 'valu_fma_f64': 2231746560, 'valu_int32': 520953856, 'valu_int64': 27066368, 'valu_cvt': 151175168, 'valu_trans_f64': 0, 'lds': 338042880, 'salu': 943480832}, 'sha': '2e3a289a8c793dc7'},
-    'fp_dpp_kernel<F64, 16, false, false, true> n=512': {'traffic': 29803520, 'valu_flops': 164213817344, 'valu_insts': 1957695488, 'mfma_flops': 0, 'classes': {'valu_add_f64': 8224768, 'valu_mul_f64': 44359680, 'valu_fma_f64': 1256628224, 'valu_int32': 282664960, 'valu_int64': 21958656, 'valu_cvt': 84000768, 'valu_trans_f64': 0, 'lds': 191954944, 'salu': 523919360}, 'sha': '2e3a289a8c793dc7'},
+    'row16_ackley_kernel<F64, 16>': {'traffic': 402787328, 'valu_flops': 3024093184, 'valu_insts': 56426496, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2424832, 'valu_mul_f64': 3276800, 'valu_fma_f64': 20709376, 'valu_int32': 983040, 'valu_int64': 1048576, 'valu_cvt': 393216, 'valu_trans_f64': 131072, 'lds': 2097152, 'salu': 9109504}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_ackley_kernel<F64, 1>': {'traffic': 402843136, 'valu_flops': 3527409664, 'valu_insts': 78118912, 'mfma_flops': 0, 'classes': {'valu_add_f64': 10551296, 'valu_mul_f64': 3538944, 'valu_fma_f64': 20447232, 'valu_int32': 2031616, 'valu_int64': 1048576, 'valu_cvt': 393216, 'valu_trans_f64': 131072, 'lds': 2097152, 'salu': 9109504}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_ackley_kernel<F64, 2>': {'traffic': 402807808, 'valu_flops': 3258974208, 'valu_insts': 67239936, 'mfma_flops': 0, 'classes': {'valu_add_f64': 6356992, 'valu_mul_f64': 3538944, 'valu_fma_f64': 20447232, 'valu_int32': 1507328, 'valu_int64': 1048576, 'valu_cvt': 393216, 'valu_trans_f64': 131072, 'lds': 2097152, 'salu': 9109504}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_ackley_kernel<F64, 4>': {'traffic': 402797568, 'valu_flops': 3124756480, 'valu_insts': 61669376, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4259840, 'valu_mul_f64': 3538944, 'valu_fma_f64': 20447232, 'valu_int32': 1179648, 'valu_int64': 1048576, 'valu_cvt': 393216, 'valu_trans_f64': 131072, 'lds': 2097152, 'salu': 9109504}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_ackley_kernel<F64, 8>': {'traffic': 402793216, 'valu_flops': 3057647616, 'valu_insts': 58785792, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3211264, 'valu_mul_f64': 3538944, 'valu_fma_f64': 20447232, 'valu_int32': 1048576, 'valu_int64': 1048576, 'valu_cvt': 393216, 'valu_trans_f64': 131072, 'lds': 2097152, 'salu': 9109504}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_kernel<F64, Rosenbrock, 16>': {'traffic': 402678784, 'valu_flops': 419430400, 'valu_insts': 15466496, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1048576, 'valu_mul_f64': 2359296, 'valu_fma_f64': 1572864, 'valu_int32': 524288, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_kernel<F64, Rosenbrock, 1>': {'traffic': 402728256, 'valu_flops': 5284823040, 'valu_insts': 100401152, 'mfma_flops': 0, 'classes': {'valu_add_f64': 4980736, 'valu_mul_f64': 37224448, 'valu_fma_f64': 20185088, 'valu_int32': 4194304, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_kernel<F64, Rosenbrock, 2>': {'traffic': 402702336, 'valu_flops': 3070230528, 'valu_insts': 70254592, 'mfma_flops': 0, 'classes': {'valu_add_f64': 3145728, 'valu_mul_f64': 23330816, 'valu_fma_f64': 10747904, 'valu_int32': 5767168, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_kernel<F64, Rosenbrock, 4>': {'traffic': 402682880, 'valu_flops': 1593835520, 'valu_insts': 40894464, 'mfma_flops': 0, 'classes': {'valu_add_f64': 2097152, 'valu_mul_f64': 11796480, 'valu_fma_f64': 5505024, 'valu_int32': 3407872, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': 'e90b3e505afc6dd6'},
+    'row16_kernel<F64, Rosenbrock, 8>': {'traffic': 402682880, 'valu_flops': 855638016, 'valu_insts': 25690112, 'mfma_flops': 0, 'classes': {'valu_add_f64': 1572864, 'valu_mul_f64': 6029312, 'valu_fma_f64': 2883584, 'valu_int32': 1835008, 'valu_int64': 1048576, 'valu_cvt': 0, 'valu_trans_f64': 0, 'lds': 0, 'salu': 2621440}, 'sha': 'e90b3e505afc6dd6'},
 }
 
 # The sources each kernel family is compiled from (with the build flags and,
